@@ -1,0 +1,345 @@
+"""Seeded synthetic 0-1 ILP generators.
+
+This module produces problem *inputs* only: a cost vector and a list of linear
+rows (Sec. 3, Def. "Binary Program" and Example "ILP": one subproblem per row).
+It holds none of the solver's arithmetic, so both the FP64 CPU reference
+implementation and the HIP path can consume the same instances.
+
+The paper's benchmark datasets (Sec. 6, "Datasets") are not available, so
+these generators stand in for them with the *shapes* of the three families it
+evaluates on: grid MRFs written as ILPs (simplex + marginalisation rows),
+graph-matching assignment problems with linearised pairwise terms, and
+cell-tracking flow problems with conflict sets.  Every generator takes an
+explicit seed and draws from ``numpy.random.default_rng(seed)``.
+
+Row encoding (CSR): ``row_ptr[n_rows+1]``, ``col[nnz]`` (int32 variable ids,
+distinct within a row), ``coef[nnz]`` (int32), ``sense[n_rows]`` in
+{-1: <=, 0: ==, +1: >=}, ``rhs[n_rows]`` (int64).  Columns inside a row are
+stored in ascending variable order; the variable numbering fixes the BDD
+variable order (Alg. 1 visits the variables of a subproblem in ascending order).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+LE, EQ, GE = -1, 0, 1
+
+
+@dataclass
+class ILP:
+    """min c^T x  s.t. each row  sum_k coef_k x_{col_k}  (<=,==,>=)  rhs,  x binary."""
+
+    n_vars: int
+    costs: np.ndarray      # float64 [n_vars]
+    row_ptr: np.ndarray    # int64 [n_rows + 1]
+    col: np.ndarray        # int32 [nnz]
+    coef: np.ndarray       # int32 [nnz]
+    sense: np.ndarray      # int8 [n_rows]
+    rhs: np.ndarray        # int64 [n_rows]
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.sense.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def row(self, r: int):
+        a, b = int(self.row_ptr[r]), int(self.row_ptr[r + 1])
+        return self.col[a:b], self.coef[a:b], int(self.sense[r]), int(self.rhs[r])
+
+
+def from_rows(n_vars, costs, rows, name="", meta=None) -> ILP:
+    """Build an ILP from a list of ``(cols, coefs, sense, rhs)`` tuples.
+
+    Columns of each row are sorted ascending; duplicates are rejected.
+    """
+    row_ptr = [0]
+    cols, coefs, senses, rhss = [], [], [], []
+    for c, a, s, b in rows:
+        c = np.asarray(c, dtype=np.int64)
+        a = np.asarray(a, dtype=np.int64)
+        order = np.argsort(c, kind="stable")
+        c, a = c[order], a[order]
+        if c.size > 1 and np.any(c[1:] == c[:-1]):
+            raise ValueError("duplicate variable in a row")
+        cols.append(c)
+        coefs.append(a)
+        senses.append(int(s))
+        rhss.append(int(b))
+        row_ptr.append(row_ptr[-1] + c.size)
+    return ILP(
+        n_vars=int(n_vars),
+        costs=np.asarray(costs, dtype=np.float64).copy(),
+        row_ptr=np.asarray(row_ptr, dtype=np.int64),
+        col=(np.concatenate(cols) if cols else np.zeros(0)).astype(np.int32),
+        coef=(np.concatenate(coefs) if coefs else np.zeros(0)).astype(np.int32),
+        sense=np.asarray(senses, dtype=np.int8),
+        rhs=np.asarray(rhss, dtype=np.int64),
+        name=name,
+        meta=dict(meta or {}),
+    )
+
+
+# --------------------------------------------------------------------------
+# Grid MRF (stand-in for the OpenGM color-seg / object-seg families)
+# --------------------------------------------------------------------------
+def mrf_grid(height: int, width: int, labels: int, pairwise: str = "potts",
+             potts_weight: float = 0.5, trunc: int = 2, seed: int = 0) -> ILP:
+    """4-connected grid MRF written as a 0-1 ILP.
+
+    Variables: x_{p,l} = p*L + l (pixel p row-major), then
+    y_{e,l,l'} = L*#px + e*L^2 + l*L + l'.  Edges: all horizontal edges
+    (row-major), then all vertical ones.  Rows: one simplex row
+    sum_l x_{p,l} = 1 per pixel; per edge e=(u,v), for each l the row
+    sum_{l'} y_{e,l,l'} - x_{u,l} = 0, then for each l' the row
+    sum_l y_{e,l,l'} - x_{v,l'} = 0.
+    Costs: unary N(0,1); pairwise either Potts ``potts_weight*[l != l']`` or
+    truncated linear ``w_e * min(|l-l'|, trunc)`` with w_e ~ U(0,1) per edge.
+    """
+    rng = np.random.default_rng(seed)
+    H, W, L = int(height), int(width), int(labels)
+    npx = H * W
+    pid = np.arange(npx, dtype=np.int64).reshape(H, W)
+    eu = np.concatenate([pid[:, :-1].ravel(), pid[:-1, :].ravel()])
+    ev = np.concatenate([pid[:, 1:].ravel(), pid[1:, :].ravel()])
+    ne = eu.size
+    nx = npx * L
+    n_vars = nx + ne * L * L
+
+    unary = rng.standard_normal(nx)
+    ll = np.arange(L)
+    dist = np.abs(ll[:, None] - ll[None, :])
+    if pairwise == "potts":
+        pw = np.broadcast_to((potts_weight * (dist != 0)).astype(np.float64), (ne, L, L))
+    elif pairwise == "trunc_linear":
+        w = rng.random(ne)
+        pw = w[:, None, None] * np.minimum(dist, trunc)[None, :, :].astype(np.float64)
+    else:
+        raise ValueError(pairwise)
+    costs = np.concatenate([unary, np.asarray(pw, dtype=np.float64).reshape(-1)])
+
+    # simplex rows
+    s_cols = (np.arange(npx)[:, None] * L + ll[None, :]).astype(np.int64)       # [npx, L]
+    # edge rows: [ne, 2L, L+1]; x has a smaller id than every y so it comes first
+    ybase = nx + np.arange(ne)[:, None, None] * L * L                            # [ne,1,1]
+    y_u = ybase + ll[None, :, None] * L + ll[None, None, :]                      # row l: y_{e,l,*}
+    y_v = ybase + ll[None, None, :] * L + ll[None, :, None]                      # row l': y_{e,*,l'}
+    x_u = (eu[:, None] * L + ll[None, :])[:, :, None]
+    x_v = (ev[:, None] * L + ll[None, :])[:, :, None]
+    e_cols = np.concatenate([np.concatenate([x_u, y_u], axis=2),
+                             np.concatenate([x_v, y_v], axis=2)], axis=1)        # [ne, 2L, L+1]
+    e_coef = np.ones(L + 1, dtype=np.int64)
+    e_coef[0] = -1
+
+    n_rows = npx + ne * 2 * L
+    col = np.concatenate([s_cols.ravel(), e_cols.ravel()]).astype(np.int32)
+    coef = np.concatenate([np.ones(npx * L, dtype=np.int64),
+                           np.tile(e_coef, ne * 2 * L)]).astype(np.int32)
+    lens = np.concatenate([np.full(npx, L, dtype=np.int64),
+                           np.full(ne * 2 * L, L + 1, dtype=np.int64)])
+    row_ptr = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    sense = np.zeros(n_rows, dtype=np.int8)
+    rhs = np.concatenate([np.ones(npx, dtype=np.int64), np.zeros(ne * 2 * L, dtype=np.int64)])
+    return ILP(n_vars, costs, row_ptr, col, coef, sense, rhs,
+               name=f"mrf{H}x{W}L{L}-{pairwise}",
+               meta=dict(height=H, width=W, labels=L, edges=ne, seed=seed))
+
+
+# --------------------------------------------------------------------------
+# Graph matching (stand-in for the hotel / house / worms families)
+# --------------------------------------------------------------------------
+def graph_matching(n_left: int = 1000, n_right: int = 1000, k: int = 10,
+                   n_pairs: int = 1000, seed: int = 3) -> ILP:
+    """Assignment problem with linearised pairwise terms.
+
+    Each left point p has ``k`` candidate right points: a planted match pi(p)
+    (pi a random injection) plus k-1 other distinct random right points,
+    stored in ascending right-index order.  x_{p,s} = p*k + s.
+    Rows: exactly-one over the candidates of every left point; at-most-one over
+    the incoming candidates of every right point (empty ones omitted).
+    ``n_pairs`` distinct random left pairs (p, p') each carry k*k variables
+    y_{q,s,t} = n_left*k + q*k*k + s*k + t, tied to x by marginalisation rows
+    sum_t y_{q,s,t} - x_{p,s} = 0 (for every s) and
+    sum_s y_{q,s,t} - x_{p',t} = 0 (for every t).  Costs N(0,1).
+    The planted matching makes the instance feasible.
+    """
+    if n_left > n_right:
+        raise ValueError("need n_left <= n_right")
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n_right)[:n_left]
+    cand = np.empty((n_left, k), dtype=np.int64)
+    for p in range(n_left):
+        others = rng.choice(n_right - 1, size=k - 1, replace=False)
+        others = others + (others >= perm[p])          # skip the planted one
+        cand[p] = np.sort(np.concatenate([[perm[p]], others]))
+    nx = n_left * k
+    pairs = []
+    seen = set()
+    while len(pairs) < n_pairs:
+        p, q = (int(v) for v in rng.integers(0, n_left, size=2))
+        if p == q:
+            continue
+        key = (min(p, q), max(p, q))
+        if key in seen:
+            continue
+        seen.add(key)
+        pairs.append(key)
+    n_vars = nx + n_pairs * k * k
+    costs = rng.standard_normal(n_vars)
+
+    rows = []
+    for p in range(n_left):
+        rows.append((np.arange(p * k, (p + 1) * k), np.ones(k), EQ, 1))
+    tgt = cand.ravel()
+    order = np.argsort(tgt, kind="stable")
+    bounds = np.searchsorted(tgt[order], np.arange(n_right + 1))
+    for b in range(n_right):
+        xs = order[bounds[b]:bounds[b + 1]]
+        if xs.size:
+            rows.append((xs, np.ones(xs.size), LE, 1))
+    kk = np.arange(k)
+    for qi, (p, pp) in enumerate(pairs):
+        yb = nx + qi * k * k
+        for s in range(k):
+            rows.append((np.concatenate([[p * k + s], yb + s * k + kk]),
+                         np.concatenate([[-1], np.ones(k)]), EQ, 0))
+        for t in range(k):
+            rows.append((np.concatenate([[pp * k + t], yb + kk * k + t]),
+                         np.concatenate([[-1], np.ones(k)]), EQ, 0))
+    return from_rows(n_vars, costs, rows, name=f"gm{n_left}x{n_right}k{k}q{n_pairs}",
+                     meta=dict(seed=seed, planted=perm))
+
+
+# --------------------------------------------------------------------------
+# Cell tracking (stand-in for the cell-tracking family)
+# --------------------------------------------------------------------------
+def cell_tracking(frames: int = 20, dets: int = 500, max_succ: int = 6,
+                  conflicts_per_frame: int = 100, max_row_len: int = 20,
+                  seed: int = 4) -> ILP:
+    """Flow-shaped tracking ILP.
+
+    Detection (t, d) owns x (active), app (appears), dis (disappears) with ids
+    3*(t*dets+d) + {0,1,2}.  Every detection of frames 0..T-2 draws
+    k ~ U{1..max_succ} distinct successors in frame t+1 (only among detections
+    whose incoming row still has room), one move variable per successor, and
+    min(2, C(k,2)) division variables, each a distinct successor pair.  Move and
+    division ids follow the detection ids in creation order.
+    Rows: incoming  app + sum(moves in) + sum(divisions in) - x = 0 for every
+    detection, then outgoing  dis + sum(moves out) + sum(divisions out) - x = 0,
+    then per frame ``conflicts_per_frame`` at-most-one rows over U{2..6}
+    distinct detections.  No row exceeds ``max_row_len`` variables.
+    Costs U(-1,1).  x = 0 is feasible.
+    """
+    rng = np.random.default_rng(seed)
+    ndet = frames * dets
+    nv = 3 * ndet
+    in_lists = [[] for _ in range(ndet)]
+    out_lists = [[] for _ in range(ndet)]
+    in_len = np.full(ndet, 2, dtype=np.int64)
+    for t in range(frames - 1):
+        for d in range(dets):
+            me = t * dets + d
+            kk = int(rng.integers(1, max_succ + 1))
+            base = (t + 1) * dets
+            avail = np.nonzero(in_len[base:base + dets] < max_row_len)[0]
+            if avail.size == 0:
+                continue
+            kk = min(kk, avail.size)
+            succ = np.sort(rng.choice(avail, size=kk, replace=False)) + base
+            for s in succ:
+                out_lists[me].append(nv)
+                in_lists[s].append(nv)
+                in_len[s] += 1
+                nv += 1
+            if kk >= 2:
+                cand_pairs = [(a, b) for ai, a in enumerate(succ) for b in succ[ai + 1:]
+                              if in_len[a] < max_row_len and in_len[b] < max_row_len]
+                ndiv = min(2, len(cand_pairs))
+                if ndiv:
+                    pick = rng.choice(len(cand_pairs), size=ndiv, replace=False)
+                    for pi in np.sort(pick):
+                        a, b = cand_pairs[pi]
+                        if in_len[a] >= max_row_len or in_len[b] >= max_row_len:
+                            continue
+                        out_lists[me].append(nv)
+                        in_lists[a].append(nv)
+                        in_lists[b].append(nv)
+                        in_len[a] += 1
+                        in_len[b] += 1
+                        nv += 1
+    rows = []
+    for det in range(ndet):
+        xv = 3 * det
+        cols = [xv + 1, xv] + in_lists[det]
+        rows.append((cols, [1, -1] + [1] * len(in_lists[det]), EQ, 0))
+    for det in range(ndet):
+        xv = 3 * det
+        cols = [xv + 2, xv] + out_lists[det]
+        rows.append((cols, [1, -1] + [1] * len(out_lists[det]), EQ, 0))
+    for t in range(frames):
+        for _ in range(conflicts_per_frame):
+            g = int(rng.integers(2, 7))
+            ds = rng.choice(dets, size=g, replace=False)
+            rows.append((3 * (t * dets + ds), np.ones(g), LE, 1))
+    costs = rng.uniform(-1.0, 1.0, size=nv)
+    return from_rows(nv, costs, rows, name=f"track{frames}x{dets}", meta=dict(seed=seed))
+
+
+# --------------------------------------------------------------------------
+# Small random ILPs for property tests
+# --------------------------------------------------------------------------
+def random_ilp(n_vars: int, n_rows: int, max_row_len: int = 5, coef_range: int = 3,
+               seed: int = 0, integer_costs: bool = False, max_slack: int = 2) -> ILP:
+    """Random feasible ILP: rows are built around a hidden binary point x*.
+
+    Row r picks U{1..max_row_len} distinct variables, nonzero coefficients in
+    [-coef_range, coef_range], a random sense, and rhs = a.x* plus a slack of
+    the sense's sign (0 for equalities), so x* satisfies every row.
+    Costs are N(0,1), or integers in [-4, 4] when ``integer_costs``.
+    """
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, 2, size=n_vars)
+    rows = []
+    for _ in range(n_rows):
+        s = int(rng.integers(1, min(max_row_len, n_vars) + 1))
+        vs = rng.choice(n_vars, size=s, replace=False)
+        mag = rng.integers(1, coef_range + 1, size=s)
+        sg = rng.choice([-1, 1], size=s)
+        a = mag * sg
+        sense = int(rng.integers(-1, 2))
+        lhs = int(np.dot(a, xs[vs]))
+        slack = int(rng.integers(0, max_slack + 1))
+        rhs = lhs + (slack if sense == LE else -slack if sense == GE else 0)
+        rows.append((vs, a, sense, rhs))
+    if integer_costs:
+        costs = rng.integers(-4, 5, size=n_vars).astype(np.float64)
+    else:
+        costs = rng.standard_normal(n_vars)
+    return from_rows(n_vars, costs, rows, name=f"rand{n_vars}x{n_rows}s{seed}",
+                     meta=dict(seed=seed, hidden=xs))
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+def workload(name: str) -> ILP:
+    """The named synthetic workloads (seed = workload number)."""
+    if name == "mrf10x10L3":
+        return mrf_grid(10, 10, 3, pairwise="potts", potts_weight=0.5, seed=1)
+    if name == "mrf256x256L8":
+        return mrf_grid(256, 256, 8, pairwise="trunc_linear", trunc=2, seed=2)
+    if name == "gm1000k10":
+        return graph_matching(1000, 1000, 10, 1000, seed=3)
+    if name == "track20x500":
+        return cell_tracking(20, 500, seed=4)
+    raise KeyError(name)
+
+
+WORKLOADS = ("mrf10x10L3", "mrf256x256L8", "gm1000k10", "track20x500")
