@@ -1,0 +1,184 @@
+"""Benchmark of the BDD Lagrange-decomposition hot path on one MI355X.
+
+One step = one whole solve of the workload with the inputs resident in HBM:
+re-initialise the multipliers (Alg. 1 initialisation), run the dual iterations
+(forward sweep, averaging, backward sweep, averaging, FP64 bound reduction per
+sweep), compute the certified FP64 bound, and run the perturbation rounding
+(Alg. 2, including its termination step and exact row check).  Prints one JSON
+line.  ``value`` counts every Alg. 1 iteration executed inside the timed steps
+(the main ones and those of the rounding's re-optimisation) per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2111_10270_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_mrf256x256L8_traffic.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mrf256x256L8")
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_sweep"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(ilp, n_iter):
+    import oracle
+
+    ref = oracle.Oracle(ilp)
+    ref.init()
+    t = time.perf_counter()
+    ref.run_dual(n_iter)
+    dt = time.perf_counter() - t
+    return dict(value=n_iter / dt, unit="dual iters/s", cores=1, kind="oracle",
+                sample=f"{n_iter} Alg. 1 iterations of the same instance, FP64, one thread "
+                       f"({dt:.1f} s; BDD construction not timed)")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if a.calibrate_copy:
+        n = a.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n}), flush=True)
+        return
+
+    from paper_2111_10270_amd import binding as B
+    from paper_2111_10270_amd import instances as I
+
+    ilp = I.workload(a.workload)
+    s = B.Solver(ilp, precision=a.precision)
+    s.bind("cuda:0")
+    st = s.stats
+    N, P, V = st.n_nodes, st.n_pairs, st.n_vars
+    stream = s.stream
+
+    def step():
+        s.reset()
+        s.run_dual(a.iters)
+        lf, lc, res = s.lower_bound()
+        r = s.round_primal()
+        return lf, lc, res, r
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    s.profile(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * a.steps + 2)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    iters = 0
+    results = []
+    dual_ms = 0.0
+    for k in range(a.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.reset()
+        s.run_dual(a.iters)
+        e1.record(stream)
+        lf, lc, res = s.lower_bound()
+        r = s.round_primal()
+        torch.cuda.synchronize()
+        dual_ms += e0.elapsed_time(e1)
+        iters += a.iters + r["rounds"] * s.options.reopt_iters
+        results.append((lf, lc, res, r))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_step = wall * 1e3 / a.steps
+
+    n_f, t_f = s.kernel_time(B.K_SWEEP_FWD)
+    n_b, t_b = s.kernel_time(B.K_SWEEP_BWD)
+    n_a, t_a = s.kernel_time(B.K_AVERAGE)
+    n_r, t_r = s.kernel_time(B.K_LB_REDUCE)
+    s.profile(False)
+    sweep_ms = (t_f + t_b) / max(1, n_f + n_b)
+    # algorithmic bytes of one sweep launch: 16 B per node + 20 B per pair
+    alg_bytes = 16.0 * N + 20.0 * P
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    traffic = read_traffic()
+    lf, lc, res, r = results[-1]
+    out = {
+        "metric": "dual iters/s & BDD arcs/s vs HBM roofline; batched solves/s, p50/p99 latency",
+        "value": iters / wall,
+        "unit": "dual iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "iterations_per_solve": a.iters, "vars": V, "bdds": st.n_bdds,
+                   "pairs": P, "nodes": N, "precision_bound_sums": "f64"},
+        "arcs_per_s": 2.0 * N * iters / wall,
+        "dual_phase_iters_per_s": a.iters * a.steps / (dual_ms * 1e-3),
+        "dual_phase_arcs_per_s": 2.0 * N * a.iters * a.steps / (dual_ms * 1e-3),
+        "solves_per_s": a.steps / wall,
+        "kernel_ms": {"sweep": sweep_ms, "average": t_a / max(1, n_a), "lb_reduce": t_r / max(1, n_r)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "result": {"lb_free": lf, "lb_cert": lc, "max_residual": res, "ub": r["ub"] if r["rc"] == 0 else None,
+                   "rounding_rc": r["rc"], "rounding_rounds": r["rounds"]},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ilp, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

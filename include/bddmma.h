@@ -1,0 +1,212 @@
+/*
+ * bddmma — C ABI of the MI355X BDD Lagrange-decomposition solver for 0-1 ILPs
+ * (FastDOG, Abbas & Swoboda, CVPR 2022).
+ *
+ * Problem (Sec. 3, Def. "Binary Program" and Example "ILP"):
+ *     min c^T x   s.t.  every row  sum_k a_k x_{i_k}  (<=, ==, >=)  b,   x in {0,1}^n.
+ * Every row becomes one subproblem j with feasible set X_j, represented by a
+ * binary decision diagram (Sec. 5, Def. "BDD").  The solver maximises the
+ * Lagrangean dual (Sec. 3, problem (D)) with the parallel deferred
+ * min-marginal averaging of Alg. 1 and decodes primal points with the
+ * perturbation rounding of Alg. 2.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: BDDMMA_OK (0) or one of the negative codes below.  No C++
+ *    exception crosses this interface.  bddmma_last_error() returns a
+ *    thread-local, NUL-terminated message for the last failing call on the
+ *    calling thread (valid until that thread's next failing call).
+ *  - Host arrays passed in are read during the call only; the caller keeps
+ *    ownership.  Host output arrays are caller-allocated with the sizes that
+ *    the matching query returns.
+ *  - Device memory: the library allocates none.  After bddmma_load_ilp the
+ *    caller asks bddmma_workspace_bytes, allocates that many bytes of device
+ *    memory (256-byte aligned) and hands them over with bddmma_bind together
+ *    with a HIP stream.  The library never frees the buffer; it must stay
+ *    allocated until bddmma_destroy.  All device work is ordered on that
+ *    stream; calls that return host values synchronise it.
+ *  - Pair order: a "pair" is a (variable i, subproblem j) with i in I_j.
+ *    Host-visible pair arrays list subproblems in ascending original row
+ *    order and, inside one subproblem, variables in ascending id order.
+ *  - A solver is not thread safe; distinct solvers may be used concurrently.
+ */
+#ifndef BDDMMA_H
+#define BDDMMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDDMMA_OK                 0
+#define BDDMMA_ERR_INVALID_ARG   (-1) /* bad pointer, size, option or ILP data           */
+#define BDDMMA_ERR_INFEASIBLE    (-2) /* some row (after presolve) admits no 0-1 point   */
+#define BDDMMA_ERR_NO_MEMORY     (-3) /* workspace too small / host allocation failed   */
+#define BDDMMA_ERR_NOT_CONVERGED (-4) /* rounding hit max_rounds; dual state unchanged   */
+#define BDDMMA_ERR_HIP           (-5) /* a HIP runtime call failed                       */
+#define BDDMMA_ERR_STATE         (-6) /* call out of order (e.g. run before bind)        */
+
+typedef struct bddmma_solver bddmma_solver; /* opaque, owned by the library */
+
+typedef struct {
+    double   omega;        /* damping of the dual update (Sec. 3, parallel update), in (0,1]; 0.5 */
+    double   rel_tol;      /* stop run_dual when |dLB|/max(1,|LB|) < rel_tol between two
+                              consecutive iterations, checked every lb_every iterations; 0 = off */
+    int32_t  lb_every;     /* stopping-test period in iterations (>= 1); 1 */
+    int32_t  precision;    /* 32: FP32 multipliers / min-marginals, FP64 bound sums;
+                              64: FP64 throughout.  32 */
+    double   delta0;       /* Alg. 2 initial perturbation strength delta; 1.0 (Sec. 6) */
+    double   alpha;        /* Alg. 2 growth factor of delta per round; 1.2 (Sec. 6) */
+    int32_t  reopt_iters;  /* Alg. 1 iterations per rounding round; 5 */
+    int32_t  max_rounds;   /* rounding rounds before BDDMMA_ERR_NOT_CONVERGED; 200 */
+    double   tau;          /* |M| <= tau counts as a zero min-marginal difference in Alg. 2;
+                              < 0 selects 0 for precision 64 and 1e-6*max(1,max|c|) for 32 */
+    uint64_t seed;         /* counter-based random draws of Alg. 2; 0 */
+    int32_t  sp_in_lds_max_nodes; /* subproblems with more nodes keep their shortest
+                              paths in device memory instead of LDS; 0 = built-in limit,
+                              -1 = never use LDS */
+    int32_t  reserved[7];  /* must be zero */
+} bddmma_options;
+
+typedef struct {
+    int64_t n_vars, n_rows;       /* as loaded */
+    int64_t n_bdds;               /* subproblems after presolve (one per kept row) */
+    int64_t n_pairs;              /* (variable, subproblem) pairs */
+    int64_t n_nodes;              /* non-terminal BDD nodes (arcs = 2 * n_nodes) */
+    int64_t n_fixed;              /* variables fixed by presolve */
+    int64_t n_free;               /* variables in no kept row */
+    int64_t n_tiles;              /* 64-lane tiles of whole subproblems */
+    int64_t n_slots;              /* padded pair slots on the device */
+    int64_t max_layers, max_width;
+    double  lb_offset;            /* constant of fixed / unconstrained variables */
+} bddmma_stats;
+
+/* Fill *opt with the defaults listed above.  INVALID_ARG if opt is NULL. */
+int bddmma_options_default(bddmma_options *opt);
+
+/* Create an empty solver.  opt may be NULL (defaults).  INVALID_ARG on a bad
+ * option (omega outside (0,1], precision not 32/64, lb_every < 1, ...). */
+int bddmma_create(const bddmma_options *opt, bddmma_solver **out);
+
+/* Release the solver and its host memory (never the bound device buffer). */
+void bddmma_destroy(bddmma_solver *s);
+
+/* Load an ILP in CSR form (host memory, copied).  Host-only: needs no GPU.
+ *   costs[n_vars] (finite doubles); row_ptr[n_rows+1] (int64, non-decreasing,
+ *   row_ptr[0] = 0); col[nnz] variable ids in [0, n_vars), distinct inside a
+ *   row, any order; coef[nnz] int32 (zeros are dropped, Example "ILP":
+ *   I_j = {i : a_ji != 0}); sense[n_rows] in {-1: <=, 0: ==, +1: >=};
+ *   rhs[n_rows] int64.
+ * Presolve fixes every variable that one row allows only one value for and
+ * repeats until nothing changes; variables in no remaining row take
+ * x_i = [c_i < 0].  Every remaining row is compiled to a reduced ordered BDD
+ * in ascending variable order (Sec. 5, Defs. "BDD" and "Constraint Set
+ * Correspondence") and packed into 64-lane tiles.
+ * Errors: INVALID_ARG (bad CSR data, |coef| sums beyond int64, a BDD layer
+ * wider than 65533 nodes), INFEASIBLE (some row cannot be satisfied),
+ * STATE (already loaded). */
+int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64_t n_rows,
+                    const int64_t *row_ptr, const int32_t *col, const int32_t *coef,
+                    const int8_t *sense, const int64_t *rhs);
+
+/* Sizes of the loaded problem.  STATE before load. */
+int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *out);
+
+/* Device bytes needed by bddmma_bind.  STATE before load. */
+int bddmma_workspace_bytes(const bddmma_solver *s, size_t *bytes);
+
+/* Bind caller-owned device memory (dev_ptr, 256-byte aligned, >= workspace
+ * bytes) and a HIP stream (hipStream_t passed as void*, NULL = null stream).
+ * Copies the packed problem to the device and initialises the dual state:
+ * lambda_i^j = c_i / |J_i| and M-bar = 0 (Alg. 1 initialisation, Sec. 3).
+ * Errors: NO_MEMORY (bytes too small), INVALID_ARG (NULL / misaligned),
+ * STATE (not loaded or already bound), HIP. */
+int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* Re-initialise the dual state of a bound solver (lambda_i^j = c_i / |J_i|,
+ * M-bar = 0, empty bound history, sweep counter 0) without re-copying the
+ * problem.  STATE if not bound. */
+int bddmma_reset(bddmma_solver *s);
+
+/* Run n_iter iterations of Alg. 1 (forward sweep, averaging, backward sweep,
+ * averaging; the deferred differences are refreshed after every sweep) from
+ * the current state.  Records LB_free after every sweep.  Stops early on the
+ * rel_tol test.  *iters_done (may be NULL) gets the iterations run.
+ * Stream-ordered; synchronises only at the end (and at stopping checks). */
+int bddmma_run_dual(bddmma_solver *s, int32_t n_iter, int32_t *iters_done);
+
+/* Run n half-sweeps, alternating direction and starting with the direction
+ * that follows the last sweep run (ascending first after bind), each followed
+ * by the averaging and the LB_free record.  run_dual(k) equals
+ * run_sweeps(2k) from an even sweep count. */
+int bddmma_run_sweeps(bddmma_solver *s, int32_t n_sweeps);
+
+/* Lower bounds of the current state (any pointer may be NULL):
+ *   lb_free  = sum_j E^j(lambda^j) + omega * sum_ij min(M_ij, 0)  of the last sweep;
+ *   lb_cert  = sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0), computed in
+ *              FP64 from the stored multipliers, with the multiplier residual
+ *              r_i = sum_j (lambda_i^j + omega M_ij) - c_i (Appendix, proof of
+ *              Prop. 1: this multiplier sum equals c_i);
+ *   max_residual = max_i |r_i|.
+ * Both bounds include the presolve constant.  Synchronises. */
+int bddmma_lower_bound(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_residual);
+
+/* LB_free after every sweep since bind (oldest first).  With out == NULL only
+ * *n is set.  Otherwise writes min(*n_total, cap) values and sets *n_total. */
+int bddmma_lb_history(const bddmma_solver *s, double *out, int64_t cap, int64_t *n_total);
+
+/* Number of pairs, and their (variable, original row) in pair order. */
+int bddmma_num_pairs(const bddmma_solver *s, int64_t *n_pairs);
+int bddmma_get_pairs(const bddmma_solver *s, int32_t *pair_var, int32_t *pair_row);
+
+/* Presolve result per variable: -1 free, 0 or 1 fixed.  fixed[n_vars]. */
+int bddmma_get_fixed(const bddmma_solver *s, int8_t *fixed);
+
+/* Feasible multipliers lambda_i^j + omega * M-bar_ij (the termination step of
+ * Alg. 1; they sum to c_i over J_i) and M-bar itself, in pair order, as
+ * doubles.  Either pointer may be NULL.  Does not change the state. */
+int bddmma_get_multipliers(bddmma_solver *s, double *lambda_out, double *mm_out);
+
+/* Raw solver state in pair order (lambda, M-bar) and per variable (the
+ * averaged term a_i = omega/|J_i| * sum_k M-bar_ik).  Either pointer may be
+ * NULL.  set_state converts to the working precision and resumes from it. */
+int bddmma_get_state(bddmma_solver *s, double *lambda, double *mm, double *avg);
+int bddmma_set_state(bddmma_solver *s, const double *lambda, const double *mm, const double *avg);
+
+/* Min-marginal differences M_ij = m^1 - m^0 (Sec. 3, defs. (MM), (MD)) of
+ * every pair at the current multipliers, without changing the state.
+ * mm_out[n_pairs] in pair order. */
+int bddmma_min_marginals(bddmma_solver *s, double *mm_out);
+
+/* Alg. 2 on a copy of the terminated multipliers; the dual state is restored
+ * afterwards.  On success x_out[n_vars] (0/1) satisfies every original row
+ * (checked exactly in int64 on the host), *ub = c^T x, *rounds = perturbation
+ * rounds used.  NOT_CONVERGED when max_rounds rounds did not remove every
+ * conflict (x_out untouched).  Any output pointer except x_out may be NULL. */
+int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds);
+
+/* Checkpoint of the dual state (multipliers, deferred differences, averaged
+ * terms, sweep counter, bound history).  With buf == NULL sets *bytes to the
+ * size needed.  load_state requires the same loaded problem and precision;
+ * resuming from it is bitwise identical to not stopping. */
+int bddmma_save_state(const bddmma_solver *s, void *buf, size_t *bytes);
+int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes);
+
+/* Per-kernel timing with HIP events recorded on the bound stream around each
+ * launch.  enable != 0 starts a new collection.  kernel ids: BDDMMA_K_*.
+ * bddmma_kernel_time synchronises and reports launches and total milliseconds. */
+#define BDDMMA_K_SWEEP_FWD 0
+#define BDDMMA_K_SWEEP_BWD 1
+#define BDDMMA_K_AVERAGE   2
+#define BDDMMA_K_LB_REDUCE 3
+#define BDDMMA_K_COUNT     4
+int bddmma_profile(bddmma_solver *s, int enable);
+int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *total_ms);
+
+const char *bddmma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDDMMA_H */

@@ -1,0 +1,232 @@
+"""ctypes binding of the solver's C ABI (include/bddmma.h).
+
+Argument marshalling only: every step of the method runs in the HIP/C++
+library.  PyTorch provides the device workspace and the stream.  There is no
+fallback: without ``libbddmma.so`` every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbddmma.so")
+
+OK, INVALID_ARG, INFEASIBLE, NO_MEMORY, NOT_CONVERGED, HIP_ERROR, STATE = 0, -1, -2, -3, -4, -5, -6
+K_SWEEP_FWD, K_SWEEP_BWD, K_AVERAGE, K_LB_REDUCE = 0, 1, 2, 3
+KERNEL_NAMES = {K_SWEEP_FWD: "sweep_fwd", K_SWEEP_BWD: "sweep_bwd", K_AVERAGE: "average", K_LB_REDUCE: "lb_reduce"}
+
+# every entry point the header declares (checked by the tests)
+EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_load_ilp", "bddmma_get_stats",
+           "bddmma_workspace_bytes", "bddmma_bind", "bddmma_reset", "bddmma_run_dual", "bddmma_run_sweeps", "bddmma_lower_bound",
+           "bddmma_lb_history", "bddmma_num_pairs", "bddmma_get_pairs", "bddmma_get_fixed",
+           "bddmma_get_multipliers", "bddmma_get_state", "bddmma_set_state", "bddmma_min_marginals",
+           "bddmma_round_primal", "bddmma_save_state", "bddmma_load_state", "bddmma_profile",
+           "bddmma_kernel_time", "bddmma_last_error")
+
+
+class BddmmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bddmma error {code}: {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("omega", C.c_double), ("rel_tol", C.c_double), ("lb_every", C.c_int32),
+                ("precision", C.c_int32), ("delta0", C.c_double), ("alpha", C.c_double),
+                ("reopt_iters", C.c_int32), ("max_rounds", C.c_int32), ("tau", C.c_double),
+                ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_vars", C.c_int64), ("n_rows", C.c_int64), ("n_bdds", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_nodes", C.c_int64), ("n_fixed", C.c_int64), ("n_free", C.c_int64), ("n_tiles", C.c_int64),
+                ("n_slots", C.c_int64), ("max_layers", C.c_int64), ("max_width", C.c_int64),
+                ("lb_offset", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbddmma.so (built by ``paper_2111_10270_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2111_10270_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "bddmma_options_default": [P], "bddmma_create": [P, P], "bddmma_destroy": [P],
+            "bddmma_load_ilp": [P, i64, P, i64, P, P, P, P, P], "bddmma_get_stats": [P, P],
+            "bddmma_workspace_bytes": [P, P], "bddmma_bind": [P, P, C.c_size_t, P], "bddmma_reset": [P],
+            "bddmma_run_dual": [P, i32, P], "bddmma_run_sweeps": [P, i32], "bddmma_lower_bound": [P, P, P, P],
+            "bddmma_lb_history": [P, P, i64, P], "bddmma_num_pairs": [P, P], "bddmma_get_pairs": [P, P, P],
+            "bddmma_get_fixed": [P, P], "bddmma_get_multipliers": [P, P, P], "bddmma_get_state": [P, P, P, P],
+            "bddmma_set_state": [P, P, P, P], "bddmma_min_marginals": [P, P], "bddmma_round_primal": [P, P, P, P],
+            "bddmma_save_state": [P, P, P], "bddmma_load_state": [P, P, C.c_size_t],
+            "bddmma_profile": [P, C.c_int], "bddmma_kernel_time": [P, C.c_int, P, P], "bddmma_last_error": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.bddmma_destroy.restype = None
+        L.bddmma_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc):
+    if rc != OK:
+        raise BddmmaError(rc, lib().bddmma_last_error().decode())
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(lib().bddmma_options_default(C.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """One ILP on one device: load (host) -> bind (device workspace) -> solve."""
+
+    def __init__(self, ilp, **options):
+        L = lib()
+        self._h = C.c_void_p()
+        self.options = default_options(**options)
+        _check(L.bddmma_create(C.byref(self.options), C.byref(self._h)))
+        self.ilp = ilp
+        arrs = [np.ascontiguousarray(ilp.costs, dtype=np.float64), np.ascontiguousarray(ilp.row_ptr, dtype=np.int64),
+                np.ascontiguousarray(ilp.col, dtype=np.int32), np.ascontiguousarray(ilp.coef, dtype=np.int32),
+                np.ascontiguousarray(ilp.sense, dtype=np.int8), np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
+        _check(L.bddmma_load_ilp(self._h, ilp.n_vars, _p(arrs[0]), ilp.n_rows, *[_p(a) for a in arrs[1:]]))
+        st = Stats()
+        _check(L.bddmma_get_stats(self._h, C.byref(st)))
+        self.stats = st
+        self.workspace = None
+        self.stream = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().bddmma_destroy(h)
+            self._h = None
+
+    # ---- device binding ----
+    def workspace_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(lib().bddmma_workspace_bytes(self._h, C.byref(n)))
+        return n.value
+
+    def bind(self, device="cuda", stream=None):
+        import torch
+        nbytes = self.workspace_bytes()
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        _check(lib().bddmma_bind(self._h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                 C.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    # ---- Alg. 1 ----
+    def reset(self):
+        _check(lib().bddmma_reset(self._h))
+
+    def run_dual(self, n_iter: int) -> int:
+        done = C.c_int32()
+        _check(lib().bddmma_run_dual(self._h, int(n_iter), C.byref(done)))
+        return done.value
+
+    def run_sweeps(self, n: int):
+        _check(lib().bddmma_run_sweeps(self._h, int(n)))
+
+    def lower_bound(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().bddmma_lower_bound(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def lb_history(self) -> np.ndarray:
+        n = C.c_int64()
+        _check(lib().bddmma_lb_history(self._h, None, 0, C.byref(n)))
+        out = np.zeros(n.value)
+        _check(lib().bddmma_lb_history(self._h, _p(out), n.value, C.byref(n)))
+        return out
+
+    # ---- structure and state ----
+    @property
+    def n_pairs(self) -> int:
+        return int(self.stats.n_pairs)
+
+    def pairs(self):
+        pv = np.zeros(self.n_pairs, dtype=np.int32)
+        pr = np.zeros(self.n_pairs, dtype=np.int32)
+        _check(lib().bddmma_get_pairs(self._h, _p(pv), _p(pr)))
+        return pv, pr
+
+    def fixed(self):
+        f = np.zeros(self.ilp.n_vars, dtype=np.int8)
+        _check(lib().bddmma_get_fixed(self._h, _p(f)))
+        return f
+
+    def multipliers(self):
+        lam = np.zeros(self.n_pairs)
+        mm = np.zeros(self.n_pairs)
+        _check(lib().bddmma_get_multipliers(self._h, _p(lam), _p(mm)))
+        return lam, mm
+
+    def get_state(self):
+        lam = np.zeros(self.n_pairs)
+        mm = np.zeros(self.n_pairs)
+        avg = np.zeros(self.ilp.n_vars)
+        _check(lib().bddmma_get_state(self._h, _p(lam), _p(mm), _p(avg)))
+        return lam, mm, avg
+
+    def set_state(self, lam=None, mm=None, avg=None):
+        conv = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (lam, mm, avg)]
+        _check(lib().bddmma_set_state(self._h, *[_p(a) for a in conv]))
+
+    def min_marginals(self):
+        out = np.zeros(self.n_pairs)
+        _check(lib().bddmma_min_marginals(self._h, _p(out)))
+        return out
+
+    # ---- Alg. 2 ----
+    def round_primal(self):
+        x = np.zeros(self.ilp.n_vars, dtype=np.uint8)
+        ub, rounds = C.c_double(), C.c_int32()
+        rc = lib().bddmma_round_primal(self._h, _p(x), C.byref(ub), C.byref(rounds))
+        if rc not in (OK, NOT_CONVERGED):
+            _check(rc)
+        return dict(rc=rc, x=x, ub=ub.value, rounds=rounds.value)
+
+    # ---- checkpoint ----
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().bddmma_save_state(self._h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(lib().bddmma_save_state(self._h, buf, C.byref(n)))
+        return bytes(buf)
+
+    def load_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().bddmma_load_state(self._h, buf, len(blob)))
+
+    # ---- profiling ----
+    def profile(self, enable: bool = True):
+        _check(lib().bddmma_profile(self._h, int(bool(enable))))
+
+    def kernel_time(self, kernel: int):
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().bddmma_kernel_time(self._h, int(kernel), C.byref(n), C.byref(ms)))
+        return n.value, ms.value

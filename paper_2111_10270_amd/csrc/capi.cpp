@@ -1,0 +1,845 @@
+// C ABI of the solver: state, workspace layout, Alg. 1 / Alg. 2 driver loops.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bddmma.h"
+#include "kernels.hpp"
+#include "problem.hpp"
+
+using namespace bddmma;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kHistCap = 4096;          // LB_free entries kept on the device between host copies
+constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t lam, mm, lam_bak, mm_bak, mmx, avg, avg_bak;
+    size_t pair_var, vptr, vslot, child, tiles, layers, cost;
+    size_t tile_lb, tile_e, red, lbh, counter, flag, x, scratch;
+    size_t total;
+};
+
+struct Events {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> used[BDDMMA_K_COUNT];
+    std::vector<hipEvent_t> pool;
+};
+
+}  // namespace
+
+struct bddmma_solver {
+    bddmma_options opt{};
+    bool loaded = false, bound = false;
+    Problem prob;
+    Packed pk;
+    int elem = 4;
+    Layout L{};
+    char *dev = nullptr;
+    hipStream_t st = nullptr;
+    DevProblem dp{};
+    int64_t sweeps = 0;           // sweeps run since bind
+    int64_t hist_synced = 0;      // history entries already on the host
+    std::vector<double> hist;     // LB_free after every sweep
+    bool prof = false;
+    Events ev;
+    double tau = 0.0;
+
+    template <typename T>
+    T *ptr(size_t off) const { return reinterpret_cast<T *>(dev + off); }
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return fail(BDDMMA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BDDMMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return BDDMMA_OK;
+}
+
+Layout make_layout(const bddmma_solver &s)
+{
+    const Packed &pk = s.pk;
+    const int64_t S = pk.n_slots, V = s.prob.ilp.n_vars, P = (int64_t)s.prob.pair_var.size();
+    const int64_t T = (int64_t)pk.tiles.size();
+    const size_t e = (size_t)s.elem;
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.lam = take(S * e);
+    L.mm = take(S * e);
+    L.lam_bak = take(S * e);
+    L.mm_bak = take(S * e);
+    L.mmx = take(S * e);
+    L.avg = take((V + 1) * e);
+    L.avg_bak = take((V + 1) * e);
+    L.pair_var = take(S * 4);
+    L.vptr = take((V + 1) * 4);
+    L.vslot = take(P * 4);
+    L.child = take(pk.child.size() * 4);
+    L.tiles = take(T * sizeof(TileDesc));
+    L.layers = take(pk.layers.size() * 4);
+    L.cost = take(V * 8);
+    L.tile_lb = take(T * 8);
+    L.tile_e = take(T * 8);
+    L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
+    L.lbh = take(kHistCap * 8);
+    L.counter = take(64);
+    L.flag = take(V);
+    L.x = take(V);
+    L.scratch = take((size_t)pk.scratch_elems * e);
+    L.total = o;
+    return L;
+}
+
+// ---- profiling ------------------------------------------------------------
+hipEvent_t ev_get(bddmma_solver *s)
+{
+    if (!s->ev.pool.empty()) {
+        hipEvent_t e = s->ev.pool.back();
+        s->ev.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Scope {
+    bddmma_solver *s;
+    int k;
+    hipEvent_t a = nullptr, b = nullptr;
+    Scope(bddmma_solver *s_, int k_) : s(s_), k(k_)
+    {
+        if (s->prof) {
+            a = ev_get(s);
+            b = ev_get(s);
+            if (a) (void)hipEventRecord(a, s->st);
+        }
+    }
+    ~Scope()
+    {
+        if (s->prof && a && b) {
+            (void)hipEventRecord(b, s->st);
+            s->ev.used[k].emplace_back(a, b);
+        }
+    }
+};
+
+// ---- Alg. 1 pieces ------------------------------------------------------------
+template <typename T>
+void one_sweep(bddmma_solver *s, int dir, bool record_lb)
+{
+    const DevProblem &p = s->dp;
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *avg = s->ptr<T>(s->L.avg);
+    const T omega = (T)s->opt.omega;
+    double *tile_lb = record_lb ? s->ptr<double>(s->L.tile_lb) : nullptr;
+    {
+        Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD);
+        launch_sweep<T>(p, lam, mm, avg, tile_lb, omega, dir, MODE_UPDATE, s->st);
+    }
+    {
+        Scope sc(s, BDDMMA_K_AVERAGE);
+        launch_average<T>(p, mm, avg, omega, s->st);
+    }
+    if (record_lb) {
+        Scope sc(s, BDDMMA_K_LB_REDUCE);
+        double *slot = s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap);
+        launch_reduce_sum(tile_lb, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, s->ptr<double>(s->L.red) + 2 * kRedBlocks + 4,
+                          slot, s->st);
+    }
+}
+
+int flush_history(bddmma_solver *s)
+{
+    int64_t pending = s->sweeps - s->hist_synced;
+    if (pending <= 0) return BDDMMA_OK;
+    s->hist.resize((size_t)s->sweeps);
+    const double *lbh = s->ptr<double>(s->L.lbh);
+    // entries [hist_synced, sweeps) live at index % kHistCap (at most kHistCap pending)
+    int64_t a = s->hist_synced;
+    while (a < s->sweeps) {
+        int64_t idx = a % kHistCap, run = std::min<int64_t>(s->sweeps - a, kHistCap - idx);
+        HIPCHK(hipMemcpyAsync(s->hist.data() + a, lbh + idx, (size_t)run * 8, hipMemcpyDeviceToHost, s->st));
+        a += run;
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->hist_synced = s->sweeps;
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int run_sweeps_T(bddmma_solver *s, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        one_sweep<T>(s, (int)(s->sweeps & 1), true);
+        s->sweeps++;
+        if (s->sweeps - s->hist_synced >= kHistCap) {
+            int rc = check_launch();
+            if (rc) return rc;
+            rc = flush_history(s);
+            if (rc) return rc;
+        }
+    }
+    int rc = check_launch();
+    if (rc) return rc;
+    return flush_history(s);
+}
+
+template <typename T>
+int lower_bound_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res)
+{
+    const DevProblem &p = s->dp;
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    double *red = s->ptr<double>(s->L.red);
+    double *tile_e = s->ptr<double>(s->L.tile_e);
+    launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
+    launch_reduce_sum(tile_e, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, red + 2 * kRedBlocks + 4,
+                      red + 3 * kRedBlocks + 8, s->st);
+    launch_residual<T>(p, lam, mm, s->opt.omega, red, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
+    double h[3];
+    HIPCHK(hipMemcpyAsync(h, red, 16, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(h + 2, red + 3 * kRedBlocks + 8, 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    const double cert = h[2] - h[0];
+    if (lb_cert) *lb_cert = cert;
+    if (max_res) *max_res = h[1];
+    if (lb_free) *lb_free = s->hist.empty() ? cert : s->hist.back();
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int download_pairs(bddmma_solver *s, size_t off, std::vector<double> &out)
+{
+    const int64_t S = s->pk.n_slots, P = (int64_t)s->prob.pair_var.size();
+    std::vector<T> buf((size_t)std::max<int64_t>(S, 1));
+    if (S > 0) HIPCHK(hipMemcpyAsync(buf.data(), s->dev + off, (size_t)S * sizeof(T), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    out.resize((size_t)P);
+    for (int64_t q = 0; q < P; ++q) out[q] = (double)buf[(size_t)s->pk.slot_of_pair[q]];
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int get_state_T(bddmma_solver *s, double *lam, double *mm, double *avg)
+{
+    std::vector<double> v;
+    int rc;
+    if (lam) {
+        if ((rc = download_pairs<T>(s, s->L.lam, v))) return rc;
+        std::copy(v.begin(), v.end(), lam);
+    }
+    if (mm) {
+        if ((rc = download_pairs<T>(s, s->L.mm, v))) return rc;
+        std::copy(v.begin(), v.end(), mm);
+    }
+    if (avg) {
+        const int64_t V = s->prob.ilp.n_vars;
+        std::vector<T> buf((size_t)std::max<int64_t>(V, 1));
+        if (V > 0) HIPCHK(hipMemcpyAsync(buf.data(), s->dev + s->L.avg, (size_t)V * sizeof(T), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        for (int64_t i = 0; i < V; ++i) avg[i] = (double)buf[(size_t)i];
+    }
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int upload_pairs(bddmma_solver *s, size_t off, const double *src)
+{
+    const int64_t S = s->pk.n_slots, P = (int64_t)s->prob.pair_var.size();
+    std::vector<T> buf((size_t)std::max<int64_t>(S, 1));
+    if (S > 0) HIPCHK(hipMemcpyAsync(buf.data(), s->dev + off, (size_t)S * sizeof(T), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (int64_t q = 0; q < P; ++q) buf[(size_t)s->pk.slot_of_pair[q]] = (T)src[q];
+    if (S > 0) HIPCHK(hipMemcpyAsync(s->dev + off, buf.data(), (size_t)S * sizeof(T), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int set_state_T(bddmma_solver *s, const double *lam, const double *mm, const double *avg)
+{
+    int rc;
+    if (lam && (rc = upload_pairs<T>(s, s->L.lam, lam))) return rc;
+    if (mm && (rc = upload_pairs<T>(s, s->L.mm, mm))) return rc;
+    if (avg) {
+        const int64_t V = s->prob.ilp.n_vars;
+        std::vector<T> buf((size_t)V + 1, T(0));
+        for (int64_t i = 0; i < V; ++i) buf[(size_t)i] = (T)avg[i];
+        HIPCHK(hipMemcpyAsync(s->dev + s->L.avg, buf.data(), (size_t)(V + 1) * sizeof(T), hipMemcpyHostToDevice, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+    }
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int multipliers_T(bddmma_solver *s, double *lam_out, double *mm_out)
+{
+    std::vector<double> l, m;
+    int rc;
+    if ((rc = download_pairs<T>(s, s->L.lam, l))) return rc;
+    if ((rc = download_pairs<T>(s, s->L.mm, m))) return rc;
+    const T w = (T)s->opt.omega;
+    for (size_t q = 0; q < l.size(); ++q) {
+        if (lam_out) lam_out[q] = (double)((T)l[q] + w * (T)m[q]);
+        if (mm_out) mm_out[q] = m[q];
+    }
+    return BDDMMA_OK;
+}
+
+template <typename T>
+int min_marginals_T(bddmma_solver *s, double *out)
+{
+    T *lam = s->ptr<T>(s->L.lam), *mmx = s->ptr<T>(s->L.mmx);
+    launch_sweep<T>(s->dp, lam, mmx, s->ptr<T>(s->L.avg), nullptr, (T)s->opt.omega, 0, MODE_FIXED, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
+    std::vector<double> v;
+    if ((rc = download_pairs<T>(s, s->L.mmx, v))) return rc;
+    std::copy(v.begin(), v.end(), out);
+    return BDDMMA_OK;
+}
+
+bool row_ok(const Ilp &ilp, int64_t r, const std::vector<uint8_t> &x)
+{
+    int64_t lhs = 0;
+    for (int64_t e = ilp.row_ptr[r]; e < ilp.row_ptr[r + 1]; ++e) lhs += ilp.coef[e] * (int64_t)x[ilp.col[e]];
+    const int sn = ilp.sense[r];
+    return sn < 0 ? lhs <= ilp.rhs[r] : sn > 0 ? lhs >= ilp.rhs[r] : lhs == ilp.rhs[r];
+}
+
+// Alg. 2 on the terminated multipliers; the dual state is restored at the end
+template <typename T>
+int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
+{
+    const DevProblem &p = s->dp;
+    const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars;
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *avg = s->ptr<T>(s->L.avg);
+    T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak), *avg_b = s->ptr<T>(s->L.avg_bak);
+    uint8_t *flag = s->ptr<uint8_t>(s->L.flag), *xd = s->ptr<uint8_t>(s->L.x);
+    int32_t *counter = s->ptr<int32_t>(s->L.counter);
+    const T omega = (T)s->opt.omega;
+    launch_copy<T>(lam_b, lam, S, s->st);
+    launch_copy<T>(mm_b, mm, S, s->st);
+    launch_copy<T>(avg_b, avg, V + 1, s->st);
+    launch_fill<uint8_t>(flag, 0, V, s->st);
+    launch_terminate<T>(p, lam, mm, omega, s->st);
+    launch_sweep<T>(p, lam, mm, avg, nullptr, omega, 0, MODE_FIXED, s->st);
+
+    const Ilp &ilp = s->prob.ilp;
+    const BddSet &B = s->prob.bdds;
+    std::vector<uint8_t> xh((size_t)V), xfull((size_t)V), fl((size_t)V);
+    double delta = s->opt.delta0;
+    int rc = BDDMMA_ERR_NOT_CONVERGED, round;
+    for (round = 0;; ++round) {
+        launch_conflicts<T>(p, mm, s->tau, flag, counter, s->st);
+        int32_t nconf = 0;
+        int e = check_launch();
+        if (e) return e;
+        HIPCHK(hipMemcpyAsync(&nconf, counter, 4, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        if (nconf == 0) {
+            launch_decode<T>(p, mm, xd, s->st);
+            if (V > 0) HIPCHK(hipMemcpyAsync(xh.data(), xd, (size_t)V, hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipStreamSynchronize(s->st));
+            for (int64_t i = 0; i < V; ++i) {
+                if (s->prob.fixed[i] >= 0) xfull[i] = (uint8_t)s->prob.fixed[i];
+                else if (s->prob.deg[i] == 0) xfull[i] = ilp.cost[i] < 0.0;
+                else xfull[i] = xh[i];
+            }
+            bool bad = false;
+            std::fill(fl.begin(), fl.end(), 0);
+            for (int64_t j = 0; j < B.n_bdds(); ++j) {
+                if (row_ok(ilp, B.row[j], xfull)) continue;
+                bad = true;
+                for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) fl[B.lay_var[q]] = 1;
+            }
+            if (!bad) {
+                rc = BDDMMA_OK;
+                break;
+            }
+            if (V > 0) HIPCHK(hipMemcpyAsync(flag, fl.data(), (size_t)V, hipMemcpyHostToDevice, s->st));
+        }
+        if (round == s->opt.max_rounds) break;
+        launch_perturb<T>(p, lam, mm, s->tau, delta, s->opt.seed, (uint64_t)round, flag, s->st);
+        launch_fill<uint8_t>(flag, 0, V, s->st);
+        delta = delta * s->opt.alpha;
+        launch_fill<T>(avg, T(0), V + 1, s->st);
+        for (int t = 0; t < s->opt.reopt_iters; ++t) {
+            one_sweep<T>(s, 0, false);
+            one_sweep<T>(s, 1, false);
+        }
+        launch_terminate<T>(p, lam, mm, omega, s->st);
+        launch_sweep<T>(p, lam, mm, avg, nullptr, omega, 0, MODE_FIXED, s->st);
+    }
+    launch_copy<T>(lam, lam_b, S, s->st);
+    launch_copy<T>(mm, mm_b, S, s->st);
+    launch_copy<T>(avg, avg_b, V + 1, s->st);
+    int e = check_launch();
+    if (e) return e;
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (rounds_out) *rounds_out = round;
+    if (rc != BDDMMA_OK) return fail(rc, "rounding did not remove all conflicts within max_rounds");
+    double u = 0.0;
+    for (int64_t i = 0; i < V; ++i) u += xfull[i] ? ilp.cost[i] : 0.0;
+    for (int64_t r = 0; r < ilp.n_rows; ++r)
+        if (!row_ok(ilp, r, xfull)) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
+    if (ub) *ub = u;
+    std::copy(xfull.begin(), xfull.end(), x_out);
+    return BDDMMA_OK;
+}
+
+struct StateHeader {
+    uint64_t magic, version, elem, n_slots, n_vars, n_pairs, sweeps, hist;
+};
+constexpr uint64_t kMagic = 0x42444D4D41535431ull;   // "BDMMAST1"
+
+int check_ready(const bddmma_solver *s)
+{
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    if (!s->bound) return fail(BDDMMA_ERR_STATE, "no device workspace bound");
+    return BDDMMA_OK;
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                                   \
+    }                                                                               \
+    catch (const std::bad_alloc &) { return fail(BDDMMA_ERR_NO_MEMORY, "host allocation failed"); } \
+    catch (const std::exception &ex) { return fail(BDDMMA_ERR_INVALID_ARG, ex.what()); }            \
+    catch (...) { return fail(BDDMMA_ERR_INVALID_ARG, "unexpected error"); }
+
+}  // namespace
+
+extern "C" {
+
+int bddmma_options_default(bddmma_options *o)
+{
+    if (!o) return fail(BDDMMA_ERR_INVALID_ARG, "options pointer is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->omega = 0.5;
+    o->rel_tol = 0.0;
+    o->lb_every = 1;
+    o->precision = 32;
+    o->delta0 = 1.0;
+    o->alpha = 1.2;
+    o->reopt_iters = 5;
+    o->max_rounds = 200;
+    o->tau = -1.0;
+    o->seed = 0;
+    o->sp_in_lds_max_nodes = 0;
+    return BDDMMA_OK;
+}
+
+int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
+{
+    GUARD_BEGIN
+    if (!out) return fail(BDDMMA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    bddmma_options o;
+    if (opt) o = *opt;
+    else bddmma_options_default(&o);
+    if (!(o.omega > 0.0 && o.omega <= 1.0)) return fail(BDDMMA_ERR_INVALID_ARG, "omega must lie in (0, 1]");
+    if (o.precision != 32 && o.precision != 64) return fail(BDDMMA_ERR_INVALID_ARG, "precision must be 32 or 64");
+    if (o.lb_every < 1) return fail(BDDMMA_ERR_INVALID_ARG, "lb_every must be >= 1");
+    if (!(o.rel_tol >= 0.0)) return fail(BDDMMA_ERR_INVALID_ARG, "rel_tol must be >= 0");
+    if (!(o.delta0 > 0.0) || !(o.alpha >= 1.0)) return fail(BDDMMA_ERR_INVALID_ARG, "need delta0 > 0 and alpha >= 1");
+    if (o.reopt_iters < 0 || o.max_rounds < 0) return fail(BDDMMA_ERR_INVALID_ARG, "reopt_iters / max_rounds must be >= 0");
+    if (o.sp_in_lds_max_nodes < -1) return fail(BDDMMA_ERR_INVALID_ARG, "sp_in_lds_max_nodes must be >= -1");
+    for (int i = 0; i < 7; ++i)
+        if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
+    bddmma_solver *s = new bddmma_solver();
+    s->opt = o;
+    s->elem = o.precision == 64 ? 8 : 4;
+    *out = s;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+void bddmma_destroy(bddmma_solver *s)
+{
+    if (!s) return;
+    for (auto &v : s->ev.used)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (auto e : s->ev.pool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                    const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs)
+{
+    GUARD_BEGIN
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (s->loaded) return fail(BDDMMA_ERR_STATE, "an ILP is already loaded");
+    std::string msg;
+    int rc = ingest_ilp(s->prob.ilp, n_vars, costs, n_rows, row_ptr, col, coef, sense, rhs, msg);
+    if (rc != ST_OK) return fail(rc, msg);
+    rc = build_problem(s->prob, msg);
+    if (rc != ST_OK) return fail(rc, msg);
+    int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
+    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->pk, msg);
+    if (rc != ST_OK) return fail(rc, msg);
+    s->L = make_layout(*s);
+    double cmax = 1.0;
+    for (double c : s->prob.ilp.cost) cmax = std::max(cmax, std::fabs(c));
+    s->tau = s->opt.tau >= 0.0 ? s->opt.tau : (s->opt.precision == 64 ? 0.0 : 1e-6 * cmax);
+    s->loaded = true;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
+{
+    if (!s || !o) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    std::memset(o, 0, sizeof(*o));
+    o->n_vars = s->prob.ilp.n_vars;
+    o->n_rows = s->prob.ilp.n_rows;
+    o->n_bdds = s->prob.bdds.n_bdds();
+    o->n_pairs = (int64_t)s->prob.pair_var.size();
+    o->n_nodes = s->prob.n_nodes;
+    o->n_fixed = s->prob.n_fixed;
+    o->n_free = s->prob.n_free;
+    o->n_tiles = (int64_t)s->pk.tiles.size();
+    o->n_slots = s->pk.n_slots;
+    o->max_layers = s->pk.max_layers;
+    o->max_width = s->pk.max_width;
+    o->lb_offset = s->prob.lb_offset;
+    return BDDMMA_OK;
+}
+
+int bddmma_workspace_bytes(const bddmma_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    *bytes = s->L.total;
+    return BDDMMA_OK;
+}
+
+int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
+{
+    GUARD_BEGIN
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    if (s->bound) return fail(BDDMMA_ERR_STATE, "workspace already bound");
+    if (!dev_ptr) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer is NULL");
+    if (((uintptr_t)dev_ptr) % kAlign) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer must be 256-byte aligned");
+    if (bytes < s->L.total) return fail(BDDMMA_ERR_NO_MEMORY, "workspace smaller than bddmma_workspace_bytes");
+    s->dev = (char *)dev_ptr;
+    s->st = (hipStream_t)hip_stream;
+    const Packed &pk = s->pk;
+    const Layout &L = s->L;
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
+    };
+    HIPCHK(up(L.pair_var, pk.pair_var.data(), pk.pair_var.size() * 4));
+    HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
+    HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
+    HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
+    HIPCHK(up(L.tiles, pk.tiles.data(), pk.tiles.size() * sizeof(TileDesc)));
+    HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
+    HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
+    DevProblem &d = s->dp;
+    d.tiles = s->ptr<TileDesc>(L.tiles);
+    d.n_tiles = (int64_t)pk.tiles.size();
+    d.n_lds_tiles = pk.n_lds_tiles;
+    d.layers = s->ptr<uint32_t>(L.layers);
+    d.child = s->ptr<uint32_t>(L.child);
+    d.pair_var = s->ptr<int32_t>(L.pair_var);
+    d.vptr = s->ptr<int32_t>(L.vptr);
+    d.vslot = s->ptr<int32_t>(L.vslot);
+    d.cost = s->ptr<double>(L.cost);
+    d.n_vars = s->prob.ilp.n_vars;
+    d.n_slots = pk.n_slots;
+    d.scratch = s->dev + L.scratch;
+    d.lds_lane_elems = pk.max_lds_lane_elems;
+    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.avg), s->st);
+    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.avg), s->st);
+    launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->bound = true;
+    s->sweeps = 0;
+    s->hist_synced = 0;
+    s->hist.clear();
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_reset(bddmma_solver *s)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    const Layout &L = s->L;
+    if (s->elem == 8) launch_init<double>(s->dp, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.avg), s->st);
+    else launch_init<float>(s->dp, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.avg), s->st);
+    rc = check_launch();
+    if (rc) return rc;
+    s->sweeps = 0;
+    s->hist_synced = 0;
+    s->hist.clear();
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_run_sweeps(bddmma_solver *s, int32_t n)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (n < 0) return fail(BDDMMA_ERR_INVALID_ARG, "n_sweeps must be >= 0");
+    return s->elem == 8 ? run_sweeps_T<double>(s, n) : run_sweeps_T<float>(s, n);
+    GUARD_END
+}
+
+int bddmma_run_dual(bddmma_solver *s, int32_t n_iter, int32_t *iters_done)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (n_iter < 0) return fail(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 0");
+    int32_t done = 0;
+    if (s->opt.rel_tol <= 0.0) {
+        rc = bddmma_run_sweeps(s, 2 * n_iter);
+        if (rc) return rc;
+        done = n_iter;
+    } else {
+        while (done < n_iter) {
+            int32_t chunk = std::min(s->opt.lb_every, n_iter - done);
+            rc = bddmma_run_sweeps(s, 2 * chunk);
+            if (rc) return rc;
+            done += chunk;
+            size_t n = s->hist.size();
+            if (n >= 4) {
+                double a = s->hist[n - 1], b = s->hist[n - 3];
+                if (std::fabs(a - b) / std::max(1.0, std::fabs(a)) < s->opt.rel_tol) break;
+            }
+        }
+    }
+    if (iters_done) *iters_done = done;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_lower_bound(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_residual)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->elem == 8 ? lower_bound_T<double>(s, lb_free, lb_cert, max_residual)
+                        : lower_bound_T<float>(s, lb_free, lb_cert, max_residual);
+    GUARD_END
+}
+
+int bddmma_lb_history(const bddmma_solver *s, double *out, int64_t cap, int64_t *n_total)
+{
+    if (!s || !n_total) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    *n_total = (int64_t)s->hist.size();
+    if (out) {
+        int64_t n = std::min<int64_t>(cap, (int64_t)s->hist.size());
+        std::copy(s->hist.begin(), s->hist.begin() + n, out);
+    }
+    return BDDMMA_OK;
+}
+
+int bddmma_num_pairs(const bddmma_solver *s, int64_t *n)
+{
+    if (!s || !n) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    *n = (int64_t)s->prob.pair_var.size();
+    return BDDMMA_OK;
+}
+
+int bddmma_get_pairs(const bddmma_solver *s, int32_t *pv, int32_t *pr)
+{
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    if (pv) std::copy(s->prob.pair_var.begin(), s->prob.pair_var.end(), pv);
+    if (pr) std::copy(s->prob.pair_row.begin(), s->prob.pair_row.end(), pr);
+    return BDDMMA_OK;
+}
+
+int bddmma_get_fixed(const bddmma_solver *s, int8_t *fixed)
+{
+    if (!s || !fixed) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    std::copy(s->prob.fixed.begin(), s->prob.fixed.end(), fixed);
+    return BDDMMA_OK;
+}
+
+int bddmma_get_multipliers(bddmma_solver *s, double *lam, double *mm)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->elem == 8 ? multipliers_T<double>(s, lam, mm) : multipliers_T<float>(s, lam, mm);
+    GUARD_END
+}
+
+int bddmma_get_state(bddmma_solver *s, double *lam, double *mm, double *avg)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->elem == 8 ? get_state_T<double>(s, lam, mm, avg) : get_state_T<float>(s, lam, mm, avg);
+    GUARD_END
+}
+
+int bddmma_set_state(bddmma_solver *s, const double *lam, const double *mm, const double *avg)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->elem == 8 ? set_state_T<double>(s, lam, mm, avg) : set_state_T<float>(s, lam, mm, avg);
+    GUARD_END
+}
+
+int bddmma_min_marginals(bddmma_solver *s, double *out)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!out) return fail(BDDMMA_ERR_INVALID_ARG, "mm_out is NULL");
+    return s->elem == 8 ? min_marginals_T<double>(s, out) : min_marginals_T<float>(s, out);
+    GUARD_END
+}
+
+int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!x_out) return fail(BDDMMA_ERR_INVALID_ARG, "x_out is NULL");
+    return s->elem == 8 ? round_T<double>(s, x_out, ub, rounds) : round_T<float>(s, x_out, ub, rounds);
+    GUARD_END
+}
+
+int bddmma_save_state(const bddmma_solver *s_, void *buf, size_t *bytes)
+{
+    GUARD_BEGIN
+    bddmma_solver *s = const_cast<bddmma_solver *>(s_);
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!bytes) return fail(BDDMMA_ERR_INVALID_ARG, "bytes is NULL");
+    const uint64_t S = (uint64_t)s->pk.n_slots, V = (uint64_t)s->prob.ilp.n_vars;
+    const size_t need = sizeof(StateHeader) + (size_t)(2 * S + V + 1) * s->elem + s->hist.size() * 8;
+    if (!buf) {
+        *bytes = need;
+        return BDDMMA_OK;
+    }
+    if (*bytes < need) return fail(BDDMMA_ERR_NO_MEMORY, "state buffer too small");
+    StateHeader h{kMagic, 1, (uint64_t)s->elem, S, V, (uint64_t)s->prob.pair_var.size(), (uint64_t)s->sweeps,
+                  (uint64_t)s->hist.size()};
+    char *p = (char *)buf;
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    if (S) HIPCHK(hipMemcpyAsync(p, s->dev + s->L.lam, S * s->elem, hipMemcpyDeviceToHost, s->st));
+    p += S * s->elem;
+    if (S) HIPCHK(hipMemcpyAsync(p, s->dev + s->L.mm, S * s->elem, hipMemcpyDeviceToHost, s->st));
+    p += S * s->elem;
+    HIPCHK(hipMemcpyAsync(p, s->dev + s->L.avg, (V + 1) * s->elem, hipMemcpyDeviceToHost, s->st));
+    p += (V + 1) * s->elem;
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (!s->hist.empty()) std::memcpy(p, s->hist.data(), s->hist.size() * 8);
+    *bytes = need;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!buf || bytes < sizeof(StateHeader)) return fail(BDDMMA_ERR_INVALID_ARG, "state buffer too small");
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const uint64_t S = (uint64_t)s->pk.n_slots, V = (uint64_t)s->prob.ilp.n_vars;
+    if (h.magic != kMagic || h.version != 1 || h.elem != (uint64_t)s->elem || h.n_slots != S || h.n_vars != V ||
+        h.n_pairs != (uint64_t)s->prob.pair_var.size())
+        return fail(BDDMMA_ERR_INVALID_ARG, "state does not belong to this problem / precision");
+    const size_t need = sizeof(StateHeader) + (size_t)(2 * S + V + 1) * s->elem + h.hist * 8;
+    if (bytes < need) return fail(BDDMMA_ERR_INVALID_ARG, "state buffer truncated");
+    const char *p = (const char *)buf + sizeof(h);
+    if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.lam, p, S * s->elem, hipMemcpyHostToDevice, s->st));
+    p += S * s->elem;
+    if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.mm, p, S * s->elem, hipMemcpyHostToDevice, s->st));
+    p += S * s->elem;
+    HIPCHK(hipMemcpyAsync(s->dev + s->L.avg, p, (V + 1) * s->elem, hipMemcpyHostToDevice, s->st));
+    p += (V + 1) * s->elem;
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->hist.assign((const double *)p, (const double *)p + h.hist);
+    s->sweeps = (int64_t)h.sweeps;
+    s->hist_synced = s->sweeps;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_profile(bddmma_solver *s, int enable)
+{
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (s->bound) HIPCHK(hipStreamSynchronize(s->st));
+    for (auto &v : s->ev.used) {
+        for (auto &pr : v) {
+            s->ev.pool.push_back(pr.first);
+            s->ev.pool.push_back(pr.second);
+        }
+        v.clear();
+    }
+    s->prof = enable != 0;
+    return BDDMMA_OK;
+}
+
+int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *total_ms)
+{
+    if (!s || kernel < 0 || kernel >= BDDMMA_K_COUNT) return fail(BDDMMA_ERR_INVALID_ARG, "bad kernel id");
+    if (s->bound) HIPCHK(hipStreamSynchronize(s->st));
+    double t = 0.0;
+    for (auto &pr : s->ev.used[kernel]) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        t += ms;
+    }
+    if (launches) *launches = (int64_t)s->ev.used[kernel].size();
+    if (total_ms) *total_ms = t;
+    return BDDMMA_OK;
+}
+
+const char *bddmma_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,693 @@
+// HIP kernels of the solver, written for CDNA4 (gfx950, 64-wide wavefronts).
+//
+// Hot path (Alg. 1): every wavefront owns one tile of 64 whole BDDs, one BDD
+// per lane, and runs the whole layer loop of a sweep inside the kernel.  The
+// shortest-path distances the min-marginal formula needs (Sec. 5, min-marginal
+// via shortest paths: SP(r, v) and SP(s(v), top)) are recomputed at the start
+// of each sweep from the current multipliers and kept in LDS (lane-minor, so
+// every LDS access is bank-conflict free); they never travel through HBM.  HBM
+// traffic per sweep is one coalesced read of the multipliers and the pair ->
+// variable map, one gather of the averaged term, and coalesced writes of the
+// updated multipliers and min-marginal differences.  No MFMA: the work is
+// min-plus arithmetic on sparse, data-dependent graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace bddmma {
+
+namespace {
+
+constexpr int kWavesPerBlock = 2;
+constexpr int kThreads = kWavesPerBlock * kLanes;
+constexpr int kRedThreads = 256;
+constexpr int kPrefetch = 8;
+
+template <typename T>
+__device__ __forceinline__ T inf_of();
+template <>
+__device__ __forceinline__ float inf_of<float>() { return __builtin_huge_valf(); }
+template <>
+__device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Blocks are handed to the 8 XCDs round robin; remap so that consecutive
+// logical blocks (and hence neighbouring tiles, which share variables) run on
+// the same XCD and share its L2.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t b = blockIdx.x, per = gridDim.x >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int64_t grid_round8(int64_t blocks) { return (blocks + 7) & ~int64_t(7); }
+
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
+
+struct TileView {
+    uint32_t pb, nb, lb, K, NN;
+    bool shared;
+};
+
+__device__ __forceinline__ TileView load_tile(const TileDesc *td)
+{
+    TileView v;
+    v.pb = uni(td->pair_base);
+    v.nb = uni(td->node_base);
+    v.lb = uni(td->layer_base);
+    v.K = uni(td->K);
+    v.NN = uni(td->nodes);
+    v.shared = (uni(td->flags) & TILE_SHARED) != 0;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t node_word(const uint32_t *__restrict__ child, const TileView &tv, uint32_t node,
+                                              int lane)
+{
+    return tv.shared ? child[tv.nb + node] : child[tv.nb + (size_t)node * kLanes + lane];
+}
+
+// value of an arc's head in the distance-to-accept array (layer offset noffn)
+template <typename T>
+__device__ __forceinline__ T head_val(uint32_t c, const T *Bk, uint32_t noffn)
+{
+    return c == kTop ? T(0) : (c == kBot ? inf_of<T>() : Bk[(size_t)(noffn + c) * kLanes]);
+}
+
+template <typename T>
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// The sweep.  DIR 0: ascending variables (Alg. 3), DIR 1: descending (Alg. 4).
+// MODE_UPDATE: at every layer compute M = m^1 - m^0 and apply the deferred
+// parallel update  lambda <- (lambda - omega M) + a_i  before the distances of
+// the next layer are propagated with the new multiplier (Alg. 1).
+// MODE_FIXED: same min-marginals at fixed multipliers.
+// ---------------------------------------------------------------------------
+template <typename T, int DIR, int MODE, bool LDS>
+__global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict__ lam, T *__restrict__ mm_out,
+                                                     const T *__restrict__ avg, double *__restrict__ tile_lb,
+                                                     T omega, int64_t tile_begin, int64_t tile_count)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int lane = threadIdx.x & (kLanes - 1);
+    const uint32_t wave = uni(threadIdx.x >> 6);
+    const int64_t lt = xcd_block() * kWavesPerBlock + wave;
+    if (lt >= tile_count) return;
+    const int64_t tile = tile_begin + lt;
+    const TileView tv = load_tile(P.tiles + tile);
+    const uint32_t *__restrict__ child = P.child;
+    const uint32_t *__restrict__ layers = P.layers + tv.lb;
+
+    T *base;
+    if (LDS)
+        base = reinterpret_cast<T *>(smem_raw) + (size_t)wave * kLanes * P.lds_lane_elems + lane;
+    else
+        base = reinterpret_cast<T *>(P.scratch) + (size_t)P.tiles[tile].scratch_base + lane;
+    T *lamS = base;                               // [K]  multipliers of this lane's BDD
+    T *avS = lamS + (size_t)tv.K * kLanes;         // [K]  averaged terms a_i
+    T *F = avS + (size_t)tv.K * kLanes;            // [NN] SP(root, v)
+    T *Bk = F + (size_t)tv.NN * kLanes;            // [NN] SP(v, top)
+    const T INF = inf_of<T>();
+
+    // stage multipliers (and averaged terms) of all layers: all loads of a
+    // chunk are issued before the first one is used
+    for (uint32_t h0 = 0; h0 < tv.K; h0 += kPrefetch) {
+        T lv[kPrefetch];
+        int32_t pv[kPrefetch];
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            const uint32_t h = h0 + u;
+            if (h < tv.K) {
+                const uint32_t s = tv.pb + h * kLanes + lane;
+                lv[u] = lam[s];
+                if (MODE == MODE_UPDATE) pv[u] = P.pair_var[s];
+            }
+        }
+        if (MODE == MODE_UPDATE) {
+            T av[kPrefetch];
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u)
+                if (h0 + u < tv.K) av[u] = avg[pv[u]];
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u)
+                if (h0 + u < tv.K) avS[(size_t)(h0 + u) * kLanes] = av[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u)
+            if (h0 + u < tv.K) lamS[(size_t)(h0 + u) * kLanes] = lv[u];
+    }
+
+    double lbacc = 0.0;   // sum over layers of min(M, 0)
+    T energy;
+
+    if (DIR == 0) {
+        // SP(v, top) under the current multipliers (Alg. 4 without updates)
+        for (int h = (int)tv.K - 1; h >= 0; --h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const T l = lamS[(size_t)h * kLanes];
+            for (uint32_t q = 0; q < W; ++q) {
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const T b0 = head_val(c & 0xFFFFu, Bk, noffn);
+                const T b1 = head_val(c >> 16, Bk, noffn) + l;
+                Bk[(size_t)(noff + q) * kLanes] = tmin(b0, b1);
+            }
+        }
+        // forward sweep with updates (Alg. 3 + the update of Alg. 1)
+        F[0] = T(0);
+        T top = INF;
+        for (uint32_t h = 0; h < tv.K; ++h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const uint32_t Wn = (h + 1 < tv.K) ? (uni(layers[h + 1]) >> 16) : 0u;
+            const T l = lamS[(size_t)h * kLanes];
+            T m0 = INF, m1 = INF;
+            for (uint32_t q = 0; q < W; ++q) {
+                const T f = F[(size_t)(noff + q) * kLanes];
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) m0 = tmin(m0, f + head_val(lo, Bk, noffn));
+                if (hi != kBot) m1 = tmin(m1, (f + l) + head_val(hi, Bk, noffn));
+            }
+            const T M = m1 - m0;
+            const uint32_t s = tv.pb + h * kLanes + lane;
+            mm_out[s] = M;
+            T lu = l;
+            if (MODE == MODE_UPDATE) {
+                lu = (l - omega * M) + avS[(size_t)h * kLanes];
+                lam[s] = lu;
+                lbacc += (double)(M < T(0) ? M : T(0));
+            }
+            for (uint32_t q = 0; q < Wn; ++q) F[(size_t)(noffn + q) * kLanes] = INF;
+            for (uint32_t q = 0; q < W; ++q) {
+                const T f = F[(size_t)(noff + q) * kLanes];
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) {
+                    if (lo == kTop) top = tmin(top, f);
+                    else {
+                        T &d = F[(size_t)(noffn + lo) * kLanes];
+                        d = tmin(d, f);
+                    }
+                }
+                if (hi != kBot) {
+                    const T v = f + lu;
+                    if (hi == kTop) top = tmin(top, v);
+                    else {
+                        T &d = F[(size_t)(noffn + hi) * kLanes];
+                        d = tmin(d, v);
+                    }
+                }
+            }
+        }
+        energy = top;
+    } else {
+        // SP(root, v) under the current multipliers (Alg. 3 without updates)
+        F[0] = T(0);
+        for (uint32_t h = 0; h + 1 < tv.K; ++h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const uint32_t Wn = uni(layers[h + 1]) >> 16;
+            const T l = lamS[(size_t)h * kLanes];
+            for (uint32_t q = 0; q < Wn; ++q) F[(size_t)(noffn + q) * kLanes] = INF;
+            for (uint32_t q = 0; q < W; ++q) {
+                const T f = F[(size_t)(noff + q) * kLanes];
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo < kTop) {
+                    T &d = F[(size_t)(noffn + lo) * kLanes];
+                    d = tmin(d, f);
+                }
+                if (hi < kTop) {
+                    T &d = F[(size_t)(noffn + hi) * kLanes];
+                    d = tmin(d, f + l);
+                }
+            }
+        }
+        // backward sweep with updates (Alg. 4 + the update of Alg. 1)
+        for (int h = (int)tv.K - 1; h >= 0; --h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const T l = lamS[(size_t)h * kLanes];
+            T m0 = INF, m1 = INF;
+            for (uint32_t q = 0; q < W; ++q) {
+                const T f = F[(size_t)(noff + q) * kLanes];
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) m0 = tmin(m0, f + head_val(lo, Bk, noffn));
+                if (hi != kBot) m1 = tmin(m1, (f + l) + head_val(hi, Bk, noffn));
+            }
+            const T M = m1 - m0;
+            const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
+            mm_out[s] = M;
+            T lu = l;
+            if (MODE == MODE_UPDATE) {
+                lu = (l - omega * M) + avS[(size_t)h * kLanes];
+                lam[s] = lu;
+                lbacc += (double)(M < T(0) ? M : T(0));
+            }
+            for (uint32_t q = 0; q < W; ++q) {
+                const uint32_t c = node_word(child, tv, noff + q, lane);
+                const T b0 = head_val(c & 0xFFFFu, Bk, noffn);
+                const T b1 = head_val(c >> 16, Bk, noffn) + lu;
+                Bk[(size_t)(noff + q) * kLanes] = tmin(b0, b1);
+            }
+        }
+        energy = Bk[0];
+    }
+    if (tile_lb) {
+        const double e = wave_sum<T>((double)energy + (double)omega * lbacc);
+        if (lane == 0) tile_lb[tile] = e;
+    }
+}
+
+// E^j(lambda + omega M) of every lane in FP64, summed per tile
+template <typename T, bool LDS>
+__global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__restrict__ lam,
+                                                    const T *__restrict__ mm, double omega,
+                                                    double *__restrict__ tile_e, int64_t tile_begin,
+                                                    int64_t tile_count)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int lane = threadIdx.x & (kLanes - 1);
+    const uint32_t wave = uni(threadIdx.x >> 6);
+    const int64_t lt = xcd_block() * kWavesPerBlock + wave;
+    if (lt >= tile_count) return;
+    const int64_t tile = tile_begin + lt;
+    const TileView tv = load_tile(P.tiles + tile);
+    const uint32_t *__restrict__ layers = P.layers + tv.lb;
+    double *F;
+    if (LDS) {
+        const size_t per_lane = (size_t)P.lds_lane_elems * sizeof(T) / sizeof(double);
+        F = reinterpret_cast<double *>(smem_raw) + (size_t)wave * kLanes * per_lane + lane;
+    } else {
+        F = reinterpret_cast<double *>(reinterpret_cast<T *>(P.scratch) + (size_t)P.tiles[tile].scratch_base) + lane;
+    }
+    const double INF = __builtin_huge_val();
+    F[0] = 0.0;
+    double top = INF;
+    for (uint32_t h = 0; h < tv.K; ++h) {
+        const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+        const uint32_t Wn = (h + 1 < tv.K) ? (uni(layers[h + 1]) >> 16) : 0u;
+        const uint32_t s = tv.pb + h * kLanes + lane;
+        const double cost = (double)lam[s] + omega * (double)mm[s];
+        for (uint32_t q = 0; q < Wn; ++q) F[(size_t)(noffn + q) * kLanes] = INF;
+        for (uint32_t q = 0; q < W; ++q) {
+            const double f = F[(size_t)(noff + q) * kLanes];
+            const uint32_t c = node_word(P.child, tv, noff + q, lane);
+            const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+            if (lo != kBot) {
+                if (lo == kTop) top = tmin(top, f);
+                else {
+                    double &d = F[(size_t)(noffn + lo) * kLanes];
+                    d = tmin(d, f);
+                }
+            }
+            if (hi != kBot) {
+                const double v = f + cost;
+                if (hi == kTop) top = tmin(top, v);
+                else {
+                    double &d = F[(size_t)(noffn + hi) * kLanes];
+                    d = tmin(d, v);
+                }
+            }
+        }
+    }
+    const double e = wave_sum<T>(top);
+    if (lane == 0) tile_e[tile] = e;
+}
+
+// a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, summed in ascending row order
+template <typename T>
+__global__ __launch_bounds__(256) void k_average(const int32_t *__restrict__ vptr, const int32_t *__restrict__ vslot,
+                                                 const T *__restrict__ mm, T *__restrict__ avg, double omega,
+                                                 int64_t V)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int32_t a = vptr[v], b = vptr[v + 1];
+    if (a == b) {
+        avg[v] = T(0);
+        return;
+    }
+    T s = T(0);
+    for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
+    avg[v] = (T)(omega / (double)(b - a)) * s;
+}
+
+// fixed-order two-stage sum: stage 1 writes one partial per block
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_sum_stage1(const double *__restrict__ part, int64_t n,
+                                                            double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per, b = a + per < n ? a + per : n;
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRedThreads) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_sum_stage2(const double *__restrict__ part, int n, double offset,
+                                                            double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = t + offset;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam, T *__restrict__ mm)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.n_slots) return;
+    const int32_t v = P.pair_var[s];
+    T l = T(0);
+    if (v < P.n_vars) {
+        const int32_t d = P.vptr[v + 1] - P.vptr[v];
+        l = (T)(P.cost[v] / (double)d);   // lambda_i^j = c_i / |J_i|
+    }
+    lam[s] = l;
+    mm[s] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_terminate(int64_t n, T *__restrict__ lam, const T *__restrict__ mm, T omega)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) lam[s] = lam[s] + omega * mm[s];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_residual(DevProblem P, const T *__restrict__ lam,
+                                                          const T *__restrict__ mm, double omega,
+                                                          double *__restrict__ red)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t per = (P.n_vars + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per, b = a + per < P.n_vars ? a + per : P.n_vars;
+    double pos = 0.0, mx = 0.0;
+    for (int64_t v = a + threadIdx.x; v < b; v += kRedThreads) {
+        const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+        if (q0 == q1) continue;
+        double s = 0.0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t sl = P.vslot[q];
+            s += (double)lam[sl] + omega * (double)mm[sl];
+        }
+        const double r = s - P.cost[v];
+        if (r > 0.0) pos += r;
+        mx = fmax(mx, fabs(r));
+    }
+    const double tp = block_sum(pos, sh);
+    const double tm = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        red[2 + blockIdx.x] = tp;
+        red[2 + gridDim.x + blockIdx.x] = tm;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_residual_stage2(double *__restrict__ red, int nb)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kRedThreads) {
+        s += red[2 + i];
+        m = fmax(m, red[2 + nb + i]);
+    }
+    const double ts = block_sum(s, sh);
+    const double tm = block_max(m, sh);
+    if (threadIdx.x == 0) {
+        red[0] = ts;
+        red[1] = tm;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_conflicts(DevProblem P, const T *__restrict__ mm, double tau,
+                                                           const uint8_t *__restrict__ flag, int32_t *counter)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t v = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    int c = 0;
+    if (v < P.n_vars) {
+        const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+        if (q0 != q1) {
+            bool pos = true, neg = true;
+            for (int32_t q = q0; q < q1; ++q) {
+                const double m = (double)mm[P.vslot[q]];
+                pos = pos && m > tau;
+                neg = neg && m < -tau;
+            }
+            c = (flag[v] || !(pos || neg)) ? 1 : 0;
+        }
+    }
+    const double t = block_sum((double)c, sh);
+    if (threadIdx.x == 0 && t > 0.0) atomicAdd(counter, (int32_t)t);
+}
+
+// SplitMix64 output function (Steele, Lea & Flood 2014) of seed ^ round*K1 ^ i*K2 -> [0, 1)
+__device__ __forceinline__ double u01(uint64_t seed, uint64_t round, uint64_t i)
+{
+    uint64_t z = seed ^ (round * 0xD1B54A32D192ED03ull) ^ (i * 0x8CB92BA72F3D8DD7ull);
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Alg. 2 perturbation: all M > 0 -> +delta, all M < 0 -> -delta, all M = 0 ->
+// r*delta, mixed -> sign(sum M)*|r|*delta; flagged variables take r*delta
+template <typename T>
+__global__ __launch_bounds__(256) void k_perturb(DevProblem P, T *__restrict__ lam, const T *__restrict__ mm,
+                                                 double tau, double delta, uint64_t seed, uint64_t round,
+                                                 const uint8_t *__restrict__ flag)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= P.n_vars) return;
+    const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+    if (q0 == q1) return;
+    const double r = (2.0 * u01(seed, round, (uint64_t)v) - 1.0) * delta;
+    bool pos = true, neg = true, zero = true;
+    double sum = 0.0;
+    for (int32_t q = q0; q < q1; ++q) {
+        const double m = (double)mm[P.vslot[q]];
+        pos = pos && m > tau;
+        neg = neg && m < -tau;
+        zero = zero && fabs(m) <= tau;
+        sum += m;
+    }
+    double pert;
+    if (flag[v]) pert = r * delta;
+    else if (pos) pert = delta;
+    else if (neg) pert = -delta;
+    else if (zero) pert = r * delta;
+    else {
+        const double mag = fabs(r) * delta;
+        const int sg = sum > 0.0 ? 1 : sum < 0.0 ? -1 : (r >= 0.0 ? 1 : -1);
+        pert = sg > 0 ? mag : -mag;
+    }
+    const T p = (T)pert;
+    for (int32_t q = q0; q < q1; ++q) {
+        const int32_t sl = P.vslot[q];
+        lam[sl] = lam[sl] + p;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_decode(DevProblem P, const T *__restrict__ mm, uint8_t *__restrict__ x)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= P.n_vars) return;
+    const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+    x[v] = (q0 != q1 && mm[P.vslot[q0]] < T(0)) ? 1 : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *__restrict__ d, T v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(T *__restrict__ d, const T *__restrict__ s, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+template <typename T>
+void launch_sweep(const DevProblem &p, T *lam, T *mm_out, const T *avg, double *tile_lb, T omega, int dir, int mode,
+                  hipStream_t st)
+{
+    const int64_t nl = p.n_lds_tiles, ng = p.n_tiles - p.n_lds_tiles;
+    if (nl > 0) {
+        const unsigned grid = (unsigned)(((nl + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
+        const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
+#define BDDMMA_SWEEP(D, M) hipLaunchKernelGGL((k_sweep<T, D, M, true>), dim3(grid), dim3(kThreads), lds, st, p, lam, mm_out, avg, tile_lb, omega, (int64_t)0, nl)
+        if (dir == 0 && mode == MODE_UPDATE) BDDMMA_SWEEP(0, MODE_UPDATE);
+        else if (dir == 0) BDDMMA_SWEEP(0, MODE_FIXED);
+        else if (mode == MODE_UPDATE) BDDMMA_SWEEP(1, MODE_UPDATE);
+        else BDDMMA_SWEEP(1, MODE_FIXED);
+#undef BDDMMA_SWEEP
+    }
+    if (ng > 0) {
+        const unsigned grid = (unsigned)(((ng + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
+#define BDDMMA_SWEEP(D, M) hipLaunchKernelGGL((k_sweep<T, D, M, false>), dim3(grid), dim3(kThreads), 0, st, p, lam, mm_out, avg, tile_lb, omega, nl, ng)
+        if (dir == 0 && mode == MODE_UPDATE) BDDMMA_SWEEP(0, MODE_UPDATE);
+        else if (dir == 0) BDDMMA_SWEEP(0, MODE_FIXED);
+        else if (mode == MODE_UPDATE) BDDMMA_SWEEP(1, MODE_UPDATE);
+        else BDDMMA_SWEEP(1, MODE_FIXED);
+#undef BDDMMA_SWEEP
+    }
+}
+
+template <typename T>
+void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, double *tile_e, hipStream_t st)
+{
+    const int64_t nl = p.n_lds_tiles, ng = p.n_tiles - p.n_lds_tiles;
+    if (nl > 0) {
+        const unsigned grid = (unsigned)(((nl + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
+        const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
+        hipLaunchKernelGGL((k_cert<T, true>), dim3(grid), dim3(kThreads), lds, st, p, lam, mm, omega, tile_e,
+                           (int64_t)0, nl);
+    }
+    if (ng > 0) {
+        const unsigned grid = (unsigned)(((ng + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
+        hipLaunchKernelGGL((k_cert<T, false>), dim3(grid), dim3(kThreads), 0, st, p, lam, mm, omega, tile_e, nl, ng);
+    }
+}
+
+template <typename T>
+void launch_average(const DevProblem &p, const T *mm, T *avg, T omega, hipStream_t st)
+{
+    if (p.n_vars == 0) return;
+    hipLaunchKernelGGL((k_average<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p.vptr, p.vslot, mm, avg,
+                       (double)omega, p.n_vars);
+}
+
+void launch_reduce_sum(const double *part, int64_t n, double offset, double *scratch, double *out, hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 1023) / 1024));
+    hipLaunchKernelGGL(k_sum_stage1, dim3(nb), dim3(kRedThreads), 0, st, part, n, scratch);
+    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(kRedThreads), 0, st, scratch, nb, offset, out);
+}
+
+template <typename T>
+void launch_init(const DevProblem &p, T *lam, T *mm, T *avg, hipStream_t st)
+{
+    if (p.n_slots > 0) hipLaunchKernelGGL((k_init<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p, lam, mm);
+    launch_fill<T>(avg, T(0), p.n_vars + 1, st);
+}
+
+template <typename T>
+void launch_terminate(const DevProblem &p, T *lam, const T *mm, T omega, hipStream_t st)
+{
+    if (p.n_slots > 0)
+        hipLaunchKernelGGL((k_terminate<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p.n_slots, lam, mm,
+                           omega);
+}
+
+template <typename T>
+void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (p.n_vars + 1023) / 1024));
+    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(kRedThreads), 0, st, p, lam, mm, omega, red);
+    hipLaunchKernelGGL(k_residual_stage2, dim3(1), dim3(kRedThreads), 0, st, red, nb);
+}
+
+template <typename T>
+void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_t *flag, int32_t *counter,
+                      hipStream_t st)
+{
+    launch_fill<int32_t>(counter, 0, 1, st);
+    if (p.n_vars > 0)
+        hipLaunchKernelGGL((k_conflicts<T>), dim3(blocks_for(p.n_vars, kRedThreads)), dim3(kRedThreads), 0, st, p, mm,
+                           tau, flag, counter);
+}
+
+template <typename T>
+void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double delta, uint64_t seed,
+                    uint64_t round, const uint8_t *flag, hipStream_t st)
+{
+    if (p.n_vars > 0)
+        hipLaunchKernelGGL((k_perturb<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p, lam, mm, tau, delta,
+                           seed, round, flag);
+}
+
+template <typename T>
+void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st)
+{
+    if (p.n_vars > 0)
+        hipLaunchKernelGGL((k_decode<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p, mm, x);
+}
+
+template <typename T>
+void launch_fill(T *dst, T value, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, dst, value, n);
+}
+
+template <typename T>
+void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL((k_copy<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, dst, src, n);
+}
+
+#define BDDMMA_INSTANTIATE(T)                                                                                        \
+    template void launch_sweep<T>(const DevProblem &, T *, T *, const T *, double *, T, int, int, hipStream_t);     \
+    template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
+    template void launch_average<T>(const DevProblem &, const T *, T *, T, hipStream_t);                            \
+    template void launch_init<T>(const DevProblem &, T *, T *, T *, hipStream_t);                                   \
+    template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \
+    template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
+    template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *,            \
+                                      hipStream_t);                                                                  \
+    template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t,         \
+                                    const uint8_t *, hipStream_t);                                                   \
+    template void launch_decode<T>(const DevProblem &, const T *, uint8_t *, hipStream_t);                          \
+    template void launch_fill<T>(T *, T, int64_t, hipStream_t);                                                      \
+    template void launch_copy<T>(T *, const T *, int64_t, hipStream_t);
+
+BDDMMA_INSTANTIATE(float)
+BDDMMA_INSTANTIATE(double)
+template void launch_fill<int32_t>(int32_t *, int32_t, int64_t, hipStream_t);
+template void launch_fill<uint8_t>(uint8_t *, uint8_t, int64_t, hipStream_t);
+template void launch_copy<uint8_t>(uint8_t *, const uint8_t *, int64_t, hipStream_t);
+
+}  // namespace bddmma

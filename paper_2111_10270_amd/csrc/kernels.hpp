@@ -1,0 +1,81 @@
+// Host-callable launchers of the solver's HIP kernels.  All pointers are
+// device pointers inside the bound workspace; all launches go to `st`.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.hpp"
+
+namespace bddmma {
+
+// Sweep flavours: UPDATE runs the deferred parallel update of Alg. 1 while it
+// sweeps; FIXED only records min-marginal differences at fixed multipliers.
+enum SweepMode { MODE_UPDATE = 0, MODE_FIXED = 1 };
+
+struct DevProblem {
+    const TileDesc *tiles;
+    int64_t n_tiles, n_lds_tiles;
+    const uint32_t *layers;
+    const uint32_t *child;
+    const int32_t *pair_var;
+    const int32_t *vptr;
+    const int32_t *vslot;
+    const double *cost;
+    int64_t n_vars, n_slots;
+    void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
+    int lds_lane_elems;     // per-lane LDS elements of the largest LDS tile
+};
+
+constexpr int kRedBlocks = 512;
+
+// One sweep over every tile.  dir 0 = ascending variables (Alg. 3), 1 =
+// descending (Alg. 4).  With tile_lb != nullptr each tile writes
+// sum_lanes E^j + omega * sum min(M, 0).  mm_out receives M.
+template <typename T>
+void launch_sweep(const DevProblem &p, T *lam, T *mm_out, const T *avg, double *tile_lb, T omega, int dir,
+                  int mode, hipStream_t st);
+
+template <typename T>
+void launch_average(const DevProblem &p, const T *mm, T *avg, T omega, hipStream_t st);
+
+// out[0] = offset + sum_t part[t] in a fixed order; scratch holds kRedBlocks doubles
+void launch_reduce_sum(const double *part, int64_t n, double offset, double *scratch, double *out, hipStream_t st);
+
+template <typename T>
+void launch_init(const DevProblem &p, T *lam, T *mm, T *avg, hipStream_t st);
+
+// lam += omega * mm on every slot
+template <typename T>
+void launch_terminate(const DevProblem &p, T *lam, const T *mm, T omega, hipStream_t st);
+
+// per-tile energies of lambda + omega * mm in FP64 into tile_e
+template <typename T>
+void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, double *tile_e, hipStream_t st);
+
+// red[0] = sum_i max(r_i, 0), red[1] = max_i |r_i| with r_i = sum_j (lam + omega mm) - c_i;
+// red holds 2 + 2 * kRedBlocks doubles
+template <typename T>
+void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, hipStream_t st);
+
+// counter[0] = number of variables with a zero / disagreeing min-marginal sign or a flag
+template <typename T>
+void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_t *flag, int32_t *counter,
+                      hipStream_t st);
+
+// one Alg. 2 perturbation of every variable
+template <typename T>
+void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double delta, uint64_t seed,
+                    uint64_t round, const uint8_t *flag, hipStream_t st);
+
+// x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
+template <typename T>
+void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st);
+
+template <typename T>
+void launch_fill(T *dst, T value, int64_t n, hipStream_t st);
+
+template <typename T>
+void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
+
+}  // namespace bddmma

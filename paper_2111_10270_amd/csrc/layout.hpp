@@ -1,0 +1,50 @@
+// Device data layout shared by the host packer and the HIP kernels.
+//
+// Subproblem BDDs (Sec. 5, Def. "BDD") are grouped into tiles of 64 whole
+// BDDs, one BDD per lane of a 64-wide wavefront.  Inside a tile everything is
+// layer-major and lane-minor, so the 64 lanes of a wave touch 64 consecutive
+// elements whenever they read or write the pair arrays:
+//
+//   pair slot (tile t, layer h, lane l) = tiles[t].pair_base + h * 64 + l
+//
+// Node structure: nodes of one layer are numbered 0..W_h-1 (W_h = tile-wide
+// layer width).  A node's two successors (Sec. 5: s^0(v), s^1(v)) are stored as
+// one 32-bit word, lo | hi << 16, each an index into the next layer or one of
+// the terminal codes.  Tiles whose 64 BDDs share one topology store the words
+// once (flag TILE_SHARED); other tiles store one word per (node, lane) at
+// node_base + node * 64 + lane, node = layer offset + index.  BDDs shorter than
+// the tile are padded with chain layers whose multiplier stays exactly 0, and
+// partially filled tiles with such chains in every lane; both are neutral for
+// every min-marginal, multiplier and energy.
+#pragma once
+#include <stdint.h>
+
+namespace bddmma {
+
+constexpr int kLanes = 64;
+constexpr uint32_t kBot = 0xFFFFu;   // arc into the rejecting terminal
+constexpr uint32_t kTop = 0xFFFEu;   // arc into the accepting terminal
+constexpr int kMaxWidth = 65533;     // largest layer width encodable in 16 bits
+
+constexpr uint16_t TILE_SHARED = 1;  // all lanes use the same node words
+
+struct TileDesc {
+    uint32_t pair_base;     // first pair slot of the tile
+    uint32_t node_base;     // first node word of the tile
+    uint32_t layer_base;    // first entry of the tile's layer table
+    uint32_t scratch_base;  // per-tile device scratch (shortest paths kept outside LDS)
+    uint16_t K;             // layers (padded length)
+    uint16_t nodes;         // nodes per lane = sum of the layer widths
+    uint16_t flags;
+    uint16_t pad0;
+    uint32_t pad1, pad2;
+};
+static_assert(sizeof(TileDesc) == 32, "TileDesc is 32 bytes");
+
+// layer table entry: node offset of the layer (low 16 bits) | width << 16
+inline uint32_t layer_entry(uint32_t noff, uint32_t width) { return noff | (width << 16); }
+
+// per-lane scratch elements a tile needs (lambda, averaged term, two distance arrays)
+inline uint32_t lane_elems(uint32_t K, uint32_t nodes) { return 2u * K + 2u * nodes; }
+
+}  // namespace bddmma

@@ -1,0 +1,564 @@
+// ILP ingestion, presolve, BDD compilation and tile packing (host side).
+//
+// BDD compilation follows Sec. 5 (Defs. "BDD", "Constraint Set
+// Correspondence"): one layer per variable of the row in ascending id order,
+// two arcs per node, every root-to-accept path a feasible point.  Nodes start
+// as partial sums of the assigned prefix, pruned by the interval of sums the
+// remaining variables can still add; a bottom-up pass then removes nodes that
+// cannot reach the accepting terminal and merges nodes with equal successor
+// pairs, which gives the reduced (canonical) quasi-reduced BDD.  The paper only
+// needs Def. "BDD"; reduction keeps the tiles small.
+#include "problem.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <thread>
+
+namespace bddmma {
+
+namespace {
+
+uint64_t mix64(uint64_t h, uint64_t v)
+{
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h * 0xFF51AFD7ED558CCDull;
+}
+
+bool sense_holds(int64_t v, int sense, int64_t b) { return sense < 0 ? v <= b : sense > 0 ? v >= b : v == b; }
+
+}  // namespace
+
+int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+               const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+               std::string &msg)
+{
+    if (n_vars < 0 || n_rows < 0 || n_vars > INT32_MAX - 1) { msg = "n_vars / n_rows out of range"; return ST_INVALID; }
+    if (n_vars > 0 && !costs) { msg = "costs is NULL"; return ST_INVALID; }
+    if (n_rows > 0 && (!row_ptr || !sense || !rhs)) { msg = "row arrays are NULL"; return ST_INVALID; }
+    if (n_rows > 0 && row_ptr[0] != 0) { msg = "row_ptr[0] must be 0"; return ST_INVALID; }
+    int64_t nnz = n_rows > 0 ? row_ptr[n_rows] : 0;
+    if (nnz > 0 && (!col || !coef)) { msg = "col / coef are NULL"; return ST_INVALID; }
+    o.n_vars = n_vars;
+    o.n_rows = n_rows;
+    o.cost.assign(costs, costs + n_vars);
+    for (int64_t i = 0; i < n_vars; ++i)
+        if (!(costs[i] == costs[i]) || costs[i] == __builtin_inf() || costs[i] == -__builtin_inf()) {
+            msg = "cost " + std::to_string(i) + " is not finite";
+            return ST_INVALID;
+        }
+    o.row_ptr.assign(1, 0);
+    o.col.clear();
+    o.coef.clear();
+    o.sense.assign(sense, sense + n_rows);
+    o.rhs.assign(rhs, rhs + n_rows);
+    std::vector<std::pair<int32_t, int64_t>> ent;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        if (row_ptr[r + 1] < row_ptr[r]) { msg = "row_ptr decreases at row " + std::to_string(r); return ST_INVALID; }
+        if (sense[r] < -1 || sense[r] > 1) { msg = "sense must be -1, 0 or +1"; return ST_INVALID; }
+        ent.clear();
+        __int128 mag = 0;
+        for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n_vars) { msg = "column out of range in row " + std::to_string(r); return ST_INVALID; }
+            if (coef[e] == 0) continue;
+            ent.emplace_back(col[e], (int64_t)coef[e]);
+            mag += coef[e] < 0 ? -(__int128)coef[e] : (__int128)coef[e];
+        }
+        __int128 rb = rhs[r] < 0 ? -(__int128)rhs[r] : (__int128)rhs[r];
+        if (mag + rb > ((__int128)1 << 62)) { msg = "row " + std::to_string(r) + ": coefficient sum too large"; return ST_INVALID; }
+        std::sort(ent.begin(), ent.end());
+        for (size_t q = 1; q < ent.size(); ++q)
+            if (ent[q].first == ent[q - 1].first) { msg = "variable repeated in row " + std::to_string(r); return ST_INVALID; }
+        for (auto &pr : ent) { o.col.push_back(pr.first); o.coef.push_back(pr.second); }
+        o.row_ptr.push_back((int64_t)o.col.size());
+    }
+    return ST_OK;
+}
+
+int compile_row(const int32_t *var, const int64_t *a_in, int k, int sense, int64_t b, BddSet &out,
+                std::string &msg)
+{
+    thread_local std::vector<int64_t> A, slo, shi, cur, nxt;
+    thread_local std::vector<std::vector<int64_t>> S;
+    thread_local std::vector<std::vector<uint32_t>> W;   // raw child words per layer
+    thread_local std::vector<std::vector<uint8_t>> alive;
+    thread_local std::vector<std::vector<int32_t>> nid;
+    thread_local std::vector<std::pair<uint64_t, int32_t>> keys;
+    thread_local std::vector<std::pair<int32_t, int32_t>> reps;
+
+    A.assign(a_in, a_in + k);
+    if (sense > 0) {   // a.x >= b  <=>  -a.x <= -b
+        for (auto &x : A) x = -x;
+        b = -b;
+        sense = -1;
+    }
+    slo.assign(k + 1, 0);
+    shi.assign(k + 1, 0);
+    for (int h = k - 1; h >= 0; --h) {
+        slo[h] = slo[h + 1] + std::min<int64_t>(A[h], 0);
+        shi[h] = shi[h + 1] + std::max<int64_t>(A[h], 0);
+    }
+    auto admissible = [&](int64_t s, int h) {
+        if (sense < 0) return s + slo[h] <= b;
+        return s + slo[h] <= b && b <= s + shi[h];
+    };
+    if (!admissible(0, 0)) return ST_INFEASIBLE;
+    if ((int)S.size() < k + 1) { S.resize(k + 1); W.resize(k + 1); alive.resize(k + 1); nid.resize(k + 1); }
+    S[0].assign(1, 0);
+    for (int h = 0; h < k; ++h) {
+        // successors of layer h: s (zero-arc) and s + a_h (one-arc); both lists sorted
+        const auto &s = S[h];
+        auto &n = S[h + 1];
+        n.clear();
+        size_t i = 0, j = 0;
+        const int64_t d = A[h];
+        while (i < s.size() || j < s.size()) {
+            int64_t v;
+            if (j >= s.size() || (i < s.size() && s[i] <= s[j] + d)) v = s[i++];
+            else v = s[j++] + d;
+            if ((n.empty() || n.back() != v) && (h + 1 == k ? (sense < 0 ? v <= b : v == b) : admissible(v, h + 1)))
+                n.push_back(v);
+        }
+        if (h + 1 < k && (int64_t)n.size() > kMaxWidth) {
+            msg = "BDD layer wider than 65533 nodes";
+            return ST_INVALID;
+        }
+        if (n.empty()) return ST_INFEASIBLE;
+    }
+    // arcs: index into the next layer, or the terminals after the last layer
+    for (int h = 0; h < k; ++h) {
+        const auto &s = S[h];
+        W[h].resize(s.size());
+        for (size_t q = 0; q < s.size(); ++q) {
+            uint32_t c[2];
+            for (int t = 0; t < 2; ++t) {
+                int64_t v = s[q] + (t ? A[h] : 0);
+                if (h + 1 == k) {
+                    c[t] = std::binary_search(S[k].begin(), S[k].end(), v) ? kTop : kBot;
+                } else {
+                    auto it = std::lower_bound(S[h + 1].begin(), S[h + 1].end(), v);
+                    c[t] = (it != S[h + 1].end() && *it == v) ? (uint32_t)(it - S[h + 1].begin()) : kBot;
+                }
+            }
+            W[h][q] = c[0] | (c[1] << 16);
+        }
+    }
+    // bottom-up: drop nodes that cannot reach the accepting terminal
+    for (int h = k - 1; h >= 0; --h) {
+        alive[h].assign(W[h].size(), 0);
+        for (size_t q = 0; q < W[h].size(); ++q) {
+            uint32_t c[2] = {W[h][q] & 0xFFFFu, W[h][q] >> 16};
+            for (int t = 0; t < 2; ++t) {
+                bool ok = c[t] == kTop || (c[t] != kBot && alive[h + 1][c[t]]);
+                if (!ok) c[t] = kBot;
+            }
+            W[h][q] = c[0] | (c[1] << 16);
+            alive[h][q] = (c[0] != kBot) || (c[1] != kBot);
+        }
+    }
+    if (!alive[0][0]) return ST_INFEASIBLE;
+    // bottom-up: merge nodes with equal successor pairs, ids in order of first appearance
+    std::vector<int32_t> width(k);
+    for (int h = k - 1; h >= 0; --h) {
+        keys.clear();
+        for (size_t q = 0; q < W[h].size(); ++q) {
+            if (!alive[h][q]) continue;
+            uint32_t c[2] = {W[h][q] & 0xFFFFu, W[h][q] >> 16};
+            if (h + 1 < k)
+                for (int t = 0; t < 2; ++t)
+                    if (c[t] != kBot) c[t] = (uint32_t)nid[h + 1][c[t]];
+            W[h][q] = c[0] | (c[1] << 16);
+            keys.emplace_back(W[h][q], (int32_t)q);
+        }
+        std::sort(keys.begin(), keys.end());
+        reps.clear();
+        for (size_t q = 0; q < keys.size(); ++q)
+            if (q == 0 || keys[q].first != keys[q - 1].first) reps.emplace_back(keys[q].second, (int32_t)q);
+        std::sort(reps.begin(), reps.end());
+        nid[h].assign(W[h].size(), -1);
+        // group start position -> final id
+        std::vector<int32_t> gid(keys.size());
+        for (size_t r = 0; r < reps.size(); ++r) gid[reps[r].second] = (int32_t)r;
+        int32_t g = -1;
+        for (size_t q = 0; q < keys.size(); ++q) {
+            if (q == 0 || keys[q].first != keys[q - 1].first) g = gid[q];
+            nid[h][keys[q].second] = g;
+        }
+        width[h] = (int32_t)reps.size();
+        // compact words into final order
+        std::vector<uint32_t> words(reps.size());
+        for (size_t r = 0; r < reps.size(); ++r) words[r] = W[h][reps[r].first];
+        W[h].swap(words);
+    }
+    for (int h = 0; h < k; ++h) {
+        out.lay_var.push_back(var[h]);
+        out.lay_width.push_back(width[h]);
+        out.child.insert(out.child.end(), W[h].begin(), W[h].end());
+    }
+    out.lay_off.push_back((int64_t)out.lay_var.size());
+    out.node_off.push_back((int64_t)out.child.size());
+    return ST_OK;
+}
+
+namespace {
+
+struct PassResult {
+    BddSet set;
+    std::vector<std::pair<int32_t, int8_t>> forced;
+    int status = ST_OK;
+    std::string msg;
+};
+
+void compile_rows(const Ilp &ilp, const std::vector<int8_t> &fixed, int64_t r0, int64_t r1, PassResult &res)
+{
+    BddSet &o = res.set;
+    o.lay_off.assign(1, 0);
+    o.node_off.assign(1, 0);
+    std::vector<int32_t> v;
+    std::vector<int64_t> a;
+    for (int64_t r = r0; r < r1; ++r) {
+        v.clear();
+        a.clear();
+        int64_t b = ilp.rhs[r];
+        for (int64_t e = ilp.row_ptr[r]; e < ilp.row_ptr[r + 1]; ++e) {
+            int32_t c = ilp.col[e];
+            if (fixed[c] >= 0) { b -= ilp.coef[e] * fixed[c]; continue; }
+            v.push_back(c);
+            a.push_back(ilp.coef[e]);
+        }
+        if (v.empty()) {
+            if (!sense_holds(0, ilp.sense[r], b)) {
+                res.status = ST_INFEASIBLE;
+                res.msg = "row " + std::to_string(r) + " is violated by the fixed variables";
+                return;
+            }
+            continue;
+        }
+        size_t l0 = o.lay_var.size(), n0 = o.child.size();
+        int st = compile_row(v.data(), a.data(), (int)v.size(), ilp.sense[r], b, o, res.msg);
+        if (st != ST_OK) {
+            res.status = st;
+            if (st == ST_INFEASIBLE) res.msg = "row " + std::to_string(r) + " has no feasible 0-1 point";
+            else res.msg = "row " + std::to_string(r) + ": " + res.msg;
+            return;
+        }
+        o.row.push_back((int32_t)r);
+        // a layer without zero-arcs (one-arcs) forces its variable to 1 (0)
+        size_t node = n0;
+        for (size_t h = l0; h < o.lay_var.size(); ++h) {
+            bool has0 = false, has1 = false;
+            for (int32_t q = 0; q < o.lay_width[h]; ++q, ++node) {
+                uint32_t w = o.child[node];
+                has0 |= (w & 0xFFFFu) != kBot;
+                has1 |= (w >> 16) != kBot;
+            }
+            if (!has0 || !has1) res.forced.emplace_back(o.lay_var[h], (int8_t)(has1 ? 1 : 0));
+        }
+    }
+}
+
+}  // namespace
+
+int build_problem(Problem &p, std::string &msg)
+{
+    const Ilp &ilp = p.ilp;
+    p.fixed.assign(ilp.n_vars, -1);
+    unsigned hw = std::thread::hardware_concurrency();
+    int nthreads = (int)std::max(1u, std::min(hw ? hw : 1u, 16u));
+    if (ilp.n_rows < 4096) nthreads = 1;
+    std::vector<PassResult> res;
+    // Presolve by rounds: compile every row against the fixings known at the
+    // start of the round, then apply all forced values; repeat until a round
+    // forces nothing.  The fixed set is the closure of single-row implications,
+    // so the order of rounds does not change it.
+    for (;;) {
+        res.assign(nthreads, PassResult());
+        std::vector<std::thread> th;
+        int64_t chunk = (ilp.n_rows + nthreads - 1) / nthreads;
+        for (int t = 0; t < nthreads; ++t) {
+            int64_t r0 = std::min<int64_t>(ilp.n_rows, t * chunk), r1 = std::min<int64_t>(ilp.n_rows, r0 + chunk);
+            if (nthreads == 1) compile_rows(ilp, p.fixed, r0, r1, res[t]);
+            else th.emplace_back(compile_rows, std::cref(ilp), std::cref(p.fixed), r0, r1, std::ref(res[t]));
+        }
+        for (auto &t : th) t.join();
+        for (auto &r : res)
+            if (r.status != ST_OK) { msg = r.msg; return r.status; }
+        bool any = false;
+        for (auto &r : res)
+            for (auto &f : r.forced) {
+                int8_t &cur = p.fixed[f.first];
+                if (cur >= 0 && cur != f.second) {
+                    msg = "variable " + std::to_string(f.first) + " is forced to both 0 and 1";
+                    return ST_INFEASIBLE;
+                }
+                if (cur < 0) { cur = f.second; any = true; }
+            }
+        if (!any) break;
+    }
+    // concatenate the per-thread stores (each already in ascending row order)
+    BddSet &B = p.bdds;
+    B = BddSet();
+    B.lay_off.assign(1, 0);
+    B.node_off.assign(1, 0);
+    for (auto &r : res) {
+        const BddSet &s = r.set;
+        int64_t lo = (int64_t)B.lay_var.size(), no = (int64_t)B.child.size();
+        B.row.insert(B.row.end(), s.row.begin(), s.row.end());
+        for (size_t j = 1; j < s.lay_off.size(); ++j) B.lay_off.push_back(lo + s.lay_off[j]);
+        for (size_t j = 1; j < s.node_off.size(); ++j) B.node_off.push_back(no + s.node_off[j]);
+        B.lay_var.insert(B.lay_var.end(), s.lay_var.begin(), s.lay_var.end());
+        B.lay_width.insert(B.lay_width.end(), s.lay_width.begin(), s.lay_width.end());
+        B.child.insert(B.child.end(), s.child.begin(), s.child.end());
+    }
+    res.clear();
+    const int64_t P = (int64_t)B.lay_var.size();
+    p.deg.assign(ilp.n_vars, 0);
+    p.pair_var.resize(P);
+    p.pair_row.resize(P);
+    for (int64_t j = 0; j < B.n_bdds(); ++j)
+        for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) {
+            p.pair_var[q] = B.lay_var[q];
+            p.pair_row[q] = B.row[j];
+            p.deg[B.lay_var[q]]++;
+        }
+    p.lb_offset = 0.0;
+    p.n_fixed = p.n_free = 0;
+    for (int64_t i = 0; i < ilp.n_vars; ++i) {
+        if (p.fixed[i] >= 0) {
+            p.lb_offset += p.fixed[i] ? ilp.cost[i] : 0.0;
+            p.n_fixed++;
+        } else if (p.deg[i] == 0) {
+            p.lb_offset += ilp.cost[i] < 0.0 ? ilp.cost[i] : 0.0;
+            p.n_free++;
+        }
+    }
+    p.n_nodes = (int64_t)B.child.size();
+    if (P >= INT32_MAX) { msg = "too many pairs"; return ST_INVALID; }
+    return ST_OK;
+}
+
+namespace {
+
+struct TilePlan {
+    std::vector<int64_t> lanes;   // BDD ids, -1 for padding lanes
+    bool shared = false;
+    int K = 0;
+    std::vector<int32_t> width;   // [K]
+    int64_t first_row = 0;
+};
+
+}  // namespace
+
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packed &o, std::string &msg)
+{
+    const BddSet &B = p.bdds;
+    const int64_t nb = B.n_bdds();
+    const int64_t V = p.ilp.n_vars;
+    auto k_of = [&](int64_t j) { return (int)(B.lay_off[j + 1] - B.lay_off[j]); };
+    auto n_of = [&](int64_t j) { return (int64_t)(B.node_off[j + 1] - B.node_off[j]); };
+    std::vector<uint64_t> hash(nb);
+    for (int64_t j = 0; j < nb; ++j) {
+        uint64_t h = mix64(0, (uint64_t)k_of(j));
+        for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) h = mix64(h, (uint64_t)B.lay_width[q]);
+        for (int64_t q = B.node_off[j]; q < B.node_off[j + 1]; ++q) h = mix64(h, B.child[q]);
+        hash[j] = h;
+    }
+    auto same_topology = [&](int64_t x, int64_t y) {
+        if (k_of(x) != k_of(y) || n_of(x) != n_of(y) || hash[x] != hash[y]) return false;
+        return std::equal(B.lay_width.begin() + B.lay_off[x], B.lay_width.begin() + B.lay_off[x + 1],
+                          B.lay_width.begin() + B.lay_off[y]) &&
+               std::equal(B.child.begin() + B.node_off[x], B.child.begin() + B.node_off[x + 1],
+                          B.child.begin() + B.node_off[y]);
+    };
+    std::vector<int64_t> order(nb);
+    for (int64_t j = 0; j < nb; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        if (k_of(x) != k_of(y)) return k_of(x) < k_of(y);
+        if (n_of(x) != n_of(y)) return n_of(x) < n_of(y);
+        if (hash[x] != hash[y]) return hash[x] < hash[y];
+        return x < y;
+    });
+    std::vector<TilePlan> plans;
+    std::vector<int64_t> mixed;
+    for (int64_t s = 0; s < nb;) {
+        int64_t e = s + 1;
+        while (e < nb && same_topology(order[s], order[e])) ++e;
+        int64_t len = e - s;
+        int64_t full = len / kLanes, rem = len % kLanes;
+        for (int64_t t = 0; t < full + (rem >= 16 ? 1 : 0); ++t) {
+            TilePlan tp;
+            tp.shared = true;
+            for (int l = 0; l < kLanes; ++l) {
+                int64_t q = s + t * kLanes + l;
+                tp.lanes.push_back(q < e ? order[q] : -1);
+            }
+            plans.push_back(std::move(tp));
+        }
+        if (rem > 0 && rem < 16)
+            for (int64_t q = s + full * kLanes; q < e; ++q) mixed.push_back(order[q]);
+        s = e;
+    }
+    std::sort(mixed.begin(), mixed.end(), [&](int64_t x, int64_t y) {
+        if (n_of(x) != n_of(y)) return n_of(x) < n_of(y);
+        if (k_of(x) != k_of(y)) return k_of(x) < k_of(y);
+        return x < y;
+    });
+    for (size_t s = 0; s < mixed.size(); s += kLanes) {
+        TilePlan tp;
+        for (int l = 0; l < kLanes; ++l) tp.lanes.push_back(s + l < mixed.size() ? mixed[s + l] : -1);
+        plans.push_back(std::move(tp));
+    }
+    // tile shapes
+    for (auto &tp : plans) {
+        int K = 0;
+        tp.first_row = INT64_MAX;
+        for (int64_t j : tp.lanes)
+            if (j >= 0) {
+                K = std::max(K, k_of(j));
+                tp.first_row = std::min<int64_t>(tp.first_row, B.row[j]);
+            }
+        K = std::max(K, 1);
+        tp.K = K;
+        tp.width.assign(K, 1);
+        for (int64_t j : tp.lanes)
+            if (j >= 0)
+                for (int h = 0; h < k_of(j); ++h)
+                    tp.width[h] = std::max(tp.width[h], B.lay_width[B.lay_off[j] + h]);
+        int64_t nodes = 0;
+        for (int w : tp.width) nodes += w;
+        if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
+    }
+    auto tile_nodes = [](const TilePlan &tp) {
+        int64_t n = 0;
+        for (int w : tp.width) n += w;
+        return n;
+    };
+    auto in_lds = [&](const TilePlan &tp) {
+        const int64_t n = tile_nodes(tp);
+        return lds_elem_budget > 0 && (int64_t)lane_elems(tp.K, (uint32_t)n) <= lds_elem_budget &&
+               (lds_max_nodes <= 0 || n <= lds_max_nodes);
+    };
+    std::stable_sort(plans.begin(), plans.end(), [&](const TilePlan &x, const TilePlan &y) {
+        bool lx = in_lds(x), ly = in_lds(y);
+        if (lx != ly) return lx;
+        return x.first_row < y.first_row;
+    });
+
+    // emit
+    o = Packed();
+    o.n_lds_tiles = 0;
+    int64_t slots = 0, scratch = 0;
+    for (auto &tp : plans) {
+        TileDesc d{};
+        d.pair_base = (uint32_t)slots;
+        d.node_base = (uint32_t)o.child.size();
+        d.layer_base = (uint32_t)o.layers.size();
+        d.K = (uint16_t)tp.K;
+        int64_t nodes = tile_nodes(tp);
+        d.nodes = (uint16_t)nodes;
+        d.flags = tp.shared ? TILE_SHARED : 0;
+        bool lds = in_lds(tp);
+        if (lds) {
+            o.n_lds_tiles++;
+            o.max_lds_lane_elems = std::max<int>(o.max_lds_lane_elems, (int)lane_elems(tp.K, (uint32_t)nodes));
+            d.scratch_base = 0;
+        } else {
+            d.scratch_base = (uint32_t)scratch;
+            scratch += (int64_t)kLanes * lane_elems(tp.K, (uint32_t)nodes);
+        }
+        std::vector<uint32_t> noff(tp.K + 1, 0);
+        for (int h = 0; h < tp.K; ++h) {
+            noff[h + 1] = noff[h] + tp.width[h];
+            o.layers.push_back(layer_entry(noff[h], tp.width[h]));
+        }
+        o.max_layers = std::max(o.max_layers, tp.K);
+        for (int w : tp.width) o.max_width = std::max(o.max_width, w);
+        if (tp.shared) {
+            int64_t j = tp.lanes[0];
+            o.child.insert(o.child.end(), B.child.begin() + B.node_off[j], B.child.begin() + B.node_off[j + 1]);
+        } else {
+            size_t base = o.child.size();
+            o.child.resize(base + (size_t)nodes * kLanes, kBot | (kBot << 16));
+            for (int l = 0; l < kLanes; ++l) {
+                int64_t j = tp.lanes[l];
+                int kj = j >= 0 ? k_of(j) : 0;
+                int64_t src = j >= 0 ? B.node_off[j] : 0;
+                for (int h = 0; h < tp.K; ++h) {
+                    if (h < kj) {
+                        int wj = B.lay_width[B.lay_off[j] + h];
+                        for (int q = 0; q < wj; ++q) {
+                            uint32_t w = B.child[src++];
+                            if (h == kj - 1 && kj < tp.K) {   // accept -> padding chain
+                                uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+                                if (lo == kTop) lo = 0;
+                                if (hi == kTop) hi = 0;
+                                w = lo | (hi << 16);
+                            }
+                            o.child[base + (size_t)(noff[h] + q) * kLanes + l] = w;
+                        }
+                    } else {
+                        uint32_t nxt = (h == tp.K - 1) ? kTop : 0u;
+                        o.child[base + (size_t)noff[h] * kLanes + l] = nxt | (nxt << 16);
+                    }
+                }
+            }
+        }
+        o.tiles.push_back(d);
+        slots += (int64_t)tp.K * kLanes;
+        if (slots >= INT32_MAX || scratch >= (int64_t)UINT32_MAX || o.child.size() >= UINT32_MAX) {
+            msg = "problem too large for 32-bit slot indices";
+            return ST_INVALID;
+        }
+    }
+    // every arc must stay inside the tile: heads index the next layer, and only
+    // the last layer may reach the accepting terminal
+    for (const TileDesc &d : o.tiles) {
+        const bool sh = (d.flags & TILE_SHARED) != 0;
+        for (uint32_t h = 0; h < d.K; ++h) {
+            const uint32_t le = o.layers[d.layer_base + h], noff = le & 0xFFFFu, W = le >> 16;
+            const uint32_t Wn = h + 1 < d.K ? (o.layers[d.layer_base + h + 1] >> 16) : 0u;
+            if (noff + W > d.nodes || (h + 1 < d.K && noff + W + Wn > d.nodes)) {
+                msg = "internal error: inconsistent layer table";
+                return ST_INVALID;
+            }
+            for (uint32_t q = 0; q < W; ++q)
+                for (int l = 0; l < (sh ? 1 : kLanes); ++l) {
+                    const uint32_t w = o.child[d.node_base + (sh ? (noff + q) : (size_t)(noff + q) * kLanes + l)];
+                    for (uint32_t c : {w & 0xFFFFu, w >> 16}) {
+                        const bool ok = c == kBot || (c == kTop ? h + 1 == d.K : (h + 1 < d.K && c < Wn));
+                        if (!ok) {
+                            msg = "internal error: BDD arc leaves its tile";
+                            return ST_INVALID;
+                        }
+                    }
+                }
+        }
+    }
+    o.n_slots = slots;
+    o.scratch_elems = scratch;
+    // slots of every pair, and the padding variable id for unused slots
+    const int64_t P = (int64_t)B.lay_var.size();
+    o.pair_var.assign(slots, (int32_t)V);
+    o.slot_of_pair.assign(P, -1);
+    for (size_t t = 0; t < plans.size(); ++t) {
+        const TilePlan &tp = plans[t];
+        for (int l = 0; l < kLanes; ++l) {
+            int64_t j = tp.lanes[l];
+            if (j < 0) continue;
+            for (int h = 0; h < k_of(j); ++h) {
+                int64_t slot = (int64_t)o.tiles[t].pair_base + (int64_t)h * kLanes + l;
+                int64_t pq = B.lay_off[j] + h;
+                o.pair_var[slot] = B.lay_var[pq];
+                o.slot_of_pair[pq] = slot;
+            }
+        }
+    }
+    // variable -> slots in ascending row order (pairs are already in row order)
+    o.vptr.assign(V + 1, 0);
+    for (int64_t i = 0; i < V; ++i) o.vptr[i + 1] = o.vptr[i] + p.deg[i];
+    o.vslot.assign(P, 0);
+    std::vector<int32_t> fill(o.vptr.begin(), o.vptr.end() - 1);
+    for (int64_t q = 0; q < P; ++q) o.vslot[fill[B.lay_var[q]]++] = (int32_t)o.slot_of_pair[q];
+    return ST_OK;
+}
+
+}  // namespace bddmma

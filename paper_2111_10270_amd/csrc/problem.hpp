@@ -1,0 +1,80 @@
+// Host side of the solver: ILP validation, presolve, BDD compilation and the
+// packing of BDDs into 64-lane tiles (see layout.hpp for the device layout).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.hpp"
+
+namespace bddmma {
+
+struct Ilp {
+    int64_t n_vars = 0, n_rows = 0;
+    std::vector<double> cost;
+    std::vector<int64_t> row_ptr;   // rows with columns sorted ascending, zero coefficients removed
+    std::vector<int32_t> col;
+    std::vector<int64_t> coef;
+    std::vector<int8_t> sense;
+    std::vector<int64_t> rhs;
+};
+
+// Flat store of compiled BDDs, in ascending original row order.
+struct BddSet {
+    std::vector<int32_t> row;        // [B] original row id
+    std::vector<int64_t> lay_off;    // [B+1] into lay_var / lay_width
+    std::vector<int32_t> lay_var;    // [P] variable of each layer
+    std::vector<int32_t> lay_width;  // [P] nodes of each layer
+    std::vector<int64_t> node_off;   // [B+1] into child
+    std::vector<uint32_t> child;     // [N] lo | hi << 16 (next-layer index or kTop / kBot)
+    int64_t n_bdds() const { return (int64_t)row.size(); }
+};
+
+struct Packed {
+    // tiles: [0, n_lds_tiles) keep shortest paths in LDS, the rest in device scratch
+    std::vector<TileDesc> tiles;
+    int64_t n_lds_tiles = 0;
+    std::vector<uint32_t> layers;     // layer table
+    std::vector<uint32_t> child;      // node words
+    std::vector<int32_t> pair_var;    // [S] variable per slot, n_vars for padding
+    std::vector<int64_t> slot_of_pair;  // [P] canonical pair -> slot
+    std::vector<int32_t> vptr;        // [V+1] variable -> its slots, ascending row order
+    std::vector<int32_t> vslot;       // [P]
+    int64_t n_slots = 0;
+    int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
+    int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile
+    int max_layers = 0, max_width = 0;
+};
+
+struct Problem {
+    Ilp ilp;
+    std::vector<int8_t> fixed;   // -1 free, else the presolved value
+    std::vector<int32_t> deg;    // |J_i| over kept rows
+    BddSet bdds;
+    std::vector<int32_t> pair_var, pair_row;   // canonical pair order
+    double lb_offset = 0.0;
+    int64_t n_nodes = 0, n_fixed = 0, n_free = 0;
+};
+
+// status codes mirror the C ABI
+enum Status { ST_OK = 0, ST_INVALID = -1, ST_INFEASIBLE = -2, ST_NOMEM = -3 };
+
+// Validate and normalise the CSR input.  Returns ST_OK or ST_INVALID (msg set).
+int ingest_ilp(Ilp &out, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+               const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+               std::string &msg);
+
+// Presolve + compile every remaining row.  ST_OK / ST_INFEASIBLE / ST_INVALID.
+int build_problem(Problem &p, std::string &msg);
+
+// Pack the compiled BDDs into tiles.  lds_elem_budget: per-lane elements a tile
+// may keep in LDS (0 disables LDS); lds_max_nodes > 0 additionally caps the
+// nodes per lane of LDS tiles.  ST_OK / ST_INVALID.
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packed &out, std::string &msg);
+
+// Compile one row  sum a_h x_h (sense) b  over ascending variables into a
+// reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.
+int compile_row(const int32_t *var, const int64_t *a, int k, int sense, int64_t b, BddSet &out,
+                std::string &msg);
+
+}  // namespace bddmma

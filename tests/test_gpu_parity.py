@@ -1,0 +1,353 @@
+"""Parity of the HIP path with the FP64 reference implementation (needs a GPU).
+
+FP64 mode performs the same operations in the same order as the reference
+(min is exact, the only sums are in fixed order), so multipliers, min-marginal
+differences and averaged terms must agree bit for bit; bound sums use a
+different association and agree to 1e-12.  FP32 mode is checked with the
+scaled tolerance |d| <= 1e-4 * max(|ref|, mean|c|).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle as O
+from paper_2111_10270_amd import binding as B
+from paper_2111_10270_amd import instances as I
+from test_oracle import example_a, example_b, tie_example
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    assert torch.cuda.get_device_properties(0).gcnArchName.startswith("gfx950")
+
+
+def solver(ilp, **kw):
+    s = B.Solver(ilp, **kw)
+    return s.bind()
+
+
+def scale_of(ilp):
+    return max(1e-12, float(np.mean(np.abs(ilp.costs)))) if ilp.n_vars else 1.0
+
+
+def fp32_close(got, ref, s, tol=1e-4):
+    got, ref = np.asarray(got), np.asarray(ref)
+    bound = tol * np.maximum(np.abs(ref), s)
+    return bool(np.all(np.abs(got - ref) <= bound)), float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), s), initial=0))
+
+
+def lockstep(ilp, sweeps, precision=64, **kw):
+    """run the GPU and the reference sweep by sweep and compare after each"""
+    note("lockstep", ilp.name, sweeps, precision, kw)
+    s = solver(ilp, precision=precision, **kw)
+    o = O.Oracle(ilp)
+    o.init()
+    sc = scale_of(ilp)
+    worst = 0.0
+    for k in range(sweeps):
+        s.run_sweeps(1)
+        o.sweep(k % 2)
+        o.average()
+        lam, mm, avg = s.get_state()
+        rl, rm, ra = o.get()
+        lbf = s.lb_history()[-1]
+        if precision == 64:
+            assert np.array_equal(lam, rl), k
+            assert np.array_equal(mm, rm), k
+            assert np.array_equal(avg, ra), k
+            assert abs(lbf - o.lb_free()) <= 1e-12 * max(1.0, abs(o.lb_free())), k
+        else:
+            for g, r in ((lam, rl), (mm, rm), (avg, ra)):
+                ok, err = fp32_close(g, r, sc)
+                worst = max(worst, err)
+                assert ok, (k, err)
+            assert abs(lbf - o.lb_free()) <= 1e-4 * max(abs(o.lb_free()), sc * max(1, o.n_bdds)), k
+    lf, lc, res = s.lower_bound()
+    rc_, rres = o.lb_cert()
+    tol = 1e-12 if precision == 64 else 1e-4
+    assert abs(lc - rc_) <= tol * max(1.0, abs(rc_)), (lc, rc_)
+    return s, o, worst
+
+
+# ---------------------------------------------------------------- paper examples
+def test_paper_examples_fp64_bitexact():
+    ilp, _ = example_a()
+    s, o, _ = lockstep(ilp, 8)
+    # the first sweep of the Fig. 2 example, derived by hand from the update rule
+    s2 = solver(ilp, precision=64)
+    s2.run_sweeps(1)
+    lam, mm, _ = s2.get_state()
+    assert list(mm) == [-5, 0.5, 2, 3.5, 5, 1.75] and list(lam) == [-2.5, 0.25, 1, -1.25, -0.5, 2.125]
+    assert s2.lb_history()[-1] == -5.0
+    lockstep(example_b(), 12)
+    lockstep(tie_example(), 4)
+
+
+def test_fig3_min_marginals():
+    ilp = I.from_rows(4, [2.0, 3.0, 1.0, 4.0], [([0, 1, 2, 3], [1, -1, -1, 1], 0, 0)])
+    for prec in (32, 64):
+        s = solver(ilp, precision=prec)
+        assert list(s.min_marginals()) == [3.0, 5.0, 3.0, 5.0]
+        assert s.lower_bound()[1] == 0.0
+
+
+# ---------------------------------------------------------------- random instances
+@pytest.mark.parametrize("lds", [0, -1])
+def test_random_fp64_bitexact(lds):
+    for seed in range(12):
+        ilp = I.random_ilp(14, 10, max_row_len=7, seed=6000 + seed)
+        if O.Oracle(ilp).status != O.OK:
+            continue
+        lockstep(ilp, 10, precision=64, sp_in_lds_max_nodes=lds)
+
+
+@pytest.mark.parametrize("lds", [0, -1])
+def test_random_fp32(lds):
+    for seed in range(12):
+        ilp = I.random_ilp(14, 10, max_row_len=7, seed=7000 + seed)
+        if O.Oracle(ilp).status != O.OK:
+            continue
+        lockstep(ilp, 10, precision=32, sp_in_lds_max_nodes=lds)
+
+
+def test_long_and_wide_rows_fp64():
+    rng = np.random.default_rng(11)
+    # one 150-variable cardinality row (width 4), one knapsack row with large
+    # coefficients (wide layers -> shortest paths outside LDS), plus short rows
+    n = 160
+    rows = [(list(range(150)), [1] * 150, -1, 3)]
+    kv = list(range(140, 156))
+    rows.append((kv, [int(v) for v in rng.integers(3, 40, size=16)], -1, 150))
+    for r in range(40):
+        vs = rng.choice(n, size=3, replace=False)
+        rows.append((vs, [1, 1, 1], -1, 2))
+    ilp = I.from_rows(n, rng.standard_normal(n), rows, name="long_wide")
+    s, o, _ = lockstep(ilp, 6, precision=64)
+    assert s.stats.max_layers >= 150 and s.stats.max_width > 8
+
+
+@pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
+def test_ragged_tile_counts_fp64(n_rows):
+    rng = np.random.default_rng(n_rows)
+    rows = []
+    for r in range(n_rows):
+        k = int(rng.integers(1, 6))
+        vs = rng.choice(40, size=k, replace=False)
+        rows.append((vs, [1] * k, -1, 1))
+    ilp = I.from_rows(40, rng.standard_normal(40), rows, name=f"ragged{n_rows}")
+    lockstep(ilp, 4, precision=64)
+
+
+def test_empty_and_fixed_problems():
+    ilp = I.from_rows(3, [1.0, -2.0, 0.5], [])
+    s = solver(ilp, precision=32)
+    s.run_dual(3)
+    lf, lc, res = s.lower_bound()
+    assert lf == lc == -2.0 and res == 0.0
+    r = s.round_primal()
+    assert r["rc"] == 0 and list(r["x"]) == [0, 1, 0] and r["ub"] == -2.0
+    ilp = I.from_rows(3, [1.0, -2.0, 0.5], [([0], [1], 0, 1), ([0, 1], [1, 1], -1, 1)])   # everything fixed
+    s = solver(ilp, precision=64)
+    s.run_dual(2)
+    assert s.lower_bound()[1] == 1.0
+    r = s.round_primal()
+    assert r["rc"] == 0 and list(r["x"]) == [1, 0, 0]
+
+
+# ---------------------------------------------------------------- the named workloads
+def test_mrf10_fp64_200_iterations():
+    ilp = I.workload("mrf10x10L3")
+    note("mrf10x10L3 fp64 200 iterations")
+    s = solver(ilp, precision=64)
+    o = O.Oracle(ilp)
+    o.init()
+    s.run_dual(200)
+    hist = o.run_dual(200)
+    g = s.lb_history()
+    assert g.shape == hist.shape
+    assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
+    lam, mm, avg = s.get_state()
+    rl, rm, ra = o.get()
+    assert np.array_equal(lam, rl) and np.array_equal(mm, rm) and np.array_equal(avg, ra)
+    lf, lc, res = s.lower_bound()
+    rc_, rres = o.lb_cert()
+    assert abs(lc - rc_) <= 1e-12 * abs(rc_) and res <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["gm1000k10", "track20x500"])
+def test_gm_tracking_fp32(name):
+    ilp = I.workload(name)
+    note(name, "fp32")
+    s = solver(ilp, precision=32)
+    o = O.Oracle(ilp)
+    o.init()
+    sc = scale_of(ilp)
+    done = 0
+    for target in (1, 2, 10):
+        while done < target:
+            s.run_sweeps(1)
+            o.sweep(done % 2)
+            o.average()
+            done += 1
+        lam, mm, avg = s.get_state()
+        rl, rm, _ = o.get()
+        for g, r in ((lam, rl), (mm, rm)):
+            ok, err = fp32_close(g, r, sc)
+            assert ok, (target, err)
+    # 100 iterations: bounds within tolerance, monotone, below the certified bound
+    s.run_sweeps(200 - done)
+    o_hist = np.concatenate([[0.0] * done, o.run_dual((200 - done) // 2)])
+    g = s.lb_history()
+    assert abs(g[-1] - o_hist[-1]) <= 1e-4 * abs(o_hist[-1])
+    lf, lc, res = s.lower_bound()
+    rc_, _ = o.lb_cert()
+    assert abs(lc - rc_) <= 1e-4 * abs(rc_)
+    # LB_free <= LB_cert holds exactly; FP32 path sums move LB_free by ~1e-5 relative
+    assert lf <= lc + 1e-4 * abs(lc)
+    r = s.round_primal()
+    assert r["rc"] == 0
+    assert o.count_violated(r["x"]) == 0
+    assert r["ub"] >= lc - 1e-6 * abs(lc)
+
+
+def test_mrf256_sampled_sweep_and_properties():
+    ilp = I.workload("mrf256x256L8")
+    note("mrf256x256L8: load")
+    s = solver(ilp, precision=32)
+    s.run_dual(20)
+    lam, mm, avg = s.get_state()
+    note("mrf256x256L8: reference")
+    o = O.Oracle(ilp)
+    o.set(lam=lam, mm=mm, avg=avg)
+    s.run_sweeps(1)   # forward sweep (even count)
+    lam2, mm2, _ = s.get_state()
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(o.n_bdds, size=4000, replace=False))
+    o.sweep_subset(0, sel)
+    rl, rm, _ = o.get()
+    rows = s.pairs()[1]
+    first = np.concatenate([[0], np.nonzero(np.diff(rows))[0] + 1, [rows.size]])
+    idx = np.concatenate([np.arange(first[j], first[j + 1]) for j in sel])
+    sc = scale_of(ilp)
+    for g, r in ((lam2[idx], rl[idx]), (mm2[idx], rm[idx])):
+        ok, err = fp32_close(g, r, sc)
+        assert ok, err
+    hist = s.lb_history()
+    assert np.all(np.diff(hist) >= -1e-5 * np.abs(hist[1:]))
+    lf, lc, res = s.lower_bound()
+    assert lf <= lc + 1e-4 * abs(lc)
+    assert res <= 1e-4 * sc * 8
+
+
+# ---------------------------------------------------------------- Alg. 2
+def test_rounding_fp64_matches_reference():
+    cases = [example_a()[0], tie_example()]
+    for seed in range(10):
+        ilp = I.random_ilp(12, 8, max_row_len=5, seed=8000 + seed)
+        if O.Oracle(ilp).status == O.OK:
+            cases.append(ilp)
+    for ilp in cases:
+        note("rounding", ilp.name)
+        s = solver(ilp, precision=64, tau=0.0, seed=3)
+        o = O.Oracle(ilp)
+        o.init()
+        s.run_dual(15)
+        o.run_dual(15)
+        r = s.round_primal()
+        ro = o.round(tau=0.0, seed=3)
+        assert r["rc"] == ro["rc"] and r["rounds"] == ro["rounds"]
+        if r["rc"] == 0:
+            assert np.array_equal(r["x"], ro["x"]) and r["ub"] == ro["ub"]
+            assert brute.check_rows(ilp, r["x"]) == 0
+        # the dual state is untouched by rounding
+        assert np.array_equal(s.get_state()[0], o.get()[0])
+
+
+def test_rounding_not_converged_keeps_state():
+    s = solver(example_b(), precision=64, max_rounds=30)
+    s.run_dual(10)
+    before = s.get_state()
+    r = s.round_primal()
+    assert r["rc"] == B.NOT_CONVERGED and r["rounds"] == 30
+    after = s.get_state()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+
+
+def test_rounding_mrf10_fp32_feasible():
+    ilp = I.workload("mrf10x10L3")
+    s = solver(ilp, precision=32)
+    s.run_dual(100)
+    lf, lc, _ = s.lower_bound()
+    r = s.round_primal()
+    assert r["rc"] == 0 and O.Oracle(ilp).count_violated(r["x"]) == 0
+    assert r["ub"] >= lc - 1e-6 * abs(lc)
+
+
+# ---------------------------------------------------------------- state handling
+@pytest.mark.parametrize("prec", [32, 64])
+def test_checkpoint_resume_is_bitwise(prec):
+    ilp = I.workload("gm1000k10")
+    a = solver(ilp, precision=prec)
+    a.run_dual(10)
+    blob = a.save_state()
+    a.run_dual(10)
+    b = solver(ilp, precision=prec)
+    b.load_state(blob)
+    b.run_dual(10)
+    c = solver(ilp, precision=prec)
+    c.run_dual(20)
+    for x, y, z in zip(a.get_state(), b.get_state(), c.get_state()):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    assert np.array_equal(a.lb_history(), b.lb_history())
+    assert np.array_equal(a.lb_history(), c.lb_history())
+
+
+def test_reset_and_determinism():
+    ilp = I.workload("track20x500")
+    s = solver(ilp, precision=32)
+    s.run_dual(15)
+    h1, st1 = s.lb_history(), s.get_state()
+    s.reset()
+    s.run_dual(15)
+    h2, st2 = s.lb_history(), s.get_state()
+    assert np.array_equal(h1, h2)
+    assert all(np.array_equal(x, y) for x, y in zip(st1, st2))
+
+
+def test_multipliers_are_feasible_and_min_marginals_match():
+    ilp = I.random_ilp(20, 14, max_row_len=6, seed=9)
+    s = solver(ilp, precision=64)
+    o = O.Oracle(ilp)
+    o.init()
+    s.run_dual(7)
+    o.run_dual(7)
+    lam, mm = s.multipliers()
+    pv, _ = s.pairs()
+    acc = np.zeros(ilp.n_vars)
+    np.add.at(acc, pv, lam)
+    used = np.bincount(pv, minlength=ilp.n_vars) > 0
+    assert np.max(np.abs(acc[used] - ilp.costs[used]), initial=0) <= 1e-12 * max(1, np.max(np.abs(ilp.costs)))
+    assert np.array_equal(s.min_marginals(), o.full_mm())
+
+
+def test_profiling_counts_launches():
+    s = solver(I.workload("mrf10x10L3"), precision=32)
+    s.profile(True)
+    s.run_dual(5)
+    for k in (B.K_SWEEP_FWD, B.K_SWEEP_BWD):
+        n, ms = s.kernel_time(k)
+        assert n == 5 and ms > 0
+    n, _ = s.kernel_time(B.K_AVERAGE)
+    assert n == 10
+    s.profile(False)
