@@ -66,7 +66,14 @@ typedef struct {
     int32_t  sp_in_lds_max_nodes; /* subproblems with more nodes keep their shortest
                               paths in device memory instead of LDS; 0 = built-in limit,
                               -1 = never use LDS */
-    int32_t  reserved[7];  /* must be zero */
+    int32_t  fast_path;    /* 1: BDDs with <= 32 layers and <= 4 nodes per layer are swept
+                              by register-resident kernels and variables with |J_i| <= 2
+                              inside one tile are averaged in the sweep; 0: general
+                              kernels and the averaging kernel only.  1 */
+    int32_t  perturb_scale;/* Alg. 2 draws r uniformly from [-delta, delta] and adds r*delta
+                              (0, magnitude up to delta^2) or draws r from [-1, 1] (1,
+                              magnitude up to delta).  0 */
+    int32_t  reserved[5];  /* must be zero */
 } bddmma_options;
 
 typedef struct {
@@ -169,8 +176,10 @@ int bddmma_get_fixed(const bddmma_solver *s, int8_t *fixed);
 int bddmma_get_multipliers(bddmma_solver *s, double *lambda_out, double *mm_out);
 
 /* Raw solver state in pair order (lambda, M-bar) and per variable (the
- * averaged term a_i = omega/|J_i| * sum_k M-bar_ik).  Either pointer may be
- * NULL.  set_state converts to the working precision and resumes from it. */
+ * averaged term a_i = omega/|J_i| * sum_k M-bar_ik, computed from M-bar).  Any
+ * pointer may be NULL.  set_state converts lambda and M-bar to the working
+ * precision and resumes from them; its avg argument is ignored because the
+ * averaged terms are a function of M-bar. */
 int bddmma_get_state(bddmma_solver *s, double *lambda, double *mm, double *avg);
 int bddmma_set_state(bddmma_solver *s, const double *lambda, const double *mm, const double *avg);
 
@@ -186,15 +195,18 @@ int bddmma_min_marginals(bddmma_solver *s, double *mm_out);
  * conflict (x_out untouched).  Any output pointer except x_out may be NULL. */
 int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds);
 
-/* Checkpoint of the dual state (multipliers, deferred differences, averaged
- * terms, sweep counter, bound history).  With buf == NULL sets *bytes to the
+/* Checkpoint of the dual state (multipliers, deferred differences, sweep
+ * counter, bound history).  With buf == NULL sets *bytes to the
  * size needed.  load_state requires the same loaded problem and precision;
  * resuming from it is bitwise identical to not stopping. */
 int bddmma_save_state(const bddmma_solver *s, void *buf, size_t *bytes);
 int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes);
 
 /* Per-kernel timing with HIP events recorded on the bound stream around each
- * launch.  enable != 0 starts a new collection.  kernel ids: BDDMMA_K_*.
+ * launch.  enable != 0 starts a new collection.  kernel ids: BDDMMA_K_*.  A
+ * sweep may be several launches (one per tile class); its events bracket all
+ * of them.  The bound reduction runs inside the averaging launch, so
+ * BDDMMA_K_LB_REDUCE stays empty; it is kept for ABI stability.
  * bddmma_kernel_time synchronises and reports launches and total milliseconds. */
 #define BDDMMA_K_SWEEP_FWD 0
 #define BDDMMA_K_SWEEP_BWD 1

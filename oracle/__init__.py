@@ -65,8 +65,8 @@ def lib():
         L.or_run_dual.argtypes = [P, i, P]
         L.or_rng_u01.restype = d
         L.or_rng_u01.argtypes = [ull, ull, ull]
-        L.or_perturb.argtypes = [P, i, d, d, ull, P]
-        L.or_round.argtypes = [P, d, d, i, i, d, ull, P, P, P, P]
+        L.or_perturb.argtypes = [P, i, d, d, ull, P, i]
+        L.or_round.argtypes = [P, d, d, i, i, d, ull, i, P, P, P, P]
         L.or_count_violated.restype = ll
         L.or_count_violated.argtypes = [P, P]
         _lib = L
@@ -189,17 +189,17 @@ class Oracle:
         return self.get()[1]
 
     # ---- Alg. 2 ----
-    def perturb(self, rnd: int, delta: float, tau: float = 0.0, seed: int = 0, flag=None):
+    def perturb(self, rnd: int, delta: float, tau: float = 0.0, seed: int = 0, flag=None, scale: int = 0):
         f = None if flag is None else np.ascontiguousarray(flag, dtype=np.uint8)
         lib().or_perturb(self.h, int(rnd), float(delta), float(tau), C.c_ulonglong(seed),
-                         None if f is None else _p(f))
+                         None if f is None else _p(f), int(scale))
 
-    def round(self, delta0=1.0, alpha=1.2, reopt_iters=5, max_rounds=200, tau=0.0, seed=0):
+    def round(self, delta0=1.0, alpha=1.2, reopt_iters=5, max_rounds=200, tau=0.0, seed=0, scale=0):
         x = np.zeros(self.ilp.n_vars, dtype=np.uint8)
         ub, rounds = C.c_double(), C.c_int()
         hist = np.zeros(max_rounds + 1, dtype=np.int64)
         rc = lib().or_round(self.h, float(delta0), float(alpha), int(reopt_iters), int(max_rounds),
-                            float(tau), C.c_ulonglong(seed), _p(x), C.byref(ub), C.byref(rounds),
+                            float(tau), C.c_ulonglong(seed), int(scale), _p(x), C.byref(ub), C.byref(rounds),
                             _p(hist))
         return dict(rc=rc, x=x, ub=ub.value, rounds=rounds.value,
                     conflicts=hist[:rounds.value + 1].copy())

@@ -718,13 +718,16 @@ static long long count_conflicts(const OSolver *s, double tau, const unsigned ch
 }
 
 /* one perturbation step of Alg. 2 for every variable (the four cases);
- * flag (may be NULL) marks variables of rows the decoded point violated */
+ * flag (may be NULL) marks variables of rows the decoded point violated.
+ * scale 0: r ~ U[-delta, delta] as the listing samples it, so r*delta reaches
+ * delta^2; scale 1: r ~ U[-1, 1], so every step is at most delta. */
 void or_perturb(OSolver *s, int round, double delta, double tau, unsigned long long seed,
-                const unsigned char *flag)
+                const unsigned char *flag, int scale)
 {
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) continue;
-        double r = (2.0 * or_rng_u01(seed, (unsigned long long)round, (unsigned long long)i) - 1.0) * delta;
+        double r = 2.0 * or_rng_u01(seed, (unsigned long long)round, (unsigned long long)i) - 1.0;
+        if (scale == 0) r = r * delta;
         int pos = 1, neg = 1, zero = 1;
         double sum = 0.0;
         for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) {
@@ -752,7 +755,7 @@ void or_perturb(OSolver *s, int round, double delta, double tau, unsigned long l
 }
 
 int or_round(OSolver *s, double delta0, double alpha, int reopt_iters, int max_rounds, double tau,
-             unsigned long long seed, unsigned char *x_out, double *ub, int *rounds_out,
+             unsigned long long seed, int scale, unsigned char *x_out, double *ub, int *rounds_out,
              long long *conflict_hist)
 {
     size_t np = (size_t)s->np, nv = (size_t)s->n_vars;
@@ -785,7 +788,7 @@ int or_round(OSolver *s, double delta0, double alpha, int reopt_iters, int max_r
             if (!bad) { rc = OR_OK; break; }
         }
         if (round == max_rounds) break;
-        or_perturb(s, round, delta, tau, seed, flag);
+        or_perturb(s, round, delta, tau, seed, flag, scale);
         memset(flag, 0, nv);
         delta = delta * alpha;
         for (long long i = 0; i < s->n_vars; ++i) s->avg[i] = 0.0;

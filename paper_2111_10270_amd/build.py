@@ -9,7 +9,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbddmma.so")
-SOURCES = ["kernels.hip", "problem.cpp", "capi.cpp"]
+# (source, object name, extra defines); sweep_reg.hip is built once per
+# (precision, direction) so its unrolled kernels compile in parallel
+UNITS = [("kernels.hip", "kernels", []), ("problem.cpp", "problem", []), ("capi.cpp", "capi", [])] + [
+    ("sweep_reg.hip", f"sweep_reg_{t}_{d}", [f"-DBDDMMA_REG_T={t}", f"-DBDDMMA_REG_DIR={d}"])
+    for t in ("float", "double") for d in (0, 1)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -17,19 +21,32 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-I", CSRC, "-I", INCLUDE]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every source (always; the call is the build check) and link libbddmma.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    cmds, objs = [], []
+    for src, name, defs in UNITS:
+        obj = os.path.join(objdir, name + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC] + FLAGS + defs + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.DEVNULL)
-        objs.append(obj)
+        r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+        return r.stderr
+
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for err in ex.map(run, cmds):
+            if verbose and err:
+                print(err, flush=True)
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)

@@ -31,8 +31,8 @@ constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 K
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t lam, mm, lam_bak, mm_bak, mmx, avg, avg_bak;
-    size_t pair_var, vptr, vslot, child, tiles, layers, cost;
+    size_t lam, mm, abar, lam_bak, mm_bak, abar_bak, mmx, avg;
+    size_t pair_var, vptr, vslot, code, gvars, child, tiles, lists, layers, cost;
     size_t tile_lb, tile_e, red, lbh, counter, flag, x, scratch;
     size_t total;
 };
@@ -95,16 +95,20 @@ Layout make_layout(const bddmma_solver &s)
     };
     L.lam = take(S * e);
     L.mm = take(S * e);
+    L.abar = take(S * e);
     L.lam_bak = take(S * e);
     L.mm_bak = take(S * e);
+    L.abar_bak = take(S * e);
     L.mmx = take(S * e);
     L.avg = take((V + 1) * e);
-    L.avg_bak = take((V + 1) * e);
     L.pair_var = take(S * 4);
     L.vptr = take((V + 1) * 4);
     L.vslot = take(P * 4);
+    L.code = take(S * 2);
+    L.gvars = take(pk.gvars.size() * 4);
     L.child = take(pk.child.size() * 4);
     L.tiles = take(T * sizeof(TileDesc));
+    L.lists = take(pk.lists.size() * 4);
     L.layers = take(pk.layers.size() * 4);
     L.cost = take(V * 8);
     L.tile_lb = take(T * 8);
@@ -155,25 +159,34 @@ struct Scope {
 
 // ---- Alg. 1 pieces ------------------------------------------------------------
 template <typename T>
+Omega<T> weights(const bddmma_solver *s)
+{
+    return Omega<T>{(T)s->opt.omega, (T)(s->opt.omega / 2.0)};
+}
+
+// averaging of the variables not averaged in-tile, optionally with the bound record
+template <typename T>
+void average(bddmma_solver *s, const double *tile_lb, double *lb_slot)
+{
+    launch_average<T>(s->dp, s->ptr<T>(s->L.mm), s->ptr<T>(s->L.abar), s->opt.omega, tile_lb, s->prob.lb_offset,
+                      s->ptr<double>(s->L.red) + 2 * kRedBlocks + 4, s->ptr<int32_t>(s->L.counter) + 4, lb_slot,
+                      s->st);
+}
+
+template <typename T>
 void one_sweep(bddmma_solver *s, int dir, bool record_lb)
 {
     const DevProblem &p = s->dp;
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *avg = s->ptr<T>(s->L.avg);
-    const T omega = (T)s->opt.omega;
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *abar = s->ptr<T>(s->L.abar);
     double *tile_lb = record_lb ? s->ptr<double>(s->L.tile_lb) : nullptr;
     {
         Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD);
-        launch_sweep<T>(p, lam, mm, avg, tile_lb, omega, dir, MODE_UPDATE, s->st);
+        launch_sweep<T>(p, lam, mm, abar, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
     }
     {
+        // averaging; with a bound record it also reduces the sweep's per-tile partials
         Scope sc(s, BDDMMA_K_AVERAGE);
-        launch_average<T>(p, mm, avg, omega, s->st);
-    }
-    if (record_lb) {
-        Scope sc(s, BDDMMA_K_LB_REDUCE);
-        double *slot = s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap);
-        launch_reduce_sum(tile_lb, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, s->ptr<double>(s->L.red) + 2 * kRedBlocks + 4,
-                          slot, s->st);
+        average<T>(s, tile_lb, s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap));
     }
 }
 
@@ -264,6 +277,8 @@ int get_state_T(bddmma_solver *s, double *lam, double *mm, double *avg)
     }
     if (avg) {
         const int64_t V = s->prob.ilp.n_vars;
+        launch_average_all<T>(s->dp, s->ptr<T>(s->L.mm), s->ptr<T>(s->L.avg), s->opt.omega, s->st);
+        if ((rc = check_launch())) return rc;
         std::vector<T> buf((size_t)std::max<int64_t>(V, 1));
         if (V > 0) HIPCHK(hipMemcpyAsync(buf.data(), s->dev + s->L.avg, (size_t)V * sizeof(T), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
@@ -286,18 +301,14 @@ int upload_pairs(bddmma_solver *s, size_t off, const double *src)
 }
 
 template <typename T>
-int set_state_T(bddmma_solver *s, const double *lam, const double *mm, const double *avg)
+int set_state_T(bddmma_solver *s, const double *lam, const double *mm)
 {
     int rc;
     if (lam && (rc = upload_pairs<T>(s, s->L.lam, lam))) return rc;
     if (mm && (rc = upload_pairs<T>(s, s->L.mm, mm))) return rc;
-    if (avg) {
-        const int64_t V = s->prob.ilp.n_vars;
-        std::vector<T> buf((size_t)V + 1, T(0));
-        for (int64_t i = 0; i < V; ++i) buf[(size_t)i] = (T)avg[i];
-        HIPCHK(hipMemcpyAsync(s->dev + s->L.avg, buf.data(), (size_t)(V + 1) * sizeof(T), hipMemcpyHostToDevice, s->st));
-        HIPCHK(hipStreamSynchronize(s->st));
-    }
+    average<T>(s, nullptr, nullptr);   // averaged terms follow from M-bar
+    if ((rc = check_launch())) return rc;
+    HIPCHK(hipStreamSynchronize(s->st));
     return BDDMMA_OK;
 }
 
@@ -320,7 +331,7 @@ template <typename T>
 int min_marginals_T(bddmma_solver *s, double *out)
 {
     T *lam = s->ptr<T>(s->L.lam), *mmx = s->ptr<T>(s->L.mmx);
-    launch_sweep<T>(s->dp, lam, mmx, s->ptr<T>(s->L.avg), nullptr, (T)s->opt.omega, 0, MODE_FIXED, s->st);
+    launch_sweep<T>(s->dp, lam, mmx, s->ptr<T>(s->L.abar), nullptr, weights<T>(s), 0, MODE_FIXED, s->st);
     int rc = check_launch();
     if (rc) return rc;
     std::vector<double> v;
@@ -343,17 +354,18 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
 {
     const DevProblem &p = s->dp;
     const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars;
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *avg = s->ptr<T>(s->L.avg);
-    T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak), *avg_b = s->ptr<T>(s->L.avg_bak);
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *abar = s->ptr<T>(s->L.abar);
+    T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak), *abar_b = s->ptr<T>(s->L.abar_bak);
     uint8_t *flag = s->ptr<uint8_t>(s->L.flag), *xd = s->ptr<uint8_t>(s->L.x);
     int32_t *counter = s->ptr<int32_t>(s->L.counter);
     const T omega = (T)s->opt.omega;
+    const Omega<T> w = weights<T>(s);
     launch_copy<T>(lam_b, lam, S, s->st);
     launch_copy<T>(mm_b, mm, S, s->st);
-    launch_copy<T>(avg_b, avg, V + 1, s->st);
+    launch_copy<T>(abar_b, abar, S, s->st);
     launch_fill<uint8_t>(flag, 0, V, s->st);
     launch_terminate<T>(p, lam, mm, omega, s->st);
-    launch_sweep<T>(p, lam, mm, avg, nullptr, omega, 0, MODE_FIXED, s->st);
+    launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
 
     const Ilp &ilp = s->prob.ilp;
     const BddSet &B = s->prob.bdds;
@@ -390,20 +402,22 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
             if (V > 0) HIPCHK(hipMemcpyAsync(flag, fl.data(), (size_t)V, hipMemcpyHostToDevice, s->st));
         }
         if (round == s->opt.max_rounds) break;
-        launch_perturb<T>(p, lam, mm, s->tau, delta, s->opt.seed, (uint64_t)round, flag, s->st);
+        launch_perturb<T>(p, lam, mm, s->tau, delta, s->opt.seed, (uint64_t)round, s->opt.perturb_scale, flag, s->st);
         launch_fill<uint8_t>(flag, 0, V, s->st);
         delta = delta * s->opt.alpha;
-        launch_fill<T>(avg, T(0), V + 1, s->st);
+        // Alg. 1 restarts with M-bar = 0
+        launch_fill<T>(mm, T(0), S, s->st);
+        launch_fill<T>(abar, T(0), S, s->st);
         for (int t = 0; t < s->opt.reopt_iters; ++t) {
             one_sweep<T>(s, 0, false);
             one_sweep<T>(s, 1, false);
         }
         launch_terminate<T>(p, lam, mm, omega, s->st);
-        launch_sweep<T>(p, lam, mm, avg, nullptr, omega, 0, MODE_FIXED, s->st);
+        launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
     }
     launch_copy<T>(lam, lam_b, S, s->st);
     launch_copy<T>(mm, mm_b, S, s->st);
-    launch_copy<T>(avg, avg_b, V + 1, s->st);
+    launch_copy<T>(abar, abar_b, S, s->st);
     int e = check_launch();
     if (e) return e;
     HIPCHK(hipStreamSynchronize(s->st));
@@ -457,6 +471,7 @@ int bddmma_options_default(bddmma_options *o)
     o->tau = -1.0;
     o->seed = 0;
     o->sp_in_lds_max_nodes = 0;
+    o->fast_path = 1;
     return BDDMMA_OK;
 }
 
@@ -475,7 +490,9 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (!(o.delta0 > 0.0) || !(o.alpha >= 1.0)) return fail(BDDMMA_ERR_INVALID_ARG, "need delta0 > 0 and alpha >= 1");
     if (o.reopt_iters < 0 || o.max_rounds < 0) return fail(BDDMMA_ERR_INVALID_ARG, "reopt_iters / max_rounds must be >= 0");
     if (o.sp_in_lds_max_nodes < -1) return fail(BDDMMA_ERR_INVALID_ARG, "sp_in_lds_max_nodes must be >= -1");
-    for (int i = 0; i < 7; ++i)
+    if (o.fast_path != 0 && o.fast_path != 1) return fail(BDDMMA_ERR_INVALID_ARG, "fast_path must be 0 or 1");
+    if (o.perturb_scale != 0 && o.perturb_scale != 1) return fail(BDDMMA_ERR_INVALID_ARG, "perturb_scale must be 0 or 1");
+    for (int i = 0; i < 5; ++i)
         if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
@@ -509,7 +526,7 @@ int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64
     rc = build_problem(s->prob, msg);
     if (rc != ST_OK) return fail(rc, msg);
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
-    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->pk, msg);
+    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0, s->pk, msg);
     if (rc != ST_OK) return fail(rc, msg);
     s->L = make_layout(*s);
     double cmax = 1.0;
@@ -568,27 +585,35 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     HIPCHK(up(L.pair_var, pk.pair_var.data(), pk.pair_var.size() * 4));
     HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
     HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
+    HIPCHK(up(L.code, pk.code.data(), pk.code.size() * 2));
+    HIPCHK(up(L.gvars, pk.gvars.data(), pk.gvars.size() * 4));
     HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
     HIPCHK(up(L.tiles, pk.tiles.data(), pk.tiles.size() * sizeof(TileDesc)));
+    HIPCHK(up(L.lists, pk.lists.data(), pk.lists.size() * 4));
     HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
     HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
     DevProblem &d = s->dp;
     d.tiles = s->ptr<TileDesc>(L.tiles);
     d.n_tiles = (int64_t)pk.tiles.size();
-    d.n_lds_tiles = pk.n_lds_tiles;
+    d.lists = s->ptr<int32_t>(L.lists);
+    for (int l = 0; l <= kNumLists; ++l) d.list_off[l] = pk.list_off[l];
     d.layers = s->ptr<uint32_t>(L.layers);
     d.child = s->ptr<uint32_t>(L.child);
     d.pair_var = s->ptr<int32_t>(L.pair_var);
     d.vptr = s->ptr<int32_t>(L.vptr);
     d.vslot = s->ptr<int32_t>(L.vslot);
+    d.code = s->ptr<uint16_t>(L.code);
+    d.gvars = s->ptr<int32_t>(L.gvars);
+    d.n_gvars = (int64_t)pk.gvars.size();
     d.cost = s->ptr<double>(L.cost);
     d.n_vars = s->prob.ilp.n_vars;
     d.n_slots = pk.n_slots;
     d.scratch = s->dev + L.scratch;
     d.lds_lane_elems = pk.max_lds_lane_elems;
-    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.avg), s->st);
-    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.avg), s->st);
+    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.abar), s->st);
+    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.abar), s->st);
     launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars, s->st);
+    launch_fill<int32_t>(s->ptr<int32_t>(L.counter), 0, 16, s->st);
     int rc = check_launch();
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
@@ -606,8 +631,8 @@ int bddmma_reset(bddmma_solver *s)
     int rc = check_ready(s);
     if (rc) return rc;
     const Layout &L = s->L;
-    if (s->elem == 8) launch_init<double>(s->dp, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.avg), s->st);
-    else launch_init<float>(s->dp, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.avg), s->st);
+    if (s->elem == 8) launch_init<double>(s->dp, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.abar), s->st);
+    else launch_init<float>(s->dp, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.abar), s->st);
     rc = check_launch();
     if (rc) return rc;
     s->sweeps = 0;
@@ -725,7 +750,8 @@ int bddmma_set_state(bddmma_solver *s, const double *lam, const double *mm, cons
     GUARD_BEGIN
     int rc = check_ready(s);
     if (rc) return rc;
-    return s->elem == 8 ? set_state_T<double>(s, lam, mm, avg) : set_state_T<float>(s, lam, mm, avg);
+    (void)avg;   // the averaged terms are a function of M-bar and are recomputed
+    return s->elem == 8 ? set_state_T<double>(s, lam, mm) : set_state_T<float>(s, lam, mm);
     GUARD_END
 }
 
@@ -757,13 +783,13 @@ int bddmma_save_state(const bddmma_solver *s_, void *buf, size_t *bytes)
     if (rc) return rc;
     if (!bytes) return fail(BDDMMA_ERR_INVALID_ARG, "bytes is NULL");
     const uint64_t S = (uint64_t)s->pk.n_slots, V = (uint64_t)s->prob.ilp.n_vars;
-    const size_t need = sizeof(StateHeader) + (size_t)(2 * S + V + 1) * s->elem + s->hist.size() * 8;
+    const size_t need = sizeof(StateHeader) + (size_t)(2 * S) * s->elem + s->hist.size() * 8;
     if (!buf) {
         *bytes = need;
         return BDDMMA_OK;
     }
     if (*bytes < need) return fail(BDDMMA_ERR_NO_MEMORY, "state buffer too small");
-    StateHeader h{kMagic, 1, (uint64_t)s->elem, S, V, (uint64_t)s->prob.pair_var.size(), (uint64_t)s->sweeps,
+    StateHeader h{kMagic, 2, (uint64_t)s->elem, S, V, (uint64_t)s->prob.pair_var.size(), (uint64_t)s->sweeps,
                   (uint64_t)s->hist.size()};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
@@ -772,8 +798,6 @@ int bddmma_save_state(const bddmma_solver *s_, void *buf, size_t *bytes)
     p += S * s->elem;
     if (S) HIPCHK(hipMemcpyAsync(p, s->dev + s->L.mm, S * s->elem, hipMemcpyDeviceToHost, s->st));
     p += S * s->elem;
-    HIPCHK(hipMemcpyAsync(p, s->dev + s->L.avg, (V + 1) * s->elem, hipMemcpyDeviceToHost, s->st));
-    p += (V + 1) * s->elem;
     HIPCHK(hipStreamSynchronize(s->st));
     if (!s->hist.empty()) std::memcpy(p, s->hist.data(), s->hist.size() * 8);
     *bytes = need;
@@ -790,18 +814,19 @@ int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
     StateHeader h;
     std::memcpy(&h, buf, sizeof(h));
     const uint64_t S = (uint64_t)s->pk.n_slots, V = (uint64_t)s->prob.ilp.n_vars;
-    if (h.magic != kMagic || h.version != 1 || h.elem != (uint64_t)s->elem || h.n_slots != S || h.n_vars != V ||
+    if (h.magic != kMagic || h.version != 2 || h.elem != (uint64_t)s->elem || h.n_slots != S || h.n_vars != V ||
         h.n_pairs != (uint64_t)s->prob.pair_var.size())
         return fail(BDDMMA_ERR_INVALID_ARG, "state does not belong to this problem / precision");
-    const size_t need = sizeof(StateHeader) + (size_t)(2 * S + V + 1) * s->elem + h.hist * 8;
+    const size_t need = sizeof(StateHeader) + (size_t)(2 * S) * s->elem + h.hist * 8;
     if (bytes < need) return fail(BDDMMA_ERR_INVALID_ARG, "state buffer truncated");
     const char *p = (const char *)buf + sizeof(h);
     if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.lam, p, S * s->elem, hipMemcpyHostToDevice, s->st));
     p += S * s->elem;
     if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.mm, p, S * s->elem, hipMemcpyHostToDevice, s->st));
     p += S * s->elem;
-    HIPCHK(hipMemcpyAsync(s->dev + s->L.avg, p, (V + 1) * s->elem, hipMemcpyHostToDevice, s->st));
-    p += (V + 1) * s->elem;
+    if (s->elem == 8) average<double>(s, nullptr, nullptr);
+    else average<float>(s, nullptr, nullptr);
+    if ((rc = check_launch())) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
     s->hist.assign((const double *)p, (const double *)p + h.hist);
     s->sweeps = (int64_t)h.sweeps;

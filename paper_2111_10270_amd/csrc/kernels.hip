@@ -14,76 +14,12 @@
 
 #include <algorithm>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace bddmma {
 
 namespace {
-
-constexpr int kWavesPerBlock = 2;
-constexpr int kThreads = kWavesPerBlock * kLanes;
-constexpr int kRedThreads = 256;
-constexpr int kPrefetch = 8;
-
-template <typename T>
-__device__ __forceinline__ T inf_of();
-template <>
-__device__ __forceinline__ float inf_of<float>() { return __builtin_huge_valf(); }
-template <>
-__device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
-
-// Blocks are handed to the 8 XCDs round robin; remap so that consecutive
-// logical blocks (and hence neighbouring tiles, which share variables) run on
-// the same XCD and share its L2.  gridDim.x is a multiple of 8.
-__device__ __forceinline__ int64_t xcd_block()
-{
-    const int64_t b = blockIdx.x, per = gridDim.x >> 3;
-    return (b & 7) * per + (b >> 3);
-}
-
-__device__ __forceinline__ int64_t grid_round8(int64_t blocks) { return (blocks + 7) & ~int64_t(7); }
-
-template <typename T>
-__device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
-
-struct TileView {
-    uint32_t pb, nb, lb, K, NN;
-    bool shared;
-};
-
-__device__ __forceinline__ TileView load_tile(const TileDesc *td)
-{
-    TileView v;
-    v.pb = uni(td->pair_base);
-    v.nb = uni(td->node_base);
-    v.lb = uni(td->layer_base);
-    v.K = uni(td->K);
-    v.NN = uni(td->nodes);
-    v.shared = (uni(td->flags) & TILE_SHARED) != 0;
-    return v;
-}
-
-__device__ __forceinline__ uint32_t node_word(const uint32_t *__restrict__ child, const TileView &tv, uint32_t node,
-                                              int lane)
-{
-    return tv.shared ? child[tv.nb + node] : child[tv.nb + (size_t)node * kLanes + lane];
-}
-
-// value of an arc's head in the distance-to-accept array (layer offset noffn)
-template <typename T>
-__device__ __forceinline__ T head_val(uint32_t c, const T *Bk, uint32_t noffn)
-{
-    return c == kTop ? T(0) : (c == kBot ? inf_of<T>() : Bk[(size_t)(noffn + c) * kLanes]);
-}
-
-template <typename T>
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // The sweep.  DIR 0: ascending variables (Alg. 3), DIR 1: descending (Alg. 4).
@@ -93,16 +29,18 @@ __device__ __forceinline__ double wave_sum(double v)
 // MODE_FIXED: same min-marginals at fixed multipliers.
 // ---------------------------------------------------------------------------
 template <typename T, int DIR, int MODE, bool LDS>
-__global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict__ lam, T *__restrict__ mm_out,
-                                                     const T *__restrict__ avg, double *__restrict__ tile_lb,
-                                                     T omega, int64_t tile_begin, int64_t tile_count)
+__global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict__ lam, T *mm,
+                                                     const T *__restrict__ abar, double *__restrict__ tile_lb,
+                                                     Omega<T> w, const int32_t *__restrict__ list, int64_t tile_count)
 {
+    const T omega = w.w1;
+    T *const mm_out = mm;   // read for the in-tile averaging before this sweep overwrites it
     extern __shared__ unsigned char smem_raw[];
     const int lane = threadIdx.x & (kLanes - 1);
     const uint32_t wave = uni(threadIdx.x >> 6);
     const int64_t lt = xcd_block() * kWavesPerBlock + wave;
     if (lt >= tile_count) return;
-    const int64_t tile = tile_begin + lt;
+    const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
     const TileView tv = load_tile(P.tiles + tile);
     const uint32_t *__restrict__ child = P.child;
     const uint32_t *__restrict__ layers = P.layers + tv.lb;
@@ -121,22 +59,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
     // stage multipliers (and averaged terms) of all layers: all loads of a
     // chunk are issued before the first one is used
     for (uint32_t h0 = 0; h0 < tv.K; h0 += kPrefetch) {
-        T lv[kPrefetch];
-        int32_t pv[kPrefetch];
+        T lv[kPrefetch], mv[kPrefetch];
+        uint32_t cv[kPrefetch];
 #pragma unroll
         for (int u = 0; u < kPrefetch; ++u) {
             const uint32_t h = h0 + u;
             if (h < tv.K) {
                 const uint32_t s = tv.pb + h * kLanes + lane;
                 lv[u] = lam[s];
-                if (MODE == MODE_UPDATE) pv[u] = P.pair_var[s];
+                if (MODE == MODE_UPDATE) {
+                    mv[u] = mm[s];
+                    cv[u] = P.code[s];
+                }
             }
         }
         if (MODE == MODE_UPDATE) {
             T av[kPrefetch];
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u)
-                if (h0 + u < tv.K) av[u] = avg[pv[u]];
+                if (h0 + u < tv.K)
+                    av[u] = averaged_term(mm, abar, tv.pb, tv.pb + (h0 + u) * kLanes + lane, cv[u], mv[u], w);
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u)
                 if (h0 + u < tv.K) avS[(size_t)(h0 + u) * kLanes] = av[u];
@@ -266,11 +208,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
     }
 }
 
+
 // E^j(lambda + omega M) of every lane in FP64, summed per tile
 template <typename T, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__restrict__ lam,
                                                     const T *__restrict__ mm, double omega,
-                                                    double *__restrict__ tile_e, int64_t tile_begin,
+                                                    double *__restrict__ tile_e, const int32_t *__restrict__ list,
                                                     int64_t tile_count)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -278,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__rest
     const uint32_t wave = uni(threadIdx.x >> 6);
     const int64_t lt = xcd_block() * kWavesPerBlock + wave;
     if (lt >= tile_count) return;
-    const int64_t tile = tile_begin + lt;
+    const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
     const TileView tv = load_tile(P.tiles + tile);
     const uint32_t *__restrict__ layers = P.layers + tv.lb;
     double *F;
@@ -320,24 +263,6 @@ __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__rest
     }
     const double e = wave_sum<T>(top);
     if (lane == 0) tile_e[tile] = e;
-}
-
-// a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, summed in ascending row order
-template <typename T>
-__global__ __launch_bounds__(256) void k_average(const int32_t *__restrict__ vptr, const int32_t *__restrict__ vslot,
-                                                 const T *__restrict__ mm, T *__restrict__ avg, double omega,
-                                                 int64_t V)
-{
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    const int32_t a = vptr[v], b = vptr[v + 1];
-    if (a == b) {
-        avg[v] = T(0);
-        return;
-    }
-    T s = T(0);
-    for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
-    avg[v] = (T)(omega / (double)(b - a)) * s;
 }
 
 // fixed-order two-stage sum: stage 1 writes one partial per block
@@ -385,8 +310,79 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_stage2(const double *__rest
     if (threadIdx.x == 0) out[0] = t + offset;
 }
 
+
+// a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, summed in ascending row order,
+// for the variables the sweep does not average in-tile; the term is stored at
+// every slot of i.  The first `nlb` blocks also reduce the per-tile bound
+// partials of the sweep that produced M: block b sums a fixed chunk, and the
+// last of those blocks to finish adds the chunk sums in block order, so the
+// result does not depend on scheduling.
 template <typename T>
-__global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam, T *__restrict__ mm)
+__global__ __launch_bounds__(kRedThreads) void k_average(const int32_t *__restrict__ gvars, int64_t n_gvars,
+                                                         const int32_t *__restrict__ vptr,
+                                                         const int32_t *__restrict__ vslot,
+                                                         const T *__restrict__ mm, T *__restrict__ abar,
+                                                         double omega, const double *__restrict__ tile_lb,
+                                                         int64_t n_tiles, int nlb, double offset,
+                                                         double *__restrict__ stage, int32_t *counter,
+                                                         double *__restrict__ lb_out)
+{
+    __shared__ double sh[kRedThreads];
+    __shared__ int last;
+    const int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    if (i < n_gvars) {
+        const int32_t v = gvars[i];
+        const int32_t a = vptr[v], b = vptr[v + 1];
+        T s = T(0);
+        for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
+        const T av = (T)(omega / (double)(b - a)) * s;
+        for (int32_t q = a; q < b; ++q) abar[vslot[q]] = av;
+    }
+    if (tile_lb == nullptr || (int)blockIdx.x >= nlb) return;
+    const int64_t per = (n_tiles + nlb - 1) / nlb;
+    const int64_t t0 = (int64_t)blockIdx.x * per, t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
+    double acc = 0.0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kRedThreads) acc += tile_lb[t];
+    const double part = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(stage + blockIdx.x, part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = (atomicAdd(counter, 1) == nlb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int j = threadIdx.x; j < nlb; j += kRedThreads)
+        t += __hip_atomic_load(stage + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double tot = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        lb_out[0] = tot + offset;
+        __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// per-variable a_i of every variable (state export)
+template <typename T>
+__global__ __launch_bounds__(256) void k_average_all(const int32_t *__restrict__ vptr,
+                                                     const int32_t *__restrict__ vslot, const T *__restrict__ mm,
+                                                     T *__restrict__ avg, double omega, int64_t V)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int32_t a = vptr[v], b = vptr[v + 1];
+    if (a == b) {
+        avg[v] = T(0);
+        return;
+    }
+    T s = T(0);
+    for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
+    avg[v] = (T)(omega / (double)(b - a)) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam, T *__restrict__ mm,
+                                              T *__restrict__ abar)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.n_slots) return;
@@ -398,6 +394,7 @@ __global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam,
     }
     lam[s] = l;
     mm[s] = T(0);
+    abar[s] = T(0);
 }
 
 template <typename T>
@@ -487,17 +484,19 @@ __device__ __forceinline__ double u01(uint64_t seed, uint64_t round, uint64_t i)
 }
 
 // Alg. 2 perturbation: all M > 0 -> +delta, all M < 0 -> -delta, all M = 0 ->
-// r*delta, mixed -> sign(sum M)*|r|*delta; flagged variables take r*delta
+// r*delta, mixed -> sign(sum M)*|r|*delta; flagged variables take r*delta.
+// r ~ U[-delta, delta] (scale 0) or U[-1, 1] (scale 1).
 template <typename T>
 __global__ __launch_bounds__(256) void k_perturb(DevProblem P, T *__restrict__ lam, const T *__restrict__ mm,
-                                                 double tau, double delta, uint64_t seed, uint64_t round,
+                                                 double tau, double delta, uint64_t seed, uint64_t round, int scale,
                                                  const uint8_t *__restrict__ flag)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= P.n_vars) return;
     const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
     if (q0 == q1) return;
-    const double r = (2.0 * u01(seed, round, (uint64_t)v) - 1.0) * delta;
+    double r = 2.0 * u01(seed, round, (uint64_t)v) - 1.0;
+    if (scale == 0) r = r * delta;
     bool pos = true, neg = true, zero = true;
     double sum = 0.0;
     for (int32_t q = q0; q < q1; ++q) {
@@ -549,56 +548,82 @@ __global__ __launch_bounds__(256) void k_copy(T *__restrict__ d, const T *__rest
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+inline unsigned grid8(int64_t tiles, int per_block)
+{
+    return (unsigned)((((tiles + per_block - 1) / per_block) + 7) & ~int64_t(7));
+}
+
+template <typename T, int DIR, int MODE>
+void launch_general(const DevProblem &p, int list_lds, int list_glob, T *lam, T *mm, const T *abar,
+                    double *tile_lb, Omega<T> w, hipStream_t st)
+{
+    const int64_t nl = p.list_off[list_lds + 1] - p.list_off[list_lds];
+    const int64_t ng = p.list_off[list_glob + 1] - p.list_off[list_glob];
+    if (nl > 0) {
+        const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
+        hipLaunchKernelGGL((k_sweep<T, DIR, MODE, true>), dim3(grid8(nl, kWavesPerBlock)), dim3(kThreads), lds, st, p,
+                           lam, mm, abar, tile_lb, w, p.lists + p.list_off[list_lds], nl);
+    }
+    if (ng > 0)
+        hipLaunchKernelGGL((k_sweep<T, DIR, MODE, false>), dim3(grid8(ng, kWavesPerBlock)), dim3(kThreads), 0, st, p,
+                           lam, mm, abar, tile_lb, w, p.lists + p.list_off[list_glob], ng);
+}
+
 }  // namespace
 
 template <typename T>
-void launch_sweep(const DevProblem &p, T *lam, T *mm_out, const T *avg, double *tile_lb, T omega, int dir, int mode,
+void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int dir, int mode,
                   hipStream_t st)
 {
-    const int64_t nl = p.n_lds_tiles, ng = p.n_tiles - p.n_lds_tiles;
-    if (nl > 0) {
-        const unsigned grid = (unsigned)(((nl + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
-        const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
-#define BDDMMA_SWEEP(D, M) hipLaunchKernelGGL((k_sweep<T, D, M, true>), dim3(grid), dim3(kThreads), lds, st, p, lam, mm_out, avg, tile_lb, omega, (int64_t)0, nl)
-        if (dir == 0 && mode == MODE_UPDATE) BDDMMA_SWEEP(0, MODE_UPDATE);
-        else if (dir == 0) BDDMMA_SWEEP(0, MODE_FIXED);
-        else if (mode == MODE_UPDATE) BDDMMA_SWEEP(1, MODE_UPDATE);
-        else BDDMMA_SWEEP(1, MODE_FIXED);
-#undef BDDMMA_SWEEP
-    }
-    if (ng > 0) {
-        const unsigned grid = (unsigned)(((ng + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
-#define BDDMMA_SWEEP(D, M) hipLaunchKernelGGL((k_sweep<T, D, M, false>), dim3(grid), dim3(kThreads), 0, st, p, lam, mm_out, avg, tile_lb, omega, nl, ng)
-        if (dir == 0 && mode == MODE_UPDATE) BDDMMA_SWEEP(0, MODE_UPDATE);
-        else if (dir == 0) BDDMMA_SWEEP(0, MODE_FIXED);
-        else if (mode == MODE_UPDATE) BDDMMA_SWEEP(1, MODE_UPDATE);
-        else BDDMMA_SWEEP(1, MODE_FIXED);
-#undef BDDMMA_SWEEP
+    if (mode == MODE_UPDATE) {
+        if (dir == 0) {
+            launch_reg<T, 0, 2>(p, 0, lam, mm, abar, tile_lb, w, st);
+            launch_reg<T, 0, 4>(p, 1, lam, mm, abar, tile_lb, w, st);
+            launch_general<T, 0, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
+        } else {
+            launch_reg<T, 1, 2>(p, 0, lam, mm, abar, tile_lb, w, st);
+            launch_reg<T, 1, 4>(p, 1, lam, mm, abar, tile_lb, w, st);
+            launch_general<T, 1, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
+        }
+    } else if (dir == 0) {
+        launch_general<T, 0, MODE_FIXED>(p, LIST_GEN_LDS_ALL, LIST_GEN_GLOB_ALL, lam, mm, abar, tile_lb, w, st);
+    } else {
+        launch_general<T, 1, MODE_FIXED>(p, LIST_GEN_LDS_ALL, LIST_GEN_GLOB_ALL, lam, mm, abar, tile_lb, w, st);
     }
 }
 
 template <typename T>
 void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, double *tile_e, hipStream_t st)
 {
-    const int64_t nl = p.n_lds_tiles, ng = p.n_tiles - p.n_lds_tiles;
+    const int64_t nl = p.list_off[LIST_GEN_LDS_ALL + 1] - p.list_off[LIST_GEN_LDS_ALL];
+    const int64_t ng = p.list_off[LIST_GEN_GLOB_ALL + 1] - p.list_off[LIST_GEN_GLOB_ALL];
     if (nl > 0) {
-        const unsigned grid = (unsigned)(((nl + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
         const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
-        hipLaunchKernelGGL((k_cert<T, true>), dim3(grid), dim3(kThreads), lds, st, p, lam, mm, omega, tile_e,
-                           (int64_t)0, nl);
+        hipLaunchKernelGGL((k_cert<T, true>), dim3(grid8(nl, kWavesPerBlock)), dim3(kThreads), lds, st, p, lam, mm,
+                           omega, tile_e, p.lists + p.list_off[LIST_GEN_LDS_ALL], nl);
     }
-    if (ng > 0) {
-        const unsigned grid = (unsigned)(((ng + kWavesPerBlock - 1) / kWavesPerBlock + 7) & ~int64_t(7));
-        hipLaunchKernelGGL((k_cert<T, false>), dim3(grid), dim3(kThreads), 0, st, p, lam, mm, omega, tile_e, nl, ng);
-    }
+    if (ng > 0)
+        hipLaunchKernelGGL((k_cert<T, false>), dim3(grid8(ng, kWavesPerBlock)), dim3(kThreads), 0, st, p, lam, mm,
+                           omega, tile_e, p.lists + p.list_off[LIST_GEN_GLOB_ALL], ng);
 }
 
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *avg, T omega, hipStream_t st)
+void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, const double *tile_lb, double offset,
+                    double *stage, int32_t *counter, double *lb_out, hipStream_t st)
 {
-    if (p.n_vars == 0) return;
-    hipLaunchKernelGGL((k_average<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p.vptr, p.vslot, mm, avg,
-                       (double)omega, p.n_vars);
+    const int nlb = tile_lb ? (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (p.n_tiles + 127) / 128)) : 0;
+    const int64_t blocks = std::max<int64_t>((p.n_gvars + kRedThreads - 1) / kRedThreads, nlb);
+    if (blocks == 0) return;
+    hipLaunchKernelGGL((k_average<T>), dim3((unsigned)blocks), dim3(kRedThreads), 0, st, p.gvars, p.n_gvars, p.vptr,
+                       p.vslot, mm, abar, omega, tile_lb, p.n_tiles, nlb, offset, stage, counter, lb_out);
+}
+
+template <typename T>
+void launch_average_all(const DevProblem &p, const T *mm, T *avg, double omega, hipStream_t st)
+{
+    if (p.n_vars > 0)
+        hipLaunchKernelGGL((k_average_all<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p.vptr, p.vslot, mm,
+                           avg, omega, p.n_vars);
 }
 
 void launch_reduce_sum(const double *part, int64_t n, double offset, double *scratch, double *out, hipStream_t st)
@@ -609,10 +634,10 @@ void launch_reduce_sum(const double *part, int64_t n, double offset, double *scr
 }
 
 template <typename T>
-void launch_init(const DevProblem &p, T *lam, T *mm, T *avg, hipStream_t st)
+void launch_init(const DevProblem &p, T *lam, T *mm, T *abar, hipStream_t st)
 {
-    if (p.n_slots > 0) hipLaunchKernelGGL((k_init<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p, lam, mm);
-    launch_fill<T>(avg, T(0), p.n_vars + 1, st);
+    if (p.n_slots > 0)
+        hipLaunchKernelGGL((k_init<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p, lam, mm, abar);
 }
 
 template <typename T>
@@ -643,11 +668,11 @@ void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_
 
 template <typename T>
 void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double delta, uint64_t seed,
-                    uint64_t round, const uint8_t *flag, hipStream_t st)
+                    uint64_t round, int scale, const uint8_t *flag, hipStream_t st)
 {
     if (p.n_vars > 0)
         hipLaunchKernelGGL((k_perturb<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p, lam, mm, tau, delta,
-                           seed, round, flag);
+                           seed, round, scale, flag);
 }
 
 template <typename T>
@@ -670,15 +695,17 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
 }
 
 #define BDDMMA_INSTANTIATE(T)                                                                                        \
-    template void launch_sweep<T>(const DevProblem &, T *, T *, const T *, double *, T, int, int, hipStream_t);     \
+    template void launch_sweep<T>(const DevProblem &, T *, T *, const T *, double *, Omega<T>, int, int, hipStream_t); \
     template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
-    template void launch_average<T>(const DevProblem &, const T *, T *, T, hipStream_t);                            \
+    template void launch_average<T>(const DevProblem &, const T *, T *, double, const double *, double, double *,    \
+                                    int32_t *, double *, hipStream_t);                                               \
+    template void launch_average_all<T>(const DevProblem &, const T *, T *, double, hipStream_t);                   \
     template void launch_init<T>(const DevProblem &, T *, T *, T *, hipStream_t);                                   \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \
     template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
     template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *,            \
                                       hipStream_t);                                                                  \
-    template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t,         \
+    template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t, int,    \
                                     const uint8_t *, hipStream_t);                                                   \
     template void launch_decode<T>(const DevProblem &, const T *, uint8_t *, hipStream_t);                          \
     template void launch_fill<T>(T *, T, int64_t, hipStream_t);                                                      \

@@ -15,12 +15,17 @@ enum SweepMode { MODE_UPDATE = 0, MODE_FIXED = 1 };
 
 struct DevProblem {
     const TileDesc *tiles;
-    int64_t n_tiles, n_lds_tiles;
+    int64_t n_tiles;
+    const int32_t *lists;              // tile ids of every TileList
+    int64_t list_off[kNumLists + 1];
     const uint32_t *layers;
     const uint32_t *child;
     const int32_t *pair_var;
     const int32_t *vptr;
     const int32_t *vslot;
+    const uint16_t *code;              // [n_slots] source of each slot's averaged term
+    const int32_t *gvars;              // variables averaged by the averaging kernel
+    int64_t n_gvars;
     const double *cost;
     int64_t n_vars, n_slots;
     void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
@@ -29,21 +34,46 @@ struct DevProblem {
 
 constexpr int kRedBlocks = 512;
 
-// One sweep over every tile.  dir 0 = ascending variables (Alg. 3), 1 =
-// descending (Alg. 4).  With tile_lb != nullptr each tile writes
-// sum_lanes E^j + omega * sum min(M, 0).  mm_out receives M.
+// Weights of the averaged term: w1 = omega, w2 = omega / 2 in working precision.
 template <typename T>
-void launch_sweep(const DevProblem &p, T *lam, T *mm_out, const T *avg, double *tile_lb, T omega, int dir,
+struct Omega {
+    T w1, w2;
+};
+
+// One sweep over every tile.  dir 0 = ascending variables (Alg. 3), 1 =
+// descending (Alg. 4).  mm holds the previous sweep's M on entry (read for the
+// in-tile averaging) and this sweep's M on exit; abar holds the averaged term
+// of slots averaged by the averaging kernel.  With tile_lb != nullptr each tile
+// writes sum_lanes E^j + omega * sum min(M, 0).  MODE_FIXED writes M to mm
+// without touching lam and ignores abar.
+template <typename T>
+void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int dir,
                   int mode, hipStream_t st);
 
+// register-resident sweeps of the fast-path tiles of width class wi
+template <typename T, int DIR, int W>
+void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w,
+                hipStream_t st);
+
+// a_i = omega/|J_i| * sum_k M_ik (ascending row order) for the variables the
+// sweep does not average itself, stored into abar at every slot of i.  With
+// tile_lb != nullptr the same launch also reduces the per-tile bound partials
+// in a fixed order: lb_out[0] = offset + sum_t tile_lb[t] (stage scratch:
+// kRedBlocks doubles, counter: one int32 that is zero between launches).
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *avg, T omega, hipStream_t st);
+void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, const double *tile_lb, double offset,
+                    double *stage, int32_t *counter, double *lb_out, hipStream_t st);
+
+// per-variable averaged terms of all variables into avg[n_vars] (state export)
+template <typename T>
+void launch_average_all(const DevProblem &p, const T *mm, T *avg, double omega, hipStream_t st);
 
 // out[0] = offset + sum_t part[t] in a fixed order; scratch holds kRedBlocks doubles
 void launch_reduce_sum(const double *part, int64_t n, double offset, double *scratch, double *out, hipStream_t st);
 
+// lambda = c_i / |J_i|, M-bar = 0, averaged terms 0
 template <typename T>
-void launch_init(const DevProblem &p, T *lam, T *mm, T *avg, hipStream_t st);
+void launch_init(const DevProblem &p, T *lam, T *mm, T *abar, hipStream_t st);
 
 // lam += omega * mm on every slot
 template <typename T>
@@ -66,7 +96,7 @@ void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_
 // one Alg. 2 perturbation of every variable
 template <typename T>
 void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double delta, uint64_t seed,
-                    uint64_t round, const uint8_t *flag, hipStream_t st);
+                    uint64_t round, int scale, const uint8_t *flag, hipStream_t st);
 
 // x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
 template <typename T>

@@ -47,4 +47,37 @@ inline uint32_t layer_entry(uint32_t noff, uint32_t width) { return noff | (widt
 // per-lane scratch elements a tile needs (lambda, averaged term, two distance arrays)
 inline uint32_t lane_elems(uint32_t K, uint32_t nodes) { return 2u * K + 2u * nodes; }
 
+// Register-resident fast path: tiles with at most kKClass[last] layers and
+// layers at most kWClass[last] wide use a fixed layer stride (node (h, q) at
+// h * W + q, unused nodes have both arcs into the rejecting terminal) and are
+// swept by kernels unrolled for a compile-time layer bound KMAX and width W.
+constexpr int kNumKClasses = 6;
+constexpr int kKClass[kNumKClasses] = {4, 8, 12, 16, 24, 32};
+constexpr int kNumWClasses = 2;
+constexpr int kWClass[kNumWClasses] = {2, 4};
+
+// Tile lists.  Every tile is in exactly one of the two *_ALL lists (shortest
+// paths in LDS or in device scratch for the general kernels); tiles outside the
+// fast path are also in the matching *_REST list; fast tiles are in the list of
+// their (width class, layer class).
+enum TileList {
+    LIST_GEN_LDS_ALL = 0,
+    LIST_GEN_GLOB_ALL = 1,
+    LIST_GEN_LDS_REST = 2,
+    LIST_GEN_GLOB_REST = 3,
+    LIST_FAST0 = 4,
+    kNumLists = LIST_FAST0 + kNumKClasses * kNumWClasses
+};
+inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + ki; }
+
+// Where a pair slot takes the averaged term a_i = omega/|J_i| * sum_k M_ik of
+// its variable from (Alg. 1 deferred update).  Variables with |J_i| <= 2 whose
+// pairs all lie in one tile are averaged inside the sweep from the tile's own
+// previous min-marginal differences: code = offset (h * 64 + lane) of the
+// partner slot in the tile, or kCodeSelf when |J_i| = 1 (padding slots too).
+// All other variables are averaged by the averaging kernel, which stores the
+// term per slot (kCodeGlobal).
+constexpr uint16_t kCodeSelf = 0xFFFEu;
+constexpr uint16_t kCodeGlobal = 0xFFFFu;
+
 }  // namespace bddmma

@@ -342,13 +342,14 @@ struct TilePlan {
     std::vector<int64_t> lanes;   // BDD ids, -1 for padding lanes
     bool shared = false;
     int K = 0;
-    std::vector<int32_t> width;   // [K]
+    std::vector<int32_t> width;   // [K] layer widths of the tile layout
     int64_t first_row = 0;
+    int wi = -1, ki = -1;         // fast-path class, -1 = general kernels only
 };
 
 }  // namespace
 
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packed &o, std::string &msg)
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, Packed &o, std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -423,6 +424,16 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packe
             if (j >= 0)
                 for (int h = 0; h < k_of(j); ++h)
                     tp.width[h] = std::max(tp.width[h], B.lay_width[B.lay_off[j] + h]);
+        const int maxw = *std::max_element(tp.width.begin(), tp.width.end());
+        for (int wi = 0; fast && wi < kNumWClasses && tp.wi < 0; ++wi)
+            if (maxw <= kWClass[wi])
+                for (int ki = 0; ki < kNumKClasses; ++ki)
+                    if (K <= kKClass[ki]) {
+                        tp.wi = wi;
+                        tp.ki = ki;
+                        break;
+                    }
+        if (tp.wi >= 0) tp.width.assign(K, kWClass[tp.wi]);   // fixed layer stride
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
@@ -437,33 +448,60 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packe
         return lds_elem_budget > 0 && (int64_t)lane_elems(tp.K, (uint32_t)n) <= lds_elem_budget &&
                (lds_max_nodes <= 0 || n <= lds_max_nodes);
     };
-    std::stable_sort(plans.begin(), plans.end(), [&](const TilePlan &x, const TilePlan &y) {
-        bool lx = in_lds(x), ly = in_lds(y);
-        if (lx != ly) return lx;
-        return x.first_row < y.first_row;
-    });
+    std::stable_sort(plans.begin(), plans.end(),
+                     [&](const TilePlan &x, const TilePlan &y) { return x.first_row < y.first_row; });
 
     // emit
     o = Packed();
-    o.n_lds_tiles = 0;
+    std::vector<std::vector<int32_t>> lists(kNumLists);
     int64_t slots = 0, scratch = 0;
+    // place the node words of BDD j into the tile layout (stride 1: shared, 64: per lane)
+    auto place = [&](int64_t j, const std::vector<uint32_t> &noff, int K, size_t base, size_t stride, int lane) {
+        const int kj = j >= 0 ? k_of(j) : 0;
+        int64_t src = j >= 0 ? B.node_off[j] : 0;
+        for (int h = 0; h < K; ++h) {
+            if (h < kj) {
+                const int wj = B.lay_width[B.lay_off[j] + h];
+                for (int q = 0; q < wj; ++q) {
+                    uint32_t w = B.child[src++];
+                    if (h == kj - 1 && kj < K) {   // accept -> padding chain
+                        uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+                        if (lo == kTop) lo = 0;
+                        if (hi == kTop) hi = 0;
+                        w = lo | (hi << 16);
+                    }
+                    o.child[base + (size_t)(noff[h] + q) * stride + lane] = w;
+                }
+            } else {
+                const uint32_t nxt = (h == K - 1) ? kTop : 0u;
+                o.child[base + (size_t)noff[h] * stride + lane] = nxt | (nxt << 16);
+            }
+        }
+    };
     for (auto &tp : plans) {
+        const int32_t tid = (int32_t)o.tiles.size();
         TileDesc d{};
         d.pair_base = (uint32_t)slots;
         d.node_base = (uint32_t)o.child.size();
         d.layer_base = (uint32_t)o.layers.size();
         d.K = (uint16_t)tp.K;
-        int64_t nodes = tile_nodes(tp);
+        const int64_t nodes = tile_nodes(tp);
         d.nodes = (uint16_t)nodes;
         d.flags = tp.shared ? TILE_SHARED : 0;
-        bool lds = in_lds(tp);
-        if (lds) {
-            o.n_lds_tiles++;
+        if (in_lds(tp)) {
             o.max_lds_lane_elems = std::max<int>(o.max_lds_lane_elems, (int)lane_elems(tp.K, (uint32_t)nodes));
             d.scratch_base = 0;
+            lists[LIST_GEN_LDS_ALL].push_back(tid);
+            if (tp.wi < 0) lists[LIST_GEN_LDS_REST].push_back(tid);
         } else {
             d.scratch_base = (uint32_t)scratch;
             scratch += (int64_t)kLanes * lane_elems(tp.K, (uint32_t)nodes);
+            lists[LIST_GEN_GLOB_ALL].push_back(tid);
+            if (tp.wi < 0) lists[LIST_GEN_GLOB_REST].push_back(tid);
+        }
+        if (tp.wi >= 0) {
+            lists[fast_list(tp.wi, tp.ki)].push_back(tid);
+            o.n_fast_tiles++;
         }
         std::vector<uint32_t> noff(tp.K + 1, 0);
         for (int h = 0; h < tp.K; ++h) {
@@ -471,36 +509,16 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packe
             o.layers.push_back(layer_entry(noff[h], tp.width[h]));
         }
         o.max_layers = std::max(o.max_layers, tp.K);
-        for (int w : tp.width) o.max_width = std::max(o.max_width, w);
+        for (int64_t j : tp.lanes)
+            if (j >= 0)
+                for (int h = 0; h < k_of(j); ++h) o.max_width = std::max(o.max_width, B.lay_width[B.lay_off[j] + h]);
+        const size_t base = o.child.size();
         if (tp.shared) {
-            int64_t j = tp.lanes[0];
-            o.child.insert(o.child.end(), B.child.begin() + B.node_off[j], B.child.begin() + B.node_off[j + 1]);
+            o.child.resize(base + (size_t)nodes, kBot | (kBot << 16));
+            place(tp.lanes[0], noff, tp.K, base, 1, 0);
         } else {
-            size_t base = o.child.size();
             o.child.resize(base + (size_t)nodes * kLanes, kBot | (kBot << 16));
-            for (int l = 0; l < kLanes; ++l) {
-                int64_t j = tp.lanes[l];
-                int kj = j >= 0 ? k_of(j) : 0;
-                int64_t src = j >= 0 ? B.node_off[j] : 0;
-                for (int h = 0; h < tp.K; ++h) {
-                    if (h < kj) {
-                        int wj = B.lay_width[B.lay_off[j] + h];
-                        for (int q = 0; q < wj; ++q) {
-                            uint32_t w = B.child[src++];
-                            if (h == kj - 1 && kj < tp.K) {   // accept -> padding chain
-                                uint32_t lo = w & 0xFFFFu, hi = w >> 16;
-                                if (lo == kTop) lo = 0;
-                                if (hi == kTop) hi = 0;
-                                w = lo | (hi << 16);
-                            }
-                            o.child[base + (size_t)(noff[h] + q) * kLanes + l] = w;
-                        }
-                    } else {
-                        uint32_t nxt = (h == tp.K - 1) ? kTop : 0u;
-                        o.child[base + (size_t)noff[h] * kLanes + l] = nxt | (nxt << 16);
-                    }
-                }
-            }
+            for (int l = 0; l < kLanes; ++l) place(tp.lanes[l], noff, tp.K, base, kLanes, l);
         }
         o.tiles.push_back(d);
         slots += (int64_t)tp.K * kLanes;
@@ -508,6 +526,11 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packe
             msg = "problem too large for 32-bit slot indices";
             return ST_INVALID;
         }
+    }
+    o.list_off.assign(kNumLists + 1, 0);
+    for (int l = 0; l < kNumLists; ++l) {
+        o.list_off[l + 1] = o.list_off[l] + (int64_t)lists[l].size();
+        o.lists.insert(o.lists.end(), lists[l].begin(), lists[l].end());
     }
     // every arc must stay inside the tile: heads index the next layer, and only
     // the last layer may reach the accepting terminal
@@ -558,6 +581,39 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packe
     o.vslot.assign(P, 0);
     std::vector<int32_t> fill(o.vptr.begin(), o.vptr.end() - 1);
     for (int64_t q = 0; q < P; ++q) o.vslot[fill[B.lay_var[q]]++] = (int32_t)o.slot_of_pair[q];
+    // source of every slot's averaged term
+    std::vector<int32_t> tile_of_slot((size_t)slots);
+    for (size_t t = 0; t < o.tiles.size(); ++t)
+        for (int64_t s = o.tiles[t].pair_base; s < (int64_t)o.tiles[t].pair_base + (int64_t)o.tiles[t].K * kLanes; ++s)
+            tile_of_slot[s] = (int32_t)t;
+    o.code.assign(slots, kCodeSelf);
+    o.gvars.clear();
+    for (int64_t i = 0; i < V; ++i) {
+        const int32_t a = o.vptr[i], b = o.vptr[i + 1];
+        if (a == b) continue;
+        bool local = fast && b - a <= 2;
+        if (local) {
+            const int32_t t = tile_of_slot[o.vslot[a]];
+            local = o.tiles[t].K * kLanes < (int)kCodeSelf && tile_of_slot[o.vslot[b - 1]] == t;
+        }
+        if (!local) {
+            o.gvars.push_back((int32_t)i);
+            for (int32_t q = a; q < b; ++q) o.code[o.vslot[q]] = kCodeGlobal;
+        } else if (b - a == 2) {
+            const int32_t base = (int32_t)o.tiles[tile_of_slot[o.vslot[a]]].pair_base;
+            o.code[o.vslot[a]] = (uint16_t)(o.vslot[a + 1] - base);
+            o.code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
+        }
+    }
+    // partner offsets must point inside their own tile
+    for (const TileDesc &d : o.tiles)
+        for (uint32_t q = 0; q < (uint32_t)d.K * kLanes; ++q) {
+            const uint16_t c = o.code[d.pair_base + q];
+            if (c < kCodeSelf && (uint32_t)c >= (uint32_t)d.K * kLanes) {
+                msg = "internal error: averaging partner outside its tile";
+                return ST_INVALID;
+            }
+        }
     return ST_OK;
 }
 

@@ -31,15 +31,18 @@ struct BddSet {
 };
 
 struct Packed {
-    // tiles: [0, n_lds_tiles) keep shortest paths in LDS, the rest in device scratch
     std::vector<TileDesc> tiles;
-    int64_t n_lds_tiles = 0;
+    std::vector<int32_t> lists;                  // tile ids of every TileList, concatenated
+    std::vector<int64_t> list_off;               // [kNumLists + 1]
+    int64_t n_fast_tiles = 0;
     std::vector<uint32_t> layers;     // layer table
     std::vector<uint32_t> child;      // node words
     std::vector<int32_t> pair_var;    // [S] variable per slot, n_vars for padding
     std::vector<int64_t> slot_of_pair;  // [P] canonical pair -> slot
     std::vector<int32_t> vptr;        // [V+1] variable -> its slots, ascending row order
     std::vector<int32_t> vslot;       // [P]
+    std::vector<uint16_t> code;       // [S] source of the averaged term (layout.hpp)
+    std::vector<int32_t> gvars;       // variables averaged by the averaging kernel, ascending
     int64_t n_slots = 0;
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
     int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile
@@ -69,8 +72,10 @@ int build_problem(Problem &p, std::string &msg);
 
 // Pack the compiled BDDs into tiles.  lds_elem_budget: per-lane elements a tile
 // may keep in LDS (0 disables LDS); lds_max_nodes > 0 additionally caps the
-// nodes per lane of LDS tiles.  ST_OK / ST_INVALID.
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, Packed &out, std::string &msg);
+// nodes per lane of LDS tiles; fast selects the register-resident path for the
+// tiles it can take.  ST_OK / ST_INVALID.
+// fast also enables the in-tile averaging of variables with |J_i| <= 2.
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, Packed &out, std::string &msg);
 
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.

@@ -103,22 +103,37 @@ def test_fig3_min_marginals():
 
 
 # ---------------------------------------------------------------- random instances
-@pytest.mark.parametrize("lds", [0, -1])
-def test_random_fp64_bitexact(lds):
+PATHS = [dict(fast_path=1), dict(fast_path=0), dict(fast_path=0, sp_in_lds_max_nodes=-1)]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_random_fp64_bitexact(path):
     for seed in range(12):
         ilp = I.random_ilp(14, 10, max_row_len=7, seed=6000 + seed)
         if O.Oracle(ilp).status != O.OK:
             continue
-        lockstep(ilp, 10, precision=64, sp_in_lds_max_nodes=lds)
+        lockstep(ilp, 10, precision=64, **path)
 
 
-@pytest.mark.parametrize("lds", [0, -1])
-def test_random_fp32(lds):
+@pytest.mark.parametrize("path", PATHS)
+def test_random_fp32(path):
     for seed in range(12):
         ilp = I.random_ilp(14, 10, max_row_len=7, seed=7000 + seed)
         if O.Oracle(ilp).status != O.OK:
             continue
-        lockstep(ilp, 10, precision=32, sp_in_lds_max_nodes=lds)
+        lockstep(ilp, 10, precision=32, **path)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_workload_paths_agree_fp64(path):
+    """the three kernel paths give bit-identical FP64 trajectories"""
+    ilp = I.workload("track20x500")
+    s = solver(ilp, precision=64, **path)
+    ref = solver(ilp, precision=64)
+    s.run_dual(6)
+    ref.run_dual(6)
+    for x, y in zip(s.get_state(), ref.get_state()):
+        assert np.array_equal(x, y)
 
 
 def test_long_and_wide_rows_fp64():
@@ -137,8 +152,9 @@ def test_long_and_wide_rows_fp64():
     assert s.stats.max_layers >= 150 and s.stats.max_width > 8
 
 
+@pytest.mark.parametrize("path", PATHS[:2])
 @pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
-def test_ragged_tile_counts_fp64(n_rows):
+def test_ragged_tile_counts_fp64(n_rows, path):
     rng = np.random.default_rng(n_rows)
     rows = []
     for r in range(n_rows):
@@ -146,7 +162,7 @@ def test_ragged_tile_counts_fp64(n_rows):
         vs = rng.choice(40, size=k, replace=False)
         rows.append((vs, [1] * k, -1, 1))
     ilp = I.from_rows(40, rng.standard_normal(40), rows, name=f"ragged{n_rows}")
-    lockstep(ilp, 4, precision=64)
+    lockstep(ilp, 4, precision=64, **path)
 
 
 def test_empty_and_fixed_problems():
@@ -166,10 +182,11 @@ def test_empty_and_fixed_problems():
 
 
 # ---------------------------------------------------------------- the named workloads
-def test_mrf10_fp64_200_iterations():
+@pytest.mark.parametrize("path", PATHS[:2])
+def test_mrf10_fp64_200_iterations(path):
     ilp = I.workload("mrf10x10L3")
-    note("mrf10x10L3 fp64 200 iterations")
-    s = solver(ilp, precision=64)
+    note("mrf10x10L3 fp64 200 iterations", path)
+    s = solver(ilp, precision=64, **path)
     o = O.Oracle(ilp)
     o.init()
     s.run_dual(200)
@@ -215,10 +232,18 @@ def test_gm_tracking_fp32(name):
     assert abs(lc - rc_) <= 1e-4 * abs(rc_)
     # LB_free <= LB_cert holds exactly; FP32 path sums move LB_free by ~1e-5 relative
     assert lf <= lc + 1e-4 * abs(lc)
+    # Alg. 2 need not terminate (Sec. 4); the graph-matching instance does not
+    # under either perturbation scale in the FP64 reference either
+    before = s.get_state()
     r = s.round_primal()
-    assert r["rc"] == 0
-    assert o.count_violated(r["x"]) == 0
-    assert r["ub"] >= lc - 1e-6 * abs(lc)
+    assert r["rc"] in (0, B.NOT_CONVERGED)
+    if r["rc"] == 0:
+        assert o.count_violated(r["x"]) == 0
+        assert r["ub"] >= lc - 1e-6 * abs(lc)
+    else:
+        assert all(np.array_equal(a, b) for a, b in zip(before, s.get_state()))
+    if name == "track20x500":
+        assert r["rc"] == 0
 
 
 def test_mrf256_sampled_sweep_and_properties():
@@ -257,15 +282,16 @@ def test_rounding_fp64_matches_reference():
         ilp = I.random_ilp(12, 8, max_row_len=5, seed=8000 + seed)
         if O.Oracle(ilp).status == O.OK:
             cases.append(ilp)
-    for ilp in cases:
-        note("rounding", ilp.name)
-        s = solver(ilp, precision=64, tau=0.0, seed=3)
+    for k, ilp in enumerate(cases):
+        scale = k % 2
+        note("rounding", ilp.name, "scale", scale)
+        s = solver(ilp, precision=64, tau=0.0, seed=3, perturb_scale=scale)
         o = O.Oracle(ilp)
         o.init()
         s.run_dual(15)
         o.run_dual(15)
         r = s.round_primal()
-        ro = o.round(tau=0.0, seed=3)
+        ro = o.round(tau=0.0, seed=3, scale=scale)
         assert r["rc"] == ro["rc"] and r["rounds"] == ro["rounds"]
         if r["rc"] == 0:
             assert np.array_equal(r["x"], ro["x"]) and r["ub"] == ro["ub"]
