@@ -203,10 +203,11 @@ int bddmma_save_state(const bddmma_solver *s, void *buf, size_t *bytes);
 int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes);
 
 /* Per-kernel timing with HIP events recorded on the bound stream around each
- * launch.  enable != 0 starts a new collection.  kernel ids: BDDMMA_K_*.  A
- * sweep may be several launches (one per tile class); its events bracket all
- * of them.  The bound reduction runs inside the averaging launch, so
- * BDDMMA_K_LB_REDUCE stays empty; it is kept for ABI stability.
+ * sweep of run_dual / run_sweeps.  enable != 0 starts a new collection.
+ * kernel ids: BDDMMA_K_*.  A sweep may be several launches (one per tile
+ * class); its events bracket all of them.  Only the sweeps are bracketed (to
+ * keep event records off the other launches), so BDDMMA_K_AVERAGE and
+ * BDDMMA_K_LB_REDUCE report no launches; they are kept for ABI stability.
  * bddmma_kernel_time synchronises and reports launches and total milliseconds. */
 #define BDDMMA_K_SWEEP_FWD 0
 #define BDDMMA_K_SWEEP_BWD 1

@@ -104,7 +104,7 @@ Layout make_layout(const bddmma_solver &s)
     L.pair_var = take(S * 4);
     L.vptr = take((V + 1) * 4);
     L.vslot = take(P * 4);
-    L.code = take(S * 2);
+    L.code = take(pk.code.size() * 2);
     L.gvars = take(pk.gvars.size() * 4);
     L.child = take(pk.child.size() * 4);
     L.tiles = take(T * sizeof(TileDesc));
@@ -183,11 +183,8 @@ void one_sweep(bddmma_solver *s, int dir, bool record_lb)
         Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD);
         launch_sweep<T>(p, lam, mm, abar, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
     }
-    {
-        // averaging; with a bound record it also reduces the sweep's per-tile partials
-        Scope sc(s, BDDMMA_K_AVERAGE);
-        average<T>(s, tile_lb, s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap));
-    }
+    // averaging; with a bound record it also reduces the sweep's per-tile partials
+    average<T>(s, tile_lb, s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap));
 }
 
 int flush_history(bddmma_solver *s)

@@ -38,7 +38,7 @@ template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
 
 struct TileView {
-    uint32_t pb, nb, lb, K, NN;
+    uint32_t pb, nb, lb, cb, K, NN;
     bool shared;
 };
 
@@ -48,6 +48,7 @@ __device__ __forceinline__ TileView load_tile(const TileDesc *td)
     v.pb = uni(td->pair_base);
     v.nb = uni(td->node_base);
     v.lb = uni(td->layer_base);
+    v.cb = uni(td->code_base);
     v.K = uni(td->K);
     v.NN = uni(td->nodes);
     v.shared = (uni(td->flags) & TILE_SHARED) != 0;

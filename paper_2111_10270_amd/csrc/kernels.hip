@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
                 lv[u] = lam[s];
                 if (MODE == MODE_UPDATE) {
                     mv[u] = mm[s];
-                    cv[u] = P.code[s];
+                    cv[u] = P.code[tv.cb + h * kLanes + lane];
                 }
             }
         }

@@ -37,7 +37,8 @@ struct TileDesc {
     uint16_t nodes;         // nodes per lane = sum of the layer widths
     uint16_t flags;
     uint16_t pad0;
-    uint32_t pad1, pad2;
+    uint32_t code_base;     // first averaging code of the tile (tiles with equal codes share them)
+    uint32_t pad1;
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc is 32 bytes");
 
@@ -47,8 +48,8 @@ inline uint32_t layer_entry(uint32_t noff, uint32_t width) { return noff | (widt
 // per-lane scratch elements a tile needs (lambda, averaged term, two distance arrays)
 inline uint32_t lane_elems(uint32_t K, uint32_t nodes) { return 2u * K + 2u * nodes; }
 
-// Register-resident fast path: tiles with at most kKClass[last] layers and
-// layers at most kWClass[last] wide use a fixed layer stride (node (h, q) at
+// Register-resident fast path: shared tiles (one topology) with at most
+// kKClass[last] layers and layers at most kWClass[last] wide use a fixed layer stride (node (h, q) at
 // h * W + q, unused nodes have both arcs into the rejecting terminal) and are
 // swept by kernels unrolled for a compile-time layer bound KMAX and width W.
 constexpr int kNumKClasses = 6;

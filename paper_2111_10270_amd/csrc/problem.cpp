@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstring>
 #include <thread>
+#include <unordered_map>
 
 namespace bddmma {
 
@@ -425,7 +426,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                 for (int h = 0; h < k_of(j); ++h)
                     tp.width[h] = std::max(tp.width[h], B.lay_width[B.lay_off[j] + h]);
         const int maxw = *std::max_element(tp.width.begin(), tp.width.end());
-        for (int wi = 0; fast && wi < kNumWClasses && tp.wi < 0; ++wi)
+        for (int wi = 0; fast && tp.shared && wi < kNumWClasses && tp.wi < 0; ++wi)
             if (maxw <= kWClass[wi])
                 for (int ki = 0; ki < kNumKClasses; ++ki)
                     if (K <= kKClass[ki]) {
@@ -437,6 +438,23 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
+    }
+    // Fewer launches: inside a width class, tiles of the smaller layer classes
+    // run in the kernel of the largest class when they are a minority (< 1/4
+    // of the class's tiles); the kernel takes the true layer count at run time.
+    for (int wi = 0; wi < kNumWClasses; ++wi) {
+        int64_t cnt[kNumKClasses] = {0};
+        for (auto &tp : plans)
+            if (tp.wi == wi) cnt[tp.ki]++;
+        int top = -1;
+        int64_t total = 0;
+        for (int ki = 0; ki < kNumKClasses; ++ki) {
+            total += cnt[ki];
+            if (cnt[ki]) top = ki;
+        }
+        if (top < 0 || 4 * (total - cnt[top]) >= total) continue;
+        for (auto &tp : plans)
+            if (tp.wi == wi) tp.ki = top;
     }
     auto tile_nodes = [](const TilePlan &tp) {
         int64_t n = 0;
@@ -455,6 +473,8 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     o = Packed();
     std::vector<std::vector<int32_t>> lists(kNumLists);
     int64_t slots = 0, scratch = 0;
+    // topology hash -> ((representative BDD, node base), width class) of emitted shared tiles
+    std::unordered_multimap<uint64_t, std::pair<std::pair<int64_t, int64_t>, int>> topo_base;
     // place the node words of BDD j into the tile layout (stride 1: shared, 64: per lane)
     auto place = [&](int64_t j, const std::vector<uint32_t> &noff, int K, size_t base, size_t stride, int lane) {
         const int kj = j >= 0 ? k_of(j) : 0;
@@ -514,8 +534,23 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                 for (int h = 0; h < k_of(j); ++h) o.max_width = std::max(o.max_width, B.lay_width[B.lay_off[j] + h]);
         const size_t base = o.child.size();
         if (tp.shared) {
-            o.child.resize(base + (size_t)nodes, kBot | (kBot << 16));
-            place(tp.lanes[0], noff, tp.K, base, 1, 0);
+            // tiles of one topology share a single copy of the node words (and
+            // hence the scalar-cache lines that hold them)
+            const int64_t rep = tp.lanes[0];
+            int64_t found = -1;
+            auto range = topo_base.equal_range(hash[rep]);
+            for (auto it = range.first; it != range.second; ++it)
+                if (it->second.second == (int)tp.wi && same_topology(it->second.first.first, rep)) {
+                    found = it->second.first.second;
+                    break;
+                }
+            if (found >= 0) {
+                d.node_base = (uint32_t)found;
+            } else {
+                o.child.resize(base + (size_t)nodes, kBot | (kBot << 16));
+                place(rep, noff, tp.K, base, 1, 0);
+                topo_base.emplace(hash[rep], std::make_pair(std::make_pair(rep, (int64_t)base), (int)tp.wi));
+            }
         } else {
             o.child.resize(base + (size_t)nodes * kLanes, kBot | (kBot << 16));
             for (int l = 0; l < kLanes; ++l) place(tp.lanes[l], noff, tp.K, base, kLanes, l);
@@ -586,7 +621,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     for (size_t t = 0; t < o.tiles.size(); ++t)
         for (int64_t s = o.tiles[t].pair_base; s < (int64_t)o.tiles[t].pair_base + (int64_t)o.tiles[t].K * kLanes; ++s)
             tile_of_slot[s] = (int32_t)t;
-    o.code.assign(slots, kCodeSelf);
+    std::vector<uint16_t> code((size_t)slots, kCodeSelf);
     o.gvars.clear();
     for (int64_t i = 0; i < V; ++i) {
         const int32_t a = o.vptr[i], b = o.vptr[i + 1];
@@ -598,17 +633,39 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         }
         if (!local) {
             o.gvars.push_back((int32_t)i);
-            for (int32_t q = a; q < b; ++q) o.code[o.vslot[q]] = kCodeGlobal;
+            for (int32_t q = a; q < b; ++q) code[o.vslot[q]] = kCodeGlobal;
         } else if (b - a == 2) {
             const int32_t base = (int32_t)o.tiles[tile_of_slot[o.vslot[a]]].pair_base;
-            o.code[o.vslot[a]] = (uint16_t)(o.vslot[a + 1] - base);
-            o.code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
+            code[o.vslot[a]] = (uint16_t)(o.vslot[a + 1] - base);
+            code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
         }
+    }
+    // tiles with the same code pattern share one copy of it
+    o.code.clear();
+    std::unordered_multimap<uint64_t, uint32_t> code_seen;
+    for (TileDesc &d : o.tiles) {
+        const size_t n = (size_t)d.K * kLanes;
+        const uint16_t *blk = code.data() + d.pair_base;
+        uint64_t h = mix64(0, n);
+        for (size_t q = 0; q < n; ++q) h = mix64(h, blk[q]);
+        int64_t found = -1;
+        auto range = code_seen.equal_range(h);
+        for (auto it = range.first; it != range.second; ++it)
+            if (std::equal(blk, blk + n, o.code.begin() + it->second) && it->second + n <= o.code.size()) {
+                found = it->second;
+                break;
+            }
+        if (found < 0) {
+            found = (int64_t)o.code.size();
+            o.code.insert(o.code.end(), blk, blk + n);
+            code_seen.emplace(h, (uint32_t)found);
+        }
+        d.code_base = (uint32_t)found;
     }
     // partner offsets must point inside their own tile
     for (const TileDesc &d : o.tiles)
         for (uint32_t q = 0; q < (uint32_t)d.K * kLanes; ++q) {
-            const uint16_t c = o.code[d.pair_base + q];
+            const uint16_t c = o.code[d.code_base + q];
             if (c < kCodeSelf && (uint32_t)c >= (uint32_t)d.K * kLanes) {
                 msg = "internal error: averaging partner outside its tile";
                 return ST_INVALID;

@@ -41,7 +41,7 @@ struct Packed {
     std::vector<int64_t> slot_of_pair;  // [P] canonical pair -> slot
     std::vector<int32_t> vptr;        // [V+1] variable -> its slots, ascending row order
     std::vector<int32_t> vslot;       // [P]
-    std::vector<uint16_t> code;       // [S] source of the averaged term (layout.hpp)
+    std::vector<uint16_t> code;       // averaging codes (layout.hpp), one K*64 block per distinct tile pattern
     std::vector<int32_t> gvars;       // variables averaged by the averaging kernel, ascending
     int64_t n_slots = 0;
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles

@@ -18,8 +18,9 @@ namespace bddmma {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Register-resident sweep for tiles of the fast path (fixed layer stride W,
-// at most KMAX layers).  The layer loop is unrolled to KMAX with a uniform
+// Register-resident sweep for tiles of the fast path (64 BDDs of one topology,
+// fixed layer stride W, at most KMAX layers).  The node words are uniform
+// across the wave, so every arc test is a scalar branch.  The layer loop is unrolled to KMAX with a uniform
 // guard h < K, so every per-lane array below lives in VGPRs: the multipliers
 // and averaged terms of all layers, the node words, and the opposite
 // direction's distances.  All loads are issued before the first use.  The
@@ -27,44 +28,44 @@ namespace {
 // ---------------------------------------------------------------------------
 // v[c] for c < W, as a tree of selects on the bits of c (no indexed access,
 // so the arrays stay in registers)
-template <int W, typename T>
-__device__ __forceinline__ T pick(const T (&v)[W], uint32_t c)
+// Uniform arc penalty: 0 when the arc's head is `target`, +inf otherwise.
+// Adding it to a value and taking a min routes the value along the arc with
+// one v_add and one v_min, without branches or per-lane selects.
+template <typename T>
+__device__ __forceinline__ T pen(uint32_t head, uint32_t target);
+
+// the selection happens on the scalar unit; the result is an SGPR operand
+template <>
+__device__ __forceinline__ float pen<float>(uint32_t head, uint32_t target)
 {
-    static_assert(W == 2 || W == 4, "fast path widths are 2 and 4");
-    if constexpr (W == 2) {
-        return (c == 1u) ? v[1] : v[0];
-    } else {
-        const T lo = (c & 1u) ? v[1] : v[0];
-        const T hi = (c & 1u) ? v[3] : v[2];
-        return (c & 2u) ? hi : lo;
-    }
+    return __uint_as_float(uni(head == target ? 0u : 0x7F800000u));
 }
 
-template <int W, typename T>
-__device__ __forceinline__ T head(uint32_t c, const T (&next)[W])
+template <>
+__device__ __forceinline__ double pen<double>(uint32_t head, uint32_t target)
 {
-    return c == kTop ? T(0) : (c == kBot ? inf_of<T>() : pick<W>(next, c));
+    const uint32_t hi = uni(head == target ? 0u : 0x7FF00000u);
+    return __hiloint2double((int)hi, 0);
 }
 
+// min over next-layer nodes t of nx[t] + pen(head, t): the value at the arc's
+// head for an arc that stays inside the BDD (heads of layers before the last)
 template <int W, typename T>
-__device__ __forceinline__ void push_min(T (&dst)[W], uint32_t c, T v)
+__device__ __forceinline__ T head_inner(uint32_t head, const T (&nx)[W])
 {
-    if constexpr (W == 2) {
+    T r = nx[0] + pen<T>(head, 0);
 #pragma unroll
-        for (int q = 0; q < W; ++q)
-            if (c == (uint32_t)q) dst[q] = tmin(dst[q], v);
-    } else {
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const T m = tmin(dst[q], v);
-            dst[q] = (c == (uint32_t)q) ? m : dst[q];
-        }
-    }
+    for (int t = 1; t < W; ++t) r = fmin(r, nx[t] + pen<T>(head, (uint32_t)t));
+    return r;
 }
 
-// mm is read (previous M, in-tile averaging) before it is overwritten, so it
-// is deliberately not __restrict__: the partner loads must stay ahead of the
-// stores of this sweep.
+// value at the head of an arc of the last layer: 0 at the accepting terminal
+template <typename T>
+__device__ __forceinline__ T head_last(uint32_t head)
+{
+    return pen<T>(head, kTop);
+}
+
 template <typename T, int DIR, int W, int KMAX>
 __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam, T *mm,
                                                                    const T *__restrict__ abar,
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
     const int K = (int)tv.K;
     const T INF = inf_of<T>();
 
+    // prologue: every load is issued before the first use
     T l[KMAX], a[KMAX], mo[KMAX];
     uint32_t cd[KMAX];
     uint32_t wd[KMAX][W];
@@ -99,9 +101,9 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
             const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
             l[h] = lam[s];
             mo[h] = mm[s];
-            cd[h] = P.code[s];
+            cd[h] = P.code[tv.cb + (uint32_t)h * kLanes + lane];
 #pragma unroll
-            for (int q = 0; q < W; ++q) wd[h][q] = node_word(P.child, tv, (uint32_t)(h * W + q), lane);
+            for (int q = 0; q < W; ++q) wd[h][q] = uni(P.child[tv.nb + (uint32_t)(h * W + q)]);
         }
     }
 #pragma unroll
@@ -111,22 +113,32 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
     double lbacc = 0.0;
     T energy;
     if (DIR == 0) {
-        // SP(v, top) of every layer under the current multipliers
-        T bk[KMAX + 1][W];
+        // SP(v, top) of every layer under the current multipliers; keep the
+        // values at the heads of every arc for the update pass
+        T hd0[KMAX][W], hd1[KMAX][W];
+        T nx[W];
 #pragma unroll
-        for (int h = 0; h <= KMAX; ++h)
-#pragma unroll
-            for (int q = 0; q < W; ++q) bk[h][q] = INF;
+        for (int q = 0; q < W; ++q) nx[q] = INF;
 #pragma unroll
         for (int h = KMAX - 1; h >= 0; --h) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                hd0[h][q] = INF;
+                hd1[h][q] = INF;
+            }
             if (h < K) {
+                T b[W];
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
-                    const uint32_t c = wd[h][q];
-                    const T b0 = head<W>(c & 0xFFFFu, bk[h + 1]);
-                    const T b1 = head<W>(c >> 16, bk[h + 1]) + l[h];
-                    bk[h][q] = tmin(b0, b1);
+                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
+                    const T v0 = (h == K - 1) ? head_last<T>(lo) : head_inner<W>(lo, nx);
+                    const T v1 = (h == K - 1) ? head_last<T>(hi) : head_inner<W>(hi, nx);
+                    hd0[h][q] = v0;
+                    hd1[h][q] = v1;
+                    b[q] = fmin(v0, v1 + l[h]);
                 }
+#pragma unroll
+                for (int q = 0; q < W; ++q) nx[q] = b[q];
             }
         }
         // forward sweep with updates
@@ -137,37 +149,40 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
         for (int h = 0; h < KMAX; ++h) {
             if (h < K) {
-                T m0 = INF, m1 = INF;
+                T m0 = f[0] + hd0[h][0];
+                T m1 = (f[0] + l[h]) + hd1[h][0];
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    if (lo != kBot) m0 = tmin(m0, f[q] + head<W>(lo, bk[h + 1]));
-                    if (hi != kBot) m1 = tmin(m1, (f[q] + l[h]) + head<W>(hi, bk[h + 1]));
+                for (int q = 1; q < W; ++q) {
+                    m0 = fmin(m0, f[q] + hd0[h][q]);
+                    m1 = fmin(m1, (f[q] + l[h]) + hd1[h][q]);
                 }
                 const T M = m1 - m0;
                 const T lu = (l[h] - omega * M) + a[h];
                 const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
                 mm[s] = M;
                 lam[s] = lu;
-                lbacc += (double)(M < T(0) ? M : T(0));
-                T fn[W];
+                lbacc += (double)fmin(M, T(0));
+                if (h == K - 1) {
 #pragma unroll
-                for (int q = 0; q < W; ++q) fn[q] = INF;
+                    for (int q = 0; q < W; ++q) {
+                        const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
+                        top = fmin(top, fmin(f[q] + head_last<T>(lo), (f[q] + lu) + head_last<T>(hi)));
+                    }
+                } else {
+                    T fn[W];
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    if (lo != kBot) {
-                        if (lo == kTop) top = tmin(top, f[q]);
-                        else push_min<W>(fn, lo, f[q]);
+                    for (int t = 0; t < W; ++t) fn[t] = INF;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
+                        const T v1 = f[q] + lu;
+#pragma unroll
+                        for (int t = 0; t < W; ++t)
+                            fn[t] = fmin(fn[t], fmin(f[q] + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
                     }
-                    if (hi != kBot) {
-                        const T v = f[q] + lu;
-                        if (hi == kTop) top = tmin(top, v);
-                        else push_min<W>(fn, hi, v);
-                    }
+#pragma unroll
+                    for (int t = 0; t < W; ++t) f[t] = fn[t];
                 }
-#pragma unroll
-                for (int q = 0; q < W; ++q) f[q] = fn[q];
             }
         }
         energy = top;
@@ -184,8 +199,11 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    if (lo < kTop) push_min<W>(fw[h + 1], lo, fw[h][q]);
-                    if (hi < kTop) push_min<W>(fw[h + 1], hi, fw[h][q] + l[h]);
+                    const T v0 = fw[h][q], v1 = fw[h][q] + l[h];
+#pragma unroll
+                    for (int t = 0; t < W; ++t)
+                        fw[h + 1][t] =
+                            fmin(fw[h + 1][t], fmin(v0 + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
                 }
             }
         }
@@ -196,29 +214,28 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
         for (int h = KMAX - 1; h >= 0; --h) {
             if (h < K) {
-                T m0 = INF, m1 = INF;
+                T v0[W], v1[W];
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    if (lo != kBot) m0 = tmin(m0, fw[h][q] + head<W>(lo, bn));
-                    if (hi != kBot) m1 = tmin(m1, (fw[h][q] + l[h]) + head<W>(hi, bn));
+                    v0[q] = (h == K - 1) ? head_last<T>(lo) : head_inner<W>(lo, bn);
+                    v1[q] = (h == K - 1) ? head_last<T>(hi) : head_inner<W>(hi, bn);
+                }
+                T m0 = fw[h][0] + v0[0];
+                T m1 = (fw[h][0] + l[h]) + v1[0];
+#pragma unroll
+                for (int q = 1; q < W; ++q) {
+                    m0 = fmin(m0, fw[h][q] + v0[q]);
+                    m1 = fmin(m1, (fw[h][q] + l[h]) + v1[q]);
                 }
                 const T M = m1 - m0;
                 const T lu = (l[h] - omega * M) + a[h];
                 const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
                 mm[s] = M;
                 lam[s] = lu;
-                lbacc += (double)(M < T(0) ? M : T(0));
-                T bc[W];
+                lbacc += (double)fmin(M, T(0));
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t c = wd[h][q];
-                    const T b0 = head<W>(c & 0xFFFFu, bn);
-                    const T b1 = head<W>(c >> 16, bn) + lu;
-                    bc[q] = tmin(b0, b1);
-                }
-#pragma unroll
-                for (int q = 0; q < W; ++q) bn[q] = bc[q];
+                for (int q = 0; q < W; ++q) bn[q] = fmin(v0[q], v1[q] + lu);
             }
         }
         energy = bn[0];
