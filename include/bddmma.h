@@ -202,13 +202,14 @@ int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *r
 int bddmma_save_state(const bddmma_solver *s, void *buf, size_t *bytes);
 int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes);
 
-/* Per-kernel timing with HIP events recorded on the bound stream around each
- * sweep of run_dual / run_sweeps.  enable != 0 starts a new collection.
- * kernel ids: BDDMMA_K_*.  A sweep may be several launches (one per tile
- * class); its events bracket all of them.  Only the sweeps are bracketed (to
- * keep event records off the other launches), so BDDMMA_K_AVERAGE and
- * BDDMMA_K_LB_REDUCE report no launches; they are kept for ABI stability.
- * bddmma_kernel_time synchronises and reports launches and total milliseconds. */
+/* Per-kernel timing with HIP events recorded on the bound stream around the
+ * sweeps of run_dual / run_sweeps.  enable = n > 0 starts a new collection
+ * that brackets the forward and backward sweep of every n-th iteration (n = 1:
+ * all of them); enable <= 0 stops collecting.  A sweep may be several launches
+ * (one per tile class); its events bracket all of them.  Only sweeps are
+ * bracketed, so BDDMMA_K_AVERAGE and BDDMMA_K_LB_REDUCE report no launches;
+ * they are kept for ABI stability.  bddmma_kernel_time synchronises and
+ * reports launches and total milliseconds. */
 #define BDDMMA_K_SWEEP_FWD 0
 #define BDDMMA_K_SWEEP_BWD 1
 #define BDDMMA_K_AVERAGE   2

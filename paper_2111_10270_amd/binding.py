@@ -224,8 +224,8 @@ class Solver:
         _check(lib().bddmma_load_state(self._h, buf, len(blob)))
 
     # ---- profiling ----
-    def profile(self, enable: bool = True):
-        _check(lib().bddmma_profile(self._h, int(bool(enable))))
+    def profile(self, enable=True, stride: int = 1):
+        _check(lib().bddmma_profile(self._h, int(stride) if enable else 0))
 
     def kernel_time(self, kernel: int):
         n, ms = C.c_int64(), C.c_double()

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "bddmma.h"
@@ -25,15 +26,15 @@ int fail(int code, const std::string &msg)
 }
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kHistCap = 4096;          // LB_free entries kept on the device between host copies
+constexpr int64_t kHistBytes = 64ll << 20;  // device budget for per-tile bound partials of pending sweeps
 constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t lam, mm, abar, lam_bak, mm_bak, abar_bak, mmx, avg;
-    size_t pair_var, vptr, vslot, code, gvars, child, tiles, lists, layers, cost;
-    size_t tile_lb, tile_e, red, lbh, counter, flag, x, scratch;
+    size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
+    size_t lbpart, tile_e, red, lbh, counter, flag, x, scratch;
     size_t total;
 };
 
@@ -56,8 +57,10 @@ struct bddmma_solver {
     DevProblem dp{};
     int64_t sweeps = 0;           // sweeps run since bind
     int64_t hist_synced = 0;      // history entries already on the host
+    int64_t hist_chunk = 1;       // sweeps whose bound partials fit on the device before a flush
     std::vector<double> hist;     // LB_free after every sweep
     bool prof = false;
+    int prof_stride = 1;          // bracket every prof_stride-th sweep
     Events ev;
     double tau = 0.0;
 
@@ -105,19 +108,20 @@ Layout make_layout(const bddmma_solver &s)
     L.vptr = take((V + 1) * 4);
     L.vslot = take(P * 4);
     L.code = take(pk.code.size() * 2);
-    L.gvars = take(pk.gvars.size() * 4);
+    L.gbuckets = take(pk.gbuckets.size() * sizeof(AvgBucket));
+    L.gslot = take(pk.gslot.size() * 4);
     L.child = take(pk.child.size() * 4);
     L.tiles = take(T * sizeof(TileDesc));
     L.lists = take(pk.lists.size() * 4);
     L.layers = take(pk.layers.size() * 4);
     L.cost = take(V * 8);
-    L.tile_lb = take(T * 8);
+    L.lbpart = take((size_t)s.hist_chunk * T * 8);
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
-    L.lbh = take(kHistCap * 8);
+    L.lbh = take((size_t)s.hist_chunk * 8);
     L.counter = take(64);
-    L.flag = take(V);
-    L.x = take(V);
+    L.flag = take(V + 1);
+    L.x = take(V + 1);
     L.scratch = take((size_t)pk.scratch_elems * e);
     L.total = o;
     return L;
@@ -140,9 +144,9 @@ struct Scope {
     bddmma_solver *s;
     int k;
     hipEvent_t a = nullptr, b = nullptr;
-    Scope(bddmma_solver *s_, int k_) : s(s_), k(k_)
+    Scope(bddmma_solver *s_, int k_, bool sample) : s(s_), k(k_)
     {
-        if (s->prof) {
+        if (s->prof && sample) {
             a = ev_get(s);
             b = ev_get(s);
             if (a) (void)hipEventRecord(a, s->st);
@@ -150,7 +154,7 @@ struct Scope {
     }
     ~Scope()
     {
-        if (s->prof && a && b) {
+        if (a && b) {
             (void)hipEventRecord(b, s->st);
             s->ev.used[k].emplace_back(a, b);
         }
@@ -164,39 +168,45 @@ Omega<T> weights(const bddmma_solver *s)
     return Omega<T>{(T)s->opt.omega, (T)(s->opt.omega / 2.0)};
 }
 
-// averaging of the variables not averaged in-tile, optionally with the bound record
+// averaging of the variables not averaged in-tile
 template <typename T>
-void average(bddmma_solver *s, const double *tile_lb, double *lb_slot)
+void average(bddmma_solver *s)
 {
-    launch_average<T>(s->dp, s->ptr<T>(s->L.mm), s->ptr<T>(s->L.abar), s->opt.omega, tile_lb, s->prob.lb_offset,
-                      s->ptr<double>(s->L.red) + 2 * kRedBlocks + 4, s->ptr<int32_t>(s->L.counter) + 4, lb_slot,
-                      s->st);
+    launch_average<T>(s->dp, s->ptr<T>(s->L.mm), s->ptr<T>(s->L.abar), s->opt.omega, s->st);
 }
 
+// one sweep plus averaging; with record_lb the sweep's per-tile bound partials
+// go to row (sweeps % hist_chunk) of the partial history
 template <typename T>
 void one_sweep(bddmma_solver *s, int dir, bool record_lb)
 {
     const DevProblem &p = s->dp;
     T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *abar = s->ptr<T>(s->L.abar);
-    double *tile_lb = record_lb ? s->ptr<double>(s->L.tile_lb) : nullptr;
+    double *tile_lb =
+        record_lb ? s->ptr<double>(s->L.lbpart) + (size_t)(s->sweeps % s->hist_chunk) * s->pk.tiles.size() : nullptr;
     {
-        Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD);
+        Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD,
+                 record_lb && (s->sweeps / 2) % s->prof_stride == 0);
         launch_sweep<T>(p, lam, mm, abar, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
     }
-    // averaging; with a bound record it also reduces the sweep's per-tile partials
-    average<T>(s, tile_lb, s->ptr<double>(s->L.lbh) + (s->sweeps % kHistCap));
+    average<T>(s);
 }
 
+// reduce the pending sweeps' partials to bounds and copy them to the host
 int flush_history(bddmma_solver *s)
 {
-    int64_t pending = s->sweeps - s->hist_synced;
+    const int64_t pending = s->sweeps - s->hist_synced;
     if (pending <= 0) return BDDMMA_OK;
+    double *lbh = s->ptr<double>(s->L.lbh);
+    launch_lb_many(s->ptr<double>(s->L.lbpart), (int64_t)s->pk.tiles.size(), s->hist_chunk, s->hist_synced, pending,
+                   s->prob.lb_offset, lbh, s->hist_chunk, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
     s->hist.resize((size_t)s->sweeps);
-    const double *lbh = s->ptr<double>(s->L.lbh);
-    // entries [hist_synced, sweeps) live at index % kHistCap (at most kHistCap pending)
+    // entries [hist_synced, sweeps) live at index % hist_chunk (at most hist_chunk pending)
     int64_t a = s->hist_synced;
     while (a < s->sweeps) {
-        int64_t idx = a % kHistCap, run = std::min<int64_t>(s->sweeps - a, kHistCap - idx);
+        const int64_t idx = a % s->hist_chunk, run = std::min<int64_t>(s->sweeps - a, s->hist_chunk - idx);
         HIPCHK(hipMemcpyAsync(s->hist.data() + a, lbh + idx, (size_t)run * 8, hipMemcpyDeviceToHost, s->st));
         a += run;
     }
@@ -211,7 +221,7 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
     for (int64_t k = 0; k < n; ++k) {
         one_sweep<T>(s, (int)(s->sweeps & 1), true);
         s->sweeps++;
-        if (s->sweeps - s->hist_synced >= kHistCap) {
+        if (s->sweeps - s->hist_synced >= s->hist_chunk) {
             int rc = check_launch();
             if (rc) return rc;
             rc = flush_history(s);
@@ -303,7 +313,7 @@ int set_state_T(bddmma_solver *s, const double *lam, const double *mm)
     int rc;
     if (lam && (rc = upload_pairs<T>(s, s->L.lam, lam))) return rc;
     if (mm && (rc = upload_pairs<T>(s, s->L.mm, mm))) return rc;
-    average<T>(s, nullptr, nullptr);   // averaged terms follow from M-bar
+    average<T>(s);   // averaged terms follow from M-bar
     if ((rc = check_launch())) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
     return BDDMMA_OK;
@@ -365,8 +375,7 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
     launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
 
     const Ilp &ilp = s->prob.ilp;
-    const BddSet &B = s->prob.bdds;
-    std::vector<uint8_t> xh((size_t)V), xfull((size_t)V), fl((size_t)V);
+    std::vector<uint8_t> xh((size_t)V), xfull((size_t)V);
     double delta = s->opt.delta0;
     int rc = BDDMMA_ERR_NOT_CONVERGED, round;
     for (round = 0;; ++round) {
@@ -377,26 +386,25 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
         HIPCHK(hipMemcpyAsync(&nconf, counter, 4, hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
         if (nconf == 0) {
+            // decode and walk every BDD with the point; rejecting rows flag
+            // their variables as conflicts for the next perturbation
             launch_decode<T>(p, mm, xd, s->st);
-            if (V > 0) HIPCHK(hipMemcpyAsync(xh.data(), xd, (size_t)V, hipMemcpyDeviceToHost, s->st));
+            launch_check(p, xd, flag, counter + 2, s->st);
+            int32_t nbad = 0;
+            if ((e = check_launch())) return e;
+            HIPCHK(hipMemcpyAsync(&nbad, counter + 2, 4, hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipStreamSynchronize(s->st));
-            for (int64_t i = 0; i < V; ++i) {
-                if (s->prob.fixed[i] >= 0) xfull[i] = (uint8_t)s->prob.fixed[i];
-                else if (s->prob.deg[i] == 0) xfull[i] = ilp.cost[i] < 0.0;
-                else xfull[i] = xh[i];
-            }
-            bool bad = false;
-            std::fill(fl.begin(), fl.end(), 0);
-            for (int64_t j = 0; j < B.n_bdds(); ++j) {
-                if (row_ok(ilp, B.row[j], xfull)) continue;
-                bad = true;
-                for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) fl[B.lay_var[q]] = 1;
-            }
-            if (!bad) {
+            if (nbad == 0) {
+                if (V > 0) HIPCHK(hipMemcpyAsync(xh.data(), xd, (size_t)V, hipMemcpyDeviceToHost, s->st));
+                HIPCHK(hipStreamSynchronize(s->st));
+                for (int64_t i = 0; i < V; ++i) {
+                    if (s->prob.fixed[i] >= 0) xfull[i] = (uint8_t)s->prob.fixed[i];
+                    else if (s->prob.deg[i] == 0) xfull[i] = ilp.cost[i] < 0.0;
+                    else xfull[i] = xh[i];
+                }
                 rc = BDDMMA_OK;
                 break;
             }
-            if (V > 0) HIPCHK(hipMemcpyAsync(flag, fl.data(), (size_t)V, hipMemcpyHostToDevice, s->st));
         }
         if (round == s->opt.max_rounds) break;
         launch_perturb<T>(p, lam, mm, s->tau, delta, s->opt.seed, (uint64_t)round, s->opt.perturb_scale, flag, s->st);
@@ -422,8 +430,20 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
     if (rc != BDDMMA_OK) return fail(rc, "rounding did not remove all conflicts within max_rounds");
     double u = 0.0;
     for (int64_t i = 0; i < V; ++i) u += xfull[i] ? ilp.cost[i] : 0.0;
-    for (int64_t r = 0; r < ilp.n_rows; ++r)
-        if (!row_ok(ilp, r, xfull)) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
+    // final exact check of every original row in int64, on host threads
+    {
+        const int64_t R = ilp.n_rows;
+        const int nt = R < 65536 ? 1 : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<int64_t> bad(nt, 0);
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t r = R * t / nt; r < R * (t + 1) / nt; ++r) bad[t] += !row_ok(ilp, r, xfull);
+            });
+        for (auto &h : th) h.join();
+        for (int64_t b : bad)
+            if (b) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
+    }
     if (ub) *ub = u;
     std::copy(xfull.begin(), xfull.end(), x_out);
     return BDDMMA_OK;
@@ -525,6 +545,10 @@ int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
     rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0, s->pk, msg);
     if (rc != ST_OK) return fail(rc, msg);
+    {
+        const int64_t nt = std::max<int64_t>(1, (int64_t)s->pk.tiles.size());
+        s->hist_chunk = std::max<int64_t>(16, std::min<int64_t>(1024, kHistBytes / (8 * nt)));
+    }
     s->L = make_layout(*s);
     double cmax = 1.0;
     for (double c : s->prob.ilp.cost) cmax = std::max(cmax, std::fabs(c));
@@ -583,7 +607,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
     HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
     HIPCHK(up(L.code, pk.code.data(), pk.code.size() * 2));
-    HIPCHK(up(L.gvars, pk.gvars.data(), pk.gvars.size() * 4));
+    HIPCHK(up(L.gbuckets, pk.gbuckets.data(), pk.gbuckets.size() * sizeof(AvgBucket)));
+    HIPCHK(up(L.gslot, pk.gslot.data(), pk.gslot.size() * 4));
     HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
     HIPCHK(up(L.tiles, pk.tiles.data(), pk.tiles.size() * sizeof(TileDesc)));
     HIPCHK(up(L.lists, pk.lists.data(), pk.lists.size() * 4));
@@ -600,8 +625,10 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     d.vptr = s->ptr<int32_t>(L.vptr);
     d.vslot = s->ptr<int32_t>(L.vslot);
     d.code = s->ptr<uint16_t>(L.code);
-    d.gvars = s->ptr<int32_t>(L.gvars);
-    d.n_gvars = (int64_t)pk.gvars.size();
+    d.gbuckets = s->ptr<AvgBucket>(L.gbuckets);
+    d.n_gbuckets = (int32_t)pk.gbuckets.size();
+    d.gblocks = pk.gblocks;
+    d.gslot = s->ptr<int32_t>(L.gslot);
     d.cost = s->ptr<double>(L.cost);
     d.n_vars = s->prob.ilp.n_vars;
     d.n_slots = pk.n_slots;
@@ -609,8 +636,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     d.lds_lane_elems = pk.max_lds_lane_elems;
     if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.abar), s->st);
     else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.abar), s->st);
-    launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars, s->st);
-    launch_fill<int32_t>(s->ptr<int32_t>(L.counter), 0, 16, s->st);
+    launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
+    launch_fill<uint8_t>(s->ptr<uint8_t>(L.x), 0, s->prob.ilp.n_vars + 1, s->st);
     int rc = check_launch();
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
@@ -821,8 +848,8 @@ int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
     p += S * s->elem;
     if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.mm, p, S * s->elem, hipMemcpyHostToDevice, s->st));
     p += S * s->elem;
-    if (s->elem == 8) average<double>(s, nullptr, nullptr);
-    else average<float>(s, nullptr, nullptr);
+    if (s->elem == 8) average<double>(s);
+    else average<float>(s);
     if ((rc = check_launch())) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
     s->hist.assign((const double *)p, (const double *)p + h.hist);
@@ -843,7 +870,8 @@ int bddmma_profile(bddmma_solver *s, int enable)
         }
         v.clear();
     }
-    s->prof = enable != 0;
+    s->prof = enable > 0;
+    s->prof_stride = enable > 0 ? enable : 1;
     return BDDMMA_OK;
 }
 

@@ -313,53 +313,72 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_stage2(const double *__rest
 
 // a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, summed in ascending row order,
 // for the variables the sweep does not average in-tile; the term is stored at
-// every slot of i.  The first `nlb` blocks also reduce the per-tile bound
-// partials of the sweep that produced M: block b sums a fixed chunk, and the
-// last of those blocks to finish adds the chunk sums in block order, so the
-// result does not depend on scheduling.
+// every slot of i.  Blocks are assigned to degree buckets (layout.hpp).
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_average(const int32_t *__restrict__ gvars, int64_t n_gvars,
+__global__ __launch_bounds__(kRedThreads) void k_average(const AvgBucket *__restrict__ buckets, int nbuckets,
+                                                         const int32_t *__restrict__ gslot,
                                                          const int32_t *__restrict__ vptr,
                                                          const int32_t *__restrict__ vslot,
                                                          const T *__restrict__ mm, T *__restrict__ abar,
-                                                         double omega, const double *__restrict__ tile_lb,
-                                                         int64_t n_tiles, int nlb, double offset,
-                                                         double *__restrict__ stage, int32_t *counter,
-                                                         double *__restrict__ lb_out)
+                                                         double omega)
+{
+    // bucket of this block (uniform)
+    int bi = -1;
+    for (int j = 0; j < nbuckets; ++j)
+        if ((int)blockIdx.x >= buckets[j].block_begin) bi = j;
+    if (bi >= 0) {
+        const AvgBucket bk = buckets[bi];
+        const int64_t i = (int64_t)((int)blockIdx.x - bk.block_begin) * kRedThreads + threadIdx.x;
+        if (i < bk.count) {
+            if (bk.deg > 0) {
+                // slots of the variable, coalesced across the block, then its M-bar values
+                int32_t sl[kEllMaxDeg];
+                T mv[kEllMaxDeg];
+#pragma unroll
+                for (int k = 0; k < kEllMaxDeg; ++k)
+                    if (k < bk.deg) sl[k] = gslot[bk.base + (int64_t)k * bk.count + i];
+#pragma unroll
+                for (int k = 0; k < kEllMaxDeg; ++k)
+                    if (k < bk.deg) mv[k] = mm[sl[k]];
+                T s = T(0);
+#pragma unroll
+                for (int k = 0; k < kEllMaxDeg; ++k)
+                    if (k < bk.deg) s += mv[k];
+                const T av = (T)(omega / (double)bk.deg) * s;
+#pragma unroll
+                for (int k = 0; k < kEllMaxDeg; ++k)
+                    if (k < bk.deg) abar[sl[k]] = av;
+            } else {
+                const int32_t v = gslot[bk.base + i];
+                const int32_t a = vptr[v], b = vptr[v + 1];
+                T s = T(0);
+                for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
+                const T av = (T)(omega / (double)(b - a)) * s;
+                for (int32_t q = a; q < b; ++q) abar[vslot[q]] = av;
+            }
+        }
+    }
+}
+
+// Bound of each of `n` sweeps from their per-tile partials (row s of `part`
+// holds sweep first + s): one block per sweep, fixed summation order, so the
+// value does not depend on scheduling.  out[(first + s) % cap] = offset + sum.
+__global__ __launch_bounds__(kRedThreads) void k_lb_many(const double *__restrict__ part, int64_t n_tiles,
+                                                         int64_t chunk, int64_t first, double offset,
+                                                         double *__restrict__ out, int64_t cap)
 {
     __shared__ double sh[kRedThreads];
-    __shared__ int last;
-    const int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
-    if (i < n_gvars) {
-        const int32_t v = gvars[i];
-        const int32_t a = vptr[v], b = vptr[v + 1];
-        T s = T(0);
-        for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
-        const T av = (T)(omega / (double)(b - a)) * s;
-        for (int32_t q = a; q < b; ++q) abar[vslot[q]] = av;
+    const int64_t sweep = first + blockIdx.x;
+    const double *row = part + (sweep % chunk) * n_tiles;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t t = threadIdx.x;
+    for (; t + 3 * kRedThreads < n_tiles; t += 4 * kRedThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += row[t + u * kRedThreads];
     }
-    if (tile_lb == nullptr || (int)blockIdx.x >= nlb) return;
-    const int64_t per = (n_tiles + nlb - 1) / nlb;
-    const int64_t t0 = (int64_t)blockIdx.x * per, t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
-    double acc = 0.0;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kRedThreads) acc += tile_lb[t];
-    const double part = block_sum(acc, sh);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(stage + blockIdx.x, part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        last = (atomicAdd(counter, 1) == nlb - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double t = 0.0;
-    for (int j = threadIdx.x; j < nlb; j += kRedThreads)
-        t += __hip_atomic_load(stage + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double tot = block_sum(t, sh);
-    if (threadIdx.x == 0) {
-        lb_out[0] = tot + offset;
-        __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int u = 0; t < n_tiles; t += kRedThreads, ++u) acc[u & 3] += row[t];
+    const double tot = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), sh);
+    if (threadIdx.x == 0) out[sweep % cap] = tot + offset;
 }
 
 // per-variable a_i of every variable (state export)
@@ -532,6 +551,39 @@ __global__ __launch_bounds__(256) void k_decode(DevProblem P, const T *__restric
     x[v] = (q0 != q1 && mm[P.vslot[q0]] < T(0)) ? 1 : 0;
 }
 
+// Exact feasibility of a decoded 0-1 point (Sec. 5, constraint set
+// correspondence): walk every BDD along x; a BDD rejects x when the walk
+// reaches the rejecting terminal.  Padding layers point at variable n_vars,
+// whose x entry is 0 and whose chain nodes accept either value.
+__global__ __launch_bounds__(kThreads) void k_check(DevProblem P, const uint8_t *__restrict__ x,
+                                                    uint8_t *__restrict__ flag, int32_t *counter,
+                                                    const int32_t *__restrict__ list, int64_t tile_count)
+{
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int64_t lt = xcd_block() * kWavesPerBlock + uni(threadIdx.x >> 6);
+    if (lt >= tile_count) return;
+    const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
+    const TileView tv = load_tile(P.tiles + tile);
+    // unused lanes of a partially filled tile carry the padding variable at
+    // layer 0; they stand for no row
+    if (P.pair_var[tv.pb + lane] >= P.n_vars) return;
+    uint32_t node = 0;        // index inside the current layer
+    bool ok = true;
+    for (uint32_t h = 0; h < tv.K; ++h) {
+        const uint32_t noff = uni(P.layers[tv.lb + h]) & 0xFFFFu;
+        const uint32_t s = tv.pb + h * kLanes + lane;
+        const uint32_t wd = node_word(P.child, tv, noff + (ok ? node : 0u), lane);
+        const uint32_t nxt = x[P.pair_var[s]] ? (wd >> 16) : (wd & 0xFFFFu);
+        if (nxt == kBot) ok = false;
+        node = nxt;
+    }
+    ok = ok && node == kTop;
+    if (!ok) {
+        atomicAdd(counter, 1);
+        for (uint32_t h = 0; h < tv.K; ++h) flag[P.pair_var[tv.pb + h * kLanes + lane]] = 1;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T *__restrict__ d, T v, int64_t n)
 {
@@ -575,20 +627,21 @@ template <typename T>
 void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int dir, int mode,
                   hipStream_t st)
 {
-    if (mode == MODE_UPDATE) {
-        if (dir == 0) {
-            launch_reg<T, 0, 2>(p, 0, lam, mm, abar, tile_lb, w, st);
-            launch_reg<T, 0, 4>(p, 1, lam, mm, abar, tile_lb, w, st);
+    const int update = mode == MODE_UPDATE;
+    if (dir == 0) {
+        launch_reg<T, 0, 2>(p, 0, lam, mm, abar, tile_lb, w, update, st);
+        launch_reg<T, 0, 4>(p, 1, lam, mm, abar, tile_lb, w, update, st);
+        if (update)
             launch_general<T, 0, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
-        } else {
-            launch_reg<T, 1, 2>(p, 0, lam, mm, abar, tile_lb, w, st);
-            launch_reg<T, 1, 4>(p, 1, lam, mm, abar, tile_lb, w, st);
-            launch_general<T, 1, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
-        }
-    } else if (dir == 0) {
-        launch_general<T, 0, MODE_FIXED>(p, LIST_GEN_LDS_ALL, LIST_GEN_GLOB_ALL, lam, mm, abar, tile_lb, w, st);
+        else
+            launch_general<T, 0, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
     } else {
-        launch_general<T, 1, MODE_FIXED>(p, LIST_GEN_LDS_ALL, LIST_GEN_GLOB_ALL, lam, mm, abar, tile_lb, w, st);
+        launch_reg<T, 1, 2>(p, 0, lam, mm, abar, tile_lb, w, update, st);
+        launch_reg<T, 1, 4>(p, 1, lam, mm, abar, tile_lb, w, update, st);
+        if (update)
+            launch_general<T, 1, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
+        else
+            launch_general<T, 1, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
     }
 }
 
@@ -608,14 +661,19 @@ void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, d
 }
 
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, const double *tile_lb, double offset,
-                    double *stage, int32_t *counter, double *lb_out, hipStream_t st)
+void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, hipStream_t st)
 {
-    const int nlb = tile_lb ? (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (p.n_tiles + 127) / 128)) : 0;
-    const int64_t blocks = std::max<int64_t>((p.n_gvars + kRedThreads - 1) / kRedThreads, nlb);
-    if (blocks == 0) return;
-    hipLaunchKernelGGL((k_average<T>), dim3((unsigned)blocks), dim3(kRedThreads), 0, st, p.gvars, p.n_gvars, p.vptr,
-                       p.vslot, mm, abar, omega, tile_lb, p.n_tiles, nlb, offset, stage, counter, lb_out);
+    if (p.gblocks == 0) return;
+    hipLaunchKernelGGL((k_average<T>), dim3((unsigned)p.gblocks), dim3(kRedThreads), 0, st, p.gbuckets, p.n_gbuckets,
+                       p.gslot, p.vptr, p.vslot, mm, abar, omega);
+}
+
+void launch_lb_many(const double *part, int64_t n_tiles, int64_t chunk, int64_t first, int64_t n, double offset,
+                    double *out, int64_t cap, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_lb_many, dim3((unsigned)n), dim3(kRedThreads), 0, st, part, n_tiles, chunk, first,
+                           offset, out, cap);
 }
 
 template <typename T>
@@ -682,6 +740,17 @@ void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st)
         hipLaunchKernelGGL((k_decode<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p, mm, x);
 }
 
+void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st)
+{
+    launch_fill<int32_t>(counter, 0, 1, st);
+    for (int l : {(int)LIST_GEN_LDS_ALL, (int)LIST_GEN_GLOB_ALL}) {
+        const int64_t n = p.list_off[l + 1] - p.list_off[l];
+        if (n > 0)
+            hipLaunchKernelGGL(k_check, dim3(grid8(n, kWavesPerBlock)), dim3(kThreads), 0, st, p, x, flag, counter,
+                               p.lists + p.list_off[l], n);
+    }
+}
+
 template <typename T>
 void launch_fill(T *dst, T value, int64_t n, hipStream_t st)
 {
@@ -697,8 +766,7 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
 #define BDDMMA_INSTANTIATE(T)                                                                                        \
     template void launch_sweep<T>(const DevProblem &, T *, T *, const T *, double *, Omega<T>, int, int, hipStream_t); \
     template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
-    template void launch_average<T>(const DevProblem &, const T *, T *, double, const double *, double, double *,    \
-                                    int32_t *, double *, hipStream_t);                                               \
+    template void launch_average<T>(const DevProblem &, const T *, T *, double, hipStream_t);                       \
     template void launch_average_all<T>(const DevProblem &, const T *, T *, double, hipStream_t);                   \
     template void launch_init<T>(const DevProblem &, T *, T *, T *, hipStream_t);                                   \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \

@@ -24,8 +24,10 @@ struct DevProblem {
     const int32_t *vptr;
     const int32_t *vslot;
     const uint16_t *code;              // [n_slots] source of each slot's averaged term
-    const int32_t *gvars;              // variables averaged by the averaging kernel
-    int64_t n_gvars;
+    const AvgBucket *gbuckets;         // variables averaged by the averaging kernel
+    int32_t n_gbuckets;
+    int64_t gblocks;
+    const int32_t *gslot;
     const double *cost;
     int64_t n_vars, n_slots;
     void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
@@ -52,17 +54,18 @@ void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *til
 
 // register-resident sweeps of the fast-path tiles of width class wi
 template <typename T, int DIR, int W>
-void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w,
+void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int update,
                 hipStream_t st);
 
 // a_i = omega/|J_i| * sum_k M_ik (ascending row order) for the variables the
-// sweep does not average itself, stored into abar at every slot of i.  With
-// tile_lb != nullptr the same launch also reduces the per-tile bound partials
-// in a fixed order: lb_out[0] = offset + sum_t tile_lb[t] (stage scratch:
-// kRedBlocks doubles, counter: one int32 that is zero between launches).
+// sweep does not average itself, stored into abar at every slot of i.
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, const double *tile_lb, double offset,
-                    double *stage, int32_t *counter, double *lb_out, hipStream_t st);
+void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, hipStream_t st);
+
+// bounds of sweeps first .. first+n-1 from their per-tile partials (row
+// (sweep % chunk) of part, n_tiles each): out[sweep % cap] = offset + sum
+void launch_lb_many(const double *part, int64_t n_tiles, int64_t chunk, int64_t first, int64_t n, double offset,
+                    double *out, int64_t cap, hipStream_t st);
 
 // per-variable averaged terms of all variables into avg[n_vars] (state export)
 template <typename T>
@@ -101,6 +104,10 @@ void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double
 // x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
 template <typename T>
 void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st);
+
+// walk every BDD with the 0-1 point x (x[n_vars] must be 0): counter[0] +=
+// number of BDDs that reject it, flag[i] = 1 for every variable of those BDDs
+void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st);
 
 template <typename T>
 void launch_fill(T *dst, T value, int64_t n, hipStream_t st);

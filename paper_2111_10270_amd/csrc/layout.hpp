@@ -81,4 +81,19 @@ inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + k
 constexpr uint16_t kCodeSelf = 0xFFFEu;
 constexpr uint16_t kCodeGlobal = 0xFFFFu;
 
+// Variables averaged by the averaging kernel are bucketed by |J_i|.  Buckets
+// with deg <= kEllMaxDeg store the slots column-major (slot k of the bucket's
+// variable i at base + k * count + i) so a thread reads its slots coalesced
+// in one round; the last bucket (deg = 0) lists variables with more
+// subproblems by id and uses the variable CSR.
+constexpr int kEllMaxDeg = 16;
+struct AvgBucket {
+    int32_t deg;            // |J_i| of the bucket, 0 = CSR bucket
+    int32_t count;          // variables in the bucket
+    int32_t block_begin;    // first averaging block of the bucket
+    int32_t pad;
+    int64_t base;           // first entry in the bucket slot / id array
+};
+static_assert(sizeof(AvgBucket) == 24, "AvgBucket is 24 bytes");
+
 }  // namespace bddmma

@@ -640,6 +640,38 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
         }
     }
+    // bucket the kernel-averaged variables by |J_i|
+    {
+        std::vector<std::vector<int32_t>> by_deg(kEllMaxDeg + 1);
+        for (int32_t v : o.gvars) {
+            const int32_t d = o.vptr[v + 1] - o.vptr[v];
+            by_deg[d <= kEllMaxDeg ? d : 0].push_back(v);
+        }
+        o.gbuckets.clear();
+        o.gslot.clear();
+        int32_t blocks = 0;
+        for (int d = 1; d <= kEllMaxDeg + 1; ++d) {
+            const int dd = d <= kEllMaxDeg ? d : 0;   // CSR bucket last
+            const std::vector<int32_t> &vs = by_deg[dd];
+            if (vs.empty()) continue;
+            AvgBucket b{};
+            b.deg = dd;
+            b.count = (int32_t)vs.size();
+            b.block_begin = blocks;
+            b.base = (int64_t)o.gslot.size();
+            if (dd == 0) {
+                o.gslot.insert(o.gslot.end(), vs.begin(), vs.end());
+            } else {
+                o.gslot.resize(o.gslot.size() + (size_t)dd * vs.size());
+                for (size_t i = 0; i < vs.size(); ++i)
+                    for (int k = 0; k < dd; ++k)
+                        o.gslot[b.base + (int64_t)k * b.count + (int64_t)i] = o.vslot[o.vptr[vs[i]] + k];
+            }
+            blocks += (b.count + 255) / 256;
+            o.gbuckets.push_back(b);
+        }
+        o.gblocks = blocks;
+    }
     // tiles with the same code pattern share one copy of it
     o.code.clear();
     std::unordered_multimap<uint64_t, uint32_t> code_seen;

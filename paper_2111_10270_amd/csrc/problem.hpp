@@ -43,6 +43,9 @@ struct Packed {
     std::vector<int32_t> vslot;       // [P]
     std::vector<uint16_t> code;       // averaging codes (layout.hpp), one K*64 block per distinct tile pattern
     std::vector<int32_t> gvars;       // variables averaged by the averaging kernel, ascending
+    std::vector<AvgBucket> gbuckets;  // the same variables bucketed by |J_i| (layout.hpp)
+    std::vector<int32_t> gslot;       // bucket slot lists (ELL) / variable ids (CSR bucket)
+    int64_t gblocks = 0;              // averaging blocks covering all buckets
     int64_t n_slots = 0;
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
     int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile

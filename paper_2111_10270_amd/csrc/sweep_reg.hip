@@ -66,12 +66,14 @@ __device__ __forceinline__ T head_last(uint32_t head)
     return pen<T>(head, kTop);
 }
 
+// update == false: min-marginal differences at fixed multipliers (Alg. 2),
+// written to mm, which is then output only.
 template <typename T, int DIR, int W, int KMAX>
 __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam, T *mm,
                                                                    const T *__restrict__ abar,
                                                                    double *__restrict__ tile_lb, Omega<T> w,
                                                                    const int32_t *__restrict__ list,
-                                                                   int64_t tile_count)
+                                                                   int64_t tile_count, int update)
 {
     const T omega = w.w1;
     const int lane = threadIdx.x & (kLanes - 1);
@@ -100,15 +102,19 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
         if (h < K) {
             const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
             l[h] = lam[s];
-            mo[h] = mm[s];
-            cd[h] = P.code[tv.cb + (uint32_t)h * kLanes + lane];
+            if (update) {
+                mo[h] = mm[s];
+                cd[h] = P.code[tv.cb + (uint32_t)h * kLanes + lane];
+            }
 #pragma unroll
             for (int q = 0; q < W; ++q) wd[h][q] = uni(P.child[tv.nb + (uint32_t)(h * W + q)]);
         }
     }
+    if (update) {
 #pragma unroll
-    for (int h = 0; h < KMAX; ++h)
-        if (h < K) a[h] = averaged_term(mm, abar, tv.pb, tv.pb + (uint32_t)h * kLanes + lane, cd[h], mo[h], w);
+        for (int h = 0; h < KMAX; ++h)
+            if (h < K) a[h] = averaged_term(mm, abar, tv.pb, tv.pb + (uint32_t)h * kLanes + lane, cd[h], mo[h], w);
+    }
 
     double lbacc = 0.0;
     T energy;
@@ -157,10 +163,10 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     m1 = fmin(m1, (f[q] + l[h]) + hd1[h][q]);
                 }
                 const T M = m1 - m0;
-                const T lu = (l[h] - omega * M) + a[h];
+                const T lu = update ? (l[h] - omega * M) + a[h] : l[h];
                 const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
                 mm[s] = M;
-                lam[s] = lu;
+                if (update) lam[s] = lu;
                 lbacc += (double)fmin(M, T(0));
                 if (h == K - 1) {
 #pragma unroll
@@ -229,10 +235,10 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     m1 = fmin(m1, (fw[h][q] + l[h]) + v1[q]);
                 }
                 const T M = m1 - m0;
-                const T lu = (l[h] - omega * M) + a[h];
+                const T lu = update ? (l[h] - omega * M) + a[h] : l[h];
                 const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
                 mm[s] = M;
-                lam[s] = lu;
+                if (update) lam[s] = lu;
                 lbacc += (double)fmin(M, T(0));
 #pragma unroll
                 for (int q = 0; q < W; ++q) bn[q] = fmin(v0[q], v1[q] + lu);
@@ -255,7 +261,7 @@ inline unsigned grid8(int64_t tiles, int per_block)
 
 template <typename T, int DIR, int W>
 void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w,
-                hipStream_t st)
+                int update, hipStream_t st)
 {
 #define BDDMMA_REG(KI, KM)                                                                                         \
     {                                                                                                              \
@@ -263,7 +269,7 @@ void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, doubl
         const int64_t n = p.list_off[l + 1] - p.list_off[l];                                                       \
         if (n > 0)                                                                                                 \
             hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, KM>), dim3(grid8(n, kRegWaves)), dim3(kRegWaves * kLanes), \
-                               0, st, p, lam, mm, abar, tile_lb, w, p.lists + p.list_off[l], n);                   \
+                               0, st, p, lam, mm, abar, tile_lb, w, p.lists + p.list_off[l], n, update);           \
     }
     BDDMMA_REG(0, 4)
     BDDMMA_REG(1, 8)
@@ -275,10 +281,10 @@ void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, doubl
 }
 
 template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 2>(const DevProblem &, int, BDDMMA_REG_T *, BDDMMA_REG_T *,
-                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>,
+                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>, int,
                                                            hipStream_t);
 template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 4>(const DevProblem &, int, BDDMMA_REG_T *, BDDMMA_REG_T *,
-                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>,
+                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>, int,
                                                            hipStream_t);
 
 }  // namespace bddmma

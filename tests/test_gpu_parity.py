@@ -310,6 +310,22 @@ def test_rounding_not_converged_keeps_state():
     assert all(np.array_equal(a, b) for a, b in zip(before, after))
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_rounding_partially_filled_shared_tile(prec):
+    """20 independent exactly-one rows share one topology; their tile has 44
+    unused lanes whose all-zero point the topology rejects"""
+    rng = np.random.default_rng(5)
+    rows = [([3 * r, 3 * r + 1, 3 * r + 2], [1, 1, 1], 0, 1) for r in range(20)]
+    ilp = I.from_rows(60, rng.standard_normal(60), rows, name="onehot20")
+    s = solver(ilp, precision=prec)
+    s.run_dual(3)
+    r = s.round_primal()
+    assert r["rc"] == 0 and r["rounds"] == 0
+    x = r["x"].reshape(20, 3)
+    assert np.all(x.sum(axis=1) == 1)
+    assert np.array_equal(np.argmax(x, axis=1), np.argmin(ilp.costs.reshape(20, 3), axis=1))
+
+
 def test_rounding_mrf10_fp32_feasible():
     ilp = I.workload("mrf10x10L3")
     s = solver(ilp, precision=32)
