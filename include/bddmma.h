@@ -189,10 +189,13 @@ int bddmma_set_state(bddmma_solver *s, const double *lambda, const double *mm, c
 int bddmma_min_marginals(bddmma_solver *s, double *mm_out);
 
 /* Alg. 2 on a copy of the terminated multipliers; the dual state is restored
- * afterwards.  On success x_out[n_vars] (0/1) satisfies every original row
- * (checked exactly in int64 on the host), *ub = c^T x, *rounds = perturbation
- * rounds used.  NOT_CONVERGED when max_rounds rounds did not remove every
- * conflict (x_out untouched).  Any output pointer except x_out may be NULL. */
+ * afterwards.  Each round that leaves no conflicting sign decodes x and walks
+ * every BDD with it; variables of rejecting rows count as conflicts.  On
+ * success x_out[n_vars] (0/1, presolved variables included) satisfies every
+ * original row (checked again exactly in int64 on the device), *ub = c^T x,
+ * *rounds = perturbation rounds used.  NOT_CONVERGED when max_rounds rounds did
+ * not remove every conflict (x_out untouched).  Any output pointer except
+ * x_out may be NULL. */
 int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds);
 
 /* Checkpoint of the dual state (multipliers, deferred differences, sweep

@@ -34,7 +34,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     size_t lam, mm, abar, lam_bak, mm_bak, abar_bak, mmx, avg;
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
-    size_t lbpart, tile_e, red, lbh, counter, flag, x, scratch;
+    size_t lbpart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
+    size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
     size_t total;
 };
 
@@ -55,6 +56,9 @@ struct bddmma_solver {
     char *dev = nullptr;
     hipStream_t st = nullptr;
     DevProblem dp{};
+    DevRows rows{};
+    std::vector<int32_t> coef32;  // host staging of the original coefficients
+    std::vector<int8_t> preset;   // host staging of presolved values
     int64_t sweeps = 0;           // sweeps run since bind
     int64_t hist_synced = 0;      // history entries already on the host
     int64_t hist_chunk = 1;       // sweeps whose bound partials fit on the device before a flush
@@ -122,6 +126,14 @@ Layout make_layout(const bddmma_solver &s)
     L.counter = take(64);
     L.flag = take(V + 1);
     L.x = take(V + 1);
+    L.xfull = take(V + 1);
+    const Ilp &ilp = s.prob.ilp;
+    L.r_ptr = take((ilp.n_rows + 1) * 8);
+    L.r_col = take(ilp.col.size() * 4);
+    L.r_coef = take(ilp.coef.size() * 4);
+    L.r_sense = take(ilp.n_rows);
+    L.r_rhs = take(ilp.n_rows * 8);
+    L.preset = take(V);
     L.scratch = take((size_t)pk.scratch_elems * e);
     L.total = o;
     return L;
@@ -347,14 +359,6 @@ int min_marginals_T(bddmma_solver *s, double *out)
     return BDDMMA_OK;
 }
 
-bool row_ok(const Ilp &ilp, int64_t r, const std::vector<uint8_t> &x)
-{
-    int64_t lhs = 0;
-    for (int64_t e = ilp.row_ptr[r]; e < ilp.row_ptr[r + 1]; ++e) lhs += ilp.coef[e] * (int64_t)x[ilp.col[e]];
-    const int sn = ilp.sense[r];
-    return sn < 0 ? lhs <= ilp.rhs[r] : sn > 0 ? lhs >= ilp.rhs[r] : lhs == ilp.rhs[r];
-}
-
 // Alg. 2 on the terminated multipliers; the dual state is restored at the end
 template <typename T>
 int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
@@ -374,8 +378,6 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
     launch_terminate<T>(p, lam, mm, omega, s->st);
     launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
 
-    const Ilp &ilp = s->prob.ilp;
-    std::vector<uint8_t> xh((size_t)V), xfull((size_t)V);
     double delta = s->opt.delta0;
     int rc = BDDMMA_ERR_NOT_CONVERGED, round;
     for (round = 0;; ++round) {
@@ -395,13 +397,6 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
             HIPCHK(hipMemcpyAsync(&nbad, counter + 2, 4, hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipStreamSynchronize(s->st));
             if (nbad == 0) {
-                if (V > 0) HIPCHK(hipMemcpyAsync(xh.data(), xd, (size_t)V, hipMemcpyDeviceToHost, s->st));
-                HIPCHK(hipStreamSynchronize(s->st));
-                for (int64_t i = 0; i < V; ++i) {
-                    if (s->prob.fixed[i] >= 0) xfull[i] = (uint8_t)s->prob.fixed[i];
-                    else if (s->prob.deg[i] == 0) xfull[i] = ilp.cost[i] < 0.0;
-                    else xfull[i] = xh[i];
-                }
                 rc = BDDMMA_OK;
                 break;
             }
@@ -428,24 +423,22 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
     HIPCHK(hipStreamSynchronize(s->st));
     if (rounds_out) *rounds_out = round;
     if (rc != BDDMMA_OK) return fail(rc, "rounding did not remove all conflicts within max_rounds");
+    // full point (presolved values included), exact int64 check of every
+    // original row and the objective, all on the device
+    uint8_t *xf = s->ptr<uint8_t>(s->L.xfull);
+    double *red = s->ptr<double>(s->L.red);
+    launch_finalize_x(s->rows, V, xd, xf, s->st);
+    launch_row_check(s->rows, xf, counter + 3, s->st);
+    launch_objective(s->ptr<double>(s->L.cost), xf, V, red + 2 * kRedBlocks + 4, red + 3 * kRedBlocks + 9, s->st);
+    if ((e = check_launch())) return e;
+    int32_t nviol = 0;
     double u = 0.0;
-    for (int64_t i = 0; i < V; ++i) u += xfull[i] ? ilp.cost[i] : 0.0;
-    // final exact check of every original row in int64, on host threads
-    {
-        const int64_t R = ilp.n_rows;
-        const int nt = R < 65536 ? 1 : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::vector<int64_t> bad(nt, 0);
-        std::vector<std::thread> th;
-        for (int t = 0; t < nt; ++t)
-            th.emplace_back([&, t]() {
-                for (int64_t r = R * t / nt; r < R * (t + 1) / nt; ++r) bad[t] += !row_ok(ilp, r, xfull);
-            });
-        for (auto &h : th) h.join();
-        for (int64_t b : bad)
-            if (b) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
-    }
+    HIPCHK(hipMemcpyAsync(&nviol, counter + 3, 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(&u, red + 3 * kRedBlocks + 9, 8, hipMemcpyDeviceToHost, s->st));
+    if (V > 0) HIPCHK(hipMemcpyAsync(x_out, xf, (size_t)V, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (nviol != 0) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
     if (ub) *ub = u;
-    std::copy(xfull.begin(), xfull.end(), x_out);
     return BDDMMA_OK;
 }
 
@@ -614,6 +607,30 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     HIPCHK(up(L.lists, pk.lists.data(), pk.lists.size() * 4));
     HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
     HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
+    {
+        // original rows and presolved values, for the final exact check of a primal point
+        const Ilp &ilp = s->prob.ilp;
+        s->coef32.assign(ilp.coef.begin(), ilp.coef.end());
+        s->preset.assign((size_t)ilp.n_vars, -1);
+        for (int64_t i = 0; i < ilp.n_vars; ++i) {
+            if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
+            else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
+        }
+        HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
+        HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
+        HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
+        HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
+        HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
+        HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
+        DevRows &r = s->rows;
+        r.row_ptr = s->ptr<int64_t>(L.r_ptr);
+        r.col = s->ptr<int32_t>(L.r_col);
+        r.coef = s->ptr<int32_t>(L.r_coef);
+        r.sense = s->ptr<int8_t>(L.r_sense);
+        r.rhs = s->ptr<int64_t>(L.r_rhs);
+        r.n_rows = ilp.n_rows;
+        r.preset = s->ptr<int8_t>(L.preset);
+    }
     DevProblem &d = s->dp;
     d.tiles = s->ptr<TileDesc>(L.tiles);
     d.n_tiles = (int64_t)pk.tiles.size();

@@ -584,6 +584,45 @@ __global__ __launch_bounds__(kThreads) void k_check(DevProblem P, const uint8_t 
     }
 }
 
+__global__ __launch_bounds__(256) void k_finalize_x(const int8_t *__restrict__ preset,
+                                                   const uint8_t *__restrict__ xdec, uint8_t *__restrict__ xfull,
+                                                   int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) xfull[i] = preset[i] >= 0 ? (uint8_t)preset[i] : xdec[i];
+}
+
+// one thread per original row: sum_k a_k x_{c_k} (sense) b in int64
+__global__ __launch_bounds__(kRedThreads) void k_row_check(DevRows R, const uint8_t *__restrict__ x,
+                                                           int32_t *counter)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t r = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    int bad = 0;
+    if (r < R.n_rows) {
+        int64_t lhs = 0;
+        for (int64_t e = R.row_ptr[r]; e < R.row_ptr[r + 1]; ++e) lhs += (int64_t)R.coef[e] * (int64_t)x[R.col[e]];
+        const int sn = R.sense[r];
+        const int64_t b = R.rhs[r];
+        bad = !(sn < 0 ? lhs <= b : sn > 0 ? lhs >= b : lhs == b);
+    }
+    const double t = block_sum((double)bad, sh);
+    if (threadIdx.x == 0 && t > 0.0) atomicAdd(counter, (int32_t)t);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_objective_stage1(const double *__restrict__ cost,
+                                                                  const uint8_t *__restrict__ x, int64_t n,
+                                                                  double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per, b = a + per < n ? a + per : n;
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRedThreads) s += x[i] ? cost[i] : 0.0;
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T *__restrict__ d, T v, int64_t n)
 {
@@ -738,6 +777,28 @@ void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st)
 {
     if (p.n_vars > 0)
         hipLaunchKernelGGL((k_decode<T>), dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p, mm, x);
+}
+
+void launch_finalize_x(const DevRows &r, int64_t n_vars, const uint8_t *xdec, uint8_t *xfull, hipStream_t st)
+{
+    if (n_vars > 0)
+        hipLaunchKernelGGL(k_finalize_x, dim3(blocks_for(n_vars, 256)), dim3(256), 0, st, r.preset, xdec, xfull, n_vars);
+}
+
+void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, hipStream_t st)
+{
+    launch_fill<int32_t>(counter, 0, 1, st);
+    if (r.n_rows > 0)
+        hipLaunchKernelGGL(k_row_check, dim3(blocks_for(r.n_rows, kRedThreads)), dim3(kRedThreads), 0, st, r, xfull,
+                           counter);
+}
+
+void launch_objective(const double *cost, const uint8_t *xfull, int64_t n_vars, double *stage, double *out,
+                      hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n_vars + 4095) / 4096));
+    hipLaunchKernelGGL(k_objective_stage1, dim3(nb), dim3(kRedThreads), 0, st, cost, xfull, n_vars, stage);
+    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(kRedThreads), 0, st, stage, nb, 0.0, out);
 }
 
 void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st)

@@ -105,6 +105,27 @@ void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double
 template <typename T>
 void launch_decode(const DevProblem &p, const T *mm, uint8_t *x, hipStream_t st);
 
+// Original rows on the device, for the final exact check of a primal point.
+struct DevRows {
+    const int64_t *row_ptr;   // [n_rows + 1]
+    const int32_t *col;       // [nnz]
+    const int32_t *coef;      // [nnz] nonzero coefficients
+    const int8_t *sense;      // [n_rows]
+    const int64_t *rhs;       // [n_rows]
+    int64_t n_rows;
+    const int8_t *preset;     // [n_vars] presolved value (0/1) or -1 when decoded
+};
+
+// full point: xfull[i] = preset[i] >= 0 ? preset[i] : xdec[i]
+void launch_finalize_x(const DevRows &r, int64_t n_vars, const uint8_t *xdec, uint8_t *xfull, hipStream_t st);
+
+// counter[0] = number of original rows xfull violates (int64 arithmetic)
+void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, hipStream_t st);
+
+// out[0] = sum_i cost_i * xfull_i in a fixed order (stage scratch: kRedBlocks doubles)
+void launch_objective(const double *cost, const uint8_t *xfull, int64_t n_vars, double *stage, double *out,
+                      hipStream_t st);
+
 // walk every BDD with the 0-1 point x (x[n_vars] must be 0): counter[0] +=
 // number of BDDs that reject it, flag[i] = 1 for every variable of those BDDs
 void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st);

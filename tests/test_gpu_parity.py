@@ -294,7 +294,10 @@ def test_rounding_fp64_matches_reference():
         ro = o.round(tau=0.0, seed=3, scale=scale)
         assert r["rc"] == ro["rc"] and r["rounds"] == ro["rounds"]
         if r["rc"] == 0:
-            assert np.array_equal(r["x"], ro["x"]) and r["ub"] == ro["ub"]
+            # the point is integer work (bit-exact); c^T x is an FP64 sum in a
+            # different order on the device
+            assert np.array_equal(r["x"], ro["x"])
+            assert abs(r["ub"] - ro["ub"]) <= 1e-12 * max(1.0, abs(ro["ub"]))
             assert brute.check_rows(ilp, r["x"]) == 0
         # the dual state is untouched by rounding
         assert np.array_equal(s.get_state()[0], o.get()[0])
