@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-KERNEL_SRC = os.path.join(ROOT, "paper_2111_10270_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2111_10270_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_mrf256x256L8_traffic.txt")
 
 
@@ -43,7 +43,12 @@ def parse():
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """fingerprint of the kernel sources the counter summary was taken on"""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
