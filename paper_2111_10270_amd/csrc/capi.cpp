@@ -32,7 +32,7 @@ constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 K
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t lam, mm, abar, lam_bak, mm_bak, abar_bak, mmx, avg;
+    size_t lam, mm, lam_bak, mm_bak, mmx, avg;
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
     size_t lbpart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
@@ -102,10 +102,8 @@ Layout make_layout(const bddmma_solver &s)
     };
     L.lam = take(S * e);
     L.mm = take(S * e);
-    L.abar = take(S * e);
     L.lam_bak = take(S * e);
     L.mm_bak = take(S * e);
-    L.abar_bak = take(S * e);
     L.mmx = take(S * e);
     L.avg = take((V + 1) * e);
     L.pair_var = take(S * 4);
@@ -180,28 +178,22 @@ Omega<T> weights(const bddmma_solver *s)
     return Omega<T>{(T)s->opt.omega, (T)(s->opt.omega / 2.0)};
 }
 
-// averaging of the variables not averaged in-tile
-template <typename T>
-void average(bddmma_solver *s)
-{
-    launch_average<T>(s->dp, s->ptr<T>(s->L.mm), s->ptr<T>(s->L.abar), s->opt.omega, s->st);
-}
-
-// one sweep plus averaging; with record_lb the sweep's per-tile bound partials
-// go to row (sweeps % hist_chunk) of the partial history
+// One Alg. 1 sweep with its deferred averaging.  Between sweeps mm holds the
+// last sweep's M at every slot (what the termination step, the bounds and the
+// state export read); the averaging of the variables not averaged in-tile
+// therefore runs right before the sweep that consumes it and stores the
+// averaged terms in place of their M.  With record_lb the sweep's per-tile
+// bound partials go to row (sweeps % hist_chunk) of the partial history.
 template <typename T>
 void one_sweep(bddmma_solver *s, int dir, bool record_lb)
 {
     const DevProblem &p = s->dp;
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *abar = s->ptr<T>(s->L.abar);
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
     double *tile_lb =
         record_lb ? s->ptr<double>(s->L.lbpart) + (size_t)(s->sweeps % s->hist_chunk) * s->pk.tiles.size() : nullptr;
-    {
-        Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD,
-                 record_lb && (s->sweeps / 2) % s->prof_stride == 0);
-        launch_sweep<T>(p, lam, mm, abar, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
-    }
-    average<T>(s);
+    launch_average<T>(p, mm, s->opt.omega, s->st);
+    Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD, record_lb && (s->sweeps / 2) % s->prof_stride == 0);
+    launch_sweep<T>(p, lam, mm, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
 }
 
 // reduce the pending sweeps' partials to bounds and copy them to the host
@@ -325,9 +317,6 @@ int set_state_T(bddmma_solver *s, const double *lam, const double *mm)
     int rc;
     if (lam && (rc = upload_pairs<T>(s, s->L.lam, lam))) return rc;
     if (mm && (rc = upload_pairs<T>(s, s->L.mm, mm))) return rc;
-    average<T>(s);   // averaged terms follow from M-bar
-    if ((rc = check_launch())) return rc;
-    HIPCHK(hipStreamSynchronize(s->st));
     return BDDMMA_OK;
 }
 
@@ -350,7 +339,7 @@ template <typename T>
 int min_marginals_T(bddmma_solver *s, double *out)
 {
     T *lam = s->ptr<T>(s->L.lam), *mmx = s->ptr<T>(s->L.mmx);
-    launch_sweep<T>(s->dp, lam, mmx, s->ptr<T>(s->L.abar), nullptr, weights<T>(s), 0, MODE_FIXED, s->st);
+    launch_sweep<T>(s->dp, lam, mmx, nullptr, weights<T>(s), 0, MODE_FIXED, s->st);
     int rc = check_launch();
     if (rc) return rc;
     std::vector<double> v;
@@ -365,18 +354,17 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
 {
     const DevProblem &p = s->dp;
     const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars;
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm), *abar = s->ptr<T>(s->L.abar);
-    T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak), *abar_b = s->ptr<T>(s->L.abar_bak);
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak);
     uint8_t *flag = s->ptr<uint8_t>(s->L.flag), *xd = s->ptr<uint8_t>(s->L.x);
     int32_t *counter = s->ptr<int32_t>(s->L.counter);
     const T omega = (T)s->opt.omega;
     const Omega<T> w = weights<T>(s);
     launch_copy<T>(lam_b, lam, S, s->st);
     launch_copy<T>(mm_b, mm, S, s->st);
-    launch_copy<T>(abar_b, abar, S, s->st);
     launch_fill<uint8_t>(flag, 0, V, s->st);
     launch_terminate<T>(p, lam, mm, omega, s->st);
-    launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
+    launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
 
     double delta = s->opt.delta0;
     int rc = BDDMMA_ERR_NOT_CONVERGED, round;
@@ -407,17 +395,15 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
         delta = delta * s->opt.alpha;
         // Alg. 1 restarts with M-bar = 0
         launch_fill<T>(mm, T(0), S, s->st);
-        launch_fill<T>(abar, T(0), S, s->st);
         for (int t = 0; t < s->opt.reopt_iters; ++t) {
             one_sweep<T>(s, 0, false);
             one_sweep<T>(s, 1, false);
         }
         launch_terminate<T>(p, lam, mm, omega, s->st);
-        launch_sweep<T>(p, lam, mm, abar, nullptr, w, 0, MODE_FIXED, s->st);
+        launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
     }
     launch_copy<T>(lam, lam_b, S, s->st);
     launch_copy<T>(mm, mm_b, S, s->st);
-    launch_copy<T>(abar, abar_b, S, s->st);
     int e = check_launch();
     if (e) return e;
     HIPCHK(hipStreamSynchronize(s->st));
@@ -651,8 +637,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     d.n_slots = pk.n_slots;
     d.scratch = s->dev + L.scratch;
     d.lds_lane_elems = pk.max_lds_lane_elems;
-    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.abar), s->st);
-    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.abar), s->st);
+    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
+    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
     launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
     launch_fill<uint8_t>(s->ptr<uint8_t>(L.x), 0, s->prob.ilp.n_vars + 1, s->st);
     int rc = check_launch();
@@ -672,8 +658,8 @@ int bddmma_reset(bddmma_solver *s)
     int rc = check_ready(s);
     if (rc) return rc;
     const Layout &L = s->L;
-    if (s->elem == 8) launch_init<double>(s->dp, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->ptr<double>(L.abar), s->st);
-    else launch_init<float>(s->dp, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->ptr<float>(L.abar), s->st);
+    if (s->elem == 8) launch_init<double>(s->dp, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
+    else launch_init<float>(s->dp, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
     rc = check_launch();
     if (rc) return rc;
     s->sweeps = 0;
@@ -865,9 +851,6 @@ int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
     p += S * s->elem;
     if (S) HIPCHK(hipMemcpyAsync(s->dev + s->L.mm, p, S * s->elem, hipMemcpyHostToDevice, s->st));
     p += S * s->elem;
-    if (s->elem == 8) average<double>(s);
-    else average<float>(s);
-    if ((rc = check_launch())) return rc;
     HIPCHK(hipStreamSynchronize(s->st));
     s->hist.assign((const double *)p, (const double *)p + h.hist);
     s->sweeps = (int64_t)h.sweeps;

@@ -38,7 +38,7 @@ template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
 
 struct TileView {
-    uint32_t pb, nb, lb, cb, K, NN;
+    uint32_t pb, nb, lb, cb, fb, K, NN;
     bool shared;
 };
 
@@ -49,6 +49,7 @@ __device__ __forceinline__ TileView load_tile(const TileDesc *td)
     v.nb = uni(td->node_base);
     v.lb = uni(td->layer_base);
     v.cb = uni(td->code_base);
+    v.fb = uni(td->fast_base);
     v.K = uni(td->K);
     v.NN = uni(td->nodes);
     v.shared = (uni(td->flags) & TILE_SHARED) != 0;
@@ -76,12 +77,12 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 
-// averaged term of slot s (layout.hpp: in-tile partner, self, or abar)
+// averaged term of slot s from its code (layout.hpp); mo = mm[s] on entry to
+// the sweep, which for slots averaged by the averaging kernel is the term itself
 template <typename T>
-__device__ __forceinline__ T averaged_term(const T *mm, const T *__restrict__ abar, uint32_t pb, uint32_t s,
-                                           uint32_t code, T mo, Omega<T> w)
+__device__ __forceinline__ T averaged_term(const T *mm, uint32_t pb, uint32_t code, T mo, Omega<T> w)
 {
-    if (code == kCodeGlobal) return abar[s];
+    if (code == kCodeGlobal) return mo;
     if (code == kCodeSelf) return w.w1 * mo;
     return w.w2 * (mo + mm[pb + code]);
 }

@@ -30,8 +30,8 @@ namespace {
 // ---------------------------------------------------------------------------
 template <typename T, int DIR, int MODE, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict__ lam, T *mm,
-                                                     const T *__restrict__ abar, double *__restrict__ tile_lb,
-                                                     Omega<T> w, const int32_t *__restrict__ list, int64_t tile_count)
+                                                     double *__restrict__ tile_lb, Omega<T> w,
+                                                     const int32_t *__restrict__ list, int64_t tile_count)
 {
     const T omega = w.w1;
     T *const mm_out = mm;   // read for the in-tile averaging before this sweep overwrites it
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u)
                 if (h0 + u < tv.K)
-                    av[u] = averaged_term(mm, abar, tv.pb, tv.pb + (h0 + u) * kLanes + lane, cv[u], mv[u], w);
+                    av[u] = averaged_term(mm, tv.pb, cv[u], mv[u], w);
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u)
                 if (h0 + u < tv.K) avS[(size_t)(h0 + u) * kLanes] = av[u];
@@ -312,14 +312,14 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_stage2(const double *__rest
 
 
 // a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, summed in ascending row order,
-// for the variables the sweep does not average in-tile; the term is stored at
-// every slot of i.  Blocks are assigned to degree buckets (layout.hpp).
+// for the variables the sweep does not average in-tile; the term replaces M_ik
+// at every slot of i (each thread owns the slots of its variable).  Blocks are
+// assigned to degree buckets (layout.hpp).
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_average(const AvgBucket *__restrict__ buckets, int nbuckets,
                                                          const int32_t *__restrict__ gslot,
                                                          const int32_t *__restrict__ vptr,
-                                                         const int32_t *__restrict__ vslot,
-                                                         const T *__restrict__ mm, T *__restrict__ abar,
+                                                         const int32_t *__restrict__ vslot, T *__restrict__ mm,
                                                          double omega)
 {
     // bucket of this block (uniform)
@@ -347,14 +347,14 @@ __global__ __launch_bounds__(kRedThreads) void k_average(const AvgBucket *__rest
                 const T av = (T)(omega / (double)bk.deg) * s;
 #pragma unroll
                 for (int k = 0; k < kEllMaxDeg; ++k)
-                    if (k < bk.deg) abar[sl[k]] = av;
+                    if (k < bk.deg) mm[sl[k]] = av;
             } else {
                 const int32_t v = gslot[bk.base + i];
                 const int32_t a = vptr[v], b = vptr[v + 1];
                 T s = T(0);
                 for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
                 const T av = (T)(omega / (double)(b - a)) * s;
-                for (int32_t q = a; q < b; ++q) abar[vslot[q]] = av;
+                for (int32_t q = a; q < b; ++q) mm[vslot[q]] = av;
             }
         }
     }
@@ -400,8 +400,7 @@ __global__ __launch_bounds__(256) void k_average_all(const int32_t *__restrict__
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam, T *__restrict__ mm,
-                                              T *__restrict__ abar)
+__global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam, T *__restrict__ mm)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.n_slots) return;
@@ -413,7 +412,6 @@ __global__ __launch_bounds__(256) void k_init(DevProblem P, T *__restrict__ lam,
     }
     lam[s] = l;
     mm[s] = T(0);
-    abar[s] = T(0);
 }
 
 template <typename T>
@@ -645,42 +643,46 @@ inline unsigned grid8(int64_t tiles, int per_block)
 }
 
 template <typename T, int DIR, int MODE>
-void launch_general(const DevProblem &p, int list_lds, int list_glob, T *lam, T *mm, const T *abar,
-                    double *tile_lb, Omega<T> w, hipStream_t st)
+void launch_general(const DevProblem &p, int list_lds, int list_glob, T *lam, T *mm, double *tile_lb, Omega<T> w,
+                    hipStream_t st)
 {
     const int64_t nl = p.list_off[list_lds + 1] - p.list_off[list_lds];
     const int64_t ng = p.list_off[list_glob + 1] - p.list_off[list_glob];
     if (nl > 0) {
         const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
         hipLaunchKernelGGL((k_sweep<T, DIR, MODE, true>), dim3(grid8(nl, kWavesPerBlock)), dim3(kThreads), lds, st, p,
-                           lam, mm, abar, tile_lb, w, p.lists + p.list_off[list_lds], nl);
+                           lam, mm, tile_lb, w, p.lists + p.list_off[list_lds], nl);
     }
     if (ng > 0)
         hipLaunchKernelGGL((k_sweep<T, DIR, MODE, false>), dim3(grid8(ng, kWavesPerBlock)), dim3(kThreads), 0, st, p,
-                           lam, mm, abar, tile_lb, w, p.lists + p.list_off[list_glob], ng);
+                           lam, mm, tile_lb, w, p.lists + p.list_off[list_glob], ng);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int dir, int mode,
-                  hipStream_t st)
+void launch_sweep(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w, int dir, int mode, hipStream_t st)
 {
-    const int update = mode == MODE_UPDATE;
-    if (dir == 0) {
-        launch_reg<T, 0, 2>(p, 0, lam, mm, abar, tile_lb, w, update, st);
-        launch_reg<T, 0, 4>(p, 1, lam, mm, abar, tile_lb, w, update, st);
-        if (update)
-            launch_general<T, 0, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
-        else
-            launch_general<T, 0, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
+    if (mode == MODE_UPDATE) {
+        if (dir == 0) {
+            launch_reg<T, 0, 2, true>(p, 0, lam, mm, tile_lb, w, st);
+            launch_reg<T, 0, 4, true>(p, 1, lam, mm, tile_lb, w, st);
+            launch_general<T, 0, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, tile_lb, w, st);
+        } else {
+            launch_reg<T, 1, 2, true>(p, 0, lam, mm, tile_lb, w, st);
+            launch_reg<T, 1, 4, true>(p, 1, lam, mm, tile_lb, w, st);
+            launch_general<T, 1, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, tile_lb, w, st);
+        }
     } else {
-        launch_reg<T, 1, 2>(p, 0, lam, mm, abar, tile_lb, w, update, st);
-        launch_reg<T, 1, 4>(p, 1, lam, mm, abar, tile_lb, w, update, st);
-        if (update)
-            launch_general<T, 1, MODE_UPDATE>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
-        else
-            launch_general<T, 1, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, abar, tile_lb, w, st);
+        if (dir == 0) {
+            launch_reg<T, 0, 2, false>(p, 0, lam, mm, nullptr, w, st);
+            launch_reg<T, 0, 4, false>(p, 1, lam, mm, nullptr, w, st);
+            launch_general<T, 0, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, nullptr, w, st);
+        } else {
+            launch_reg<T, 1, 2, false>(p, 0, lam, mm, nullptr, w, st);
+            launch_reg<T, 1, 4, false>(p, 1, lam, mm, nullptr, w, st);
+            launch_general<T, 1, MODE_FIXED>(p, LIST_GEN_LDS_REST, LIST_GEN_GLOB_REST, lam, mm, nullptr, w, st);
+        }
     }
 }
 
@@ -700,11 +702,11 @@ void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, d
 }
 
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, hipStream_t st)
+void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st)
 {
     if (p.gblocks == 0) return;
     hipLaunchKernelGGL((k_average<T>), dim3((unsigned)p.gblocks), dim3(kRedThreads), 0, st, p.gbuckets, p.n_gbuckets,
-                       p.gslot, p.vptr, p.vslot, mm, abar, omega);
+                       p.gslot, p.vptr, p.vslot, mm, omega);
 }
 
 void launch_lb_many(const double *part, int64_t n_tiles, int64_t chunk, int64_t first, int64_t n, double offset,
@@ -731,10 +733,10 @@ void launch_reduce_sum(const double *part, int64_t n, double offset, double *scr
 }
 
 template <typename T>
-void launch_init(const DevProblem &p, T *lam, T *mm, T *abar, hipStream_t st)
+void launch_init(const DevProblem &p, T *lam, T *mm, hipStream_t st)
 {
     if (p.n_slots > 0)
-        hipLaunchKernelGGL((k_init<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p, lam, mm, abar);
+        hipLaunchKernelGGL((k_init<T>), dim3(blocks_for(p.n_slots, 256)), dim3(256), 0, st, p, lam, mm);
 }
 
 template <typename T>
@@ -825,11 +827,11 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
 }
 
 #define BDDMMA_INSTANTIATE(T)                                                                                        \
-    template void launch_sweep<T>(const DevProblem &, T *, T *, const T *, double *, Omega<T>, int, int, hipStream_t); \
+    template void launch_sweep<T>(const DevProblem &, T *, T *, double *, Omega<T>, int, int, hipStream_t);         \
     template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
-    template void launch_average<T>(const DevProblem &, const T *, T *, double, hipStream_t);                       \
+    template void launch_average<T>(const DevProblem &, T *, double, hipStream_t);                                  \
     template void launch_average_all<T>(const DevProblem &, const T *, T *, double, hipStream_t);                   \
-    template void launch_init<T>(const DevProblem &, T *, T *, T *, hipStream_t);                                   \
+    template void launch_init<T>(const DevProblem &, T *, T *, hipStream_t);                                        \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \
     template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
     template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *,            \

@@ -43,24 +43,23 @@ struct Omega {
 };
 
 // One sweep over every tile.  dir 0 = ascending variables (Alg. 3), 1 =
-// descending (Alg. 4).  mm holds the previous sweep's M on entry (read for the
-// in-tile averaging) and this sweep's M on exit; abar holds the averaged term
-// of slots averaged by the averaging kernel.  With tile_lb != nullptr each tile
-// writes sum_lanes E^j + omega * sum min(M, 0).  MODE_FIXED writes M to mm
-// without touching lam and ignores abar.
+// descending (Alg. 4).  MODE_UPDATE: on entry mm holds the previous sweep's M
+// (read for the in-tile averaging), except at the slots of variables averaged
+// by the averaging kernel, which hold their averaged term (launch_average runs
+// right before); on exit mm holds this sweep's M everywhere.  With tile_lb !=
+// nullptr each tile writes sum_lanes E^j + omega * sum min(M, 0).  MODE_FIXED
+// writes M to mm without reading it or touching lam.
 template <typename T>
-void launch_sweep(const DevProblem &p, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int dir,
-                  int mode, hipStream_t st);
+void launch_sweep(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w, int dir, int mode, hipStream_t st);
 
 // register-resident sweeps of the fast-path tiles of width class wi
-template <typename T, int DIR, int W>
-void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w, int update,
-                hipStream_t st);
+template <typename T, int DIR, int W, bool UPD>
+void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st);
 
 // a_i = omega/|J_i| * sum_k M_ik (ascending row order) for the variables the
-// sweep does not average itself, stored into abar at every slot of i.
+// sweep does not average itself; the term replaces M_ik at every slot of i.
 template <typename T>
-void launch_average(const DevProblem &p, const T *mm, T *abar, double omega, hipStream_t st);
+void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st);
 
 // bounds of sweeps first .. first+n-1 from their per-tile partials (row
 // (sweep % chunk) of part, n_tiles each): out[sweep % cap] = offset + sum
@@ -74,9 +73,9 @@ void launch_average_all(const DevProblem &p, const T *mm, T *avg, double omega, 
 // out[0] = offset + sum_t part[t] in a fixed order; scratch holds kRedBlocks doubles
 void launch_reduce_sum(const double *part, int64_t n, double offset, double *scratch, double *out, hipStream_t st);
 
-// lambda = c_i / |J_i|, M-bar = 0, averaged terms 0
+// lambda = c_i / |J_i|, M-bar = 0
 template <typename T>
-void launch_init(const DevProblem &p, T *lam, T *mm, T *abar, hipStream_t st);
+void launch_init(const DevProblem &p, T *lam, T *mm, hipStream_t st);
 
 // lam += omega * mm on every slot
 template <typename T>

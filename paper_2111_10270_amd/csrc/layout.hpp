@@ -38,7 +38,7 @@ struct TileDesc {
     uint16_t flags;
     uint16_t pad0;
     uint32_t code_base;     // first averaging code of the tile (tiles with equal codes share them)
-    uint32_t pad1;
+    uint32_t fast_base;     // fast-path tiles: first word of the register kernel's copy of the node words
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc is 32 bytes");
 
@@ -49,13 +49,22 @@ inline uint32_t layer_entry(uint32_t noff, uint32_t width) { return noff | (widt
 inline uint32_t lane_elems(uint32_t K, uint32_t nodes) { return 2u * K + 2u * nodes; }
 
 // Register-resident fast path: shared tiles (one topology) with at most
-// kKClass[last] layers and layers at most kWClass[last] wide use a fixed layer stride (node (h, q) at
-// h * W + q, unused nodes have both arcs into the rejecting terminal) and are
-// swept by kernels unrolled for a compile-time layer bound KMAX and width W.
-constexpr int kNumKClasses = 6;
-constexpr int kKClass[kNumKClasses] = {4, 8, 12, 16, 24, 32};
+// kKClass[last] layers and layers at most kWClass[last] wide use a fixed layer
+// stride (node (h, q) at h * W + q, unused nodes have both arcs into the
+// rejecting terminal) and are swept by kernels unrolled for a compile-time
+// layer count KMAX and width W: a fast tile has exactly kKClass[ki] layers
+// (shorter BDDs are padded with neutral chain layers, as in mixed tiles), so
+// the kernels run without per-layer guards.  Their register kernel reads a second copy of
+// the node words at fast_base in which the last layer's arcs into the
+// accepting terminal point at node 0 of a virtual layer K (the terminal
+// layer: node 0 = accept at distance 0), so every layer is handled alike.
+constexpr int kNumKClasses = 20;
+constexpr int kKClass[kNumKClasses] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 28, 32};
 constexpr int kNumWClasses = 2;
 constexpr int kWClass[kNumWClasses] = {2, 4};
+// width-4 tiles deeper than 16 layers would need more than 170 VGPRs per lane
+// (one wave per SIMD); they stay on the general kernels
+constexpr bool fast_class_ok(int wi, int ki) { return kWClass[wi] * kKClass[ki] <= 64; }
 
 // Tile lists.  Every tile is in exactly one of the two *_ALL lists (shortest
 // paths in LDS or in device scratch for the general kernels); tiles outside the

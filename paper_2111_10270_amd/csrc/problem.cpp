@@ -429,33 +429,57 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         for (int wi = 0; fast && tp.shared && wi < kNumWClasses && tp.wi < 0; ++wi)
             if (maxw <= kWClass[wi])
                 for (int ki = 0; ki < kNumKClasses; ++ki)
-                    if (K <= kKClass[ki]) {
+                    if (K <= kKClass[ki] && fast_class_ok(wi, ki)) {
                         tp.wi = wi;
                         tp.ki = ki;
                         break;
                     }
-        if (tp.wi >= 0) tp.width.assign(K, kWClass[tp.wi]);   // fixed layer stride
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
     }
-    // Fewer launches: inside a width class, tiles of the smaller layer classes
-    // run in the kernel of the largest class when they are a minority (< 1/4
-    // of the class's tiles); the kernel takes the true layer count at run time.
+    // Fewer launches: inside a width class, the tiles of a layer class join
+    // the next larger class present (padded to its layer count) while the
+    // padding moves fewer bytes per sweep than a separate launch costs (a
+    // small launch runs for about one wave lifetime at low occupancy).
+    constexpr double kMergeBytes = 32.0 * (1 << 20);   // ~7 us of HBM traffic
+    constexpr double kSlotBytes = 16.0;                // lambda and M read + written (FP32)
     for (int wi = 0; wi < kNumWClasses; ++wi) {
         int64_t cnt[kNumKClasses] = {0};
         for (auto &tp : plans)
             if (tp.wi == wi) cnt[tp.ki]++;
-        int top = -1;
-        int64_t total = 0;
-        for (int ki = 0; ki < kNumKClasses; ++ki) {
-            total += cnt[ki];
-            if (cnt[ki]) top = ki;
+        int into[kNumKClasses];
+        for (int ki = 0; ki < kNumKClasses; ++ki) into[ki] = ki;
+        for (;;) {
+            int best = -1, best_to = -1;
+            double best_cost = kMergeBytes;
+            for (int ki = 0; ki < kNumKClasses; ++ki) {
+                if (!cnt[ki]) continue;
+                int kj = ki + 1;
+                while (kj < kNumKClasses && !cnt[kj]) ++kj;
+                if (kj == kNumKClasses) break;
+                const double cost = (double)cnt[ki] * (kKClass[kj] - kKClass[ki]) * kLanes * kSlotBytes;
+                if (cost <= best_cost) {
+                    best_cost = cost;
+                    best = ki;
+                    best_to = kj;
+                }
+            }
+            if (best < 0) break;
+            cnt[best_to] += cnt[best];
+            cnt[best] = 0;
+            for (int ki = 0; ki < kNumKClasses; ++ki)
+                if (into[ki] == best) into[ki] = best_to;
         }
-        if (top < 0 || 4 * (total - cnt[top]) >= total) continue;
         for (auto &tp : plans)
-            if (tp.wi == wi) tp.ki = top;
+            if (tp.wi == wi) tp.ki = into[tp.ki];
     }
+    // fast tiles: exactly the class's layer count, fixed layer stride
+    for (auto &tp : plans)
+        if (tp.wi >= 0) {
+            tp.K = kKClass[tp.ki];
+            tp.width.assign(tp.K, kWClass[tp.wi]);
+        }
     auto tile_nodes = [](const TilePlan &tp) {
         int64_t n = 0;
         for (int w : tp.width) n += w;
@@ -547,13 +571,29 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             if (found >= 0) {
                 d.node_base = (uint32_t)found;
             } else {
-                o.child.resize(base + (size_t)nodes, kBot | (kBot << 16));
+                // fast tiles: the standard words, then the register kernel's
+                // copy whose last layer points accepting arcs at node 0
+                const size_t copies = tp.wi >= 0 ? 2 : 1;
+                o.child.resize(base + copies * (size_t)nodes, kBot | (kBot << 16));
                 place(rep, noff, tp.K, base, 1, 0);
+                if (tp.wi >= 0)
+                    for (int64_t n = 0; n < nodes; ++n) {
+                        uint32_t w = o.child[base + (size_t)n];
+                        if ((int64_t)noff[tp.K - 1] <= n) {
+                            uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+                            if (lo == kTop) lo = 0;
+                            if (hi == kTop) hi = 0;
+                            w = lo | (hi << 16);
+                        }
+                        o.child[base + (size_t)nodes + (size_t)n] = w;
+                    }
                 topo_base.emplace(hash[rep], std::make_pair(std::make_pair(rep, (int64_t)base), (int)tp.wi));
             }
+            d.fast_base = tp.wi >= 0 ? d.node_base + (uint32_t)nodes : d.node_base;
         } else {
             o.child.resize(base + (size_t)nodes * kLanes, kBot | (kBot << 16));
             for (int l = 0; l < kLanes; ++l) place(tp.lanes[l], noff, tp.K, base, kLanes, l);
+            d.fast_base = d.node_base;
         }
         o.tiles.push_back(d);
         slots += (int64_t)tp.K * kLanes;
@@ -590,6 +630,36 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                     }
                 }
         }
+    }
+    // the register kernel's copy: fixed stride W, heads below W, node 0 of the
+    // virtual terminal layer only from the last layer; layer count = class
+    for (int wi = 0; wi < kNumWClasses; ++wi)
+        for (int ki = 0; ki < kNumKClasses; ++ki) {
+            const auto &ls = lists[fast_list(wi, ki)];
+            for (int32_t t : ls)
+                if (o.tiles[t].K != kKClass[ki] || (o.layers[o.tiles[t].layer_base] >> 16) != (uint32_t)kWClass[wi] ||
+                    o.tiles[t].fast_base == o.tiles[t].node_base) {
+                    msg = "internal error: fast-path tile does not match its kernel class";
+                    return ST_INVALID;
+                }
+        }
+    for (size_t t = 0; t < o.tiles.size(); ++t) {
+        const TileDesc &d = o.tiles[t];
+        if (d.fast_base == d.node_base) continue;
+        const uint32_t W = o.layers[d.layer_base] >> 16;
+        if (!(d.flags & TILE_SHARED) || (uint64_t)d.fast_base + (uint64_t)d.K * W > o.child.size()) {
+            msg = "internal error: inconsistent fast-path words";
+            return ST_INVALID;
+        }
+        for (uint32_t h = 0; h < d.K; ++h)
+            for (uint32_t q = 0; q < W; ++q) {
+                const uint32_t w = o.child[d.fast_base + h * W + q];
+                for (uint32_t c : {w & 0xFFFFu, w >> 16})
+                    if (!(c == kBot || (h + 1 < d.K ? c < W : c == 0))) {
+                        msg = "internal error: fast-path arc out of range";
+                        return ST_INVALID;
+                    }
+            }
     }
     o.n_slots = slots;
     o.scratch_elems = scratch;
@@ -683,7 +753,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         int64_t found = -1;
         auto range = code_seen.equal_range(h);
         for (auto it = range.first; it != range.second; ++it)
-            if (std::equal(blk, blk + n, o.code.begin() + it->second) && it->second + n <= o.code.size()) {
+            if (it->second + n <= o.code.size() && std::equal(blk, blk + n, o.code.begin() + it->second)) {
                 found = it->second;
                 break;
             }

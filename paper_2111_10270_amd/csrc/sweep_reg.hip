@@ -1,7 +1,10 @@
 // Register-resident sweep kernels of the fast path.  This file is compiled
-// once per (precision, direction) pair, selected by BDDMMA_REG_T and
-// BDDMMA_REG_DIR, so the heavily unrolled instantiations build in parallel.
+// once per (precision, direction, update) triple, selected by BDDMMA_REG_T,
+// BDDMMA_REG_DIR and BDDMMA_REG_UPD, so the heavily unrolled instantiations
+// build in parallel.
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -12,6 +15,9 @@
 #ifndef BDDMMA_REG_DIR
 #define BDDMMA_REG_DIR 0
 #endif
+#ifndef BDDMMA_REG_UPD
+#define BDDMMA_REG_UPD true
+#endif
 
 namespace bddmma {
 
@@ -19,15 +25,13 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Register-resident sweep for tiles of the fast path (64 BDDs of one topology,
-// fixed layer stride W, at most KMAX layers).  The node words are uniform
-// across the wave, so every arc test is a scalar branch.  The layer loop is unrolled to KMAX with a uniform
-// guard h < K, so every per-lane array below lives in VGPRs: the multipliers
-// and averaged terms of all layers, the node words, and the opposite
-// direction's distances.  All loads are issued before the first use.  The
-// arithmetic is the same as in k_sweep (same operations, same order).
+// fixed layer stride W, exactly KMAX layers).  The layer loops are unrolled,
+// so every per-lane array below lives in VGPRs: the multipliers and averaged terms of all layers and the opposite
+// direction's distances.  The node words are uniform across the wave and live
+// in SGPRs; each arc test becomes a scalar penalty (see pen).  All loads are
+// issued before the first use.  The arithmetic is the same as in k_sweep
+// (same operations, same order).
 // ---------------------------------------------------------------------------
-// v[c] for c < W, as a tree of selects on the bits of c (no indexed access,
-// so the arrays stay in registers)
 // Uniform arc penalty: 0 when the arc's head is `target`, +inf otherwise.
 // Adding it to a value and taking a min routes the value along the arc with
 // one v_add and one v_min, without branches or per-lane selects.
@@ -49,7 +53,7 @@ __device__ __forceinline__ double pen<double>(uint32_t head, uint32_t target)
 }
 
 // min over next-layer nodes t of nx[t] + pen(head, t): the value at the arc's
-// head for an arc that stays inside the BDD (heads of layers before the last)
+// head (after the last layer, nx is the terminal layer {0, inf, ...})
 template <int W, typename T>
 __device__ __forceinline__ T head_inner(uint32_t head, const T (&nx)[W])
 {
@@ -59,21 +63,15 @@ __device__ __forceinline__ T head_inner(uint32_t head, const T (&nx)[W])
     return r;
 }
 
-// value at the head of an arc of the last layer: 0 at the accepting terminal
-template <typename T>
-__device__ __forceinline__ T head_last(uint32_t head)
-{
-    return pen<T>(head, kTop);
-}
-
-// update == false: min-marginal differences at fixed multipliers (Alg. 2),
-// written to mm, which is then output only.
-template <typename T, int DIR, int W, int KMAX>
-__global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam, T *mm,
-                                                                   const T *__restrict__ abar,
-                                                                   double *__restrict__ tile_lb, Omega<T> w,
-                                                                   const int32_t *__restrict__ list,
-                                                                   int64_t tile_count, int update)
+// UPD = false: min-marginal differences at fixed multipliers (Alg. 2),
+// written to mm, which is then output only.  With UPD the slots averaged by
+// the averaging kernel hold their averaged term in mm on entry (stored there
+// just before this sweep); every other slot holds its previous M.
+template <typename T, int DIR, int W, int KMAX, bool UPD>
+__global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam,
+                                                                   T *__restrict__ mm, double *__restrict__ tile_lb,
+                                                                   Omega<T> w, const int32_t *__restrict__ list,
+                                                                   int64_t tile_count)
 {
     const T omega = w.w1;
     const int lane = threadIdx.x & (kLanes - 1);
@@ -81,8 +79,14 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
     if (lt >= tile_count) return;
     const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
     const TileView tv = load_tile(P.tiles + tile);
-    const int K = (int)tv.K;
+    constexpr int K = KMAX;   // fast tiles have exactly their class's layer count
     const T INF = inf_of<T>();
+    // 64-bit bases: every per-layer access below is base + constant offset
+    T *const lrow = lam + tv.pb + lane;
+    T *const mtile = mm + tv.pb;
+    T *const mrow = mtile + lane;
+    const uint16_t *const crow = P.code + tv.cb + lane;
+    const uint32_t *const wrow = P.child + tv.fb;
 
     // prologue: every load is issued before the first use
     T l[KMAX], a[KMAX], mo[KMAX];
@@ -100,20 +104,29 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
     for (int h = 0; h < KMAX; ++h) {
         if (h < K) {
-            const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
-            l[h] = lam[s];
-            if (update) {
-                mo[h] = mm[s];
-                cd[h] = P.code[tv.cb + (uint32_t)h * kLanes + lane];
+            l[h] = lrow[h * kLanes];
+            if (UPD) {
+                mo[h] = mrow[h * kLanes];
+                cd[h] = crow[h * kLanes];
             }
 #pragma unroll
-            for (int q = 0; q < W; ++q) wd[h][q] = uni(P.child[tv.nb + (uint32_t)(h * W + q)]);
+            for (int q = 0; q < W; ++q) wd[h][q] = uni(wrow[h * W + q]);
         }
     }
-    if (update) {
+    if (UPD) {
+        // a = c * (M + x) with one load and no branch: an in-tile partner
+        // gives c = w2, x = M_partner; a variable of this BDD only gives
+        // c = w2, x = M (w2 * 2M = w1 * M exactly, w2 = w1 / 2); a slot
+        // averaged by the averaging kernel holds its term t in mm and gives
+        // c = 1/2, x = t (t exactly)
 #pragma unroll
-        for (int h = 0; h < KMAX; ++h)
-            if (h < K) a[h] = averaged_term(mm, abar, tv.pb, tv.pb + (uint32_t)h * kLanes + lane, cd[h], mo[h], w);
+        for (int h = 0; h < KMAX; ++h) {
+            if (h < K) {
+                const uint32_t off = cd[h] < kCodeSelf ? cd[h] : (uint32_t)(h * kLanes + lane);
+                const T c = cd[h] == kCodeGlobal ? T(0.5) : w.w2;
+                a[h] = c * (mo[h] + mtile[off]);
+            }
+        }
     }
 
     double lbacc = 0.0;
@@ -124,7 +137,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
         T hd0[KMAX][W], hd1[KMAX][W];
         T nx[W];
 #pragma unroll
-        for (int q = 0; q < W; ++q) nx[q] = INF;
+        for (int q = 0; q < W; ++q) nx[q] = q == 0 ? T(0) : INF;   // terminal layer
 #pragma unroll
         for (int h = KMAX - 1; h >= 0; --h) {
 #pragma unroll
@@ -137,8 +150,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    const T v0 = (h == K - 1) ? head_last<T>(lo) : head_inner<W>(lo, nx);
-                    const T v1 = (h == K - 1) ? head_last<T>(hi) : head_inner<W>(hi, nx);
+                    const T v0 = head_inner<W>(lo, nx);
+                    const T v1 = head_inner<W>(hi, nx);
                     hd0[h][q] = v0;
                     hd1[h][q] = v1;
                     b[q] = fmin(v0, v1 + l[h]);
@@ -151,7 +164,6 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
         T f[W];
 #pragma unroll
         for (int q = 0; q < W; ++q) f[q] = q == 0 ? T(0) : INF;
-        T top = INF;
 #pragma unroll
         for (int h = 0; h < KMAX; ++h) {
             if (h < K) {
@@ -163,35 +175,28 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     m1 = fmin(m1, (f[q] + l[h]) + hd1[h][q]);
                 }
                 const T M = m1 - m0;
-                const T lu = update ? (l[h] - omega * M) + a[h] : l[h];
-                const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
-                mm[s] = M;
-                if (update) lam[s] = lu;
-                lbacc += (double)fmin(M, T(0));
-                if (h == K - 1) {
-#pragma unroll
-                    for (int q = 0; q < W; ++q) {
-                        const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                        top = fmin(top, fmin(f[q] + head_last<T>(lo), (f[q] + lu) + head_last<T>(hi)));
-                    }
-                } else {
-                    T fn[W];
-#pragma unroll
-                    for (int t = 0; t < W; ++t) fn[t] = INF;
-#pragma unroll
-                    for (int q = 0; q < W; ++q) {
-                        const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                        const T v1 = f[q] + lu;
-#pragma unroll
-                        for (int t = 0; t < W; ++t)
-                            fn[t] = fmin(fn[t], fmin(f[q] + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
-                    }
-#pragma unroll
-                    for (int t = 0; t < W; ++t) f[t] = fn[t];
+                const T lu = UPD ? (l[h] - omega * M) + a[h] : l[h];
+                mrow[h * kLanes] = M;
+                if (UPD) {
+                    lrow[h * kLanes] = lu;
+                    lbacc += (double)fmin(M, T(0));
                 }
+                T fn[W];
+#pragma unroll
+                for (int t = 0; t < W; ++t) fn[t] = INF;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
+                    const T v1 = f[q] + lu;
+#pragma unroll
+                    for (int t = 0; t < W; ++t)
+                        fn[t] = fmin(fn[t], fmin(f[q] + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
+                }
+#pragma unroll
+                for (int t = 0; t < W; ++t) f[t] = fn[t];
             }
         }
-        energy = top;
+        energy = f[0];   // node 0 of the terminal layer: accept
     } else {
         // SP(root, v) of every layer under the current multipliers
         T fw[KMAX][W];
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
         // backward sweep with updates
         T bn[W];
 #pragma unroll
-        for (int q = 0; q < W; ++q) bn[q] = INF;
+        for (int q = 0; q < W; ++q) bn[q] = q == 0 ? T(0) : INF;   // terminal layer
 #pragma unroll
         for (int h = KMAX - 1; h >= 0; --h) {
             if (h < K) {
@@ -224,8 +229,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    v0[q] = (h == K - 1) ? head_last<T>(lo) : head_inner<W>(lo, bn);
-                    v1[q] = (h == K - 1) ? head_last<T>(hi) : head_inner<W>(hi, bn);
+                    v0[q] = head_inner<W>(lo, bn);
+                    v1[q] = head_inner<W>(hi, bn);
                 }
                 T m0 = fw[h][0] + v0[0];
                 T m1 = (fw[h][0] + l[h]) + v1[0];
@@ -235,18 +240,19 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     m1 = fmin(m1, (fw[h][q] + l[h]) + v1[q]);
                 }
                 const T M = m1 - m0;
-                const T lu = update ? (l[h] - omega * M) + a[h] : l[h];
-                const uint32_t s = tv.pb + (uint32_t)h * kLanes + lane;
-                mm[s] = M;
-                if (update) lam[s] = lu;
-                lbacc += (double)fmin(M, T(0));
+                const T lu = UPD ? (l[h] - omega * M) + a[h] : l[h];
+                mrow[h * kLanes] = M;
+                if (UPD) {
+                    lrow[h * kLanes] = lu;
+                    lbacc += (double)fmin(M, T(0));
+                }
 #pragma unroll
                 for (int q = 0; q < W; ++q) bn[q] = fmin(v0[q], v1[q] + lu);
             }
         }
         energy = bn[0];
     }
-    if (tile_lb) {
+    if (UPD && tile_lb) {
         const double e = wave_sum<T>((double)energy + (double)omega * lbacc);
         if (lane == 0) tile_lb[tile] = e;
     }
@@ -257,34 +263,38 @@ inline unsigned grid8(int64_t tiles, int per_block)
     return (unsigned)((((tiles + per_block - 1) / per_block) + 7) & ~int64_t(7));
 }
 
-}  // namespace
-
-template <typename T, int DIR, int W>
-void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, const T *abar, double *tile_lb, Omega<T> w,
-                int update, hipStream_t st)
+template <typename T, int DIR, int W, bool UPD, int KI>
+void launch_class(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st)
 {
-#define BDDMMA_REG(KI, KM)                                                                                         \
-    {                                                                                                              \
-        const int l = fast_list(wi, KI);                                                                           \
-        const int64_t n = p.list_off[l + 1] - p.list_off[l];                                                       \
-        if (n > 0)                                                                                                 \
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, KM>), dim3(grid8(n, kRegWaves)), dim3(kRegWaves * kLanes), \
-                               0, st, p, lam, mm, abar, tile_lb, w, p.lists + p.list_off[l], n, update);           \
+    if constexpr (fast_class_ok(W == 2 ? 0 : 1, KI)) {
+        const int l = fast_list(wi, KI);
+        const int64_t n = p.list_off[l + 1] - p.list_off[l];
+        if (n > 0)
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD>), dim3(grid8(n, kRegWaves)),
+                               dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
     }
-    BDDMMA_REG(0, 4)
-    BDDMMA_REG(1, 8)
-    BDDMMA_REG(2, 12)
-    BDDMMA_REG(3, 16)
-    BDDMMA_REG(4, 24)
-    BDDMMA_REG(5, 32)
-#undef BDDMMA_REG
 }
 
-template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 2>(const DevProblem &, int, BDDMMA_REG_T *, BDDMMA_REG_T *,
-                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>, int,
-                                                           hipStream_t);
-template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 4>(const DevProblem &, int, BDDMMA_REG_T *, BDDMMA_REG_T *,
-                                                           const BDDMMA_REG_T *, double *, Omega<BDDMMA_REG_T>, int,
-                                                           hipStream_t);
+template <typename T, int DIR, int W, bool UPD, int... KI>
+void launch_classes(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st,
+                    std::integer_sequence<int, KI...>)
+{
+    (launch_class<T, DIR, W, UPD, KI>(p, wi, lam, mm, tile_lb, w, st), ...);
+}
+
+}  // namespace
+
+template <typename T, int DIR, int W, bool UPD>
+void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st)
+{
+    launch_classes<T, DIR, W, UPD>(p, wi, lam, mm, tile_lb, w, st, std::make_integer_sequence<int, kNumKClasses>{});
+}
+
+template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 2, BDDMMA_REG_UPD>(const DevProblem &, int, BDDMMA_REG_T *,
+                                                                          BDDMMA_REG_T *, double *,
+                                                                          Omega<BDDMMA_REG_T>, hipStream_t);
+template void launch_reg<BDDMMA_REG_T, BDDMMA_REG_DIR, 4, BDDMMA_REG_UPD>(const DevProblem &, int, BDDMMA_REG_T *,
+                                                                          BDDMMA_REG_T *, double *,
+                                                                          Omega<BDDMMA_REG_T>, hipStream_t);
 
 }  // namespace bddmma
