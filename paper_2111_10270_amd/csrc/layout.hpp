@@ -65,20 +65,27 @@ constexpr int kWClass[kNumWClasses] = {2, 4};
 // width-4 tiles deeper than 16 layers would need more than 170 VGPRs per lane
 // (one wave per SIMD); they stay on the general kernels
 constexpr bool fast_class_ok(int wi, int ki) { return kWClass[wi] * kKClass[ki] <= 64; }
+// Mixed tiles (lanes of different topologies) of width <= 2 and at most 20
+// layers run on the register kernel too, with per-lane node words in VGPRs
+// (same fixed stride and layer classes, words at fast_base + node * 64 + lane).
+constexpr bool mix_class_ok(int ki) { return kKClass[ki] <= 20; }
 
 // Tile lists.  Every tile is in exactly one of the two *_ALL lists (shortest
 // paths in LDS or in device scratch for the general kernels); tiles outside the
 // fast path are also in the matching *_REST list; fast tiles are in the list of
-// their (width class, layer class).
+// their (width class, layer class), mixed fast tiles (width 2) in that of their
+// layer class.
 enum TileList {
     LIST_GEN_LDS_ALL = 0,
     LIST_GEN_GLOB_ALL = 1,
     LIST_GEN_LDS_REST = 2,
     LIST_GEN_GLOB_REST = 3,
     LIST_FAST0 = 4,
-    kNumLists = LIST_FAST0 + kNumKClasses * kNumWClasses
+    LIST_MIX0 = LIST_FAST0 + kNumKClasses * kNumWClasses,
+    kNumLists = LIST_MIX0 + kNumKClasses
 };
 inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + ki; }
+inline int mix_list(int ki) { return LIST_MIX0 + ki; }
 
 // Where a pair slot takes the averaged term a_i = omega/|J_i| * sum_k M_ik of
 // its variable from (Alg. 1 deferred update).  Variables with |J_i| <= 2 whose

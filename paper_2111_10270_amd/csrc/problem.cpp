@@ -346,6 +346,7 @@ struct TilePlan {
     std::vector<int32_t> width;   // [K] layer widths of the tile layout
     int64_t first_row = 0;
     int wi = -1, ki = -1;         // fast-path class, -1 = general kernels only
+    bool mix = false;             // fast path with per-lane topologies
 };
 
 }  // namespace
@@ -434,6 +435,14 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                         tp.ki = ki;
                         break;
                     }
+        if (fast && !tp.shared && maxw <= kWClass[0])
+            for (int ki = 0; ki < kNumKClasses; ++ki)
+                if (K <= kKClass[ki] && mix_class_ok(ki)) {
+                    tp.wi = 0;
+                    tp.ki = ki;
+                    tp.mix = true;
+                    break;
+                }
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
@@ -444,10 +453,14 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     // small launch runs for about one wave lifetime at low occupancy).
     constexpr double kMergeBytes = 32.0 * (1 << 20);   // ~7 us of HBM traffic
     constexpr double kSlotBytes = 16.0;                // lambda and M read + written (FP32)
-    for (int wi = 0; wi < kNumWClasses; ++wi) {
+    for (int g = 0; g < kNumWClasses + 1; ++g) {
+        // groups: shared tiles of each width class, then the mixed tiles
+        const int wi = g < kNumWClasses ? g : 0;
+        const bool mix = g == kNumWClasses;
+        auto in_group = [&](const TilePlan &tp) { return tp.wi == wi && tp.mix == mix; };
         int64_t cnt[kNumKClasses] = {0};
         for (auto &tp : plans)
-            if (tp.wi == wi) cnt[tp.ki]++;
+            if (in_group(tp)) cnt[tp.ki]++;
         int into[kNumKClasses];
         for (int ki = 0; ki < kNumKClasses; ++ki) into[ki] = ki;
         for (;;) {
@@ -472,7 +485,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                 if (into[ki] == best) into[ki] = best_to;
         }
         for (auto &tp : plans)
-            if (tp.wi == wi) tp.ki = into[tp.ki];
+            if (in_group(tp)) tp.ki = into[tp.ki];
     }
     // fast tiles: exactly the class's layer count, fixed layer stride
     for (auto &tp : plans)
@@ -544,7 +557,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             if (tp.wi < 0) lists[LIST_GEN_GLOB_REST].push_back(tid);
         }
         if (tp.wi >= 0) {
-            lists[fast_list(tp.wi, tp.ki)].push_back(tid);
+            lists[tp.mix ? mix_list(tp.ki) : fast_list(tp.wi, tp.ki)].push_back(tid);
             o.n_fast_tiles++;
         }
         std::vector<uint32_t> noff(tp.K + 1, 0);
@@ -591,9 +604,26 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             }
             d.fast_base = tp.wi >= 0 ? d.node_base + (uint32_t)nodes : d.node_base;
         } else {
-            o.child.resize(base + (size_t)nodes * kLanes, kBot | (kBot << 16));
+            const size_t copies = tp.wi >= 0 ? 2 : 1;
+            const size_t per = (size_t)nodes * kLanes;
+            o.child.resize(base + copies * per, kBot | (kBot << 16));
             for (int l = 0; l < kLanes; ++l) place(tp.lanes[l], noff, tp.K, base, kLanes, l);
             d.fast_base = d.node_base;
+            if (tp.wi >= 0) {
+                // the register kernel's per-lane copy (accepting arcs of the last layer -> node 0)
+                const size_t last = (size_t)noff[tp.K - 1] * kLanes;
+                for (size_t n = 0; n < per; ++n) {
+                    uint32_t w = o.child[base + n];
+                    if (n >= last) {
+                        uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+                        if (lo == kTop) lo = 0;
+                        if (hi == kTop) hi = 0;
+                        w = lo | (hi << 16);
+                    }
+                    o.child[base + per + n] = w;
+                }
+                d.fast_base = d.node_base + (uint32_t)per;
+            }
         }
         o.tiles.push_back(d);
         slots += (int64_t)tp.K * kLanes;
@@ -633,33 +663,41 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     }
     // the register kernel's copy: fixed stride W, heads below W, node 0 of the
     // virtual terminal layer only from the last layer; layer count = class
-    for (int wi = 0; wi < kNumWClasses; ++wi)
-        for (int ki = 0; ki < kNumKClasses; ++ki) {
-            const auto &ls = lists[fast_list(wi, ki)];
-            for (int32_t t : ls)
-                if (o.tiles[t].K != kKClass[ki] || (o.layers[o.tiles[t].layer_base] >> 16) != (uint32_t)kWClass[wi] ||
-                    o.tiles[t].fast_base == o.tiles[t].node_base) {
-                    msg = "internal error: fast-path tile does not match its kernel class";
-                    return ST_INVALID;
-                }
+    for (int l = LIST_FAST0; l < kNumLists; ++l) {
+        const bool mix = l >= LIST_MIX0;
+        const int wi = mix ? 0 : (l - LIST_FAST0) / kNumKClasses;
+        const int ki = mix ? l - LIST_MIX0 : (l - LIST_FAST0) % kNumKClasses;
+        for (int32_t t : lists[l]) {
+            const TileDesc &d = o.tiles[t];
+            const bool ok = d.K == kKClass[ki] && (o.layers[d.layer_base] >> 16) == (uint32_t)kWClass[wi] &&
+                            d.fast_base != d.node_base && ((d.flags & TILE_SHARED) != 0) == !mix &&
+                            (mix ? mix_class_ok(ki) : fast_class_ok(wi, ki));
+            if (!ok) {
+                msg = "internal error: fast-path tile does not match its kernel class";
+                return ST_INVALID;
+            }
         }
+    }
     for (size_t t = 0; t < o.tiles.size(); ++t) {
         const TileDesc &d = o.tiles[t];
         if (d.fast_base == d.node_base) continue;
         const uint32_t W = o.layers[d.layer_base] >> 16;
-        if (!(d.flags & TILE_SHARED) || (uint64_t)d.fast_base + (uint64_t)d.K * W > o.child.size()) {
+        const bool sh = (d.flags & TILE_SHARED) != 0;
+        const uint32_t lanes = sh ? 1 : kLanes;
+        if ((uint64_t)d.fast_base + (uint64_t)d.K * W * lanes > o.child.size()) {
             msg = "internal error: inconsistent fast-path words";
             return ST_INVALID;
         }
         for (uint32_t h = 0; h < d.K; ++h)
-            for (uint32_t q = 0; q < W; ++q) {
-                const uint32_t w = o.child[d.fast_base + h * W + q];
-                for (uint32_t c : {w & 0xFFFFu, w >> 16})
-                    if (!(c == kBot || (h + 1 < d.K ? c < W : c == 0))) {
-                        msg = "internal error: fast-path arc out of range";
-                        return ST_INVALID;
-                    }
-            }
+            for (uint32_t q = 0; q < W; ++q)
+                for (uint32_t l = 0; l < lanes; ++l) {
+                    const uint32_t w = o.child[d.fast_base + (h * W + q) * lanes + l];
+                    for (uint32_t c : {w & 0xFFFFu, w >> 16})
+                        if (!(c == kBot || (h + 1 < d.K ? c < W : c == 0))) {
+                            msg = "internal error: fast-path arc out of range";
+                            return ST_INVALID;
+                        }
+                }
     }
     o.n_slots = slots;
     o.scratch_elems = scratch;

@@ -24,11 +24,12 @@ namespace bddmma {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Register-resident sweep for tiles of the fast path (64 BDDs of one topology,
-// fixed layer stride W, exactly KMAX layers).  The layer loops are unrolled,
+// Register-resident sweep for tiles of the fast path (64 BDDs of one topology
+// if SH, else of any topologies; fixed layer stride W, exactly KMAX layers).  The layer loops are unrolled,
 // so every per-lane array below lives in VGPRs: the multipliers and averaged terms of all layers and the opposite
-// direction's distances.  The node words are uniform across the wave and live
-// in SGPRs; each arc test becomes a scalar penalty (see pen).  All loads are
+// direction's distances.  With SH the node words are uniform across the wave
+// and live in SGPRs, and each arc test becomes a scalar penalty (see pen);
+// otherwise each lane holds its own words in VGPRs and selects per lane.  All loads are
 // issued before the first use.  The arithmetic is the same as in k_sweep
 // (same operations, same order).
 // ---------------------------------------------------------------------------
@@ -63,11 +64,41 @@ __device__ __forceinline__ T head_inner(uint32_t head, const T (&nx)[W])
     return r;
 }
 
+// Per-lane topologies (mixed tiles): the value at the arc's head is selected
+// per lane; the same values as the penalty form up to the sign of a zero.
+template <int W, typename T>
+__device__ __forceinline__ T head_lane(uint32_t head, const T (&nx)[W])
+{
+    T r = inf_of<T>();
+#pragma unroll
+    for (int t = 0; t < W; ++t) r = head == (uint32_t)t ? nx[t] : r;
+    return r;
+}
+
+// value an arc pair of one node contributes to next-layer node t: v0 along
+// the 0-arc lo, v1 along the 1-arc hi
+template <bool SH, typename T>
+__device__ __forceinline__ T arc_to(uint32_t lo, uint32_t hi, uint32_t t, T v0, T v1)
+{
+    if constexpr (SH) return fmin(v0 + pen<T>(lo, t), v1 + pen<T>(hi, t));
+    else {
+        const T INF = inf_of<T>();
+        return fmin(lo == t ? v0 : INF, hi == t ? v1 : INF);
+    }
+}
+
+template <bool SH, int W, typename T>
+__device__ __forceinline__ T head_at(uint32_t head, const T (&nx)[W])
+{
+    if constexpr (SH) return head_inner<W>(head, nx);
+    else return head_lane<W>(head, nx);
+}
+
 // UPD = false: min-marginal differences at fixed multipliers (Alg. 2),
 // written to mm, which is then output only.  With UPD the slots averaged by
 // the averaging kernel hold their averaged term in mm on entry (stored there
 // just before this sweep); every other slot holds its previous M.
-template <typename T, int DIR, int W, int KMAX, bool UPD>
+template <typename T, int DIR, int W, int KMAX, bool UPD, bool SH>
 __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam,
                                                                    T *__restrict__ mm, double *__restrict__ tile_lb,
                                                                    Omega<T> w, const int32_t *__restrict__ list,
@@ -86,7 +117,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
     T *const mtile = mm + tv.pb;
     T *const mrow = mtile + lane;
     const uint16_t *const crow = P.code + tv.cb + lane;
-    const uint32_t *const wrow = P.child + tv.fb;
+    // node words: one copy per tile (SH) or one per lane at stride 64
+    const uint32_t *const wrow = P.child + tv.fb + (SH ? 0 : lane);
 
     // prologue: every load is issued before the first use
     T l[KMAX], a[KMAX], mo[KMAX];
@@ -110,7 +142,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                 cd[h] = crow[h * kLanes];
             }
 #pragma unroll
-            for (int q = 0; q < W; ++q) wd[h][q] = uni(wrow[h * W + q]);
+            for (int q = 0; q < W; ++q)
+                wd[h][q] = SH ? uni(wrow[h * W + q]) : wrow[(h * W + q) * kLanes];
         }
     }
     if (UPD) {
@@ -150,8 +183,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    const T v0 = head_inner<W>(lo, nx);
-                    const T v1 = head_inner<W>(hi, nx);
+                    const T v0 = head_at<SH, W>(lo, nx);
+                    const T v1 = head_at<SH, W>(hi, nx);
                     hd0[h][q] = v0;
                     hd1[h][q] = v1;
                     b[q] = fmin(v0, v1 + l[h]);
@@ -189,8 +222,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
                     const T v1 = f[q] + lu;
 #pragma unroll
-                    for (int t = 0; t < W; ++t)
-                        fn[t] = fmin(fn[t], fmin(f[q] + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
+                    for (int t = 0; t < W; ++t) fn[t] = fmin(fn[t], arc_to<SH>(lo, hi, (uint32_t)t, f[q], v1));
                 }
 #pragma unroll
                 for (int t = 0; t < W; ++t) f[t] = fn[t];
@@ -212,9 +244,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
                     const T v0 = fw[h][q], v1 = fw[h][q] + l[h];
 #pragma unroll
-                    for (int t = 0; t < W; ++t)
-                        fw[h + 1][t] =
-                            fmin(fw[h + 1][t], fmin(v0 + pen<T>(lo, (uint32_t)t), v1 + pen<T>(hi, (uint32_t)t)));
+                    for (int t = 0; t < W; ++t) fw[h + 1][t] = fmin(fw[h + 1][t], arc_to<SH>(lo, hi, (uint32_t)t, v0, v1));
                 }
             }
         }
@@ -229,8 +259,8 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    v0[q] = head_inner<W>(lo, bn);
-                    v1[q] = head_inner<W>(hi, bn);
+                    v0[q] = head_at<SH, W>(lo, bn);
+                    v1[q] = head_at<SH, W>(hi, bn);
                 }
                 T m0 = fw[h][0] + v0[0];
                 T m1 = (fw[h][0] + l[h]) + v1[0];
@@ -270,7 +300,14 @@ void launch_class(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, O
         const int l = fast_list(wi, KI);
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
         if (n > 0)
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD>), dim3(grid8(n, kRegWaves)),
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, true>), dim3(grid8(n, kRegWaves)),
+                               dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+    }
+    if constexpr (W == 2 && mix_class_ok(KI)) {
+        const int l = mix_list(KI);
+        const int64_t n = p.list_off[l + 1] - p.list_off[l];
+        if (n > 0)
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false>), dim3(grid8(n, kRegWaves)),
                                dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
     }
 }
