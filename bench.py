@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="diagnostic: time the steps without per-sweep HIP events (no roofline)")
+    ap.add_argument("--graph-sweeps", type=int, default=0, metavar="G",
+                    help="replay blocks of G sweeps from a captured HIP graph (kernel time then comes from a "
+                         "separate profiled pass after the timed steps); 0 = eager launches, whose sampled "
+                         "sweeps are timed inside the timed steps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -110,7 +114,7 @@ def main():
     from paper_2111_10270_amd import instances as I
 
     ilp = I.workload(a.workload)
-    s = B.Solver(ilp, precision=a.precision)
+    s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps)
     s.bind("cuda:0")
     st = s.stats
     N, P, V = st.n_nodes, st.n_pairs, st.n_vars
@@ -127,7 +131,8 @@ def main():
         step()
     torch.cuda.synchronize()
     # HIP events around the sweeps of every 10th iteration of the timed steps
-    s.profile(not a.no_profile, stride=10)
+    # (graph replay records no per-sweep events: profiled separately below)
+    s.profile(not a.no_profile and not a.graph_sweeps, stride=10)
     t0 = time.perf_counter()
     iters = 0
     results = []
@@ -150,6 +155,11 @@ def main():
     wall = t1 - t0
     ms_step = wall * 1e3 / a.steps
 
+    if a.graph_sweeps and not a.no_profile:
+        s.profile(True, stride=1)
+        s.reset()
+        s.run_dual(50)
+        torch.cuda.synchronize()
     n_f, t_f = s.kernel_time(B.K_SWEEP_FWD)
     n_b, t_b = s.kernel_time(B.K_SWEEP_BWD)
     s.profile(False)
@@ -173,7 +183,7 @@ def main():
         "dtype": "f32" if a.precision == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "iterations_per_solve": a.iters, "vars": V, "bdds": st.n_bdds,
-                   "pairs": P, "nodes": N, "precision_bound_sums": "f64"},
+                   "pairs": P, "nodes": N, "precision_bound_sums": "f64", "graph_sweeps": a.graph_sweeps},
         "arcs_per_s": 2.0 * N * iters / wall,
         "dual_phase_iters_per_s": a.iters * a.steps / (dual_ms * 1e-3),
         "dual_phase_arcs_per_s": 2.0 * N * a.iters * a.steps / (dual_ms * 1e-3),

@@ -66,14 +66,22 @@ typedef struct {
     int32_t  sp_in_lds_max_nodes; /* subproblems with more nodes keep their shortest
                               paths in device memory instead of LDS; 0 = built-in limit,
                               -1 = never use LDS */
-    int32_t  fast_path;    /* 1: BDDs with <= 32 layers and <= 4 nodes per layer are swept
-                              by register-resident kernels and variables with |J_i| <= 2
+    int32_t  fast_path;    /* 1: tiles of 64 identical BDDs with <= 4 nodes per layer (and
+                              width x layers <= 64), and tiles of different BDDs with <= 2
+                              nodes per layer and <= 20 layers, are swept by
+                              register-resident kernels, and variables with |J_i| <= 2
                               inside one tile are averaged in the sweep; 0: general
                               kernels and the averaging kernel only.  1 */
     int32_t  perturb_scale;/* Alg. 2 draws r uniformly from [-delta, delta] and adds r*delta
                               (0, magnitude up to delta^2) or draws r from [-1, 1] (1,
                               magnitude up to delta).  0 */
-    int32_t  reserved[5];  /* must be zero */
+    int32_t  graph_sweeps; /* > 0: run_sweeps / run_dual replay blocks of this many sweeps
+                              (rounded down to an even number, capped by the bound-history
+                              capacity) from a captured HIP graph, which removes the
+                              per-launch host cost of small problems; results are
+                              identical to eager launches.  Not used while profiling.
+                              0 = eager launches.  64 */
+    int32_t  reserved[4];  /* must be zero */
 } bddmma_options;
 
 typedef struct {

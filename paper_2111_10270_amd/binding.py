@@ -38,7 +38,7 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("delta0", C.c_double), ("alpha", C.c_double),
                 ("reopt_iters", C.c_int32), ("max_rounds", C.c_int32), ("tau", C.c_double),
                 ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("fast_path", C.c_int32),
-                ("perturb_scale", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):

@@ -27,6 +27,7 @@ int fail(int code, const std::string &msg)
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kHistBytes = 64ll << 20;  // device budget for per-tile bound partials of pending sweeps
+constexpr int64_t kLbhCap = 4096;           // reduced bounds kept on the device before a copy to the host
 constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -60,9 +61,17 @@ struct bddmma_solver {
     std::vector<int32_t> coef32;  // host staging of the original coefficients
     std::vector<int8_t> preset;   // host staging of presolved values
     int64_t sweeps = 0;           // sweeps run since bind
-    int64_t hist_synced = 0;      // history entries already on the host
-    int64_t hist_chunk = 1;       // sweeps whose bound partials fit on the device before a flush
+    // bound history: sweeps [0, hist_synced) are on the host, the next lbh_n
+    // are reduced on the device (lbh), the next part_n have per-tile partials
+    // in rows 0 .. part_n-1 of lbpart (part_n + lbh_n + hist_synced = sweeps)
+    int64_t hist_synced = 0;
+    int64_t lbh_n = 0;
+    int64_t part_n = 0;
+    int64_t hist_chunk = 1;       // rows of lbpart
     std::vector<double> hist;     // LB_free after every sweep
+    hipStream_t cap_st = nullptr; // private stream the sweep graph is captured on
+    hipGraphExec_t graph = nullptr;
+    int64_t graph_len = 0;        // sweeps per replay
     bool prof = false;
     int prof_stride = 1;          // bracket every prof_stride-th sweep
     Events ev;
@@ -120,7 +129,7 @@ Layout make_layout(const bddmma_solver &s)
     L.lbpart = take((size_t)s.hist_chunk * T * 8);
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
-    L.lbh = take((size_t)s.hist_chunk * 8);
+    L.lbh = take((size_t)kLbhCap * 8);
     L.counter = take(64);
     L.flag = take(V + 1);
     L.x = take(V + 1);
@@ -182,58 +191,125 @@ Omega<T> weights(const bddmma_solver *s)
 // last sweep's M at every slot (what the termination step, the bounds and the
 // state export read); the averaging of the variables not averaged in-tile
 // therefore runs right before the sweep that consumes it and stores the
-// averaged terms in place of their M.  With record_lb the sweep's per-tile
-// bound partials go to row (sweeps % hist_chunk) of the partial history.
+// averaged terms in place of their M.  With row >= 0 the sweep's per-tile
+// bound partials go to that row of lbpart.
 template <typename T>
-void one_sweep(bddmma_solver *s, int dir, bool record_lb)
+void one_sweep(bddmma_solver *s, int dir, int64_t row, bool sample)
 {
     const DevProblem &p = s->dp;
     T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
-    double *tile_lb =
-        record_lb ? s->ptr<double>(s->L.lbpart) + (size_t)(s->sweeps % s->hist_chunk) * s->pk.tiles.size() : nullptr;
+    double *tile_lb = row >= 0 ? s->ptr<double>(s->L.lbpart) + (size_t)row * s->pk.tiles.size() : nullptr;
     launch_average<T>(p, mm, s->opt.omega, s->st);
-    Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD, record_lb && (s->sweeps / 2) % s->prof_stride == 0);
+    Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD, sample);
     launch_sweep<T>(p, lam, mm, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
 }
 
-// reduce the pending sweeps' partials to bounds and copy them to the host
+// sweeps of Alg. 2's re-optimisation: no bound record
+template <typename T>
+void plain_sweep(bddmma_solver *s, int dir)
+{
+    one_sweep<T>(s, dir, -1, false);
+}
+
+// per-tile partials of the part_n pending sweeps -> bounds in lbh (stream-ordered)
+int reduce_history(bddmma_solver *s)
+{
+    if (s->part_n == 0) return BDDMMA_OK;
+    launch_lb_many(s->ptr<double>(s->L.lbpart), (int64_t)s->pk.tiles.size(), s->part_n, s->prob.lb_offset,
+                   s->ptr<double>(s->L.lbh) + s->lbh_n, s->st);
+    s->lbh_n += s->part_n;
+    s->part_n = 0;
+    return check_launch();
+}
+
+// every pending bound to the host
 int flush_history(bddmma_solver *s)
 {
-    const int64_t pending = s->sweeps - s->hist_synced;
-    if (pending <= 0) return BDDMMA_OK;
-    double *lbh = s->ptr<double>(s->L.lbh);
-    launch_lb_many(s->ptr<double>(s->L.lbpart), (int64_t)s->pk.tiles.size(), s->hist_chunk, s->hist_synced, pending,
-                   s->prob.lb_offset, lbh, s->hist_chunk, s->st);
-    int rc = check_launch();
+    int rc = reduce_history(s);
     if (rc) return rc;
-    s->hist.resize((size_t)s->sweeps);
-    // entries [hist_synced, sweeps) live at index % hist_chunk (at most hist_chunk pending)
-    int64_t a = s->hist_synced;
-    while (a < s->sweeps) {
-        const int64_t idx = a % s->hist_chunk, run = std::min<int64_t>(s->sweeps - a, s->hist_chunk - idx);
-        HIPCHK(hipMemcpyAsync(s->hist.data() + a, lbh + idx, (size_t)run * 8, hipMemcpyDeviceToHost, s->st));
-        a += run;
-    }
+    if (s->lbh_n == 0) return BDDMMA_OK;
+    s->hist.resize((size_t)(s->hist_synced + s->lbh_n));
+    HIPCHK(hipMemcpyAsync(s->hist.data() + s->hist_synced, s->ptr<double>(s->L.lbh), (size_t)s->lbh_n * 8,
+                          hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    s->hist_synced = s->sweeps;
+    s->hist_synced += s->lbh_n;
+    s->lbh_n = 0;
+    return BDDMMA_OK;
+}
+
+// room for `rows` more rows of partials (and their bounds later)
+int make_room(bddmma_solver *s, int64_t rows)
+{
+    int rc;
+    if (s->part_n + rows > s->hist_chunk && (rc = reduce_history(s))) return rc;
+    if (s->lbh_n + s->hist_chunk > kLbhCap && (rc = flush_history(s))) return rc;
+    return BDDMMA_OK;
+}
+
+void drop_graph(bddmma_solver *s)
+{
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+    s->graph_len = 0;
+}
+
+// Capture graph_len sweeps (starting with a forward sweep, partial rows
+// 0 .. graph_len-1) on the private stream.  Any failure leaves no graph and
+// the caller runs eager launches.
+template <typename T>
+int capture_graph(bddmma_solver *s, int64_t len)
+{
+    if (!s->cap_st) HIPCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+    hipStream_t keep = s->st;
+    s->st = s->cap_st;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int64_t k = 0; k < len; ++k) one_sweep<T>(s, (int)(k & 1), k, false);
+        e = hipStreamEndCapture(s->st, &g);
+    }
+    s->st = keep;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BDDMMA_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(BDDMMA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    s->graph = x;
+    s->graph_len = len;
     return BDDMMA_OK;
 }
 
 template <typename T>
 int run_sweeps_T(bddmma_solver *s, int64_t n)
 {
-    for (int64_t k = 0; k < n; ++k) {
-        one_sweep<T>(s, (int)(s->sweeps & 1), true);
-        s->sweeps++;
-        if (s->sweeps - s->hist_synced >= s->hist_chunk) {
-            int rc = check_launch();
-            if (rc) return rc;
-            rc = flush_history(s);
-            if (rc) return rc;
+    int rc;
+    int64_t len = std::min<int64_t>(s->opt.graph_sweeps, s->hist_chunk) & ~int64_t(1);
+    const bool graphs = len >= 2 && !s->prof;
+    int64_t k = 0;
+    while (k < n) {
+        if (graphs && (s->sweeps & 1) == 0 && n - k >= len) {
+            if (s->graph_len != len) {
+                drop_graph(s);
+                if ((rc = capture_graph<T>(s, len))) return rc;
+            }
+            if ((rc = reduce_history(s)) || (rc = make_room(s, len))) return rc;
+            HIPCHK(hipGraphLaunch(s->graph, s->st));
+            s->part_n = len;
+            s->sweeps += len;
+            k += len;
+            if ((rc = reduce_history(s))) return rc;
+            continue;
         }
+        if ((rc = make_room(s, 1))) return rc;
+        one_sweep<T>(s, (int)(s->sweeps & 1), s->part_n, s->prof && (s->sweeps / 2) % s->prof_stride == 0);
+        s->part_n++;
+        s->sweeps++;
+        ++k;
     }
-    int rc = check_launch();
-    if (rc) return rc;
+    if ((rc = check_launch())) return rc;
     return flush_history(s);
 }
 
@@ -396,8 +472,8 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
         // Alg. 1 restarts with M-bar = 0
         launch_fill<T>(mm, T(0), S, s->st);
         for (int t = 0; t < s->opt.reopt_iters; ++t) {
-            one_sweep<T>(s, 0, false);
-            one_sweep<T>(s, 1, false);
+            plain_sweep<T>(s, 0);
+            plain_sweep<T>(s, 1);
         }
         launch_terminate<T>(p, lam, mm, omega, s->st);
         launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
@@ -468,6 +544,7 @@ int bddmma_options_default(bddmma_options *o)
     o->seed = 0;
     o->sp_in_lds_max_nodes = 0;
     o->fast_path = 1;
+    o->graph_sweeps = 64;
     return BDDMMA_OK;
 }
 
@@ -488,7 +565,8 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.sp_in_lds_max_nodes < -1) return fail(BDDMMA_ERR_INVALID_ARG, "sp_in_lds_max_nodes must be >= -1");
     if (o.fast_path != 0 && o.fast_path != 1) return fail(BDDMMA_ERR_INVALID_ARG, "fast_path must be 0 or 1");
     if (o.perturb_scale != 0 && o.perturb_scale != 1) return fail(BDDMMA_ERR_INVALID_ARG, "perturb_scale must be 0 or 1");
-    for (int i = 0; i < 5; ++i)
+    if (o.graph_sweeps < 0) return fail(BDDMMA_ERR_INVALID_ARG, "graph_sweeps must be >= 0");
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
@@ -507,6 +585,8 @@ void bddmma_destroy(bddmma_solver *s)
             (void)hipEventDestroy(pr.second);
         }
     for (auto e : s->ev.pool) (void)hipEventDestroy(e);
+    drop_graph(s);
+    if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
     delete s;
 }
 
@@ -647,6 +727,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     s->bound = true;
     s->sweeps = 0;
     s->hist_synced = 0;
+    s->lbh_n = 0;
+    s->part_n = 0;
     s->hist.clear();
     return BDDMMA_OK;
     GUARD_END
@@ -664,6 +746,8 @@ int bddmma_reset(bddmma_solver *s)
     if (rc) return rc;
     s->sweeps = 0;
     s->hist_synced = 0;
+    s->lbh_n = 0;
+    s->part_n = 0;
     s->hist.clear();
     return BDDMMA_OK;
     GUARD_END
@@ -855,6 +939,8 @@ int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
     s->hist.assign((const double *)p, (const double *)p + h.hist);
     s->sweeps = (int64_t)h.sweeps;
     s->hist_synced = s->sweeps;
+    s->lbh_n = 0;
+    s->part_n = 0;
     return BDDMMA_OK;
     GUARD_END
 }

@@ -360,16 +360,14 @@ __global__ __launch_bounds__(kRedThreads) void k_average(const AvgBucket *__rest
     }
 }
 
-// Bound of each of `n` sweeps from their per-tile partials (row s of `part`
-// holds sweep first + s): one block per sweep, fixed summation order, so the
-// value does not depend on scheduling.  out[(first + s) % cap] = offset + sum.
+// Bound of each of the recorded sweeps from its per-tile partials (row r of
+// `part`): one block per sweep, fixed summation order, so the value does not
+// depend on scheduling.  out[r] = offset + sum.
 __global__ __launch_bounds__(kRedThreads) void k_lb_many(const double *__restrict__ part, int64_t n_tiles,
-                                                         int64_t chunk, int64_t first, double offset,
-                                                         double *__restrict__ out, int64_t cap)
+                                                         double offset, double *__restrict__ out)
 {
     __shared__ double sh[kRedThreads];
-    const int64_t sweep = first + blockIdx.x;
-    const double *row = part + (sweep % chunk) * n_tiles;
+    const double *row = part + (int64_t)blockIdx.x * n_tiles;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t t = threadIdx.x;
     for (; t + 3 * kRedThreads < n_tiles; t += 4 * kRedThreads) {
@@ -378,7 +376,7 @@ __global__ __launch_bounds__(kRedThreads) void k_lb_many(const double *__restric
     }
     for (int u = 0; t < n_tiles; t += kRedThreads, ++u) acc[u & 3] += row[t];
     const double tot = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), sh);
-    if (threadIdx.x == 0) out[sweep % cap] = tot + offset;
+    if (threadIdx.x == 0) out[blockIdx.x] = tot + offset;
 }
 
 // per-variable a_i of every variable (state export)
@@ -709,12 +707,9 @@ void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st)
                        p.gslot, p.vptr, p.vslot, mm, omega);
 }
 
-void launch_lb_many(const double *part, int64_t n_tiles, int64_t chunk, int64_t first, int64_t n, double offset,
-                    double *out, int64_t cap, hipStream_t st)
+void launch_lb_many(const double *part, int64_t n_tiles, int64_t n, double offset, double *out, hipStream_t st)
 {
-    if (n > 0)
-        hipLaunchKernelGGL(k_lb_many, dim3((unsigned)n), dim3(kRedThreads), 0, st, part, n_tiles, chunk, first,
-                           offset, out, cap);
+    if (n > 0) hipLaunchKernelGGL(k_lb_many, dim3((unsigned)n), dim3(kRedThreads), 0, st, part, n_tiles, offset, out);
 }
 
 template <typename T>

@@ -61,10 +61,9 @@ void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Ome
 template <typename T>
 void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st);
 
-// bounds of sweeps first .. first+n-1 from their per-tile partials (row
-// (sweep % chunk) of part, n_tiles each): out[sweep % cap] = offset + sum
-void launch_lb_many(const double *part, int64_t n_tiles, int64_t chunk, int64_t first, int64_t n, double offset,
-                    double *out, int64_t cap, hipStream_t st);
+// bounds of n sweeps from their per-tile partials (row r of part, n_tiles
+// each): out[r] = offset + sum of row r, in a fixed order
+void launch_lb_many(const double *part, int64_t n_tiles, int64_t n, double offset, double *out, hipStream_t st);
 
 // per-variable averaged terms of all variables into avg[n_vars] (state export)
 template <typename T>

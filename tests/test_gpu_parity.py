@@ -396,3 +396,39 @@ def test_profiling_counts_launches():
     n, _ = s.kernel_time(B.K_AVERAGE)
     assert n == 0   # only sweeps are bracketed
     s.profile(False)
+
+
+# ---------------------------------------------------------------- graph replay
+def _same_run(a, b, what):
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y), what
+    assert np.array_equal(a.lb_history(), b.lb_history()), what
+
+
+@pytest.mark.parametrize("name,prec", [("random", 64), ("gm1000k10", 32), ("mrf10x10L3", 64)])
+def test_graph_replay_matches_eager(name, prec):
+    """sweeps replayed from a captured graph equal eager launches bit for bit,
+    over several replays with eager work and synchronisation in between"""
+    ilp = I.random_ilp(40, 30, max_row_len=7, seed=21) if name == "random" else I.workload(name)
+    note("graph replay", name, prec)
+    eager = solver(ilp, precision=prec, graph_sweeps=0)
+    graph = solver(ilp, precision=prec, graph_sweeps=8)
+    # odd start (eager sweep first), two replays, eager tail
+    for s in (eager, graph):
+        s.run_sweeps(1)
+        s.run_sweeps(20)
+    _same_run(eager, graph, "after 21 sweeps")
+    for s in (eager, graph):
+        s.lower_bound()                 # eager kernels between replays
+    for s in (eager, graph):
+        s.run_dual(30)                  # seven replays + eager sweeps
+    _same_run(eager, graph, "after run_dual(30)")
+    assert eager.lower_bound() == graph.lower_bound()
+    ra, rb = eager.round_primal(), graph.round_primal()
+    assert ra["rc"] == rb["rc"] and ra["rounds"] == rb["rounds"]
+    if ra["rc"] == 0:
+        assert np.array_equal(ra["x"], rb["x"]) and ra["ub"] == rb["ub"]
+    for s in (eager, graph):
+        s.reset()
+        s.run_dual(12)
+    _same_run(eager, graph, "after reset")
