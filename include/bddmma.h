@@ -81,7 +81,11 @@ typedef struct {
                               per-launch host cost of small problems; results are
                               identical to eager launches.  Not used while profiling.
                               0 = eager launches.  64 */
-    int32_t  reserved[4];  /* must be zero */
+    int32_t  class_merge_kib; /* register-kernel tiles of a layer class are padded into the
+                              next larger class of their kind while the padding costs at
+                              most this many KiB of traffic per sweep (fewer launches);
+                              0 = one launch per non-empty class.  32768 */
+    int32_t  reserved[3];  /* must be zero */
 } bddmma_options;
 
 typedef struct {
@@ -95,6 +99,9 @@ typedef struct {
     int64_t n_slots;              /* padded pair slots on the device */
     int64_t max_layers, max_width;
     double  lb_offset;            /* constant of fixed / unconstrained variables */
+    int64_t n_reg_tiles;          /* tiles swept by the register kernels (one topology) */
+    int64_t n_reg_mixed_tiles;    /* tiles swept by the register kernels (per-lane topologies) */
+    int64_t n_reg_launches;       /* register-kernel launches per sweep (non-empty classes) */
 } bddmma_stats;
 
 /* Fill *opt with the defaults listed above.  INVALID_ARG if opt is NULL. */

@@ -38,14 +38,16 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("delta0", C.c_double), ("alpha", C.c_double),
                 ("reopt_iters", C.c_int32), ("max_rounds", C.c_int32), ("tau", C.c_double),
                 ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("fast_path", C.c_int32),
-                ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32),
+                ("class_merge_kib", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n_vars", C.c_int64), ("n_rows", C.c_int64), ("n_bdds", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_nodes", C.c_int64), ("n_fixed", C.c_int64), ("n_free", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_slots", C.c_int64), ("max_layers", C.c_int64), ("max_width", C.c_int64),
-                ("lb_offset", C.c_double)]
+                ("lb_offset", C.c_double), ("n_reg_tiles", C.c_int64), ("n_reg_mixed_tiles", C.c_int64),
+                ("n_reg_launches", C.c_int64)]
 
 
 _lib = None

@@ -545,6 +545,7 @@ int bddmma_options_default(bddmma_options *o)
     o->sp_in_lds_max_nodes = 0;
     o->fast_path = 1;
     o->graph_sweeps = 64;
+    o->class_merge_kib = 32768;
     return BDDMMA_OK;
 }
 
@@ -566,7 +567,8 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.fast_path != 0 && o.fast_path != 1) return fail(BDDMMA_ERR_INVALID_ARG, "fast_path must be 0 or 1");
     if (o.perturb_scale != 0 && o.perturb_scale != 1) return fail(BDDMMA_ERR_INVALID_ARG, "perturb_scale must be 0 or 1");
     if (o.graph_sweeps < 0) return fail(BDDMMA_ERR_INVALID_ARG, "graph_sweeps must be >= 0");
-    for (int i = 0; i < 4; ++i)
+    if (o.class_merge_kib < 0) return fail(BDDMMA_ERR_INVALID_ARG, "class_merge_kib must be >= 0");
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
@@ -602,7 +604,8 @@ int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64
     rc = build_problem(s->prob, msg);
     if (rc != ST_OK) return fail(rc, msg);
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
-    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0, s->pk, msg);
+    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
+                      1024.0 * s->opt.class_merge_kib, s->pk, msg);
     if (rc != ST_OK) return fail(rc, msg);
     {
         const int64_t nt = std::max<int64_t>(1, (int64_t)s->pk.tiles.size());
@@ -634,6 +637,11 @@ int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
     o->max_layers = s->pk.max_layers;
     o->max_width = s->pk.max_width;
     o->lb_offset = s->prob.lb_offset;
+    for (int l = LIST_FAST0; l < kNumLists; ++l) {
+        const int64_t n = s->pk.list_off[l + 1] - s->pk.list_off[l];
+        (l >= LIST_MIX0 ? o->n_reg_mixed_tiles : o->n_reg_tiles) += n;
+        o->n_reg_launches += n > 0;
+    }
     return BDDMMA_OK;
 }
 

@@ -351,7 +351,8 @@ struct TilePlan {
 
 }  // namespace
 
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, Packed &o, std::string &msg)
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes, Packed &o,
+                 std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -450,8 +451,8 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     // Fewer launches: inside a width class, the tiles of a layer class join
     // the next larger class present (padded to its layer count) while the
     // padding moves fewer bytes per sweep than a separate launch costs (a
-    // small launch runs for about one wave lifetime at low occupancy).
-    constexpr double kMergeBytes = 32.0 * (1 << 20);   // ~7 us of HBM traffic
+    // small launch runs for about one wave lifetime at low occupancy):
+    // merge_bytes, 0 = every class launches on its own.
     constexpr double kSlotBytes = 16.0;                // lambda and M read + written (FP32)
     for (int g = 0; g < kNumWClasses + 1; ++g) {
         // groups: shared tiles of each width class, then the mixed tiles
@@ -465,7 +466,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         for (int ki = 0; ki < kNumKClasses; ++ki) into[ki] = ki;
         for (;;) {
             int best = -1, best_to = -1;
-            double best_cost = kMergeBytes;
+            double best_cost = merge_bytes;
             for (int ki = 0; ki < kNumKClasses; ++ki) {
                 if (!cnt[ki]) continue;
                 int kj = ki + 1;
@@ -478,7 +479,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                     best_to = kj;
                 }
             }
-            if (best < 0) break;
+            if (best < 0 || merge_bytes <= 0.0) break;
             cnt[best_to] += cnt[best];
             cnt[best] = 0;
             for (int ki = 0; ki < kNumKClasses; ++ki)
@@ -558,7 +559,6 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         }
         if (tp.wi >= 0) {
             lists[tp.mix ? mix_list(tp.ki) : fast_list(tp.wi, tp.ki)].push_back(tid);
-            o.n_fast_tiles++;
         }
         std::vector<uint32_t> noff(tp.K + 1, 0);
         for (int h = 0; h < tp.K; ++h) {

@@ -34,7 +34,6 @@ struct Packed {
     std::vector<TileDesc> tiles;
     std::vector<int32_t> lists;                  // tile ids of every TileList, concatenated
     std::vector<int64_t> list_off;               // [kNumLists + 1]
-    int64_t n_fast_tiles = 0;
     std::vector<uint32_t> layers;     // layer table
     std::vector<uint32_t> child;      // node words
     std::vector<int32_t> pair_var;    // [S] variable per slot, n_vars for padding
@@ -76,9 +75,11 @@ int build_problem(Problem &p, std::string &msg);
 // Pack the compiled BDDs into tiles.  lds_elem_budget: per-lane elements a tile
 // may keep in LDS (0 disables LDS); lds_max_nodes > 0 additionally caps the
 // nodes per lane of LDS tiles; fast selects the register-resident path for the
-// tiles it can take.  ST_OK / ST_INVALID.
+// tiles it can take; merge_bytes is the padding traffic per sweep a layer
+// class may add to join a larger class (0: no merging).  ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, Packed &out, std::string &msg);
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes, Packed &out,
+                 std::string &msg);
 
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.

@@ -152,6 +152,19 @@ def test_long_and_wide_rows_fp64():
     assert s.stats.max_layers >= 150 and s.stats.max_width > 8
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("merge", [0, 32768])
+def test_layer_classes(prec, merge):
+    """many register classes (shared at widths 2 and 4, mixed), class merging
+    with padding, and general tiles, against the reference sweep by sweep"""
+    from layer_classes import layer_class_ilp
+    ilp = layer_class_ilp()
+    s, o, _ = lockstep(ilp, 6, precision=prec, class_merge_kib=merge)
+    st = s.stats
+    assert st.n_reg_tiles > 0 and st.n_reg_mixed_tiles > 0
+    assert st.n_reg_launches >= (12 if merge == 0 else 2)
+
+
 @pytest.mark.parametrize("path", PATHS[:2])
 @pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
 def test_ragged_tile_counts_fp64(n_rows, path):
