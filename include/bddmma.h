@@ -213,6 +213,46 @@ int bddmma_min_marginals(bddmma_solver *s, double *mm_out);
  * x_out may be NULL. */
 int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds);
 
+/* ---- Batches of independent instances (many small problems per launch) ----
+ * A batch is k independent ILPs loaded as one block-diagonal ILP: instance k
+ * owns the next inst_vars[k] variables and inst_rows[k] rows of the
+ * concatenated CSR arrays (same formats as bddmma_load_ilp), and its rows may
+ * reference its own variables only.  Tiles never mix instances, so every
+ * sweep launch covers the tiles of all instances while each instance follows
+ * exactly the trajectory it follows when loaded alone: multipliers, deferred
+ * differences and rounded points are bitwise identical (bound sums agree to
+ * the last few bits: their summation tree differs).  run_dual / run_sweeps /
+ * lower_bound / lb_history act on the whole batch (bounds are sums over the
+ * instances); the calls below report per instance.  INFEASIBLE when any
+ * instance is.  Instance k's random draws in Alg. 2 use instance-local
+ * variable indices and its zero threshold tau from its own costs. */
+int bddmma_load_batch(bddmma_solver *s, int64_t n_inst, const int64_t *inst_vars, const int64_t *inst_rows,
+                      int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                      const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs);
+
+/* Number of instances (1 after bddmma_load_ilp).  STATE before load. */
+int bddmma_num_instances(const bddmma_solver *s, int64_t *n_inst);
+
+/* Per-instance bounds (arrays of n_inst doubles, each may be NULL):
+ * lb_free of the most recent recorded sweep (STATE if there is none since
+ * bind / reset / load_state), lb_cert with its residual correction and the
+ * largest multiplier residual, as bddmma_lower_bound computes them for the
+ * whole problem.  Synchronises the stream. */
+int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res);
+
+/* Alg. 2 for every instance of the loaded problem (dual state restored
+ * afterwards).  Rounds run while some instance has conflicts; each instance
+ * closes, and its point is taken, in the first round in which it has no
+ * conflict and all of its BDDs accept the decoded point: the round at which
+ * Alg. 2 on that instance alone stops.  Per instance k (arrays of n_inst):
+ * status[k] = OK, NOT_CONVERGED (max_rounds reached) or STATE (point
+ * violates an original row); rounds[k] = round at which it closed (or the
+ * last round); for OK instances ub[k] = objective and x_out[i] for its
+ * variables (x_out has n_vars entries; other entries untouched).
+ * bddmma_round_primal is this call followed by: OK only if every instance is
+ * OK, *ub = sum of the instance objectives, *rounds = largest round. */
+int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds, int32_t *status);
+
 /* Checkpoint of the dual state (multipliers, deferred differences, sweep
  * counter, bound history).  With buf == NULL sets *bytes to the
  * size needed.  load_state requires the same loaded problem and precision;

@@ -24,7 +24,8 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_lb_history", "bddmma_num_pairs", "bddmma_get_pairs", "bddmma_get_fixed",
            "bddmma_get_multipliers", "bddmma_get_state", "bddmma_set_state", "bddmma_min_marginals",
            "bddmma_round_primal", "bddmma_save_state", "bddmma_load_state", "bddmma_profile",
-           "bddmma_kernel_time", "bddmma_last_error")
+           "bddmma_kernel_time", "bddmma_last_error", "bddmma_load_batch", "bddmma_num_instances",
+           "bddmma_batch_bounds", "bddmma_batch_round")
 
 
 class BddmmaError(RuntimeError):
@@ -71,6 +72,8 @@ def lib():
             "bddmma_set_state": [P, P, P, P], "bddmma_min_marginals": [P, P], "bddmma_round_primal": [P, P, P, P],
             "bddmma_save_state": [P, P, P], "bddmma_load_state": [P, P, C.c_size_t],
             "bddmma_profile": [P, C.c_int], "bddmma_kernel_time": [P, C.c_int, P, P], "bddmma_last_error": [],
+            "bddmma_load_batch": [P, i64, P, P, i64, P, i64, P, P, P, P, P], "bddmma_num_instances": [P, P],
+            "bddmma_batch_bounds": [P, P, P, P], "bddmma_batch_round": [P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -103,18 +106,32 @@ def default_options(**kw) -> Options:
 
 
 class Solver:
-    """One ILP on one device: load (host) -> bind (device workspace) -> solve."""
+    """One ILP (or a batch of independent ILPs, given as a list) on one
+    device: load (host) -> bind (device workspace) -> solve."""
 
     def __init__(self, ilp, **options):
         L = lib()
         self._h = C.c_void_p()
         self.options = default_options(**options)
         _check(L.bddmma_create(C.byref(self.options), C.byref(self._h)))
+        batch = isinstance(ilp, (list, tuple))
+        if batch:
+            from . import instances
+            ilp = instances.concat(ilp)
         self.ilp = ilp
         arrs = [np.ascontiguousarray(ilp.costs, dtype=np.float64), np.ascontiguousarray(ilp.row_ptr, dtype=np.int64),
                 np.ascontiguousarray(ilp.col, dtype=np.int32), np.ascontiguousarray(ilp.coef, dtype=np.int32),
                 np.ascontiguousarray(ilp.sense, dtype=np.int8), np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
-        _check(L.bddmma_load_ilp(self._h, ilp.n_vars, _p(arrs[0]), ilp.n_rows, *[_p(a) for a in arrs[1:]]))
+        if batch:
+            nv = np.ascontiguousarray(ilp.meta["inst_vars"], dtype=np.int64)
+            nr = np.ascontiguousarray(ilp.meta["inst_rows"], dtype=np.int64)
+            _check(L.bddmma_load_batch(self._h, len(nv), _p(nv), _p(nr), ilp.n_vars, _p(arrs[0]), ilp.n_rows,
+                                       *[_p(a) for a in arrs[1:]]))
+        else:
+            _check(L.bddmma_load_ilp(self._h, ilp.n_vars, _p(arrs[0]), ilp.n_rows, *[_p(a) for a in arrs[1:]]))
+        n = C.c_int64()
+        _check(L.bddmma_num_instances(self._h, C.byref(n)))
+        self.n_inst = n.value
         st = Stats()
         _check(L.bddmma_get_stats(self._h, C.byref(st)))
         self.stats = st
@@ -212,6 +229,22 @@ class Solver:
         if rc not in (OK, NOT_CONVERGED):
             _check(rc)
         return dict(rc=rc, x=x, ub=ub.value, rounds=rounds.value)
+
+    # ---- batches ----
+    def batch_bounds(self):
+        """per-instance (lb_free, lb_cert, max_residual) arrays"""
+        out = [np.zeros(self.n_inst) for _ in range(3)]
+        _check(lib().bddmma_batch_bounds(self._h, *[_p(a) for a in out]))
+        return tuple(out)
+
+    def batch_round(self):
+        """per-instance Alg. 2: dict(status, rounds, ub, x)"""
+        x = np.zeros(self.ilp.n_vars, dtype=np.uint8)
+        ub = np.full(self.n_inst, np.nan)
+        rounds = np.zeros(self.n_inst, dtype=np.int32)
+        status = np.zeros(self.n_inst, dtype=np.int32)
+        _check(lib().bddmma_batch_round(self._h, _p(x), _p(ub), _p(rounds), _p(status)))
+        return dict(status=status, rounds=rounds, ub=ub, x=x)
 
     # ---- checkpoint ----
     def save_state(self) -> bytes:

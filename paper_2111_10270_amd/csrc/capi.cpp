@@ -37,6 +37,8 @@ struct Layout {
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
     size_t lbpart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
+    size_t var_inst, tile_inst, row_inst, inst_var, inst_tile, inst_off, inst_tau, ochunk, oseg, opart, imask, xbest,
+        ires;
     size_t total;
 };
 
@@ -60,6 +62,11 @@ struct bddmma_solver {
     DevRows rows{};
     std::vector<int32_t> coef32;  // host staging of the original coefficients
     std::vector<int8_t> preset;   // host staging of presolved values
+    std::vector<int64_t> ochunk;  // objective chunk starts (kObjChunk variables from each instance start)
+    std::vector<int64_t> oseg;    // [n_inst + 1] chunk range of every instance
+    int64_t last_row = -1;        // lbpart row of the most recent recorded sweep
+    std::vector<double> inst_tau; // Alg. 2 zero threshold per instance
+    int64_t n_inst() const { return prob.ilp.n_inst(); }
     int64_t sweeps = 0;           // sweeps run since bind
     // bound history: sweeps [0, hist_synced) are on the host, the next lbh_n
     // are reduced on the device (lbh), the next part_n have per-tile partials
@@ -130,7 +137,8 @@ Layout make_layout(const bddmma_solver &s)
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
     L.lbh = take((size_t)kLbhCap * 8);
-    L.counter = take(64);
+    const int64_t NI = s.prob.ilp.n_inst();
+    L.counter = take((size_t)(3 * NI + 16) * 4);
     L.flag = take(V + 1);
     L.x = take(V + 1);
     L.xfull = take(V + 1);
@@ -141,6 +149,19 @@ Layout make_layout(const bddmma_solver &s)
     L.r_sense = take(ilp.n_rows);
     L.r_rhs = take(ilp.n_rows * 8);
     L.preset = take(V);
+    L.var_inst = take(pk.var_inst.size() * 4);
+    L.tile_inst = take(pk.tile_inst.size() * 4);
+    L.row_inst = take(pk.row_inst.size() * 4);
+    L.inst_var = take((size_t)(NI + 1) * 8);
+    L.inst_tile = take((size_t)(NI + 1) * 8);
+    L.inst_off = take((size_t)NI * 8);
+    L.inst_tau = take((size_t)NI * 8);
+    L.ochunk = take(s.ochunk.size() * 8);
+    L.oseg = take(s.oseg.size() * 8);
+    L.opart = take(s.ochunk.size() * 8);
+    L.imask = take((size_t)NI);
+    L.xbest = take(V + 1);
+    L.ires = take((size_t)NI * 4 * 8);   // per instance: lb_free, cert, residual pos, residual max / ub
     L.scratch = take((size_t)pk.scratch_elems * e);
     L.total = o;
     return L;
@@ -298,6 +319,7 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
             if ((rc = reduce_history(s)) || (rc = make_room(s, len))) return rc;
             HIPCHK(hipGraphLaunch(s->graph, s->st));
             s->part_n = len;
+            s->last_row = len - 1;
             s->sweeps += len;
             k += len;
             if ((rc = reduce_history(s))) return rc;
@@ -305,6 +327,7 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
         }
         if ((rc = make_room(s, 1))) return rc;
         one_sweep<T>(s, (int)(s->sweeps & 1), s->part_n, s->prof && (s->sweeps / 2) % s->prof_stride == 0);
+        s->last_row = s->part_n;
         s->part_n++;
         s->sweeps++;
         ++k;
@@ -424,48 +447,79 @@ int min_marginals_T(bddmma_solver *s, double *out)
     return BDDMMA_OK;
 }
 
-// Alg. 2 on the terminated multipliers; the dual state is restored at the end
+// Alg. 2 on the terminated multipliers, for every instance (one for a single
+// ILP); the dual state is restored at the end.  Rounds run while some
+// instance is open.  An instance closes in the first round in which it has no
+// conflict and each of its BDDs accepts the decoded point, which is the round
+// where Alg. 2 run on that instance alone stops; its point is kept from that
+// round.  Instances are independent (their random draws use instance-local
+// variable indices), so later rounds do not change a closed instance's
+// result.  Per instance: rounds (round index reached), status (OK,
+// NOT_CONVERGED, or STATE if the point violates an original row), ub; xfull
+// holds the points of the closed instances.
 template <typename T>
-int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
+int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t> &status, std::vector<double> &ub,
+            std::vector<uint8_t> &xfull)
 {
     const DevProblem &p = s->dp;
-    const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars;
+    const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars, n = s->n_inst();
     T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
     T *lam_b = s->ptr<T>(s->L.lam_bak), *mm_b = s->ptr<T>(s->L.mm_bak);
-    uint8_t *flag = s->ptr<uint8_t>(s->L.flag), *xd = s->ptr<uint8_t>(s->L.x);
-    int32_t *counter = s->ptr<int32_t>(s->L.counter);
+    uint8_t *flag = s->ptr<uint8_t>(s->L.flag), *xd = s->ptr<uint8_t>(s->L.x), *xb = s->ptr<uint8_t>(s->L.xbest);
+    uint8_t *mask = s->ptr<uint8_t>(s->L.imask);
+    int32_t *cnt = s->ptr<int32_t>(s->L.counter);   // [3n]: conflicts, rejecting BDDs, violated rows
     const T omega = (T)s->opt.omega;
     const Omega<T> w = weights<T>(s);
     launch_copy<T>(lam_b, lam, S, s->st);
     launch_copy<T>(mm_b, mm, S, s->st);
     launch_fill<uint8_t>(flag, 0, V, s->st);
+    launch_fill<uint8_t>(xb, 0, V + 1, s->st);
     launch_terminate<T>(p, lam, mm, omega, s->st);
     launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
 
+    std::vector<int32_t> conf((size_t)n), bad((size_t)n), viol((size_t)n);
+    std::vector<uint8_t> open((size_t)n, 1), cand((size_t)n), take((size_t)n);
+    rounds.assign((size_t)n, 0);
+    int64_t n_open = n;
     double delta = s->opt.delta0;
-    int rc = BDDMMA_ERR_NOT_CONVERGED, round;
-    for (round = 0;; ++round) {
-        launch_conflicts<T>(p, mm, s->tau, flag, counter, s->st);
-        int32_t nconf = 0;
-        int e = check_launch();
-        if (e) return e;
-        HIPCHK(hipMemcpyAsync(&nconf, counter, 4, hipMemcpyDeviceToHost, s->st));
+    int e;
+    for (int round = 0;; ++round) {
+        launch_conflicts<T>(p, mm, s->tau, flag, cnt, n, s->st);
+        if ((e = check_launch())) return e;
+        HIPCHK(hipMemcpyAsync(conf.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
-        if (nconf == 0) {
-            // decode and walk every BDD with the point; rejecting rows flag
+        bool any = false;
+        for (int64_t k = 0; k < n; ++k) {
+            cand[k] = open[k] && conf[k] == 0;
+            any = any || cand[k];
+        }
+        if (any) {
+            // decode and walk the BDDs of the candidates; rejecting rows flag
             // their variables as conflicts for the next perturbation
+            HIPCHK(hipMemcpyAsync(mask, cand.data(), (size_t)n, hipMemcpyHostToDevice, s->st));
             launch_decode<T>(p, mm, xd, s->st);
-            launch_check(p, xd, flag, counter + 2, s->st);
-            int32_t nbad = 0;
+            launch_check(p, xd, flag, cnt + n, mask, n, s->st);
             if ((e = check_launch())) return e;
-            HIPCHK(hipMemcpyAsync(&nbad, counter + 2, 4, hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipMemcpyAsync(bad.data(), cnt + n, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipStreamSynchronize(s->st));
-            if (nbad == 0) {
-                rc = BDDMMA_OK;
-                break;
+            bool got = false;
+            for (int64_t k = 0; k < n; ++k) {
+                take[k] = cand[k] && bad[k] == 0;
+                if (take[k]) {
+                    open[k] = 0;
+                    rounds[k] = round;
+                    --n_open;
+                    got = true;
+                }
+            }
+            if (got) {
+                HIPCHK(hipMemcpyAsync(mask, take.data(), (size_t)n, hipMemcpyHostToDevice, s->st));
+                launch_take_x(p, xd, xb, mask, s->st);
             }
         }
-        if (round == s->opt.max_rounds) break;
+        for (int64_t k = 0; k < n; ++k)
+            if (open[k]) rounds[k] = round;
+        if (n_open == 0 || round == s->opt.max_rounds) break;
         launch_perturb<T>(p, lam, mm, s->tau, delta, s->opt.seed, (uint64_t)round, s->opt.perturb_scale, flag, s->st);
         launch_fill<uint8_t>(flag, 0, V, s->st);
         delta = delta * s->opt.alpha;
@@ -480,27 +534,57 @@ int round_T(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds_out)
     }
     launch_copy<T>(lam, lam_b, S, s->st);
     launch_copy<T>(mm, mm_b, S, s->st);
-    int e = check_launch();
-    if (e) return e;
-    HIPCHK(hipStreamSynchronize(s->st));
-    if (rounds_out) *rounds_out = round;
-    if (rc != BDDMMA_OK) return fail(rc, "rounding did not remove all conflicts within max_rounds");
-    // full point (presolved values included), exact int64 check of every
-    // original row and the objective, all on the device
+    // full points (presolved values included), exact int64 check of every
+    // original row and the objective per instance, all on the device
     uint8_t *xf = s->ptr<uint8_t>(s->L.xfull);
-    double *red = s->ptr<double>(s->L.red);
-    launch_finalize_x(s->rows, V, xd, xf, s->st);
-    launch_row_check(s->rows, xf, counter + 3, s->st);
-    launch_objective(s->ptr<double>(s->L.cost), xf, V, red + 2 * kRedBlocks + 4, red + 3 * kRedBlocks + 9, s->st);
+    double *res = s->ptr<double>(s->L.ires);
+    launch_finalize_x(s->rows, V, xb, xf, s->st);
+    launch_row_check(s->rows, xf, cnt + 2 * n, n, s->st);
+    double *opart = s->ptr<double>(s->L.opart);
+    launch_obj_chunks(s->ptr<double>(s->L.cost), xf, s->ptr<int64_t>(s->L.ochunk), (int64_t)s->ochunk.size() - 1, V,
+                      opart, s->st);
+    launch_seg_sum(opart, s->ptr<int64_t>(s->L.oseg), n, nullptr, res, s->st);
     if ((e = check_launch())) return e;
-    int32_t nviol = 0;
-    double u = 0.0;
-    HIPCHK(hipMemcpyAsync(&nviol, counter + 3, 4, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipMemcpyAsync(&u, red + 3 * kRedBlocks + 9, 8, hipMemcpyDeviceToHost, s->st));
-    if (V > 0) HIPCHK(hipMemcpyAsync(x_out, xf, (size_t)V, hipMemcpyDeviceToHost, s->st));
+    ub.resize((size_t)n);
+    xfull.resize((size_t)V);
+    HIPCHK(hipMemcpyAsync(viol.data(), cnt + 2 * n, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(ub.data(), res, (size_t)n * 8, hipMemcpyDeviceToHost, s->st));
+    if (V > 0) HIPCHK(hipMemcpyAsync(xfull.data(), xf, (size_t)V, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    if (nviol != 0) return fail(BDDMMA_ERR_STATE, "decoded point violates an original row");
-    if (ub) *ub = u;
+    status.resize((size_t)n);
+    for (int64_t k = 0; k < n; ++k)
+        status[k] = open[k] ? BDDMMA_ERR_NOT_CONVERGED : viol[k] ? BDDMMA_ERR_STATE : BDDMMA_OK;
+    return BDDMMA_OK;
+}
+
+// per-instance bounds: LB_free of the last recorded sweep, LB_cert (with the
+// residual correction) and the largest multiplier residual
+template <typename T>
+int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res)
+{
+    const DevProblem &p = s->dp;
+    const int64_t n = s->n_inst(), nt = (int64_t)s->pk.tiles.size();
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    double *res = s->ptr<double>(s->L.ires), *tile_e = s->ptr<double>(s->L.tile_e);
+    const int64_t *seg = s->ptr<int64_t>(s->L.inst_tile);
+    const double *off = s->ptr<double>(s->L.inst_off);
+    if (lb_free) {
+        if (s->last_row < 0) return fail(BDDMMA_ERR_STATE, "no sweep recorded since bind / reset / load");
+        launch_seg_sum(s->ptr<double>(s->L.lbpart) + (size_t)s->last_row * nt, seg, n, off, res, s->st);
+    }
+    launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
+    launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
+    launch_residual_seg<T>(p, lam, mm, s->opt.omega, n, res + 2 * n, res + 3 * n, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
+    std::vector<double> h((size_t)(4 * n));
+    HIPCHK(hipMemcpyAsync(h.data(), res, (size_t)(4 * n) * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (int64_t k = 0; k < n; ++k) {
+        if (lb_free) lb_free[k] = h[k];
+        if (lb_cert) lb_cert[k] = h[n + k] - h[2 * n + k];
+        if (max_res) max_res[k] = h[3 * n + k];
+    }
     return BDDMMA_OK;
 }
 
@@ -592,6 +676,53 @@ void bddmma_destroy(bddmma_solver *s)
     delete s;
 }
 
+namespace {
+
+// presolve, compile, pack and lay out the ingested ILP (or batch)
+int load_compiled(bddmma_solver *s)
+{
+    std::string msg;
+    int rc = build_problem(s->prob, msg);
+    if (rc == ST_OK) {
+        int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
+        rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
+                          1024.0 * s->opt.class_merge_kib, s->pk, msg);
+    }
+    if (rc != ST_OK) {
+        s->prob = Problem();
+        s->pk = Packed();
+        return fail(rc, msg);
+    }
+    {
+        const int64_t nt = std::max<int64_t>(1, (int64_t)s->pk.tiles.size());
+        s->hist_chunk = std::max<int64_t>(16, std::min<int64_t>(1024, kHistBytes / (8 * nt)));
+    }
+    const Ilp &il = s->prob.ilp;
+    {
+        // objective chunks: kObjChunk variables from every instance start
+        s->ochunk.clear();
+        s->oseg.assign(1, 0);
+        for (int64_t k = 0; k < il.n_inst(); ++k) {
+            for (int64_t b = il.inst_var[k]; b < il.inst_var[k + 1]; b += kObjChunk) s->ochunk.push_back(b);
+            s->oseg.push_back((int64_t)s->ochunk.size());
+        }
+        s->ochunk.push_back(il.n_vars);
+    }
+    // zero threshold of Alg. 2 per instance (from that instance's costs)
+    s->inst_tau.assign((size_t)il.n_inst(), 0.0);
+    for (int64_t k = 0; k < il.n_inst(); ++k) {
+        double cmax = 1.0;
+        for (int64_t i = il.inst_var[k]; i < il.inst_var[k + 1]; ++i) cmax = std::max(cmax, std::fabs(il.cost[i]));
+        s->inst_tau[k] = s->opt.tau >= 0.0 ? s->opt.tau : (s->opt.precision == 64 ? 0.0 : 1e-6 * cmax);
+    }
+    s->tau = s->inst_tau.empty() ? 0.0 : s->inst_tau[0];
+    s->L = make_layout(*s);
+    s->loaded = true;
+    return BDDMMA_OK;
+}
+
+}  // namespace
+
 int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
                     const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs)
 {
@@ -600,23 +731,11 @@ int bddmma_load_ilp(bddmma_solver *s, int64_t n_vars, const double *costs, int64
     if (s->loaded) return fail(BDDMMA_ERR_STATE, "an ILP is already loaded");
     std::string msg;
     int rc = ingest_ilp(s->prob.ilp, n_vars, costs, n_rows, row_ptr, col, coef, sense, rhs, msg);
-    if (rc != ST_OK) return fail(rc, msg);
-    rc = build_problem(s->prob, msg);
-    if (rc != ST_OK) return fail(rc, msg);
-    int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
-    rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                      1024.0 * s->opt.class_merge_kib, s->pk, msg);
-    if (rc != ST_OK) return fail(rc, msg);
-    {
-        const int64_t nt = std::max<int64_t>(1, (int64_t)s->pk.tiles.size());
-        s->hist_chunk = std::max<int64_t>(16, std::min<int64_t>(1024, kHistBytes / (8 * nt)));
+    if (rc != ST_OK) {
+        s->prob = Problem();
+        return fail(rc, msg);
     }
-    s->L = make_layout(*s);
-    double cmax = 1.0;
-    for (double c : s->prob.ilp.cost) cmax = std::max(cmax, std::fabs(c));
-    s->tau = s->opt.tau >= 0.0 ? s->opt.tau : (s->opt.precision == 64 ? 0.0 : 1e-6 * cmax);
-    s->loaded = true;
-    return BDDMMA_OK;
+    return load_compiled(s);
     GUARD_END
 }
 
@@ -704,6 +823,17 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
         r.rhs = s->ptr<int64_t>(L.r_rhs);
         r.n_rows = ilp.n_rows;
         r.preset = s->ptr<int8_t>(L.preset);
+        // instances (batches)
+        HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
+        HIPCHK(up(L.tile_inst, pk.tile_inst.data(), pk.tile_inst.size() * 4));
+        HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
+        HIPCHK(up(L.inst_var, ilp.inst_var.data(), ilp.inst_var.size() * 8));
+        HIPCHK(up(L.inst_tile, pk.inst_tile.data(), pk.inst_tile.size() * 8));
+        HIPCHK(up(L.inst_off, s->prob.inst_offset.data(), s->prob.inst_offset.size() * 8));
+        HIPCHK(up(L.inst_tau, s->inst_tau.data(), s->inst_tau.size() * 8));
+        HIPCHK(up(L.ochunk, s->ochunk.data(), s->ochunk.size() * 8));
+        HIPCHK(up(L.oseg, s->oseg.data(), s->oseg.size() * 8));
+        r.row_inst = pk.row_inst.empty() ? nullptr : s->ptr<int32_t>(L.row_inst);
     }
     DevProblem &d = s->dp;
     d.tiles = s->ptr<TileDesc>(L.tiles);
@@ -725,6 +855,11 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     d.n_slots = pk.n_slots;
     d.scratch = s->dev + L.scratch;
     d.lds_lane_elems = pk.max_lds_lane_elems;
+    const bool batch = s->n_inst() > 1;
+    d.var_inst = batch ? s->ptr<int32_t>(L.var_inst) : nullptr;
+    d.tile_inst = batch ? s->ptr<int32_t>(L.tile_inst) : nullptr;
+    d.inst_var = batch ? s->ptr<int64_t>(L.inst_var) : nullptr;
+    d.inst_tau = batch ? s->ptr<double>(L.inst_tau) : nullptr;
     if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
     else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
     launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
@@ -737,6 +872,7 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     s->hist_synced = 0;
     s->lbh_n = 0;
     s->part_n = 0;
+    s->last_row = -1;
     s->hist.clear();
     return BDDMMA_OK;
     GUARD_END
@@ -756,6 +892,7 @@ int bddmma_reset(bddmma_solver *s)
     s->hist_synced = 0;
     s->lbh_n = 0;
     s->part_n = 0;
+    s->last_row = -1;
     s->hist.clear();
     return BDDMMA_OK;
     GUARD_END
@@ -890,7 +1027,85 @@ int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *r
     int rc = check_ready(s);
     if (rc) return rc;
     if (!x_out) return fail(BDDMMA_ERR_INVALID_ARG, "x_out is NULL");
-    return s->elem == 8 ? round_T<double>(s, x_out, ub, rounds) : round_T<float>(s, x_out, ub, rounds);
+    std::vector<int32_t> rk, st;
+    std::vector<double> u;
+    std::vector<uint8_t> x;
+    rc = s->elem == 8 ? round_T<double>(s, rk, st, u, x) : round_T<float>(s, rk, st, u, x);
+    if (rc) return rc;
+    // all instances must close (a single ILP is one instance)
+    int32_t rmax = 0, worst = BDDMMA_OK;
+    double total = 0.0;
+    for (size_t k = 0; k < st.size(); ++k) {
+        rmax = std::max(rmax, rk[k]);
+        total += u[k];
+        if (st[k] != BDDMMA_OK && worst == BDDMMA_OK) worst = st[k];
+    }
+    if (rounds) *rounds = rmax;
+    if (worst == BDDMMA_ERR_NOT_CONVERGED) return fail(worst, "rounding did not remove all conflicts within max_rounds");
+    if (worst != BDDMMA_OK) return fail(worst, "decoded point violates an original row");
+    std::copy(x.begin(), x.end(), x_out);
+    if (ub) *ub = total;
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_load_batch(bddmma_solver *s, int64_t n_inst, const int64_t *inst_vars, const int64_t *inst_rows,
+                      int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                      const int32_t *coef, const int8_t *sense, const int64_t *rhs)
+{
+    GUARD_BEGIN
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (s->loaded) return fail(BDDMMA_ERR_STATE, "an ILP is already loaded");
+    std::string msg;
+    int rc = ingest_ilp(s->prob.ilp, n_vars, costs, n_rows, row_ptr, col, coef, sense, rhs, msg);
+    if (rc == ST_OK) rc = set_instances(s->prob.ilp, n_inst, inst_vars, inst_rows, msg);
+    if (rc != ST_OK) {
+        s->prob = Problem();
+        return fail(rc, msg);
+    }
+    return load_compiled(s);
+    GUARD_END
+}
+
+int bddmma_num_instances(const bddmma_solver *s, int64_t *n)
+{
+    if (!s || !n) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    *n = s->n_inst();
+    return BDDMMA_OK;
+}
+
+int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    return s->elem == 8 ? batch_bounds_T<double>(s, lb_free, lb_cert, max_res)
+                        : batch_bounds_T<float>(s, lb_free, lb_cert, max_res);
+    GUARD_END
+}
+
+int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds, int32_t *status)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!x_out || !ub || !rounds || !status) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    std::vector<int32_t> rk, st;
+    std::vector<double> u;
+    std::vector<uint8_t> x;
+    rc = s->elem == 8 ? round_T<double>(s, rk, st, u, x) : round_T<float>(s, rk, st, u, x);
+    if (rc) return rc;
+    const Ilp &ilp = s->prob.ilp;
+    for (int64_t k = 0; k < s->n_inst(); ++k) {
+        rounds[k] = rk[k];
+        status[k] = st[k];
+        if (st[k] == BDDMMA_OK) {
+            ub[k] = u[k];
+            std::copy(x.begin() + ilp.inst_var[k], x.begin() + ilp.inst_var[k + 1], x_out + ilp.inst_var[k]);
+        }
+    }
+    return BDDMMA_OK;
     GUARD_END
 }
 
@@ -949,6 +1164,7 @@ int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes)
     s->hist_synced = s->sweeps;
     s->lbh_n = 0;
     s->part_n = 0;
+    s->last_row = -1;
     return BDDMMA_OK;
     GUARD_END
 }

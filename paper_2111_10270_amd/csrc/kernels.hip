@@ -473,6 +473,7 @@ __global__ __launch_bounds__(kRedThreads) void k_conflicts(DevProblem P, const T
     int c = 0;
     if (v < P.n_vars) {
         const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+        if (P.inst_tau) tau = P.inst_tau[P.var_inst[v]];
         if (q0 != q1) {
             bool pos = true, neg = true;
             for (int32_t q = q0; q < q1; ++q) {
@@ -482,6 +483,11 @@ __global__ __launch_bounds__(kRedThreads) void k_conflicts(DevProblem P, const T
             }
             c = (flag[v] || !(pos || neg)) ? 1 : 0;
         }
+    }
+    if (P.var_inst) {
+        // batch: one count per instance
+        if (c) atomicAdd(counter + P.var_inst[v], 1);
+        return;
     }
     const double t = block_sum((double)c, sh);
     if (threadIdx.x == 0 && t > 0.0) atomicAdd(counter, (int32_t)t);
@@ -510,7 +516,10 @@ __global__ __launch_bounds__(256) void k_perturb(DevProblem P, T *__restrict__ l
     if (v >= P.n_vars) return;
     const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
     if (q0 == q1) return;
-    double r = 2.0 * u01(seed, round, (uint64_t)v) - 1.0;
+    // the draw depends on the variable's index inside its instance only
+    const uint64_t li = P.var_inst ? (uint64_t)(v - P.inst_var[P.var_inst[v]]) : (uint64_t)v;
+    if (P.inst_tau) tau = P.inst_tau[P.var_inst[v]];
+    double r = 2.0 * u01(seed, round, li) - 1.0;
     if (scale == 0) r = r * delta;
     bool pos = true, neg = true, zero = true;
     double sum = 0.0;
@@ -553,12 +562,15 @@ __global__ __launch_bounds__(256) void k_decode(DevProblem P, const T *__restric
 // whose x entry is 0 and whose chain nodes accept either value.
 __global__ __launch_bounds__(kThreads) void k_check(DevProblem P, const uint8_t *__restrict__ x,
                                                     uint8_t *__restrict__ flag, int32_t *counter,
+                                                    const uint8_t *__restrict__ only,
                                                     const int32_t *__restrict__ list, int64_t tile_count)
 {
     const int lane = threadIdx.x & (kLanes - 1);
     const int64_t lt = xcd_block() * kWavesPerBlock + uni(threadIdx.x >> 6);
     if (lt >= tile_count) return;
     const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
+    const int32_t inst = P.tile_inst ? P.tile_inst[tile] : 0;
+    if (only && !only[inst]) return;
     const TileView tv = load_tile(P.tiles + tile);
     // unused lanes of a partially filled tile carry the padding variable at
     // layer 0; they stand for no row
@@ -575,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_check(DevProblem P, const uint8_t 
     }
     ok = ok && node == kTop;
     if (!ok) {
-        atomicAdd(counter, 1);
+        atomicAdd(counter + inst, 1);
         for (uint32_t h = 0; h < tv.K; ++h) flag[P.pair_var[tv.pb + h * kLanes + lane]] = 1;
     }
 }
@@ -602,21 +614,78 @@ __global__ __launch_bounds__(kRedThreads) void k_row_check(DevRows R, const uint
         const int64_t b = R.rhs[r];
         bad = !(sn < 0 ? lhs <= b : sn > 0 ? lhs >= b : lhs == b);
     }
+    if (R.row_inst) {
+        if (bad) atomicAdd(counter + R.row_inst[r], 1);
+        return;
+    }
     const double t = block_sum((double)bad, sh);
     if (threadIdx.x == 0 && t > 0.0) atomicAdd(counter, (int32_t)t);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_objective_stage1(const double *__restrict__ cost,
-                                                                  const uint8_t *__restrict__ x, int64_t n,
-                                                                  double *__restrict__ out)
+// objective of one chunk of variables [b, b + kObjChunk) (clipped to the
+// chunk list's next start), fixed order
+__global__ __launch_bounds__(kRedThreads) void k_obj_chunk(const double *__restrict__ cost,
+                                                           const uint8_t *__restrict__ x,
+                                                           const int64_t *__restrict__ chunk_begin,
+                                                           double *__restrict__ part)
 {
     __shared__ double sh[kRedThreads];
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t a = (int64_t)blockIdx.x * per, b = a + per < n ? a + per : n;
+    const int64_t a = chunk_begin[blockIdx.x], b = chunk_begin[blockIdx.x + 1];
     double s = 0.0;
     for (int64_t i = a + threadIdx.x; i < b; i += kRedThreads) s += x[i] ? cost[i] : 0.0;
     const double t = block_sum(s, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = t;
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[k] = offset[k] + sum of part[seg[k] .. seg[k+1]), fixed order; one block per segment
+__global__ __launch_bounds__(kRedThreads) void k_seg_sum(const double *__restrict__ part,
+                                                         const int64_t *__restrict__ seg,
+                                                         const double *__restrict__ offset, double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t a = seg[blockIdx.x], b = seg[blockIdx.x + 1];
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRedThreads) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t + (offset ? offset[blockIdx.x] : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_take_x(const int32_t *__restrict__ var_inst, const uint8_t *__restrict__ x,
+                                                uint8_t *__restrict__ xbest, const uint8_t *__restrict__ take,
+                                                int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && take[var_inst ? var_inst[i] : 0]) xbest[i] = x[i];
+}
+
+// residual of one instance per block: r_i = sum_j (lam + omega M) - c_i
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_residual_seg(DevProblem P, const T *__restrict__ lam,
+                                                              const T *__restrict__ mm, double omega,
+                                                              double *__restrict__ pos_out,
+                                                              double *__restrict__ max_out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t a = P.inst_var ? P.inst_var[blockIdx.x] : 0, b = P.inst_var ? P.inst_var[blockIdx.x + 1] : P.n_vars;
+    double pos = 0.0, mx = 0.0;
+    for (int64_t v = a + threadIdx.x; v < b; v += kRedThreads) {
+        const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
+        if (q0 == q1) continue;
+        double s = 0.0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t sl = P.vslot[q];
+            s += (double)lam[sl] + omega * (double)mm[sl];
+        }
+        const double r = s - P.cost[v];
+        if (r > 0.0) pos += r;
+        mx = fmax(mx, fabs(r));
+    }
+    const double tp = block_sum(pos, sh);
+    const double tm = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        pos_out[blockIdx.x] = tp;
+        max_out[blockIdx.x] = tm;
+    }
 }
 
 template <typename T>
@@ -752,9 +821,9 @@ void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omeg
 
 template <typename T>
 void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_t *flag, int32_t *counter,
-                      hipStream_t st)
+                      int64_t n_inst, hipStream_t st)
 {
-    launch_fill<int32_t>(counter, 0, 1, st);
+    launch_fill<int32_t>(counter, 0, n_inst, st);
     if (p.n_vars > 0)
         hipLaunchKernelGGL((k_conflicts<T>), dim3(blocks_for(p.n_vars, kRedThreads)), dim3(kRedThreads), 0, st, p, mm,
                            tau, flag, counter);
@@ -782,30 +851,53 @@ void launch_finalize_x(const DevRows &r, int64_t n_vars, const uint8_t *xdec, ui
         hipLaunchKernelGGL(k_finalize_x, dim3(blocks_for(n_vars, 256)), dim3(256), 0, st, r.preset, xdec, xfull, n_vars);
 }
 
-void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, hipStream_t st)
+void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, int64_t n_inst, hipStream_t st)
 {
-    launch_fill<int32_t>(counter, 0, 1, st);
+    launch_fill<int32_t>(counter, 0, n_inst, st);
     if (r.n_rows > 0)
         hipLaunchKernelGGL(k_row_check, dim3(blocks_for(r.n_rows, kRedThreads)), dim3(kRedThreads), 0, st, r, xfull,
                            counter);
 }
 
-void launch_objective(const double *cost, const uint8_t *xfull, int64_t n_vars, double *stage, double *out,
-                      hipStream_t st)
+void launch_obj_chunks(const double *cost, const uint8_t *x, const int64_t *chunk_begin, int64_t n_chunks,
+                       int64_t n_vars, double *part, hipStream_t st)
 {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n_vars + 4095) / 4096));
-    hipLaunchKernelGGL(k_objective_stage1, dim3(nb), dim3(kRedThreads), 0, st, cost, xfull, n_vars, stage);
-    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(kRedThreads), 0, st, stage, nb, 0.0, out);
+    (void)n_vars;
+    if (n_chunks > 0)
+        hipLaunchKernelGGL(k_obj_chunk, dim3((unsigned)n_chunks), dim3(kRedThreads), 0, st, cost, x, chunk_begin, part);
 }
 
-void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st)
+void launch_seg_sum(const double *part, const int64_t *seg, int64_t n_seg, const double *offset, double *out,
+                    hipStream_t st)
 {
-    launch_fill<int32_t>(counter, 0, 1, st);
+    if (n_seg > 0) hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)n_seg), dim3(kRedThreads), 0, st, part, seg, offset, out);
+}
+
+void launch_take_x(const DevProblem &p, const uint8_t *x, uint8_t *xbest, const uint8_t *take, hipStream_t st)
+{
+    if (p.n_vars > 0)
+        hipLaunchKernelGGL(k_take_x, dim3(blocks_for(p.n_vars, 256)), dim3(256), 0, st, p.var_inst, x, xbest, take,
+                           p.n_vars);
+}
+
+template <typename T>
+void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, int64_t n_inst, double *pos,
+                         double *mx, hipStream_t st)
+{
+    if (n_inst > 0)
+        hipLaunchKernelGGL((k_residual_seg<T>), dim3((unsigned)n_inst), dim3(kRedThreads), 0, st, p, lam, mm, omega,
+                           pos, mx);
+}
+
+void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, const uint8_t *only,
+                  int64_t n_inst, hipStream_t st)
+{
+    launch_fill<int32_t>(counter, 0, n_inst, st);
     for (int l : {(int)LIST_GEN_LDS_ALL, (int)LIST_GEN_GLOB_ALL}) {
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
         if (n > 0)
             hipLaunchKernelGGL(k_check, dim3(grid8(n, kWavesPerBlock)), dim3(kThreads), 0, st, p, x, flag, counter,
-                               p.lists + p.list_off[l], n);
+                               only, p.lists + p.list_off[l], n);
     }
 }
 
@@ -829,8 +921,10 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
     template void launch_init<T>(const DevProblem &, T *, T *, hipStream_t);                                        \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \
     template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
-    template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *,            \
+    template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *, int64_t,   \
                                       hipStream_t);                                                                  \
+    template void launch_residual_seg<T>(const DevProblem &, const T *, const T *, double, int64_t, double *,       \
+                                         double *, hipStream_t);                                                     \
     template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t, int,    \
                                     const uint8_t *, hipStream_t);                                                   \
     template void launch_decode<T>(const DevProblem &, const T *, uint8_t *, hipStream_t);                          \

@@ -32,6 +32,12 @@ struct DevProblem {
     int64_t n_vars, n_slots;
     void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
     int lds_lane_elems;     // per-lane LDS elements of the largest LDS tile
+    // batches of independent instances (nullptr for a single ILP): instance
+    // of every variable and tile, and the first variable of every instance
+    const int32_t *var_inst;
+    const int32_t *tile_inst;
+    const int64_t *inst_var;
+    const double *inst_tau;   // Alg. 2 zero threshold per instance (replaces tau)
 };
 
 constexpr int kRedBlocks = 512;
@@ -89,15 +95,36 @@ void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, d
 template <typename T>
 void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, hipStream_t st);
 
-// counter[0] = number of variables with a zero / disagreeing min-marginal sign or a flag
+// counter[k] = number of variables of instance k with a zero / disagreeing
+// min-marginal sign or a flag (counter[0..n_inst) is cleared first)
 template <typename T>
 void launch_conflicts(const DevProblem &p, const T *mm, double tau, const uint8_t *flag, int32_t *counter,
-                      hipStream_t st);
+                      int64_t n_inst, hipStream_t st);
 
-// one Alg. 2 perturbation of every variable
+// one Alg. 2 perturbation of every variable; the random draw of variable i
+// uses its index inside its instance
 template <typename T>
 void launch_perturb(const DevProblem &p, T *lam, const T *mm, double tau, double delta, uint64_t seed,
                     uint64_t round, int scale, const uint8_t *flag, hipStream_t st);
+
+// xbest[i] = x[i] for the variables of instances k with take[k] != 0
+void launch_take_x(const DevProblem &p, const uint8_t *x, uint8_t *xbest, const uint8_t *take, hipStream_t st);
+
+// out[k] = offset[k] (0 if offset is null) + sum of part[seg[k] .. seg[k+1]) in a fixed order
+void launch_seg_sum(const double *part, const int64_t *seg, int64_t n_seg, const double *offset, double *out,
+                    hipStream_t st);
+
+// per-instance objective sum_i cost_i x_i over [inst_var[k], inst_var[k+1]) in
+// chunks of kObjChunk variables from the instance start: part[c] per chunk
+// (chunk list from the host), then launch_seg_sum over each instance's chunks
+constexpr int64_t kObjChunk = 1 << 16;
+void launch_obj_chunks(const double *cost, const uint8_t *x, const int64_t *chunk_begin, int64_t n_chunks,
+                       int64_t n_vars, double *part, hipStream_t st);
+
+// per instance: pos[k] = sum max(r_i, 0), mx[k] = max |r_i| over its variables
+template <typename T>
+void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, int64_t n_inst, double *pos,
+                         double *mx, hipStream_t st);
 
 // x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
 template <typename T>
@@ -112,21 +139,23 @@ struct DevRows {
     const int64_t *rhs;       // [n_rows]
     int64_t n_rows;
     const int8_t *preset;     // [n_vars] presolved value (0/1) or -1 when decoded
+    const int32_t *row_inst;  // [n_rows] instance of every row (batches), else nullptr
 };
 
 // full point: xfull[i] = preset[i] >= 0 ? preset[i] : xdec[i]
 void launch_finalize_x(const DevRows &r, int64_t n_vars, const uint8_t *xdec, uint8_t *xfull, hipStream_t st);
 
-// counter[0] = number of original rows xfull violates (int64 arithmetic)
-void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, hipStream_t st);
+// counter[k] = number of original rows of instance k xfull violates (int64
+// arithmetic; counter[0..n_inst) is cleared first)
+void launch_row_check(const DevRows &r, const uint8_t *xfull, int32_t *counter, int64_t n_inst, hipStream_t st);
 
-// out[0] = sum_i cost_i * xfull_i in a fixed order (stage scratch: kRedBlocks doubles)
-void launch_objective(const double *cost, const uint8_t *xfull, int64_t n_vars, double *stage, double *out,
-                      hipStream_t st);
 
-// walk every BDD with the 0-1 point x (x[n_vars] must be 0): counter[0] +=
-// number of BDDs that reject it, flag[i] = 1 for every variable of those BDDs
-void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, hipStream_t st);
+// walk the BDDs of the instances k with only[k] != 0 (every BDD if only is
+// null) with the 0-1 point x (x[n_vars] must be 0): counter[k] += number of
+// BDDs of instance k that reject it, flag[i] = 1 for every variable of those
+// BDDs (counter[0..n_inst) is cleared first)
+void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, const uint8_t *only,
+                  int64_t n_inst, hipStream_t st);
 
 template <typename T>
 void launch_fill(T *dst, T value, int64_t n, hipStream_t st);

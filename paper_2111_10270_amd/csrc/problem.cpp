@@ -41,6 +41,8 @@ int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, cons
     if (nnz > 0 && (!col || !coef)) { msg = "col / coef are NULL"; return ST_INVALID; }
     o.n_vars = n_vars;
     o.n_rows = n_rows;
+    o.inst_var = {0, n_vars};
+    o.inst_row = {0, n_rows};
     o.cost.assign(costs, costs + n_vars);
     for (int64_t i = 0; i < n_vars; ++i)
         if (!(costs[i] == costs[i]) || costs[i] == __builtin_inf() || costs[i] == -__builtin_inf()) {
@@ -72,6 +74,31 @@ int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, cons
         for (auto &pr : ent) { o.col.push_back(pr.first); o.coef.push_back(pr.second); }
         o.row_ptr.push_back((int64_t)o.col.size());
     }
+    return ST_OK;
+}
+
+int set_instances(Ilp &ilp, int64_t n_inst, const int64_t *inst_vars, const int64_t *inst_rows, std::string &msg)
+{
+    if (n_inst < 1 || !inst_vars || !inst_rows) { msg = "a batch needs n_inst >= 1 and both count arrays"; return ST_INVALID; }
+    if (n_inst > INT32_MAX - 1) { msg = "too many instances"; return ST_INVALID; }
+    ilp.inst_var.assign(1, 0);
+    ilp.inst_row.assign(1, 0);
+    for (int64_t k = 0; k < n_inst; ++k) {
+        if (inst_vars[k] < 0 || inst_rows[k] < 0) { msg = "negative instance size"; return ST_INVALID; }
+        ilp.inst_var.push_back(ilp.inst_var.back() + inst_vars[k]);
+        ilp.inst_row.push_back(ilp.inst_row.back() + inst_rows[k]);
+    }
+    if (ilp.inst_var.back() != ilp.n_vars || ilp.inst_row.back() != ilp.n_rows) {
+        msg = "instance sizes do not add up to n_vars / n_rows";
+        return ST_INVALID;
+    }
+    for (int64_t k = 0; k < n_inst; ++k)
+        for (int64_t r = ilp.inst_row[k]; r < ilp.inst_row[k + 1]; ++r)
+            for (int64_t e = ilp.row_ptr[r]; e < ilp.row_ptr[r + 1]; ++e)
+                if (ilp.col[e] < ilp.inst_var[k] || ilp.col[e] >= ilp.inst_var[k + 1]) {
+                    msg = "row " + std::to_string(r) + " references a variable of another instance";
+                    return ST_INVALID;
+                }
     return ST_OK;
 }
 
@@ -323,15 +350,20 @@ int build_problem(Problem &p, std::string &msg)
         }
     p.lb_offset = 0.0;
     p.n_fixed = p.n_free = 0;
-    for (int64_t i = 0; i < ilp.n_vars; ++i) {
-        if (p.fixed[i] >= 0) {
-            p.lb_offset += p.fixed[i] ? ilp.cost[i] : 0.0;
-            p.n_fixed++;
-        } else if (p.deg[i] == 0) {
-            p.lb_offset += ilp.cost[i] < 0.0 ? ilp.cost[i] : 0.0;
-            p.n_free++;
+    p.inst_offset.assign((size_t)ilp.n_inst(), 0.0);
+    for (int64_t k = 0; k < ilp.n_inst(); ++k)
+        for (int64_t i = ilp.inst_var[k]; i < ilp.inst_var[k + 1]; ++i) {
+            double c = 0.0;
+            if (p.fixed[i] >= 0) {
+                c = p.fixed[i] ? ilp.cost[i] : 0.0;
+                p.n_fixed++;
+            } else if (p.deg[i] == 0) {
+                c = ilp.cost[i] < 0.0 ? ilp.cost[i] : 0.0;
+                p.n_free++;
+            }
+            p.lb_offset += c;
+            p.inst_offset[k] += c;
         }
-    }
     p.n_nodes = (int64_t)B.child.size();
     if (P >= INT32_MAX) { msg = "too many pairs"; return ST_INVALID; }
     return ST_OK;
@@ -366,7 +398,18 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         for (int64_t q = B.node_off[j]; q < B.node_off[j + 1]; ++q) h = mix64(h, B.child[q]);
         hash[j] = h;
     }
+    // instance of every BDD (tiles never mix instances of a batch)
+    const Ilp &ilp = p.ilp;
+    const bool batch = ilp.n_inst() > 1;
+    std::vector<int32_t> row_inst;
+    if (batch) {
+        row_inst.resize((size_t)ilp.n_rows);
+        for (int64_t k = 0; k < ilp.n_inst(); ++k)
+            for (int64_t r = ilp.inst_row[k]; r < ilp.inst_row[k + 1]; ++r) row_inst[r] = (int32_t)k;
+    }
+    auto inst_of = [&](int64_t j) { return batch ? row_inst[B.row[j]] : 0; };
     auto same_topology = [&](int64_t x, int64_t y) {
+        if (inst_of(x) != inst_of(y)) return false;
         if (k_of(x) != k_of(y) || n_of(x) != n_of(y) || hash[x] != hash[y]) return false;
         return std::equal(B.lay_width.begin() + B.lay_off[x], B.lay_width.begin() + B.lay_off[x + 1],
                           B.lay_width.begin() + B.lay_off[y]) &&
@@ -376,6 +419,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     std::vector<int64_t> order(nb);
     for (int64_t j = 0; j < nb; ++j) order[j] = j;
     std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        if (inst_of(x) != inst_of(y)) return inst_of(x) < inst_of(y);
         if (k_of(x) != k_of(y)) return k_of(x) < k_of(y);
         if (n_of(x) != n_of(y)) return n_of(x) < n_of(y);
         if (hash[x] != hash[y]) return hash[x] < hash[y];
@@ -402,14 +446,18 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         s = e;
     }
     std::sort(mixed.begin(), mixed.end(), [&](int64_t x, int64_t y) {
+        if (inst_of(x) != inst_of(y)) return inst_of(x) < inst_of(y);
         if (n_of(x) != n_of(y)) return n_of(x) < n_of(y);
         if (k_of(x) != k_of(y)) return k_of(x) < k_of(y);
         return x < y;
     });
-    for (size_t s = 0; s < mixed.size(); s += kLanes) {
+    for (size_t s = 0; s < mixed.size();) {
+        size_t e = s;
+        while (e < mixed.size() && e - s < (size_t)kLanes && inst_of(mixed[e]) == inst_of(mixed[s])) ++e;
         TilePlan tp;
-        for (int l = 0; l < kLanes; ++l) tp.lanes.push_back(s + l < mixed.size() ? mixed[s + l] : -1);
+        for (int l = 0; l < kLanes; ++l) tp.lanes.push_back(s + l < e ? mixed[s + l] : -1);
         plans.push_back(std::move(tp));
+        s = e;
     }
     // tile shapes
     for (auto &tp : plans) {
@@ -698,6 +746,38 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                             return ST_INVALID;
                         }
                 }
+    }
+    // instance ranges of the tiles (tiles are sorted by first row, and the rows
+    // of instance k precede those of instance k+1)
+    o.inst_tile.assign(1, 0);
+    o.tile_inst.clear();
+    o.var_inst.clear();
+    o.row_inst.clear();
+    for (size_t t = 0; t < plans.size(); ++t) {
+        int32_t k = 0;
+        for (int64_t j : plans[t].lanes)
+            if (j >= 0) {
+                k = inst_of(j);
+                break;
+            }
+        for (int64_t j : plans[t].lanes)
+            if (j >= 0 && inst_of(j) != k) {
+                msg = "internal error: a tile mixes instances";
+                return ST_INVALID;
+            }
+        if (batch) o.tile_inst.push_back(k);
+        while ((int64_t)o.inst_tile.size() <= (int64_t)k) o.inst_tile.push_back((int64_t)t);
+        if ((int64_t)o.inst_tile.size() != (int64_t)k + 1) {
+            msg = "internal error: tiles not ordered by instance";
+            return ST_INVALID;
+        }
+    }
+    while ((int64_t)o.inst_tile.size() <= ilp.n_inst()) o.inst_tile.push_back((int64_t)plans.size());
+    if (batch) {
+        o.row_inst = row_inst;
+        o.var_inst.resize((size_t)V);
+        for (int64_t k = 0; k < ilp.n_inst(); ++k)
+            for (int64_t i = ilp.inst_var[k]; i < ilp.inst_var[k + 1]; ++i) o.var_inst[i] = (int32_t)k;
     }
     o.n_slots = slots;
     o.scratch_elems = scratch;

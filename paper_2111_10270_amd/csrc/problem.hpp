@@ -17,6 +17,11 @@ struct Ilp {
     std::vector<int64_t> coef;
     std::vector<int8_t> sense;
     std::vector<int64_t> rhs;
+    // independent instances of a batch: instance k owns variables
+    // [inst_var[k], inst_var[k+1]) and rows [inst_row[k], inst_row[k+1]); a
+    // single ILP is one instance
+    std::vector<int64_t> inst_var, inst_row;
+    int64_t n_inst() const { return (int64_t)inst_var.size() - 1; }
 };
 
 // Flat store of compiled BDDs, in ascending original row order.
@@ -49,6 +54,10 @@ struct Packed {
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
     int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile
     int max_layers = 0, max_width = 0;
+    // batches: tiles are instance-pure and instance k owns tiles
+    // [inst_tile[k], inst_tile[k+1]); the id arrays are filled for batches only
+    std::vector<int64_t> inst_tile;
+    std::vector<int32_t> tile_inst, var_inst, row_inst;
 };
 
 struct Problem {
@@ -58,6 +67,7 @@ struct Problem {
     BddSet bdds;
     std::vector<int32_t> pair_var, pair_row;   // canonical pair order
     double lb_offset = 0.0;
+    std::vector<double> inst_offset;   // lb_offset per instance
     int64_t n_nodes = 0, n_fixed = 0, n_free = 0;
 };
 
@@ -68,6 +78,10 @@ enum Status { ST_OK = 0, ST_INVALID = -1, ST_INFEASIBLE = -2, ST_NOMEM = -3 };
 int ingest_ilp(Ilp &out, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
                const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
                std::string &msg);
+
+// Instance boundaries of a batch (n_inst counts of variables and rows, in
+// order); every row must reference variables of its own instance only.
+int set_instances(Ilp &ilp, int64_t n_inst, const int64_t *inst_vars, const int64_t *inst_rows, std::string &msg);
 
 // Presolve + compile every remaining row.  ST_OK / ST_INFEASIBLE / ST_INVALID.
 int build_problem(Problem &p, std::string &msg);

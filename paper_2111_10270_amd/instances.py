@@ -326,6 +326,30 @@ def random_ilp(n_vars: int, n_rows: int, max_row_len: int = 5, coef_range: int =
                      meta=dict(seed=seed, hidden=xs))
 
 
+def concat(ilps) -> ILP:
+    """Block-diagonal union of independent ILPs (variables and rows of
+    instance k follow those of instance k-1); meta holds the per-instance
+    variable and row counts."""
+    ilps = list(ilps)
+    nv = np.array([p.n_vars for p in ilps], dtype=np.int64)
+    nr = np.array([p.n_rows for p in ilps], dtype=np.int64)
+    voff = np.concatenate([[0], np.cumsum(nv)])
+    nnz_off = np.concatenate([[0], np.cumsum([p.nnz for p in ilps])])
+    row_ptr = np.concatenate([[0]] + [p.row_ptr[1:] + nnz_off[k] for k, p in enumerate(ilps)]).astype(np.int64)
+    return ILP(
+        n_vars=int(voff[-1]),
+        costs=np.concatenate([p.costs for p in ilps]) if ilps else np.zeros(0),
+        row_ptr=row_ptr,
+        col=np.concatenate([p.col.astype(np.int64) + voff[k] for k, p in enumerate(ilps)]).astype(np.int32)
+        if ilps else np.zeros(0, dtype=np.int32),
+        coef=np.concatenate([p.coef for p in ilps]).astype(np.int32) if ilps else np.zeros(0, dtype=np.int32),
+        sense=np.concatenate([p.sense for p in ilps]).astype(np.int8) if ilps else np.zeros(0, dtype=np.int8),
+        rhs=np.concatenate([p.rhs for p in ilps]).astype(np.int64) if ilps else np.zeros(0, dtype=np.int64),
+        name=f"batch{len(ilps)}",
+        meta=dict(inst_vars=nv, inst_rows=nr, names=[p.name for p in ilps]),
+    )
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------

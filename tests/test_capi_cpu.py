@@ -142,3 +142,52 @@ def test_register_path_tile_counts():
     assert merged.n_reg_tiles == st.n_reg_tiles and merged.n_reg_mixed_tiles == st.n_reg_mixed_tiles
     st = B.Solver(layer_class_ilp(), fast_path=0).stats
     assert st.n_reg_tiles == st.n_reg_mixed_tiles == st.n_reg_launches == 0
+
+
+# ---------------------------------------------------------------- batches
+def _batch_members():
+    return [I.random_ilp(14, 10, max_row_len=6, seed=4100), I.mrf_grid(4, 5, 3, pairwise="potts", seed=3),
+            I.random_ilp(30, 24, max_row_len=7, seed=4102), I.from_rows(3, [1.0, -1.0, 0.5], [])]
+
+
+def test_batch_structure_is_the_union_of_instances():
+    ilps = [p for p in _batch_members() if O.Oracle(p).status == O.OK]
+    b = B.Solver(ilps)
+    alone = [B.Solver(p) for p in ilps]
+    assert b.n_inst == len(ilps) and all(a.n_inst == 1 for a in alone)
+    st = b.stats
+    for f in ("n_bdds", "n_pairs", "n_nodes", "n_fixed", "n_free", "n_tiles"):
+        assert getattr(st, f) == sum(getattr(a.stats, f) for a in alone), f
+    assert st.lb_offset == sum(a.stats.lb_offset for a in alone)
+    pv, pr = b.pairs()
+    voff = np.cumsum([0] + [p.n_vars for p in ilps])
+    roff = np.cumsum([0] + [p.n_rows for p in ilps])
+    ref_v = np.concatenate([a.pairs()[0] + voff[k] for k, a in enumerate(alone)])
+    ref_r = np.concatenate([a.pairs()[1] + roff[k] for k, a in enumerate(alone)])
+    assert np.array_equal(pv, ref_v) and np.array_equal(pr, ref_r)
+
+
+def test_batch_rejects_cross_instance_rows_and_bad_counts():
+    a = I.from_rows(2, [1.0, 1.0], [([0, 1], [1, 1], -1, 1)])
+    u = I.concat([a, a])
+    bad = I.ILP(n_vars=u.n_vars, costs=u.costs, row_ptr=u.row_ptr, col=np.array([0, 1, 1, 2], dtype=np.int32),
+                coef=u.coef, sense=u.sense, rhs=u.rhs, meta=u.meta)
+    L = B.lib()
+    import ctypes as C
+    for ilp, nv, nr in ((bad, [2, 2], [1, 1]), (u, [2, 1], [1, 1]), (u, [2, 2], [2, 1])):
+        h = C.c_void_p()
+        assert L.bddmma_create(None, C.byref(h)) == 0
+        arrs = [np.ascontiguousarray(x) for x in (ilp.costs, ilp.row_ptr, ilp.col, ilp.coef, ilp.sense, ilp.rhs)]
+        nva, nra = np.array(nv, dtype=np.int64), np.array(nr, dtype=np.int64)
+        rc = L.bddmma_load_batch(h, len(nv), B._p(nva), B._p(nra), ilp.n_vars, B._p(arrs[0]), ilp.n_rows,
+                                 *[B._p(x) for x in arrs[1:]])
+        assert rc == B.INVALID_ARG
+        L.bddmma_destroy(h)
+
+
+def test_batch_with_an_infeasible_instance():
+    good = I.from_rows(2, [1.0, 1.0], [([0, 1], [1, 1], -1, 1)])
+    infeasible = I.from_rows(2, [1.0, 1.0], [([0, 1], [1, 1], 1, 3)])
+    with pytest.raises(B.BddmmaError) as e:
+        B.Solver([good, infeasible])
+    assert e.value.code == B.INFEASIBLE

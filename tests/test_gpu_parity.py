@@ -445,3 +445,51 @@ def test_graph_replay_matches_eager(name, prec):
         s.reset()
         s.run_dual(12)
     _same_run(eager, graph, "after reset")
+
+
+# ---------------------------------------------------------------- batches
+def _members():
+    ms = [I.random_ilp(14, 10, max_row_len=6, seed=4100 + k) for k in range(6)]
+    ms += [I.mrf_grid(5, 6, 3, pairwise="potts", seed=3), I.workload("mrf10x10L3"),
+           I.random_ilp(40, 30, max_row_len=7, seed=4107), I.from_rows(3, [1.0, -1.0, 0.5], [])]
+    return [p for p in ms if O.Oracle(p).status == O.OK]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_batch_matches_each_instance_alone(prec):
+    """every instance of a batch follows its solo trajectory bit for bit"""
+    ilps = _members()
+    note("batch of", len(ilps), "prec", prec)
+    b = solver(ilps, precision=prec)
+    alone = [solver(p, precision=prec) for p in ilps]
+    b.run_dual(25)
+    for a in alone:
+        a.run_dual(25)
+    lam, mm = b.multipliers()
+    pv, _ = b.pairs()
+    voff = np.cumsum([0] + [p.n_vars for p in ilps])
+    lbf, lbc, res = b.batch_bounds()
+    at = 0
+    for k, a in enumerate(alone):
+        la, ma = a.multipliers()
+        n = la.size
+        assert np.array_equal(lam[at:at + n], la) and np.array_equal(mm[at:at + n], ma), k
+        assert np.array_equal(pv[at:at + n] - voff[k], a.pairs()[0]), k
+        at += n
+        f, c, r = a.lower_bound()
+        tol = 1e-12 if prec == 64 else 1e-6
+        assert abs(lbf[k] - a.lb_history()[-1]) <= tol * max(1.0, abs(f)), k
+        assert abs(lbc[k] - c) <= tol * max(1.0, abs(c)), k
+        assert abs(res[k] - r) <= tol * max(1.0, abs(r)), k
+    assert abs(sum(lbf) - b.lb_history()[-1]) <= 1e-9 * max(1.0, abs(sum(lbf)))
+    rb = b.batch_round()
+    for k, a in enumerate(alone):
+        ra = a.round_primal()
+        assert rb["status"][k] == ra["rc"], k
+        assert rb["rounds"][k] == ra["rounds"], k
+        if ra["rc"] == 0:
+            assert np.array_equal(rb["x"][voff[k]:voff[k + 1]], ra["x"]), k
+            assert rb["ub"][k] == ra["ub"], k
+    # the dual state is untouched by the rounding
+    l2, m2 = b.multipliers()
+    assert np.array_equal(l2, lam) and np.array_equal(m2, mm)
