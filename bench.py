@@ -41,9 +41,17 @@ def parse():
                     help="replay blocks of G sweeps from a captured HIP graph (kernel time then comes from a "
                          "separate profiled pass after the timed steps); 0 = eager launches, whose sampled "
                          "sweeps are timed inside the timed steps")
+    ap.add_argument("--serve", type=int, default=64, metavar="N",
+                    help="batched serving measurement over N instances of the mixed stream (0 = skip)")
+    ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-iters", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sha() -> str:
@@ -84,6 +92,73 @@ def cpu_baseline(ilp, n_iter):
     return dict(value=n_iter / dt, unit="dual iters/s", cores=1, kind="oracle",
                 sample=f"{n_iter} Alg. 1 iterations of the same instance, FP64, one thread "
                        f"({dt:.1f} s; BDD construction not timed)")
+
+
+def serve(a, B, I, torch):
+    """Batched serving of a seeded stream of small instances (four families,
+    sizes drawn per instance).  A solve is serve_iters Alg. 1 iterations plus
+    the per-instance bounds (the serving target is the solo lower bound, which
+    every batched instance reproduces exactly).  Service times are measured on
+    the GPU, instance by instance (sequential) and in batches of consecutive
+    arrivals; latencies come from Poisson arrivals at twice the sequential
+    solve rate replayed against those service times (FIFO server)."""
+    import numpy as np
+
+    insts = I.serving_mix(a.serve, seed=5)
+    alone = [B.Solver(p, precision=a.precision) for p in insts]
+    groups = [list(range(i, min(i + a.serve_batch, len(insts)))) for i in range(0, len(insts), a.serve_batch)]
+    batches = [B.Solver([insts[k] for k in g], precision=a.precision) for g in groups]
+    log(f"serving: {len(insts)} instances and {len(groups)} batches loaded")
+
+    def run(solvers, k):
+        """bind + solve solvers[k], then drop it (and its workspace)"""
+        s = solvers[k]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.bind("cuda:0")
+        s.run_dual(a.serve_iters)
+        lbf, _, _ = s.batch_bounds()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        solvers[k] = None
+        return dt, lbf
+
+    run([B.Solver(insts[0], precision=a.precision)], 0)   # warm-up (allocator, code objects)
+    seq_t, seq_lb = [], []
+    for k in range(len(alone)):
+        dt, lbf = run(alone, k)
+        seq_t.append(dt)
+        seq_lb.append(lbf[0])
+    log("serving: sequential solves done")
+    bat_t, diff = [], 0.0
+    for j, g in enumerate(groups):
+        dt, lbf = run(batches, j)
+        bat_t.append(dt)
+        for q, k in enumerate(g):
+            diff = max(diff, abs(lbf[q] - seq_lb[k]) / max(1.0, abs(seq_lb[k])))
+    n = len(insts)
+    seq_rate = n / sum(seq_t)
+    rate = 2.0 * seq_rate
+    rng = np.random.default_rng(7)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    # sequential FIFO server
+    t, lat_seq = 0.0, []
+    for k in range(n):
+        t = max(t, arrive[k]) + seq_t[k]
+        lat_seq.append(t - arrive[k])
+    # batched server: a batch starts once its last member has arrived
+    t, lat_b = 0.0, []
+    for g, dt in zip(groups, bat_t):
+        t = max(t, arrive[g[-1]]) + dt
+        lat_b += [t - arrive[k] for k in g]
+    pct = lambda v, q: float(np.percentile(np.asarray(v) * 1e3, q))
+    return {"instances": n, "batch": a.serve_batch, "iterations": a.serve_iters,
+            "vars": int(sum(p.n_vars for p in insts)),
+            "seq_solves_per_s": seq_rate, "batched_solves_per_s": n / sum(bat_t),
+            "speedup": (n / sum(bat_t)) / seq_rate, "arrival_rate_per_s": rate,
+            "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99),
+            "seq_p50_ms": pct(lat_seq, 50), "seq_p99_ms": pct(lat_seq, 99),
+            "lb_max_rel_diff_vs_solo": diff}
 
 
 def main():
@@ -153,6 +228,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    log(f"{a.steps} timed steps done")
     ms_step = wall * 1e3 / a.steps
 
     if a.graph_sweeps and not a.no_profile:
@@ -195,6 +271,10 @@ def main():
         "result": {"lb_free": lf, "lb_cert": lc, "max_residual": res, "ub": r["ub"] if r["rc"] == 0 else None,
                    "rounding_rc": r["rc"], "rounding_rounds": r["rounds"]},
     }
+    if a.serve > 0:
+        s = None
+        torch.cuda.empty_cache()
+        out["batched"] = serve(a, B, I, torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ilp, a.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -350,6 +350,30 @@ def concat(ilps) -> ILP:
     )
 
 
+def serving_mix(n: int, seed: int = 5):
+    """A seeded stream of small instances for batched serving: the family is
+    uniform over {Potts MRF with 3 labels, truncated-linear MRF with 8 labels,
+    graph matching, cell tracking}; MRF side U{16..128}, matching points
+    U{50..1000}, tracking frames U{5..20} x detections U{50..500}."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        fam = int(rng.integers(0, 4))
+        sd = int(rng.integers(0, 2**31 - 1))
+        if fam == 0:
+            side = int(rng.integers(16, 129))
+            out.append(mrf_grid(side, side, 3, pairwise="potts", potts_weight=0.5, seed=sd))
+        elif fam == 1:
+            side = int(rng.integers(16, 129))
+            out.append(mrf_grid(side, side, 8, pairwise="trunc_linear", trunc=2, seed=sd))
+        elif fam == 2:
+            m = int(rng.integers(50, 1001))
+            out.append(graph_matching(n_left=m, n_right=m, k=10, n_pairs=m, seed=sd))
+        else:
+            out.append(cell_tracking(frames=int(rng.integers(5, 21)), dets=int(rng.integers(50, 501)), seed=sd))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------
