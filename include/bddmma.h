@@ -68,7 +68,7 @@ typedef struct {
                               -1 = never use LDS */
     int32_t  fast_path;    /* 1: tiles of 64 identical BDDs with <= 4 nodes per layer (and
                               width x layers <= 64), and tiles of different BDDs with <= 2
-                              nodes per layer and <= 20 layers, are swept by
+                              nodes per layer and <= 32 layers, are swept by
                               register-resident kernels, and variables with |J_i| <= 2
                               inside one tile are averaged in the sweep; 0: general
                               kernels and the averaging kernel only.  1 */

@@ -158,7 +158,7 @@ Layout make_layout(const bddmma_solver &s)
     L.inst_tau = take((size_t)NI * 8);
     L.ochunk = take(s.ochunk.size() * 8);
     L.oseg = take(s.oseg.size() * 8);
-    L.opart = take(s.ochunk.size() * 8);
+    L.opart = take(s.ochunk.size() * 2 * 8);
     L.imask = take((size_t)NI);
     L.xbest = take(V + 1);
     L.ires = take((size_t)NI * 4 * 8);   // per instance: lb_free, cert, residual pos, residual max / ub
@@ -574,7 +574,10 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
     }
     launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
     launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
-    launch_residual_seg<T>(p, lam, mm, s->opt.omega, n, res + 2 * n, res + 3 * n, s->st);
+    const int64_t nc = (int64_t)s->ochunk.size() - 1;
+    double *opart = s->ptr<double>(s->L.opart);
+    launch_residual_seg<T>(p, lam, mm, s->opt.omega, s->ptr<int64_t>(s->L.ochunk), nc, s->ptr<int64_t>(s->L.oseg), n,
+                           opart, opart + nc + 1, res + 2 * n, res + 3 * n, s->st);
     int rc = check_launch();
     if (rc) return rc;
     std::vector<double> h((size_t)(4 * n));

@@ -637,6 +637,18 @@ __global__ __launch_bounds__(kRedThreads) void k_obj_chunk(const double *__restr
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// out[k] = max of part[seg[k] .. seg[k+1]) (0 for an empty segment); one block per segment
+__global__ __launch_bounds__(kRedThreads) void k_seg_max(const double *__restrict__ part,
+                                                         const int64_t *__restrict__ seg, double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t a = seg[blockIdx.x], b = seg[blockIdx.x + 1];
+    double m = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kRedThreads) m = fmax(m, part[i]);
+    const double t = block_max(m, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 // out[k] = offset[k] + sum of part[seg[k] .. seg[k+1]), fixed order; one block per segment
 __global__ __launch_bounds__(kRedThreads) void k_seg_sum(const double *__restrict__ part,
                                                          const int64_t *__restrict__ seg,
@@ -658,15 +670,17 @@ __global__ __launch_bounds__(256) void k_take_x(const int32_t *__restrict__ var_
     if (i < n && take[var_inst ? var_inst[i] : 0]) xbest[i] = x[i];
 }
 
-// residual of one instance per block: r_i = sum_j (lam + omega M) - c_i
+// residual r_i = sum_j (lam + omega M) - c_i over one chunk of variables
+// [chunk_begin[c], chunk_begin[c+1]) per block: sum of max(r_i, 0) and max |r_i|
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_residual_seg(DevProblem P, const T *__restrict__ lam,
-                                                              const T *__restrict__ mm, double omega,
-                                                              double *__restrict__ pos_out,
-                                                              double *__restrict__ max_out)
+__global__ __launch_bounds__(kRedThreads) void k_residual_chunk(DevProblem P, const T *__restrict__ lam,
+                                                                const T *__restrict__ mm, double omega,
+                                                                const int64_t *__restrict__ chunk_begin,
+                                                                double *__restrict__ pos_out,
+                                                                double *__restrict__ max_out)
 {
     __shared__ double sh[kRedThreads];
-    const int64_t a = P.inst_var ? P.inst_var[blockIdx.x] : 0, b = P.inst_var ? P.inst_var[blockIdx.x + 1] : P.n_vars;
+    const int64_t a = chunk_begin[blockIdx.x], b = chunk_begin[blockIdx.x + 1];
     double pos = 0.0, mx = 0.0;
     for (int64_t v = a + threadIdx.x; v < b; v += kRedThreads) {
         const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
@@ -881,12 +895,18 @@ void launch_take_x(const DevProblem &p, const uint8_t *x, uint8_t *xbest, const 
 }
 
 template <typename T>
-void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, int64_t n_inst, double *pos,
-                         double *mx, hipStream_t st)
+void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, const int64_t *chunk_begin,
+                         int64_t n_chunks, const int64_t *seg, int64_t n_inst, double *part_pos, double *part_max,
+                         double *pos, double *mx, hipStream_t st)
 {
-    if (n_inst > 0)
-        hipLaunchKernelGGL((k_residual_seg<T>), dim3((unsigned)n_inst), dim3(kRedThreads), 0, st, p, lam, mm, omega,
-                           pos, mx);
+    if (n_chunks > 0)
+        hipLaunchKernelGGL((k_residual_chunk<T>), dim3((unsigned)n_chunks), dim3(kRedThreads), 0, st, p, lam, mm,
+                           omega, chunk_begin, part_pos, part_max);
+    if (n_inst > 0) {
+        hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)n_inst), dim3(kRedThreads), 0, st, part_pos, seg,
+                           (const double *)nullptr, pos);
+        hipLaunchKernelGGL(k_seg_max, dim3((unsigned)n_inst), dim3(kRedThreads), 0, st, part_max, seg, mx);
+    }
 }
 
 void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t *counter, const uint8_t *only,
@@ -923,8 +943,9 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
     template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
     template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *, int64_t,   \
                                       hipStream_t);                                                                  \
-    template void launch_residual_seg<T>(const DevProblem &, const T *, const T *, double, int64_t, double *,       \
-                                         double *, hipStream_t);                                                     \
+    template void launch_residual_seg<T>(const DevProblem &, const T *, const T *, double, const int64_t *,         \
+                                         int64_t, const int64_t *, int64_t, double *, double *, double *, double *, \
+                                         hipStream_t);                                                               \
     template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t, int,    \
                                     const uint8_t *, hipStream_t);                                                   \
     template void launch_decode<T>(const DevProblem &, const T *, uint8_t *, hipStream_t);                          \

@@ -121,10 +121,12 @@ constexpr int64_t kObjChunk = 1 << 16;
 void launch_obj_chunks(const double *cost, const uint8_t *x, const int64_t *chunk_begin, int64_t n_chunks,
                        int64_t n_vars, double *part, hipStream_t st);
 
-// per instance: pos[k] = sum max(r_i, 0), mx[k] = max |r_i| over its variables
+// per instance: pos[k] = sum max(r_i, 0), mx[k] = max |r_i| over its
+// variables, in the objective's chunks (part_* hold one value per chunk)
 template <typename T>
-void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, int64_t n_inst, double *pos,
-                         double *mx, hipStream_t st);
+void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, const int64_t *chunk_begin,
+                         int64_t n_chunks, const int64_t *seg, int64_t n_inst, double *part_pos, double *part_max,
+                         double *pos, double *mx, hipStream_t st);
 
 // x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
 template <typename T>

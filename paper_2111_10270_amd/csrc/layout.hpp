@@ -65,10 +65,10 @@ constexpr int kWClass[kNumWClasses] = {2, 4};
 // width-4 tiles deeper than 16 layers would need more than 170 VGPRs per lane
 // (one wave per SIMD); they stay on the general kernels
 constexpr bool fast_class_ok(int wi, int ki) { return kWClass[wi] * kKClass[ki] <= 64; }
-// Mixed tiles (lanes of different topologies) of width <= 2 and at most 20
+// Mixed tiles (lanes of different topologies) of width <= 2 and at most 32
 // layers run on the register kernel too, with per-lane node words in VGPRs
 // (same fixed stride and layer classes, words at fast_base + node * 64 + lane).
-constexpr bool mix_class_ok(int ki) { return kKClass[ki] <= 20; }
+constexpr bool mix_class_ok(int ki) { return kKClass[ki] <= 32; }
 
 // Tile lists.  Every tile is in exactly one of the two *_ALL lists (shortest
 // paths in LDS or in device scratch for the general kernels); tiles outside the
