@@ -267,7 +267,11 @@ def main():
         "kernel_ms": {"sweep": sweep_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # counter-measured bytes of one sweep launch over its event time
+                     "traffic_GBs": traffic / (sweep_ms * 1e-3) / 1e9 if traffic and sweep_ms > 0 else None,
+                     "traffic_frac": traffic / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                     if traffic and sweep_ms > 0 else None},
         "result": {"lb_free": lf, "lb_cert": lc, "max_residual": res, "ub": r["ub"] if r["rc"] == 0 else None,
                    "rounding_rc": r["rc"], "rounding_rounds": r["rounds"]},
     }
