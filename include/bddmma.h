@@ -85,7 +85,12 @@ typedef struct {
                               next larger class of their kind while the padding costs at
                               most this many KiB of traffic per sweep (fewer launches);
                               0 = one launch per non-empty class.  32768 */
-    int32_t  reserved[3];  /* must be zero */
+    int32_t  small_tiles;  /* problems of at most this many tiles sweep their tiles of 64
+                              identical width-2 BDDs with the per-lane (mixed) register
+                              kernel, so a sweep is one launch per layer class: the
+                              launches of small problems are latency-bound.  0 = never.
+                              2048 */
+    int32_t  reserved[2];  /* must be zero */
 } bddmma_options;
 
 typedef struct {

@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("reopt_iters", C.c_int32), ("max_rounds", C.c_int32), ("tau", C.c_double),
                 ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("fast_path", C.c_int32),
                 ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32),
-                ("class_merge_kib", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("class_merge_kib", C.c_int32), ("small_tiles", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):

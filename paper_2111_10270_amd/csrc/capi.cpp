@@ -633,6 +633,7 @@ int bddmma_options_default(bddmma_options *o)
     o->fast_path = 1;
     o->graph_sweeps = 64;
     o->class_merge_kib = 32768;
+    o->small_tiles = 2048;
     return BDDMMA_OK;
 }
 
@@ -655,7 +656,8 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.perturb_scale != 0 && o.perturb_scale != 1) return fail(BDDMMA_ERR_INVALID_ARG, "perturb_scale must be 0 or 1");
     if (o.graph_sweeps < 0) return fail(BDDMMA_ERR_INVALID_ARG, "graph_sweeps must be >= 0");
     if (o.class_merge_kib < 0) return fail(BDDMMA_ERR_INVALID_ARG, "class_merge_kib must be >= 0");
-    for (int i = 0; i < 3; ++i)
+    if (o.small_tiles < 0) return fail(BDDMMA_ERR_INVALID_ARG, "small_tiles must be >= 0");
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
@@ -689,7 +691,7 @@ int load_compiled(bddmma_solver *s)
     if (rc == ST_OK) {
         int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
         rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                          1024.0 * s->opt.class_merge_kib, s->pk, msg);
+                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, s->pk, msg);
     }
     if (rc != ST_OK) {
         s->prob = Problem();

@@ -383,8 +383,8 @@ struct TilePlan {
 
 }  // namespace
 
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes, Packed &o,
-                 std::string &msg)
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
+                 int64_t small_tiles, Packed &o, std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -460,6 +460,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         s = e;
     }
     // tile shapes
+    const bool small = (int64_t)plans.size() <= small_tiles;
     for (auto &tp : plans) {
         int K = 0;
         tp.first_row = INT64_MAX;
@@ -484,6 +485,11 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                         tp.ki = ki;
                         break;
                     }
+        // small problems: width-2 tiles of one topology join the mixed tiles
+        // (per-lane words), so each sweep needs one launch per layer class
+        // instead of one per class and kind; the launches of a small problem
+        // are latency-bound, so fewer of them beats cheaper lanes
+        if (fast && tp.shared && small && maxw <= kWClass[0]) tp.shared = false;
         if (fast && !tp.shared && maxw <= kWClass[0])
             for (int ki = 0; ki < kNumKClasses; ++ki)
                 if (K <= kKClass[ki] && mix_class_ok(ki)) {

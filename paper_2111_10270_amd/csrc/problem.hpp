@@ -90,10 +90,12 @@ int build_problem(Problem &p, std::string &msg);
 // may keep in LDS (0 disables LDS); lds_max_nodes > 0 additionally caps the
 // nodes per lane of LDS tiles; fast selects the register-resident path for the
 // tiles it can take; merge_bytes is the padding traffic per sweep a layer
-// class may add to join a larger class (0: no merging).  ST_OK / ST_INVALID.
+// class may add to join a larger class (0: no merging); problems of at most
+// small_tiles tiles sweep their width-2 tiles of one topology as mixed tiles
+// (one launch per layer class).  ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
-int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes, Packed &out,
-                 std::string &msg);
+int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
+                 int64_t small_tiles, Packed &out, std::string &msg);
 
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.

@@ -27,13 +27,13 @@ def test_default_options():
     assert (o.omega, o.precision, o.delta0, o.alpha, o.reopt_iters, o.max_rounds) == (0.5, 32, 1.0, 1.2, 5, 200)
     assert o.lb_every == 1 and o.rel_tol == 0.0 and o.tau < 0
     assert (o.fast_path, o.perturb_scale, o.sp_in_lds_max_nodes, o.graph_sweeps) == (1, 0, 0, 64)
-    assert o.class_merge_kib == 32768
+    assert o.class_merge_kib == 32768 and o.small_tiles == 2048
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=1.5), dict(precision=16), dict(lb_every=0),
                                  dict(alpha=0.5), dict(delta0=0.0), dict(max_rounds=-1),
                                  dict(sp_in_lds_max_nodes=-2), dict(fast_path=2), dict(perturb_scale=2),
-                                 dict(graph_sweeps=-1), dict(class_merge_kib=-1)])
+                                 dict(graph_sweeps=-1), dict(class_merge_kib=-1), dict(small_tiles=-1)])
 def test_invalid_options(bad):
     ilp = I.random_ilp(5, 3, seed=1)
     with pytest.raises(B.BddmmaError) as e:
@@ -132,10 +132,12 @@ def test_empty_and_free_variables():
 
 def test_register_path_tile_counts():
     from layer_classes import layer_class_ilp
-    st = B.Solver(I.workload("mrf10x10L3")).stats
+    st = B.Solver(I.workload("mrf10x10L3"), small_tiles=0).stats
     assert st.n_reg_tiles == st.n_tiles and st.n_reg_mixed_tiles == 0
-    merged = B.Solver(layer_class_ilp()).stats          # small: classes merge (padding)
-    st = B.Solver(layer_class_ilp(), class_merge_kib=0).stats
+    st = B.Solver(I.workload("mrf10x10L3")).stats       # small problem: all tiles run as mixed tiles
+    assert st.n_reg_mixed_tiles == st.n_tiles and st.n_reg_tiles == 0 and st.n_reg_launches == 1
+    merged = B.Solver(layer_class_ilp(), small_tiles=0).stats          # classes merge (padding)
+    st = B.Solver(layer_class_ilp(), class_merge_kib=0, small_tiles=0).stats
     assert st.n_reg_tiles > 0 and st.n_reg_mixed_tiles > 0 and st.n_reg_launches >= 12
     assert st.n_reg_tiles + st.n_reg_mixed_tiles < st.n_tiles   # wide or long rows stay general
     assert merged.n_reg_launches < st.n_reg_launches and merged.n_slots > st.n_slots

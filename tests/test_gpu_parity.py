@@ -103,7 +103,11 @@ def test_fig3_min_marginals():
 
 
 # ---------------------------------------------------------------- random instances
-PATHS = [dict(fast_path=1), dict(fast_path=0), dict(fast_path=0, sp_in_lds_max_nodes=-1)]
+# register kernels (small problems: per-lane topologies only), register kernels
+# with one-topology tiles, general kernels with LDS, general kernels with
+# device scratch
+PATHS = [dict(fast_path=1), dict(fast_path=1, small_tiles=0), dict(fast_path=0),
+         dict(fast_path=0, sp_in_lds_max_nodes=-1)]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -159,13 +163,13 @@ def test_layer_classes(prec, merge):
     with padding, and general tiles, against the reference sweep by sweep"""
     from layer_classes import layer_class_ilp
     ilp = layer_class_ilp()
-    s, o, _ = lockstep(ilp, 6, precision=prec, class_merge_kib=merge)
+    s, o, _ = lockstep(ilp, 6, precision=prec, class_merge_kib=merge, small_tiles=0)
     st = s.stats
     assert st.n_reg_tiles > 0 and st.n_reg_mixed_tiles > 0
     assert st.n_reg_launches >= (12 if merge == 0 else 2)
 
 
-@pytest.mark.parametrize("path", PATHS[:2])
+@pytest.mark.parametrize("path", PATHS[:3])
 @pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
 def test_ragged_tile_counts_fp64(n_rows, path):
     rng = np.random.default_rng(n_rows)
@@ -195,7 +199,7 @@ def test_empty_and_fixed_problems():
 
 
 # ---------------------------------------------------------------- the named workloads
-@pytest.mark.parametrize("path", PATHS[:2])
+@pytest.mark.parametrize("path", PATHS[:3])
 def test_mrf10_fp64_200_iterations(path):
     ilp = I.workload("mrf10x10L3")
     note("mrf10x10L3 fp64 200 iterations", path)
