@@ -497,3 +497,33 @@ def test_batch_matches_each_instance_alone(prec):
     # the dual state is untouched by the rounding
     l2, m2 = b.multipliers()
     assert np.array_equal(l2, lam) and np.array_equal(m2, mm)
+
+
+def test_batch_with_graph_replay_and_checkpoint():
+    """batches replayed from captured graphs, checkpointed and resumed, stay
+    identical to the instances run alone with eager launches"""
+    ilps = _members()[:6]
+    b = solver(ilps, precision=64)
+    with pytest.raises(B.BddmmaError) as e:
+        b.batch_bounds()                       # no recorded sweep yet
+    assert e.value.code == B.STATE
+    b.run_dual(40)                             # 80 sweeps: one 64-sweep replay + 16 eager
+    blob = b.save_state()
+    b.run_dual(30)
+    c = solver(ilps, precision=64)
+    c.load_state(blob)
+    c.run_dual(30)
+    alone = [solver(p, precision=64, graph_sweeps=0) for p in ilps]
+    for a in alone:
+        a.run_dual(70)
+    for s in (b, c):
+        lam, mm = s.multipliers()
+        at = 0
+        for a in alone:
+            la, ma = a.multipliers()
+            assert np.array_equal(lam[at:at + la.size], la) and np.array_equal(mm[at:at + la.size], ma)
+            at += la.size
+    assert np.array_equal(b.lb_history(), c.lb_history())
+    lbf, _, _ = b.batch_bounds()
+    for k, a in enumerate(alone):
+        assert abs(lbf[k] - a.lb_history()[-1]) <= 1e-12 * max(1.0, abs(lbf[k]))
