@@ -49,7 +49,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             if verbose and err:
                 print(err, flush=True)
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+                   ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"], check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,5 +1,6 @@
 // C ABI of the solver: state, workspace layout, Alg. 1 / Alg. 2 driver loops.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -180,6 +181,20 @@ hipEvent_t ev_get(bddmma_solver *s)
     return e;
 }
 
+// roctx range (rocprofv3 --marker-trace) around a host call; free when no
+// tool is attached
+struct Range {
+    bool on;
+    Range(bool enable, const char *name) : on(enable)
+    {
+        if (on) roctxRangePushA(name);
+    }
+    ~Range()
+    {
+        if (on) roctxRangePop();
+    }
+};
+
 struct Scope {
     bddmma_solver *s;
     int k;
@@ -220,6 +235,7 @@ void one_sweep(bddmma_solver *s, int dir, int64_t row, bool sample)
     const DevProblem &p = s->dp;
     T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
     double *tile_lb = row >= 0 ? s->ptr<double>(s->L.lbpart) + (size_t)row * s->pk.tiles.size() : nullptr;
+    Range rg(sample, dir == 0 ? "bddmma sweep fwd" : "bddmma sweep bwd");
     launch_average<T>(p, mm, s->opt.omega, s->st);
     Scope sc(s, dir == 0 ? BDDMMA_K_SWEEP_FWD : BDDMMA_K_SWEEP_BWD, sample);
     launch_sweep<T>(p, lam, mm, tile_lb, weights<T>(s), dir, MODE_UPDATE, s->st);
@@ -780,6 +796,7 @@ int bddmma_workspace_bytes(const bddmma_solver *s, size_t *bytes)
 int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
 {
     GUARD_BEGIN
+    Range rg(true, "bddmma bind");
     if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
     if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
     if (s->bound) return fail(BDDMMA_ERR_STATE, "workspace already bound");
@@ -916,6 +933,7 @@ int bddmma_run_sweeps(bddmma_solver *s, int32_t n)
 int bddmma_run_dual(bddmma_solver *s, int32_t n_iter, int32_t *iters_done)
 {
     GUARD_BEGIN
+    Range rg(true, "bddmma run_dual");
     int rc = check_ready(s);
     if (rc) return rc;
     if (n_iter < 0) return fail(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 0");
@@ -945,6 +963,7 @@ int bddmma_run_dual(bddmma_solver *s, int32_t n_iter, int32_t *iters_done)
 int bddmma_lower_bound(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_residual)
 {
     GUARD_BEGIN
+    Range rg(true, "bddmma lower_bound");
     int rc = check_ready(s);
     if (rc) return rc;
     return s->elem == 8 ? lower_bound_T<double>(s, lb_free, lb_cert, max_residual)
@@ -1029,6 +1048,7 @@ int bddmma_min_marginals(bddmma_solver *s, double *out)
 int bddmma_round_primal(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds)
 {
     GUARD_BEGIN
+    Range rg(true, "bddmma round_primal");
     int rc = check_ready(s);
     if (rc) return rc;
     if (!x_out) return fail(BDDMMA_ERR_INVALID_ARG, "x_out is NULL");
@@ -1093,6 +1113,7 @@ int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, doub
 int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds, int32_t *status)
 {
     GUARD_BEGIN
+    Range rg(true, "bddmma batch_round");
     int rc = check_ready(s);
     if (rc) return rc;
     if (!x_out || !ub || !rounds || !status) return fail(BDDMMA_ERR_INVALID_ARG, "NULL argument");
