@@ -779,7 +779,8 @@ int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
     o->lb_offset = s->prob.lb_offset;
     for (int l = LIST_FAST0; l < kNumLists; ++l) {
         const int64_t n = s->pk.list_off[l + 1] - s->pk.list_off[l];
-        (l >= LIST_MIX0 ? o->n_reg_mixed_tiles : o->n_reg_tiles) += n;
+        const bool mixed = l == LIST_LONG_MIX || (l >= LIST_MIX0 && l < LIST_LONG_SH);
+        (mixed ? o->n_reg_mixed_tiles : o->n_reg_tiles) += n;
         o->n_reg_launches += n > 0;
     }
     return BDDMMA_OK;

@@ -82,10 +82,17 @@ enum TileList {
     LIST_GEN_GLOB_REST = 3,
     LIST_FAST0 = 4,
     LIST_MIX0 = LIST_FAST0 + kNumKClasses * kNumWClasses,
-    kNumLists = LIST_MIX0 + kNumKClasses
+    LIST_LONG_SH = LIST_MIX0 + kNumKClasses,   // width-2 tiles longer than every class, one topology
+    LIST_LONG_MIX = LIST_LONG_SH + 1,          // the same, per-lane topologies
+    kNumLists = LIST_LONG_MIX + 1
 };
 inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + ki; }
 inline int mix_list(int ki) { return LIST_MIX0 + ki; }
+
+// Long tiles (width <= 2, more layers than the largest class) run a
+// chunked register kernel that keeps per-layer values in the tile's device
+// scratch: 2 distances per layer at [(2h + q) * 64 + lane] and the averaged
+// term at [(2K + h) * 64 + lane] (3K elements per lane, within lane_elems).
 
 // Where a pair slot takes the averaged term a_i = omega/|J_i| * sum_k M_ik of
 // its variable from (Alg. 1 deferred update).  Variables with |J_i| <= 2 whose

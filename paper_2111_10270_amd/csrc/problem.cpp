@@ -379,6 +379,7 @@ struct TilePlan {
     int64_t first_row = 0;
     int wi = -1, ki = -1;         // fast-path class, -1 = general kernels only
     bool mix = false;             // fast path with per-lane topologies
+    bool lng = false;             // chunked register kernel (width 2, K beyond the classes)
 };
 
 }  // namespace
@@ -498,6 +499,11 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
                     tp.mix = true;
                     break;
                 }
+        if (fast && tp.wi < 0 && maxw <= kWClass[0] && K > kKClass[kNumKClasses - 1]) {
+            tp.wi = 0;
+            tp.lng = true;
+            tp.mix = !tp.shared;
+        }
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
@@ -512,7 +518,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         // groups: shared tiles of each width class, then the mixed tiles
         const int wi = g < kNumWClasses ? g : 0;
         const bool mix = g == kNumWClasses;
-        auto in_group = [&](const TilePlan &tp) { return tp.wi == wi && tp.mix == mix; };
+        auto in_group = [&](const TilePlan &tp) { return tp.wi == wi && tp.mix == mix && !tp.lng; };
         int64_t cnt[kNumKClasses] = {0};
         for (auto &tp : plans)
             if (in_group(tp)) cnt[tp.ki]++;
@@ -542,10 +548,11 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         for (auto &tp : plans)
             if (in_group(tp)) tp.ki = into[tp.ki];
     }
-    // fast tiles: exactly the class's layer count, fixed layer stride
+    // fast tiles: exactly the class's layer count (long tiles keep theirs),
+    // fixed layer stride
     for (auto &tp : plans)
         if (tp.wi >= 0) {
-            tp.K = kKClass[tp.ki];
+            if (!tp.lng) tp.K = kKClass[tp.ki];
             tp.width.assign(tp.K, kWClass[tp.wi]);
         }
     auto tile_nodes = [](const TilePlan &tp) {
@@ -554,6 +561,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         return n;
     };
     auto in_lds = [&](const TilePlan &tp) {
+        if (tp.lng) return false;   // the chunked kernel keeps its values in device scratch
         const int64_t n = tile_nodes(tp);
         return lds_elem_budget > 0 && (int64_t)lane_elems(tp.K, (uint32_t)n) <= lds_elem_budget &&
                (lds_max_nodes <= 0 || n <= lds_max_nodes);
@@ -612,7 +620,8 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             if (tp.wi < 0) lists[LIST_GEN_GLOB_REST].push_back(tid);
         }
         if (tp.wi >= 0) {
-            lists[tp.mix ? mix_list(tp.ki) : fast_list(tp.wi, tp.ki)].push_back(tid);
+            lists[tp.lng ? (tp.mix ? LIST_LONG_MIX : LIST_LONG_SH) : tp.mix ? mix_list(tp.ki) : fast_list(tp.wi, tp.ki)]
+                .push_back(tid);
         }
         std::vector<uint32_t> noff(tp.K + 1, 0);
         for (int h = 0; h < tp.K; ++h) {
@@ -718,14 +727,21 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     // the register kernel's copy: fixed stride W, heads below W, node 0 of the
     // virtual terminal layer only from the last layer; layer count = class
     for (int l = LIST_FAST0; l < kNumLists; ++l) {
-        const bool mix = l >= LIST_MIX0;
-        const int wi = mix ? 0 : (l - LIST_FAST0) / kNumKClasses;
-        const int ki = mix ? l - LIST_MIX0 : (l - LIST_FAST0) % kNumKClasses;
+        const bool lng = l >= LIST_LONG_SH;
+        const bool mix = lng ? l == LIST_LONG_MIX : l >= LIST_MIX0;
+        const int wi = mix || lng ? 0 : (l - LIST_FAST0) / kNumKClasses;
+        const int ki = lng ? -1 : mix ? l - LIST_MIX0 : (l - LIST_FAST0) % kNumKClasses;
         for (int32_t t : lists[l]) {
             const TileDesc &d = o.tiles[t];
-            const bool ok = d.K == kKClass[ki] && (o.layers[d.layer_base] >> 16) == (uint32_t)kWClass[wi] &&
+            // long tiles keep 3K values per lane in their device scratch
+            const bool ok = (lng ? d.K > kKClass[kNumKClasses - 1] &&
+                                       3ull * d.K <= lane_elems(d.K, d.nodes) &&
+                                       (uint64_t)d.scratch_base + 64ull * lane_elems(d.K, d.nodes) <=
+                                           (uint64_t)scratch
+                                 : d.K == kKClass[ki]) &&
+                            (o.layers[d.layer_base] >> 16) == (uint32_t)kWClass[wi] &&
                             d.fast_base != d.node_base && ((d.flags & TILE_SHARED) != 0) == !mix &&
-                            (mix ? mix_class_ok(ki) : fast_class_ok(wi, ki));
+                            (lng || (mix ? mix_class_ok(ki) : fast_class_ok(wi, ki)));
             if (!ok) {
                 msg = "internal error: fast-path tile does not match its kernel class";
                 return ST_INVALID;

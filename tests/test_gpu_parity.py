@@ -169,6 +169,29 @@ def test_layer_classes(prec, merge):
     assert st.n_reg_launches >= (12 if merge == 0 else 2)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("kw", [dict(), dict(small_tiles=0)])
+def test_long_rows_chunked_kernel(prec, kw):
+    """width-2 BDDs longer than every register class (assignment-type rows of a
+    QAP-like instance, plus rows of scattered lengths 33..90) on the chunked
+    register kernel, sweep by sweep against the reference"""
+    rng = np.random.default_rng(17)
+    qap = I.graph_matching(n_left=40, n_right=40, k=40, n_pairs=6, seed=7)
+    n = 300
+    rows = []
+    for _ in range(70):
+        k = int(rng.integers(33, 91))
+        vs = rng.choice(n, size=k, replace=False)
+        a = [1] * k
+        a[int(rng.integers(0, k))] = -1
+        rows.append((vs, a, -1, 0))
+    mixed = I.from_rows(n, rng.standard_normal(n), rows, name="long_mixed")
+    for ilp in (qap, mixed):
+        s, o, _ = lockstep(ilp, 6, precision=prec, **kw)
+        st = s.stats
+        assert st.max_layers > 32 and st.n_reg_tiles + st.n_reg_mixed_tiles == st.n_tiles
+
+
 @pytest.mark.parametrize("path", PATHS[:3])
 @pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
 def test_ragged_tile_counts_fp64(n_rows, path):
