@@ -107,6 +107,7 @@ typedef struct {
     int64_t n_reg_tiles;          /* tiles swept by the register kernels (one topology) */
     int64_t n_reg_mixed_tiles;    /* tiles swept by the register kernels (per-lane topologies) */
     int64_t n_reg_launches;       /* register-kernel launches per sweep (non-empty classes) */
+    int64_t n_wide_tiles;         /* tiles swept one BDD per wave (layers of >= 16 nodes) */
 } bddmma_stats;
 
 /* Fill *opt with the defaults listed above.  INVALID_ARG if opt is NULL. */

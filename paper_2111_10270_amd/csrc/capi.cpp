@@ -29,6 +29,7 @@ int fail(int code, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int64_t kHistBytes = 64ll << 20;  // device budget for per-tile bound partials of pending sweeps
 constexpr int64_t kLbhCap = 4096;           // reduced bounds kept on the device before a copy to the host
+constexpr int kWideLdsBytes = 64 << 10;     // LDS of one wide-kernel block (one BDD)
 constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -36,7 +37,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     size_t lam, mm, lam_bak, mm_bak, mmx, avg;
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
-    size_t lbpart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
+    size_t lbpart, widepart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
     size_t var_inst, tile_inst, row_inst, inst_var, inst_tile, inst_off, inst_tau, ochunk, oseg, opart, imask, xbest,
         ires;
@@ -135,6 +136,7 @@ Layout make_layout(const bddmma_solver &s)
     L.layers = take(pk.layers.size() * 4);
     L.cost = take(V * 8);
     L.lbpart = take((size_t)s.hist_chunk * T * 8);
+    L.widepart = take((size_t)(pk.list_off[LIST_WIDE + 1] - pk.list_off[LIST_WIDE]) * kLanes * 8);
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
     L.lbh = take((size_t)kLbhCap * 8);
@@ -707,7 +709,7 @@ int load_compiled(bddmma_solver *s)
     if (rc == ST_OK) {
         int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
         rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, s->pk, msg);
+                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem, s->pk, msg);
     }
     if (rc != ST_OK) {
         s->prob = Problem();
@@ -777,12 +779,13 @@ int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
     o->max_layers = s->pk.max_layers;
     o->max_width = s->pk.max_width;
     o->lb_offset = s->prob.lb_offset;
-    for (int l = LIST_FAST0; l < kNumLists; ++l) {
+    for (int l = LIST_FAST0; l < LIST_WIDE; ++l) {
         const int64_t n = s->pk.list_off[l + 1] - s->pk.list_off[l];
         const bool mixed = l == LIST_LONG_MIX || (l >= LIST_MIX0 && l < LIST_LONG_SH);
         (mixed ? o->n_reg_mixed_tiles : o->n_reg_tiles) += n;
         o->n_reg_launches += n > 0;
     }
+    o->n_wide_tiles = s->pk.list_off[LIST_WIDE + 1] - s->pk.list_off[LIST_WIDE];
     return BDDMMA_OK;
 }
 
@@ -878,6 +881,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
     d.n_slots = pk.n_slots;
     d.scratch = s->dev + L.scratch;
     d.lds_lane_elems = pk.max_lds_lane_elems;
+    d.wide_elems = pk.max_wide_elems;
+    d.wide_part = s->ptr<double>(L.widepart);
     const bool batch = s->n_inst() > 1;
     d.var_inst = batch ? s->ptr<int32_t>(L.var_inst) : nullptr;
     d.tile_inst = batch ? s->ptr<int32_t>(L.tile_inst) : nullptr;

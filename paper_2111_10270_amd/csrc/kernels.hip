@@ -209,6 +209,210 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
 }
 
 
+// ---------------------------------------------------------------------------
+// Wide tiles: one BDD per single-wave block, the lanes spread over the nodes
+// of a layer (the paper's node-parallel scheme, inside one wave).  Same
+// arithmetic as k_sweep: distances to top by a gather over each node's two
+// arcs, distances from the root by a scatter with an LDS minimum (min is
+// order free, so the result does not depend on the order of the updates),
+// min-marginals as wave minima over the layer's nodes.  Multipliers and
+// averaged terms of the BDD are staged in LDS first; only lane 0 writes the
+// BDD's lambda and M.  The BDDs of one tile run in different blocks, so the
+// packer gives wide tiles no in-tile averaging partners (only the BDD's own
+// slot or the averaging kernel's term are read).  Blocks of dummy lanes (padding BDDs) return at once:
+// a padding BDD keeps lambda = 0 and M = 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = tmin(v, (T)__shfl_xor(v, off, kLanes));
+    return v;
+}
+
+__device__ __forceinline__ void lds_min(float *p, float v)
+{
+    unsigned int *ip = reinterpret_cast<unsigned int *>(p);
+    unsigned int old = *ip;
+    while (v < __uint_as_float(old)) {
+        const unsigned int seen = atomicCAS(ip, old, __float_as_uint(v));
+        if (seen == old) break;
+        old = seen;
+    }
+}
+
+__device__ __forceinline__ void lds_min(double *p, double v)
+{
+    unsigned long long *ip = reinterpret_cast<unsigned long long *>(p);
+    unsigned long long old = *ip;
+    while (v < __longlong_as_double((long long)old)) {
+        const unsigned long long seen = atomicCAS(ip, old, (unsigned long long)__double_as_longlong(v));
+        if (seen == old) break;
+        old = seen;
+    }
+}
+
+template <typename T, int DIR, bool UPD>
+__global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restrict__ lam, T *mm,
+                                                        Omega<T> w, const int32_t *__restrict__ list,
+                                                        int64_t count)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int t = threadIdx.x;
+    const int64_t wt = (int64_t)blockIdx.x / kLanes;     // index in the wide list
+    const int j = (int)(blockIdx.x % kLanes);             // lane (BDD) of the tile
+    if (wt >= count) return;
+    const int64_t tile = (int64_t)uni((uint32_t)list[wt]);
+    const TileView tv = load_tile(P.tiles + tile);
+    double *const part = P.wide_part + wt * kLanes + j;
+    if (P.pair_var[tv.pb + j] >= P.n_vars) {           // padding BDD
+        if (UPD && t == 0) *part = 0.0;
+        return;
+    }
+    const T omega = w.w1;
+    const int K = (int)tv.K, NN = (int)tv.NN;
+    const T INF = inf_of<T>();
+    const uint32_t *__restrict__ layers = P.layers + tv.lb;
+    const uint32_t *__restrict__ words = tv.shared ? P.child + tv.nb : P.child + tv.fb + (size_t)j * NN;
+    T *const F = reinterpret_cast<T *>(smem_raw);       // [NN] SP(root, v)
+    T *const Bk = F + NN;                                // [NN] SP(v, top)
+    T *const lamS = Bk + NN;                             // [K]
+    T *const avS = lamS + K;                             // [K]
+    auto head = [&](uint32_t c, uint32_t noffn) -> T {
+        return c == kTop ? T(0) : (c == kBot ? INF : Bk[noffn + c]);
+    };
+
+    for (int h = t; h < K; h += kLanes) {
+        const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+        lamS[h] = lam[s];
+        if (UPD) {
+            const uint32_t cd = P.code[tv.cb + (uint32_t)h * kLanes + j];
+            avS[h] = averaged_term(mm, tv.pb, cd, mm[s], w);
+        }
+    }
+    __syncthreads();
+
+    double lbacc = 0.0;   // lane 0 only
+    T energy;
+    if (DIR == 0) {
+        // SP(v, top) under the current multipliers
+        for (int h = K - 1; h >= 0; --h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const T l = lamS[h];
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const uint32_t c = words[noff + q];
+                Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + l);
+            }
+            __syncthreads();
+        }
+        if (t == 0) F[0] = T(0);
+        __syncthreads();
+        T top = INF;
+        for (int h = 0; h < K; ++h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const uint32_t Wn = h + 1 < K ? (uni(layers[h + 1]) >> 16) : 0u;
+            const T l = lamS[h];
+            T m0 = INF, m1 = INF;
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const T f = F[noff + q];
+                const uint32_t c = words[noff + q];
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
+                if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
+            }
+            m0 = wave_min(m0);
+            m1 = wave_min(m1);
+            const T M = m1 - m0;
+            const T lu = UPD ? (l - omega * M) + avS[h] : l;
+            if (t == 0) {
+                const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+                mm[s] = M;
+                if (UPD) {
+                    lam[s] = lu;
+                    lbacc += (double)(M < T(0) ? M : T(0));
+                }
+            }
+            for (uint32_t q = t; q < Wn; q += kLanes) F[noffn + q] = INF;
+            __syncthreads();
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const T f = F[noff + q];
+                const uint32_t c = words[noff + q];
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) {
+                    if (lo == kTop) top = tmin(top, f);
+                    else lds_min(&F[noffn + lo], f);
+                }
+                if (hi != kBot) {
+                    const T v = f + lu;
+                    if (hi == kTop) top = tmin(top, v);
+                    else lds_min(&F[noffn + hi], v);
+                }
+            }
+            __syncthreads();
+        }
+        energy = wave_min(top);
+    } else {
+        // SP(root, v) under the current multipliers
+        if (t == 0) F[0] = T(0);
+        __syncthreads();
+        for (int h = 0; h + 1 < K; ++h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const uint32_t Wn = uni(layers[h + 1]) >> 16;
+            const T l = lamS[h];
+            for (uint32_t q = t; q < Wn; q += kLanes) F[noffn + q] = INF;
+            __syncthreads();
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const T f = F[noff + q];
+                const uint32_t c = words[noff + q];
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo < kTop) lds_min(&F[noffn + lo], f);
+                if (hi < kTop) lds_min(&F[noffn + hi], f + l);
+            }
+            __syncthreads();
+        }
+        // backward sweep with updates
+        for (int h = K - 1; h >= 0; --h) {
+            const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
+            const T l = lamS[h];
+            T m0 = INF, m1 = INF;
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const T f = F[noff + q];
+                const uint32_t c = words[noff + q];
+                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
+                if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
+            }
+            m0 = wave_min(m0);
+            m1 = wave_min(m1);
+            const T M = m1 - m0;
+            const T lu = UPD ? (l - omega * M) + avS[h] : l;
+            if (t == 0) {
+                const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+                mm[s] = M;
+                if (UPD) {
+                    lam[s] = lu;
+                    lbacc += (double)(M < T(0) ? M : T(0));
+                }
+            }
+            for (uint32_t q = t; q < W; q += kLanes) {
+                const uint32_t c = words[noff + q];
+                Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + lu);
+            }
+            __syncthreads();
+        }
+        energy = Bk[0];
+    }
+    if (UPD && t == 0) *part = (double)energy + (double)omega * lbacc;
+}
+
+// per-tile bound partial of the wide tiles: the 64 BDD partials of the tile
+// summed in the shuffle order of the other sweep kernels
+__global__ __launch_bounds__(kLanes) void k_wide_lb(const double *__restrict__ part,
+                                                   const int32_t *__restrict__ list, double *__restrict__ tile_lb)
+{
+    const double e = wave_sum<float>(part[(int64_t)blockIdx.x * kLanes + threadIdx.x]);
+    if (threadIdx.x == 0) tile_lb[list[blockIdx.x]] = e;
+}
+
 // E^j(lambda + omega M) of every lane in FP64, summed per tile
 template <typename T, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__restrict__ lam,
@@ -741,9 +945,29 @@ void launch_general(const DevProblem &p, int list_lds, int list_glob, T *lam, T 
 
 }  // namespace
 
+template <typename T, int DIR, bool UPD>
+void launch_wide(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st)
+{
+    const int64_t n = p.list_off[LIST_WIDE + 1] - p.list_off[LIST_WIDE];
+    if (n == 0) return;
+    const int32_t *list = p.lists + p.list_off[LIST_WIDE];
+    const size_t lds = (size_t)p.wide_elems * sizeof(T);
+    hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD>), dim3((unsigned)(n * kLanes)), dim3(kLanes), lds, st, p, lam, mm, w,
+                       list, n);
+    if (UPD && tile_lb)
+        hipLaunchKernelGGL(k_wide_lb, dim3((unsigned)n), dim3(kLanes), 0, st, p.wide_part, list, tile_lb);
+}
+
 template <typename T>
 void launch_sweep(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w, int dir, int mode, hipStream_t st)
 {
+    if (mode == MODE_UPDATE) {
+        if (dir == 0) launch_wide<T, 0, true>(p, lam, mm, tile_lb, w, st);
+        else launch_wide<T, 1, true>(p, lam, mm, tile_lb, w, st);
+    } else {
+        if (dir == 0) launch_wide<T, 0, false>(p, lam, mm, nullptr, w, st);
+        else launch_wide<T, 1, false>(p, lam, mm, nullptr, w, st);
+    }
     if (mode == MODE_UPDATE) {
         if (dir == 0) {
             launch_reg<T, 0, 2, true>(p, 0, lam, mm, tile_lb, w, st);

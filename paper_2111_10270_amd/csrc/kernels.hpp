@@ -32,6 +32,8 @@ struct DevProblem {
     int64_t n_vars, n_slots;
     void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
     int lds_lane_elems;     // per-lane LDS elements of the largest LDS tile
+    int wide_elems;         // LDS elements of the largest wide tile (2 * nodes + 2 * K)
+    double *wide_part;      // [wide tiles * 64] per-BDD bound partials of the wide kernel
     // batches of independent instances (nullptr for a single ILP): instance
     // of every variable and tile, and the first variable of every instance
     const int32_t *var_inst;

@@ -380,12 +380,13 @@ struct TilePlan {
     int wi = -1, ki = -1;         // fast-path class, -1 = general kernels only
     bool mix = false;             // fast path with per-lane topologies
     bool lng = false;             // chunked register kernel (width 2, K beyond the classes)
+    bool wide = false;            // wide kernel (one wave per BDD)
 };
 
 }  // namespace
 
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, Packed &o, std::string &msg)
+                 int64_t small_tiles, int wide_lds_elems, Packed &o, std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -507,6 +508,8 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
+        tp.wide = fast && tp.wi < 0 && maxw >= kWideMinWidth && wide_lds_elems > 0 &&
+                  2 * nodes + 2 * (int64_t)K <= (int64_t)wide_lds_elems;
     }
     // Fewer launches: inside a width class, the tiles of a layer class join
     // the next larger class present (padded to its layer count) while the
@@ -612,12 +615,16 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             o.max_lds_lane_elems = std::max<int>(o.max_lds_lane_elems, (int)lane_elems(tp.K, (uint32_t)nodes));
             d.scratch_base = 0;
             lists[LIST_GEN_LDS_ALL].push_back(tid);
-            if (tp.wi < 0) lists[LIST_GEN_LDS_REST].push_back(tid);
+            if (tp.wi < 0 && !tp.wide) lists[LIST_GEN_LDS_REST].push_back(tid);
         } else {
             d.scratch_base = (uint32_t)scratch;
             scratch += (int64_t)kLanes * lane_elems(tp.K, (uint32_t)nodes);
             lists[LIST_GEN_GLOB_ALL].push_back(tid);
-            if (tp.wi < 0) lists[LIST_GEN_GLOB_REST].push_back(tid);
+            if (tp.wi < 0 && !tp.wide) lists[LIST_GEN_GLOB_REST].push_back(tid);
+        }
+        if (tp.wide) {
+            lists[LIST_WIDE].push_back(tid);
+            o.max_wide_elems = std::max<int>(o.max_wide_elems, (int)(2 * nodes + 2 * tp.K));
         }
         if (tp.wi >= 0) {
             lists[tp.lng ? (tp.mix ? LIST_LONG_MIX : LIST_LONG_SH) : tp.mix ? mix_list(tp.ki) : fast_list(tp.wi, tp.ki)]
@@ -667,11 +674,18 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             }
             d.fast_base = tp.wi >= 0 ? d.node_base + (uint32_t)nodes : d.node_base;
         } else {
-            const size_t copies = tp.wi >= 0 ? 2 : 1;
+            const size_t copies = tp.wi >= 0 || tp.wide ? 2 : 1;
             const size_t per = (size_t)nodes * kLanes;
             o.child.resize(base + copies * per, kBot | (kBot << 16));
             for (int l = 0; l < kLanes; ++l) place(tp.lanes[l], noff, tp.K, base, kLanes, l);
             d.fast_base = d.node_base;
+            if (tp.wide) {
+                // BDD-major copy for the wide kernel
+                for (int l = 0; l < kLanes; ++l)
+                    for (int64_t n = 0; n < nodes; ++n)
+                        o.child[base + per + (size_t)l * nodes + n] = o.child[base + (size_t)n * kLanes + l];
+                d.fast_base = d.node_base + (uint32_t)per;
+            }
             if (tp.wi >= 0) {
                 // the register kernel's per-lane copy (accepting arcs of the last layer -> node 0)
                 const size_t last = (size_t)noff[tp.K - 1] * kLanes;
@@ -726,7 +740,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     }
     // the register kernel's copy: fixed stride W, heads below W, node 0 of the
     // virtual terminal layer only from the last layer; layer count = class
-    for (int l = LIST_FAST0; l < kNumLists; ++l) {
+    for (int l = LIST_FAST0; l < LIST_WIDE; ++l) {
         const bool lng = l >= LIST_LONG_SH;
         const bool mix = lng ? l == LIST_LONG_MIX : l >= LIST_MIX0;
         const int wi = mix || lng ? 0 : (l - LIST_FAST0) / kNumKClasses;
@@ -748,9 +762,21 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             }
         }
     }
+    std::vector<char> on_fast(o.tiles.size(), 0);
+    for (int l = LIST_FAST0; l < LIST_WIDE; ++l)
+        for (int32_t t : lists[l]) on_fast[t] = 1;
+    for (int32_t t : lists[LIST_WIDE]) {
+        const TileDesc &d = o.tiles[t];
+        const bool sh = (d.flags & TILE_SHARED) != 0;
+        if (on_fast[t] || (!sh && (uint64_t)d.fast_base + 64ull * d.nodes > o.child.size()) ||
+            (sh && d.fast_base != d.node_base) || 2 * d.nodes + 2 * d.K > o.max_wide_elems) {
+            msg = "internal error: inconsistent wide tile";
+            return ST_INVALID;
+        }
+    }
     for (size_t t = 0; t < o.tiles.size(); ++t) {
         const TileDesc &d = o.tiles[t];
-        if (d.fast_base == d.node_base) continue;
+        if (!on_fast[t]) continue;
         const uint32_t W = o.layers[d.layer_base] >> 16;
         const bool sh = (d.flags & TILE_SHARED) != 0;
         const uint32_t lanes = sh ? 1 : kLanes;
@@ -832,6 +858,9 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         for (int64_t s = o.tiles[t].pair_base; s < (int64_t)o.tiles[t].pair_base + (int64_t)o.tiles[t].K * kLanes; ++s)
             tile_of_slot[s] = (int32_t)t;
     std::vector<uint16_t> code((size_t)slots, kCodeSelf);
+    // a wide tile's BDDs run in different blocks, so no in-tile partner there
+    std::vector<char> wide_tile(o.tiles.size(), 0);
+    for (int32_t t : lists[LIST_WIDE]) wide_tile[t] = 1;
     o.gvars.clear();
     for (int64_t i = 0; i < V; ++i) {
         const int32_t a = o.vptr[i], b = o.vptr[i + 1];
@@ -839,7 +868,8 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         bool local = fast && b - a <= 2;
         if (local) {
             const int32_t t = tile_of_slot[o.vslot[a]];
-            local = o.tiles[t].K * kLanes < (int)kCodeSelf && tile_of_slot[o.vslot[b - 1]] == t;
+            local = o.tiles[t].K * kLanes < (int)kCodeSelf && tile_of_slot[o.vslot[b - 1]] == t &&
+                    (b - a == 1 || !wide_tile[t]);
         }
         if (!local) {
             o.gvars.push_back((int32_t)i);

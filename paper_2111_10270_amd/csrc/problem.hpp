@@ -53,6 +53,7 @@ struct Packed {
     int64_t n_slots = 0;
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
     int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile
+    int max_wide_elems = 0;           // LDS elements (2 * nodes + 2 * K) of the largest wide tile
     int max_layers = 0, max_width = 0;
     // batches: tiles are instance-pure and instance k owns tiles
     // [inst_tile[k], inst_tile[k+1]); the id arrays are filled for batches only
@@ -92,10 +93,12 @@ int build_problem(Problem &p, std::string &msg);
 // tiles it can take; merge_bytes is the padding traffic per sweep a layer
 // class may add to join a larger class (0: no merging); problems of at most
 // small_tiles tiles sweep their width-2 tiles of one topology as mixed tiles
-// (one launch per layer class).  ST_OK / ST_INVALID.
+// (one launch per layer class); wide_lds_elems > 0 lets tiles with layers of
+// >= kWideMinWidth nodes whose per-BDD LDS need fits use the wide kernel.
+// ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, Packed &out, std::string &msg);
+                 int64_t small_tiles, int wide_lds_elems, Packed &out, std::string &msg);
 
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.

@@ -105,7 +105,7 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
         const int lds = variant == 3 ? 0 : 128;
         const double merge = variant == 1 ? 0.0 : 32.0 * (1 << 20);
         const int64_t small = variant == 2 ? 0 : 2048;
-        rc = pack_problem(p, lds, 0, fast, merge, small, pk, msg);
+        rc = pack_problem(p, lds, 0, fast, merge, small, variant == 0 ? 0 : 16384, pk, msg);
         check(rc == ST_OK, "pack", seed);
         if (rc != ST_OK) {
             std::fprintf(stderr, "  %s\n", msg.c_str());

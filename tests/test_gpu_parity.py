@@ -169,6 +169,43 @@ def test_layer_classes(prec, merge):
     assert st.n_reg_launches >= (12 if merge == 0 else 2)
 
 
+def wide_ilp(seed=23):
+    """knapsack rows with coefficients up to 20 (layers of tens to hundreds of
+    nodes): 70 rows sharing one coefficient pattern (a one-topology tile) and
+    60 rows with their own patterns (mixed tiles)"""
+    rng = np.random.default_rng(seed)
+    n = 300
+    rows = []
+    pat = rng.integers(1, 21, size=12)
+    for _ in range(70):
+        vs = np.sort(rng.choice(n, size=12, replace=False))
+        rows.append((vs, pat, -1, int(pat.sum() // 2)))
+    hidden = rng.integers(0, 2, size=n)
+    for _ in range(60):
+        k = int(rng.integers(8, 15))
+        vs = rng.choice(n, size=k, replace=False)
+        a = rng.integers(1, 21, size=k) * rng.choice([-1, 1], size=k)
+        sense = int(rng.integers(-1, 2))
+        lhs = int(np.dot(a, hidden[vs]))
+        rows.append((vs, a, sense, lhs + (3 if sense < 0 else -3 if sense > 0 else 0)))
+    ilp = I.from_rows(n, rng.standard_normal(n), rows, name="wide")
+    return ilp
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_wide_rows_node_parallel_kernel(prec):
+    """BDDs with wide layers on the wave-per-BDD kernel (LDS scatter minima),
+    sweep by sweep against the reference, and the rounding's fixed-multiplier
+    sweeps"""
+    ilp = wide_ilp()
+    if O.Oracle(ilp).status != O.OK:
+        pytest.skip("generated instance infeasible")
+    s, o, _ = lockstep(ilp, 6, precision=prec)
+    assert s.stats.n_wide_tiles >= 2 and s.stats.max_width >= 16
+    if prec == 64:
+        assert np.array_equal(s.min_marginals(), o.full_mm())
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("kw", [dict(), dict(small_tiles=0)])
 def test_long_rows_chunked_kernel(prec, kw):
