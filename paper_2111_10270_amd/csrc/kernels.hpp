@@ -119,7 +119,7 @@ void launch_seg_sum(const double *part, const int64_t *seg, int64_t n_seg, const
 // per-instance objective sum_i cost_i x_i over [inst_var[k], inst_var[k+1]) in
 // chunks of kObjChunk variables from the instance start: part[c] per chunk
 // (chunk list from the host), then launch_seg_sum over each instance's chunks
-constexpr int64_t kObjChunk = 1 << 16;
+constexpr int64_t kObjChunk = 1 << 12;
 void launch_obj_chunks(const double *cost, const uint8_t *x, const int64_t *chunk_begin, int64_t n_chunks,
                        int64_t n_vars, double *part, hipStream_t st);
 
