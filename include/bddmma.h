@@ -259,6 +259,89 @@ int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, doub
  * OK, *ub = sum of the instance objectives, *rounds = largest round. */
 int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *rounds, int32_t *status);
 
+/* ---- Serving pool: continuous batching of independent instances ----
+ * Instances arrive at any time (bddmma_pool_submit); host worker threads
+ * presolve, compile and pack each one alone (Sec. 5 construction, the tile
+ * layout it has in a solver of its own).  Each bddmma_pool_step admits ready
+ * instances in submission order while the resident batch fits its half of the
+ * bound arena and holds at most max_active instances, re-assembles the batch
+ * when its membership changed (tables of the members concatenated, lambda and
+ * M of continuing members copied device to device), runs the given number of
+ * Alg. 1 iterations on all members at once, computes every member's bounds
+ * (as bddmma_batch_bounds) and retires the members that reached their
+ * iteration count or, with options.rel_tol > 0, whose lb_free moved by less
+ * than rel_tol * max(1, |lb_free|) over the step.  A member follows exactly
+ * the trajectory of a solver loaded with it alone and run for the same
+ * number of iterations (its iterations are counted in whole steps), so its
+ * multipliers are bitwise those of the solo run.  Retiring copies the
+ * member's terminated multipliers and M to the host.  Primal rounding is not
+ * part of the pool (load the instance in a solver of its own for Alg. 2). */
+typedef struct bddmma_pool bddmma_pool;
+
+#define BDDMMA_POOL_QUEUED 0   /* submitted, host compilation pending or running */
+#define BDDMMA_POOL_READY  1   /* compiled, waiting for admission */
+#define BDDMMA_POOL_ACTIVE 2   /* member of the resident batch */
+#define BDDMMA_POOL_DONE   3   /* retired; bounds and multipliers final */
+#define BDDMMA_POOL_FAILED 4   /* compilation failed (error holds the code) or
+                                  it can never fit (NO_MEMORY) */
+
+typedef struct {
+    int32_t state;           /* BDDMMA_POOL_* */
+    int32_t error;           /* FAILED: INVALID_ARG / INFEASIBLE / NO_MEMORY */
+    int32_t iters;           /* Alg. 1 iterations run so far */
+    int32_t n_iter;          /* iterations requested at submission */
+    int64_t n_vars, n_pairs; /* of the instance (valid from READY on) */
+    int64_t steps;           /* pool steps it has been a member of */
+    double lb_free, lb_cert, max_residual;   /* after its last step (NaN before) */
+    uint64_t workspace_bytes; /* device bytes of the instance alone */
+} bddmma_pool_info;
+
+/* opt as for bddmma_create (rel_tol is applied per step as described above);
+ * max_active >= 1; host_threads = compilation threads, 0 = min(8, cores). */
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, bddmma_pool **out);
+
+/* Device arena owned by the caller (256-byte aligned) and the stream every
+ * pool launch is ordered on.  The resident batch lives in one half while the
+ * next is assembled in the other, so an instance fits when the workspace
+ * bytes of all members (each as if alone, an upper bound on the batch's)
+ * stay within bytes / 2.  Once per pool. */
+int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* Queue one ILP (arguments as bddmma_load_ilp, copied during the call) for
+ * n_iter >= 1 iterations; *ticket identifies it until released.  Input errors
+ * are reported by the state FAILED, not by this call. */
+int bddmma_pool_submit(bddmma_pool *p, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                       const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+                       int32_t n_iter, int64_t *ticket);
+
+/* Queue an instance the caller has already loaded alone (bddmma_load_ilp,
+ * not bound) with the pool's options; the pool takes ownership of s, also on
+ * failure. */
+int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, int64_t *ticket);
+
+/* One step: admission, re-assembly, iters >= 1 Alg. 1 iterations, bounds,
+ * retirement (see above).  *n_active = members after retirement, *n_retired =
+ * instances retired by this step (either may be NULL).  With no member and no
+ * ready instance the step returns at once.  Synchronises the stream. */
+int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *n_retired);
+
+/* Block until no submitted instance is still being compiled. */
+int bddmma_pool_wait_compiled(bddmma_pool *p);
+
+int bddmma_pool_poll(bddmma_pool *p, int64_t ticket, bddmma_pool_info *info);
+
+/* DONE instances: terminated multipliers lambda + omega M and M in the
+ * instance's own pair order, and the pairs (variable, row) as
+ * bddmma_get_pairs gives them for the instance alone; every pointer may be
+ * NULL, arrays hold n_pairs entries. */
+int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *mm, int32_t *pair_var,
+                       int32_t *pair_row);
+
+/* Forget a DONE or FAILED instance (STATE otherwise). */
+int bddmma_pool_release(bddmma_pool *p, int64_t ticket);
+
+void bddmma_pool_destroy(bddmma_pool *p);
+
 /* Checkpoint of the dual state (multipliers, deferred differences, sweep
  * counter, bound history).  With buf == NULL sets *bytes to the
  * size needed.  load_state requires the same loaded problem and precision;

@@ -25,7 +25,11 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_get_multipliers", "bddmma_get_state", "bddmma_set_state", "bddmma_min_marginals",
            "bddmma_round_primal", "bddmma_save_state", "bddmma_load_state", "bddmma_profile",
            "bddmma_kernel_time", "bddmma_last_error", "bddmma_load_batch", "bddmma_num_instances",
-           "bddmma_batch_bounds", "bddmma_batch_round")
+           "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
+           "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
+           "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy")
+
+POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 
 
 class BddmmaError(RuntimeError):
@@ -51,6 +55,12 @@ class Stats(C.Structure):
                 ("n_reg_launches", C.c_int64), ("n_wide_tiles", C.c_int64)]
 
 
+class PoolInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("iters", C.c_int32), ("n_iter", C.c_int32),
+                ("n_vars", C.c_int64), ("n_pairs", C.c_int64), ("steps", C.c_int64), ("lb_free", C.c_double),
+                ("lb_cert", C.c_double), ("max_residual", C.c_double), ("workspace_bytes", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -74,12 +84,18 @@ def lib():
             "bddmma_profile": [P, C.c_int], "bddmma_kernel_time": [P, C.c_int, P, P], "bddmma_last_error": [],
             "bddmma_load_batch": [P, i64, P, P, i64, P, i64, P, P, P, P, P], "bddmma_num_instances": [P, P],
             "bddmma_batch_bounds": [P, P, P, P], "bddmma_batch_round": [P, P, P, P, P],
+            "bddmma_pool_create": [P, i32, i32, P], "bddmma_pool_bind": [P, P, C.c_size_t, P],
+            "bddmma_pool_submit": [P, i64, P, i64, P, P, P, P, P, i32, P],
+            "bddmma_pool_submit_loaded": [P, P, i32, P], "bddmma_pool_step": [P, i32, P, P],
+            "bddmma_pool_wait_compiled": [P], "bddmma_pool_poll": [P, i64, P],
+            "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
         L.bddmma_destroy.restype = None
+        L.bddmma_pool_destroy.restype = None
         L.bddmma_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -266,3 +282,71 @@ class Solver:
         n, ms = C.c_int64(), C.c_double()
         _check(lib().bddmma_kernel_time(self._h, int(kernel), C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+class Pool:
+    """Serving pool (continuous batching): submit ILPs at any time, step the
+    resident batch, poll each ticket; see bddmma_pool_* in the header."""
+
+    def __init__(self, max_active: int = 16, host_threads: int = 0, **options):
+        self._h = C.c_void_p()
+        self.options = default_options(**options)
+        _check(lib().bddmma_pool_create(C.byref(self.options), int(max_active), int(host_threads),
+                                        C.byref(self._h)))
+        self.arena = None
+        self.stream = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().bddmma_pool_destroy(h)
+            self._h = None
+
+    def bind(self, nbytes: int, device="cuda", stream=None):
+        import torch
+        self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        _check(lib().bddmma_pool_bind(self._h, C.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                      C.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def submit(self, ilp, n_iter: int) -> int:
+        arrs = [np.ascontiguousarray(ilp.costs, dtype=np.float64), np.ascontiguousarray(ilp.row_ptr, dtype=np.int64),
+                np.ascontiguousarray(ilp.col, dtype=np.int32), np.ascontiguousarray(ilp.coef, dtype=np.int32),
+                np.ascontiguousarray(ilp.sense, dtype=np.int8), np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
+        t = C.c_int64()
+        _check(lib().bddmma_pool_submit(self._h, ilp.n_vars, _p(arrs[0]), ilp.n_rows, *[_p(a) for a in arrs[1:]],
+                                        int(n_iter), C.byref(t)))
+        return t.value
+
+    def submit_loaded(self, solver: "Solver", n_iter: int) -> int:
+        """hand over a loaded, unbound Solver (it is emptied: the pool owns it now)"""
+        h, solver._h = solver._h, None
+        t = C.c_int64()
+        _check(lib().bddmma_pool_submit_loaded(self._h, h, int(n_iter), C.byref(t)))
+        return t.value
+
+    def step(self, iters: int):
+        """-> (members after retirement, retired by this step)"""
+        a, r = C.c_int32(), C.c_int32()
+        _check(lib().bddmma_pool_step(self._h, int(iters), C.byref(a), C.byref(r)))
+        return a.value, r.value
+
+    def wait_compiled(self):
+        _check(lib().bddmma_pool_wait_compiled(self._h))
+
+    def poll(self, ticket: int) -> dict:
+        i = PoolInfo()
+        _check(lib().bddmma_pool_poll(self._h, int(ticket), C.byref(i)))
+        return {k: getattr(i, k) for k, _ in PoolInfo._fields_}
+
+    def result(self, ticket: int):
+        """-> (lambda + omega M, M, pair_var, pair_row) of a retired instance"""
+        n = self.poll(ticket)["n_pairs"]
+        lam, mm = np.zeros(n), np.zeros(n)
+        pv, pr = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
+        _check(lib().bddmma_pool_result(self._h, int(ticket), _p(lam), _p(mm), _p(pv), _p(pr)))
+        return lam, mm, pv, pr
+
+    def release(self, ticket: int):
+        _check(lib().bddmma_pool_release(self._h, int(ticket)))

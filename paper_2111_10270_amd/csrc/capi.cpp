@@ -13,6 +13,7 @@
 #include "bddmma.h"
 #include "kernels.hpp"
 #include "problem.hpp"
+#include "solver_internal.hpp"
 
 using namespace bddmma;
 
@@ -701,6 +702,8 @@ void bddmma_destroy(bddmma_solver *s)
 
 namespace {
 
+int finish_load(bddmma_solver *s);
+
 // presolve, compile, pack and lay out the ingested ILP (or batch)
 int load_compiled(bddmma_solver *s)
 {
@@ -716,6 +719,12 @@ int load_compiled(bddmma_solver *s)
         s->pk = Packed();
         return fail(rc, msg);
     }
+    return finish_load(s);
+}
+
+// host tables and the workspace layout of a packed problem (or batch)
+int finish_load(bddmma_solver *s)
+{
     {
         const int64_t nt = std::max<int64_t>(1, (int64_t)s->pk.tiles.size());
         s->hist_chunk = std::max<int64_t>(16, std::min<int64_t>(1024, kHistBytes / (8 * nt)));
@@ -1235,3 +1244,88 @@ int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *
 const char *bddmma_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---- hooks for the serving pool ----------------------------------------------
+namespace bddmma {
+
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+int solver_load_merged(bddmma_solver *s, const std::vector<const bddmma_solver *> &parts,
+                       std::vector<int64_t> &slot_off)
+{
+    GUARD_BEGIN
+    if (!s || s->loaded) return fail(BDDMMA_ERR_STATE, "merged load needs a fresh solver");
+    std::vector<Part> pv;
+    for (const bddmma_solver *q : parts) {
+        if (!q || !q->loaded || q->n_inst() != 1 || q->elem != s->elem)
+            return fail(BDDMMA_ERR_INVALID_ARG, "merged load: parts must be loaded single instances of one precision");
+        pv.push_back(Part{&q->prob, &q->pk});
+    }
+    std::string msg;
+    int rc = merge_instances(pv, s->prob, s->pk, slot_off, msg);
+    if (rc != ST_OK) {
+        s->prob = Problem();
+        s->pk = Packed();
+        return fail(rc, msg);
+    }
+    return finish_load(s);
+    GUARD_END
+}
+
+int64_t solver_slots(const bddmma_solver *s) { return s && s->loaded ? s->pk.n_slots : 0; }
+
+int solver_precision(const bddmma_solver *s) { return s && s->loaded ? 8 * s->elem : 0; }
+
+int solver_copy_slots(bddmma_solver *dst, int64_t dst_off, const bddmma_solver *src, int64_t src_off, int64_t n)
+{
+    if (check_ready(dst) || check_ready(src)) return BDDMMA_ERR_STATE;
+    if (dst->elem != src->elem || n < 0 || dst_off < 0 || src_off < 0 || dst_off + n > dst->pk.n_slots ||
+        src_off + n > src->pk.n_slots)
+        return fail(BDDMMA_ERR_INVALID_ARG, "slot copy out of range");
+    if (n == 0) return BDDMMA_OK;
+    const size_t e = (size_t)dst->elem;
+    HIPCHK(hipMemcpyAsync(dst->dev + dst->L.lam + (size_t)dst_off * e, src->dev + src->L.lam + (size_t)src_off * e,
+                          (size_t)n * e, hipMemcpyDeviceToDevice, dst->st));
+    HIPCHK(hipMemcpyAsync(dst->dev + dst->L.mm + (size_t)dst_off * e, src->dev + src->L.mm + (size_t)src_off * e,
+                          (size_t)n * e, hipMemcpyDeviceToDevice, dst->st));
+    return BDDMMA_OK;
+}
+
+namespace {
+template <typename T>
+int instance_multipliers_T(bddmma_solver *s, int64_t off, const bddmma_solver *part, double *lam, double *mm)
+{
+    const int64_t S = part->pk.n_slots, P = (int64_t)part->prob.pair_var.size();
+    std::vector<T> l((size_t)std::max<int64_t>(S, 1)), m((size_t)std::max<int64_t>(S, 1));
+    if (S > 0) {
+        HIPCHK(hipMemcpyAsync(l.data(), s->dev + s->L.lam + (size_t)off * sizeof(T), (size_t)S * sizeof(T),
+                              hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipMemcpyAsync(m.data(), s->dev + s->L.mm + (size_t)off * sizeof(T), (size_t)S * sizeof(T),
+                              hipMemcpyDeviceToHost, s->st));
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    const T w = (T)s->opt.omega;
+    for (int64_t q = 0; q < P; ++q) {
+        const size_t at = (size_t)part->pk.slot_of_pair[q];
+        if (lam) lam[q] = (double)(l[at] + w * m[at]);
+        if (mm) mm[q] = (double)m[at];
+    }
+    return BDDMMA_OK;
+}
+}  // namespace
+
+int solver_instance_multipliers(bddmma_solver *s, int64_t slot_off, const bddmma_solver *part, double *lam,
+                                double *mm)
+{
+    GUARD_BEGIN
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!part || !part->loaded || part->elem != s->elem || slot_off < 0 ||
+        slot_off + part->pk.n_slots > s->pk.n_slots)
+        return fail(BDDMMA_ERR_INVALID_ARG, "instance slots out of range");
+    return s->elem == 8 ? instance_multipliers_T<double>(s, slot_off, part, lam, mm)
+                        : instance_multipliers_T<float>(s, slot_off, part, lam, mm);
+    GUARD_END
+}
+
+}  // namespace bddmma

@@ -1,0 +1,450 @@
+// Serving pool: continuous batching of independent instances.  Host side
+// only: instances are compiled on worker threads, the resident batch is the
+// solver's batch (every step of the method runs in its kernels), and
+// membership changes re-assemble it from the members' own packed tables
+// with their dual state carried over device to device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bddmma.h"
+#include "solver_internal.hpp"
+
+using namespace bddmma;
+
+namespace {
+
+struct Inst {
+    int32_t state = BDDMMA_POOL_QUEUED;
+    int32_t error = 0;
+    int32_t iters = 0, n_iter = 0;
+    int64_t steps = 0;
+    double lb_free = NAN, lb_cert = NAN, res = NAN;
+    size_t bytes = 0;
+    int64_t n_vars = 0, n_pairs = 0;
+    bddmma_solver *s = nullptr;     // the instance alone: loaded, never bound
+    int64_t slot_off = -1;          // first slot in the resident batch (-1: not in it)
+    std::vector<double> lam, mm;    // terminated multipliers and M at retirement
+    // input, until compiled
+    int64_t nv = 0, nr = 0;
+    std::vector<double> cost;
+    std::vector<int64_t> row_ptr, rhs;
+    std::vector<int32_t> col, coef;
+    std::vector<int8_t> sense;
+};
+
+constexpr double kNaN = std::numeric_limits<double>::quiet_NaN();
+
+}  // namespace
+
+struct bddmma_pool {
+    bddmma_options opt{};
+    int32_t max_active = 1;
+    std::mutex mu;
+    std::condition_variable cv_job, cv_idle;
+    std::deque<Inst *> jobs;
+    int64_t compiling = 0;          // submitted and not yet READY / FAILED
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::map<int64_t, std::unique_ptr<Inst>> inst;   // by ticket (submission order)
+    int64_t next_ticket = 1;
+    std::vector<int64_t> members;   // tickets of the resident batch, in batch order
+    bool changed = false;           // membership differs from the assembled batch
+    char *arena = nullptr;
+    size_t half = 0;
+    int side = 0;                   // arena half holding the assembled batch
+    hipStream_t st = nullptr;
+    bddmma_solver *batch = nullptr;
+    bool bound = false;
+};
+
+namespace {
+
+#define POOL_GUARD_BEGIN try {
+#define POOL_GUARD_END                                                                            \
+    }                                                                                             \
+    catch (const std::bad_alloc &) { return set_error(BDDMMA_ERR_NO_MEMORY, "host allocation failed"); } \
+    catch (const std::exception &ex) { return set_error(BDDMMA_ERR_INVALID_ARG, ex.what()); }            \
+    catch (...) { return set_error(BDDMMA_ERR_INVALID_ARG, "unexpected error"); }
+
+// finish a compiled (or failed) instance; called with the lock held
+void settle(bddmma_pool *p, Inst *in, int rc, bddmma_solver *s)
+{
+    if (rc == BDDMMA_OK) {
+        size_t bytes = 0;
+        bddmma_stats stt{};
+        rc = bddmma_workspace_bytes(s, &bytes);
+        if (rc == BDDMMA_OK) rc = bddmma_get_stats(s, &stt);
+        if (rc == BDDMMA_OK) {
+            in->s = s;
+            in->bytes = bytes;
+            in->n_vars = stt.n_vars;
+            in->n_pairs = stt.n_pairs;
+            in->state = BDDMMA_POOL_READY;
+        }
+    }
+    if (rc != BDDMMA_OK) {
+        bddmma_destroy(s);
+        in->s = nullptr;
+        in->state = BDDMMA_POOL_FAILED;
+        in->error = rc;
+    }
+    in->cost = {};
+    in->row_ptr = {};
+    in->rhs = {};
+    in->col = {};
+    in->coef = {};
+    in->sense = {};
+    if (--p->compiling == 0) p->cv_idle.notify_all();
+}
+
+void worker(bddmma_pool *p)
+{
+    for (;;) {
+        Inst *in;
+        {
+            std::unique_lock<std::mutex> lk(p->mu);
+            p->cv_job.wait(lk, [&] { return p->stop || !p->jobs.empty(); });
+            if (p->stop) return;
+            in = p->jobs.front();
+            p->jobs.pop_front();
+        }
+        // a queued instance cannot be released and the pool joins its workers
+        // before freeing anything, so `in` stays valid without the lock
+        bddmma_solver *s = nullptr;
+        int rc = bddmma_create(&p->opt, &s);
+        if (rc == BDDMMA_OK)
+            rc = bddmma_load_ilp(s, in->nv, in->cost.data(), in->nr, in->row_ptr.data(), in->col.data(),
+                                 in->coef.data(), in->sense.data(), in->rhs.data());
+        std::lock_guard<std::mutex> lk(p->mu);
+        settle(p, in, rc, s);
+    }
+}
+
+// Build the batch of the current members in the other arena half and carry
+// the dual state of continuing members over.
+int reassemble(bddmma_pool *p)
+{
+    std::vector<const bddmma_solver *> parts;
+    std::vector<Inst *> mem;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (int64_t t : p->members) {
+            mem.push_back(p->inst.at(t).get());
+            parts.push_back(mem.back()->s);
+        }
+    }
+    bddmma_options o = p->opt;
+    o.rel_tol = 0.0;   // the pool applies the tolerance per member
+    bddmma_solver *nb = nullptr;
+    int rc = bddmma_create(&o, &nb);
+    if (rc) return rc;
+    std::vector<int64_t> off;
+    size_t need = 0;
+    rc = solver_load_merged(nb, parts, off);
+    if (!rc) rc = bddmma_workspace_bytes(nb, &need);
+    if (!rc && need > p->half) rc = set_error(BDDMMA_ERR_NO_MEMORY, "resident batch exceeds its half of the pool arena");
+    if (!rc) rc = bddmma_bind(nb, p->arena + (size_t)(p->side ^ 1) * p->half, p->half, p->st);
+    for (size_t k = 0; !rc && k < mem.size(); ++k)
+        if (p->batch && mem[k]->slot_off >= 0)
+            rc = solver_copy_slots(nb, off[k], p->batch, mem[k]->slot_off, solver_slots(mem[k]->s));
+    if (!rc && hipStreamSynchronize(p->st) != hipSuccess) rc = set_error(BDDMMA_ERR_HIP, "pool stream synchronise failed");
+    if (rc) {
+        bddmma_destroy(nb);
+        return rc;
+    }
+    bddmma_destroy(p->batch);
+    p->batch = nb;
+    p->side ^= 1;
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (size_t k = 0; k < mem.size(); ++k) mem[k]->slot_off = off[k];
+    p->changed = false;
+    return BDDMMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, bddmma_pool **out)
+{
+    POOL_GUARD_BEGIN
+    if (!out) return set_error(BDDMMA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_active < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "max_active must be >= 1");
+    if (host_threads < 0) return set_error(BDDMMA_ERR_INVALID_ARG, "host_threads must be >= 0");
+    bddmma_options o;
+    if (opt) o = *opt;
+    else bddmma_options_default(&o);
+    // validate the options once, as bddmma_create does
+    bddmma_solver *probe = nullptr;
+    int rc = bddmma_create(&o, &probe);
+    if (rc) return rc;
+    bddmma_destroy(probe);
+    std::unique_ptr<bddmma_pool> p(new bddmma_pool());
+    p->opt = o;
+    p->max_active = max_active;
+    unsigned hw = std::thread::hardware_concurrency();
+    int n = host_threads > 0 ? host_threads : (int)std::max(1u, std::min(hw ? hw : 1u, 8u));
+    for (int i = 0; i < n; ++i) p->workers.emplace_back(worker, p.get());
+    *out = p.release();
+    return BDDMMA_OK;
+    POOL_GUARD_END
+}
+
+int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stream)
+{
+    if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    if (p->bound) return set_error(BDDMMA_ERR_STATE, "pool arena already bound");
+    if (!dev_ptr) return set_error(BDDMMA_ERR_INVALID_ARG, "device pointer is NULL");
+    if (((uintptr_t)dev_ptr) % 256) return set_error(BDDMMA_ERR_INVALID_ARG, "device pointer must be 256-byte aligned");
+    const size_t half = (bytes / 2) & ~(size_t)255;
+    if (half == 0) return set_error(BDDMMA_ERR_NO_MEMORY, "pool arena too small");
+    p->arena = (char *)dev_ptr;
+    p->half = half;
+    p->st = (hipStream_t)hip_stream;
+    p->bound = true;
+    return BDDMMA_OK;
+}
+
+int bddmma_pool_submit(bddmma_pool *p, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                       const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+                       int32_t n_iter, int64_t *ticket)
+{
+    POOL_GUARD_BEGIN
+    if (!p || !ticket) return set_error(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    if (n_iter < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 1");
+    if (n_vars < 0 || n_rows < 0 || (n_vars > 0 && !costs) || !row_ptr || (n_rows > 0 && (!sense || !rhs)))
+        return set_error(BDDMMA_ERR_INVALID_ARG, "bad ILP arrays");
+    const int64_t nnz = row_ptr[n_rows];
+    if (nnz < 0 || (nnz > 0 && (!col || !coef))) return set_error(BDDMMA_ERR_INVALID_ARG, "bad ILP arrays");
+    std::unique_ptr<Inst> in(new Inst());
+    in->n_iter = n_iter;
+    in->nv = n_vars;
+    in->nr = n_rows;
+    in->cost.assign(costs, costs + n_vars);
+    in->row_ptr.assign(row_ptr, row_ptr + n_rows + 1);
+    in->col.assign(col, col + nnz);
+    in->coef.assign(coef, coef + nnz);
+    in->sense.assign(sense, sense + n_rows);
+    in->rhs.assign(rhs, rhs + n_rows);
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int64_t t = p->next_ticket++;
+    p->jobs.push_back(in.get());
+    p->compiling++;
+    p->inst.emplace(t, std::move(in));
+    *ticket = t;
+    p->cv_job.notify_one();
+    return BDDMMA_OK;
+    POOL_GUARD_END
+}
+
+int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, int64_t *ticket)
+{
+    POOL_GUARD_BEGIN
+    if (!p || !s || !ticket) {
+        bddmma_destroy(s);
+        return set_error(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    }
+    if (n_iter < 1) {
+        bddmma_destroy(s);
+        return set_error(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 1");
+    }
+    int64_t ni = 0;
+    int rc = bddmma_num_instances(s, &ni);
+    if (!rc && ni != 1) rc = set_error(BDDMMA_ERR_INVALID_ARG, "a pool instance must be a single ILP");
+    if (!rc && solver_precision(s) != p->opt.precision)
+        rc = set_error(BDDMMA_ERR_INVALID_ARG, "instance precision differs from the pool's");
+    std::unique_ptr<Inst> in(new Inst());
+    in->n_iter = n_iter;
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int64_t t = p->next_ticket++;
+    p->compiling++;
+    settle(p, in.get(), rc, s);
+    p->inst.emplace(t, std::move(in));
+    *ticket = t;
+    return BDDMMA_OK;
+    POOL_GUARD_END
+}
+
+int bddmma_pool_wait_compiled(bddmma_pool *p)
+{
+    if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    std::unique_lock<std::mutex> lk(p->mu);
+    p->cv_idle.wait(lk, [&] { return p->compiling == 0; });
+    return BDDMMA_OK;
+}
+
+int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *n_retired)
+{
+    POOL_GUARD_BEGIN
+    if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    if (!p->bound) return set_error(BDDMMA_ERR_STATE, "no pool arena bound");
+    if (iters < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "iters must be >= 1");
+    if (n_active) *n_active = 0;
+    if (n_retired) *n_retired = 0;
+    {
+        // admission in submission order while the batch fits
+        std::lock_guard<std::mutex> lk(p->mu);
+        size_t used = 0;
+        for (int64_t t : p->members) used += p->inst.at(t)->bytes;
+        for (auto &kv : p->inst) {
+            Inst *in = kv.second.get();
+            if (in->state != BDDMMA_POOL_READY) continue;
+            if (in->bytes > p->half) {
+                bddmma_destroy(in->s);
+                in->s = nullptr;
+                in->state = BDDMMA_POOL_FAILED;
+                in->error = BDDMMA_ERR_NO_MEMORY;
+                continue;
+            }
+            if ((int32_t)p->members.size() >= p->max_active || used + in->bytes > p->half) break;
+            in->state = BDDMMA_POOL_ACTIVE;
+            in->slot_off = -1;
+            used += in->bytes;
+            p->members.push_back(kv.first);
+            p->changed = true;
+        }
+        if (p->members.empty()) {
+            bddmma_destroy(p->batch);
+            p->batch = nullptr;
+            p->changed = false;
+            return BDDMMA_OK;
+        }
+    }
+    int rc;
+    if ((p->changed || !p->batch) && (rc = reassemble(p))) return rc;
+    if ((rc = bddmma_run_dual(p->batch, iters, nullptr))) return rc;
+    const size_t n = p->members.size();
+    std::vector<double> lbf(n), lbc(n), res(n);
+    if ((rc = bddmma_batch_bounds(p->batch, lbf.data(), lbc.data(), res.data()))) return rc;
+    std::vector<Inst *> mem;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (int64_t t : p->members) mem.push_back(p->inst.at(t).get());
+    }
+    std::vector<char> done(n, 0);
+    for (size_t k = 0; k < n; ++k) {
+        Inst *in = mem[k];
+        const bool flat = p->opt.rel_tol > 0.0 && in->steps >= 1 &&
+                          std::fabs(lbf[k] - in->lb_free) <= p->opt.rel_tol * std::max(1.0, std::fabs(lbf[k]));
+        done[k] = in->iters + iters >= in->n_iter || flat;
+        if (done[k]) {
+            std::vector<double> lam((size_t)in->n_pairs), mm((size_t)in->n_pairs);
+            if ((rc = solver_instance_multipliers(p->batch, in->slot_off, in->s, lam.data(), mm.data()))) return rc;
+            std::lock_guard<std::mutex> lk(p->mu);
+            in->lam.swap(lam);
+            in->mm.swap(mm);
+        }
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<int64_t> keep;
+    int32_t retired = 0;
+    for (size_t k = 0; k < n; ++k) {
+        Inst *in = mem[k];
+        in->iters += iters;
+        in->steps++;
+        in->lb_free = lbf[k];
+        in->lb_cert = lbc[k];
+        in->res = res[k];
+        if (done[k]) {
+            in->state = BDDMMA_POOL_DONE;
+            in->slot_off = -1;
+            ++retired;
+            p->changed = true;
+        } else {
+            keep.push_back(p->members[k]);
+        }
+    }
+    p->members.swap(keep);
+    if (n_active) *n_active = (int32_t)p->members.size();
+    if (n_retired) *n_retired = retired;
+    return BDDMMA_OK;
+    POOL_GUARD_END
+}
+
+int bddmma_pool_poll(bddmma_pool *p, int64_t ticket, bddmma_pool_info *info)
+{
+    if (!p || !info) return set_error(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->inst.find(ticket);
+    if (it == p->inst.end()) return set_error(BDDMMA_ERR_INVALID_ARG, "unknown ticket");
+    const Inst &in = *it->second;
+    *info = bddmma_pool_info{};
+    info->state = in.state;
+    info->error = in.error;
+    info->iters = in.iters;
+    info->n_iter = in.n_iter;
+    info->n_vars = in.n_vars;
+    info->n_pairs = in.n_pairs;
+    info->steps = in.steps;
+    info->lb_free = in.steps ? in.lb_free : kNaN;
+    info->lb_cert = in.steps ? in.lb_cert : kNaN;
+    info->max_residual = in.steps ? in.res : kNaN;
+    info->workspace_bytes = in.bytes;
+    return BDDMMA_OK;
+}
+
+int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *mm, int32_t *pair_var,
+                       int32_t *pair_row)
+{
+    POOL_GUARD_BEGIN
+    if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->inst.find(ticket);
+    if (it == p->inst.end()) return set_error(BDDMMA_ERR_INVALID_ARG, "unknown ticket");
+    const Inst &in = *it->second;
+    if (in.state != BDDMMA_POOL_DONE) return set_error(BDDMMA_ERR_STATE, "instance not retired");
+    if (lambda) std::copy(in.lam.begin(), in.lam.end(), lambda);
+    if (mm) std::copy(in.mm.begin(), in.mm.end(), mm);
+    if (pair_var || pair_row) {
+        std::vector<int32_t> pv((size_t)in.n_pairs), pr((size_t)in.n_pairs);
+        int rc = bddmma_get_pairs(in.s, pv.data(), pr.data());
+        if (rc) return rc;
+        if (pair_var) std::copy(pv.begin(), pv.end(), pair_var);
+        if (pair_row) std::copy(pr.begin(), pr.end(), pair_row);
+    }
+    return BDDMMA_OK;
+    POOL_GUARD_END
+}
+
+int bddmma_pool_release(bddmma_pool *p, int64_t ticket)
+{
+    if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->inst.find(ticket);
+    if (it == p->inst.end()) return set_error(BDDMMA_ERR_INVALID_ARG, "unknown ticket");
+    Inst &in = *it->second;
+    if (in.state != BDDMMA_POOL_DONE && in.state != BDDMMA_POOL_FAILED)
+        return set_error(BDDMMA_ERR_STATE, "only retired or failed instances can be released");
+    bddmma_destroy(in.s);
+    p->inst.erase(it);
+    return BDDMMA_OK;
+}
+
+void bddmma_pool_destroy(bddmma_pool *p)
+{
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->stop = true;
+    }
+    p->cv_job.notify_all();
+    for (auto &w : p->workers) w.join();
+    if (p->bound && p->st) (void)hipStreamSynchronize(p->st);
+    bddmma_destroy(p->batch);
+    for (auto &kv : p->inst) bddmma_destroy(kv.second->s);
+    delete p;
+}
+
+}  // extern "C"

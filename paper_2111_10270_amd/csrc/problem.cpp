@@ -946,4 +946,187 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     return ST_OK;
 }
 
+int merge_instances(const std::vector<Part> &parts, Problem &P, Packed &O, std::vector<int64_t> &slot_off,
+                    std::string &msg)
+{
+    P = Problem();
+    O = Packed();
+    const int64_t n = (int64_t)parts.size();
+    slot_off.assign((size_t)n, 0);
+    int64_t V = 0, R = 0, PP = 0, S = 0, T = 0, NODES = 0, LAY = 0, CODE = 0, SCR = 0;
+    for (const Part &pt : parts) {
+        if (!pt.p || !pt.pk || pt.p->ilp.n_inst() != 1) {
+            msg = "merge_instances: every part must be one compiled and packed instance";
+            return ST_INVALID;
+        }
+        V += pt.p->ilp.n_vars;
+        R += pt.p->ilp.n_rows;
+        PP += (int64_t)pt.p->pair_var.size();
+        S += pt.pk->n_slots;
+        T += (int64_t)pt.pk->tiles.size();
+        NODES += (int64_t)pt.pk->child.size();
+        LAY += (int64_t)pt.pk->layers.size();
+        CODE += (int64_t)pt.pk->code.size();
+        SCR += pt.pk->scratch_elems;
+    }
+    if (V >= INT32_MAX || PP >= INT32_MAX || S >= INT32_MAX || T >= INT32_MAX || NODES >= (int64_t)UINT32_MAX ||
+        LAY >= (int64_t)UINT32_MAX || CODE >= (int64_t)UINT32_MAX || SCR >= (int64_t)UINT32_MAX) {
+        msg = "batch too large for 32-bit indices";
+        return ST_INVALID;
+    }
+    const bool batch = n > 1;
+    Ilp &U = P.ilp;
+    U.n_vars = V;
+    U.n_rows = R;
+    U.row_ptr.assign(1, 0);
+    U.inst_var.assign(1, 0);
+    U.inst_row.assign(1, 0);
+    BddSet &B = P.bdds;
+    B.lay_off.assign(1, 0);
+    B.node_off.assign(1, 0);
+    O.vptr.assign(1, 0);
+    O.inst_tile.assign(1, 0);
+    O.list_off.assign(kNumLists + 1, 0);
+    std::vector<std::vector<int32_t>> lists(kNumLists);
+    int64_t voff = 0, roff = 0, poff = 0, soff = 0, toff = 0, coff = 0, loff = 0, kodeoff = 0, scroff = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const Problem &p = *parts[k].p;
+        const Packed &pk = *parts[k].pk;
+        const Ilp &il = p.ilp;
+        slot_off[k] = soff;
+        // problem
+        const int64_t nnz0 = U.row_ptr.back();
+        U.cost.insert(U.cost.end(), il.cost.begin(), il.cost.end());
+        for (int64_t r = 0; r < il.n_rows; ++r) U.row_ptr.push_back(nnz0 + il.row_ptr[r + 1]);
+        for (int32_t c : il.col) U.col.push_back((int32_t)(c + voff));
+        U.coef.insert(U.coef.end(), il.coef.begin(), il.coef.end());
+        U.sense.insert(U.sense.end(), il.sense.begin(), il.sense.end());
+        U.rhs.insert(U.rhs.end(), il.rhs.begin(), il.rhs.end());
+        U.inst_var.push_back(voff + il.n_vars);
+        U.inst_row.push_back(roff + il.n_rows);
+        P.fixed.insert(P.fixed.end(), p.fixed.begin(), p.fixed.end());
+        P.deg.insert(P.deg.end(), p.deg.begin(), p.deg.end());
+        const int64_t blo = (int64_t)B.lay_var.size(), bno = (int64_t)B.child.size();
+        for (int32_t r : p.bdds.row) B.row.push_back((int32_t)(r + roff));
+        for (size_t j = 1; j < p.bdds.lay_off.size(); ++j) B.lay_off.push_back(blo + p.bdds.lay_off[j]);
+        for (size_t j = 1; j < p.bdds.node_off.size(); ++j) B.node_off.push_back(bno + p.bdds.node_off[j]);
+        for (int32_t v : p.bdds.lay_var) B.lay_var.push_back((int32_t)(v + voff));
+        B.lay_width.insert(B.lay_width.end(), p.bdds.lay_width.begin(), p.bdds.lay_width.end());
+        B.child.insert(B.child.end(), p.bdds.child.begin(), p.bdds.child.end());
+        for (int32_t v : p.pair_var) P.pair_var.push_back((int32_t)(v + voff));
+        for (int32_t r : p.pair_row) P.pair_row.push_back((int32_t)(r + roff));
+        P.lb_offset += p.lb_offset;
+        P.inst_offset.push_back(p.lb_offset);
+        P.n_nodes += p.n_nodes;
+        P.n_fixed += p.n_fixed;
+        P.n_free += p.n_free;
+        // tiles and their tables
+        std::vector<char> glob(pk.tiles.size(), 0);
+        for (int64_t q = pk.list_off[LIST_GEN_GLOB_ALL]; q < pk.list_off[LIST_GEN_GLOB_ALL + 1]; ++q)
+            glob[(size_t)pk.lists[q]] = 1;
+        for (size_t t = 0; t < pk.tiles.size(); ++t) {
+            TileDesc d = pk.tiles[t];
+            d.pair_base += (uint32_t)soff;
+            d.node_base += (uint32_t)coff;
+            d.fast_base += (uint32_t)coff;
+            d.layer_base += (uint32_t)loff;
+            d.code_base += (uint32_t)kodeoff;
+            if (glob[t]) d.scratch_base += (uint32_t)scroff;
+            O.tiles.push_back(d);
+            if (batch) O.tile_inst.push_back((int32_t)k);
+        }
+        for (int l = 0; l < kNumLists; ++l)
+            for (int64_t q = pk.list_off[l]; q < pk.list_off[l + 1]; ++q)
+                lists[l].push_back((int32_t)(pk.lists[q] + toff));
+        O.layers.insert(O.layers.end(), pk.layers.begin(), pk.layers.end());
+        O.child.insert(O.child.end(), pk.child.begin(), pk.child.end());
+        O.code.insert(O.code.end(), pk.code.begin(), pk.code.end());
+        for (int32_t v : pk.pair_var) O.pair_var.push_back(v == (int32_t)il.n_vars ? (int32_t)V : (int32_t)(v + voff));
+        for (int64_t s : pk.slot_of_pair) O.slot_of_pair.push_back(s + soff);
+        for (int64_t i = 0; i < il.n_vars; ++i) O.vptr.push_back((int32_t)(poff + pk.vptr[i + 1]));
+        for (int32_t s : pk.vslot) O.vslot.push_back((int32_t)(s + soff));
+        for (int32_t v : pk.gvars) O.gvars.push_back((int32_t)(v + voff));
+        O.max_lds_lane_elems = std::max(O.max_lds_lane_elems, pk.max_lds_lane_elems);
+        O.max_wide_elems = std::max(O.max_wide_elems, pk.max_wide_elems);
+        O.max_layers = std::max(O.max_layers, pk.max_layers);
+        O.max_width = std::max(O.max_width, pk.max_width);
+        if (batch) {
+            O.var_inst.insert(O.var_inst.end(), (size_t)il.n_vars, (int32_t)k);
+            O.row_inst.insert(O.row_inst.end(), (size_t)il.n_rows, (int32_t)k);
+        }
+        voff += il.n_vars;
+        roff += il.n_rows;
+        poff += (int64_t)p.pair_var.size();
+        soff += pk.n_slots;
+        toff += (int64_t)pk.tiles.size();
+        coff += (int64_t)pk.child.size();
+        loff += (int64_t)pk.layers.size();
+        kodeoff += (int64_t)pk.code.size();
+        scroff += pk.scratch_elems;
+        O.inst_tile.push_back(toff);
+    }
+    for (int l = 0; l < kNumLists; ++l) {
+        O.list_off[l + 1] = O.list_off[l] + (int64_t)lists[l].size();
+        O.lists.insert(O.lists.end(), lists[l].begin(), lists[l].end());
+    }
+    O.n_slots = S;
+    O.scratch_elems = SCR;
+    // averaging buckets: one per degree over all instances (variables in
+    // instance order), the CSR bucket last, as the packer orders them
+    int32_t blocks = 0;
+    for (int d = 1; d <= kEllMaxDeg + 1; ++d) {
+        const int dd = d <= kEllMaxDeg ? d : 0;
+        int64_t count = 0;
+        for (const Part &pt : parts)
+            for (const AvgBucket &b : pt.pk->gbuckets)
+                if (b.deg == dd) count += b.count;
+        if (count == 0) continue;
+        if (count >= INT32_MAX) {
+            msg = "batch too large for 32-bit indices";
+            return ST_INVALID;
+        }
+        AvgBucket nb{};
+        nb.deg = dd;
+        nb.count = (int32_t)count;
+        nb.block_begin = blocks;
+        nb.base = (int64_t)O.gslot.size();
+        O.gslot.resize(O.gslot.size() + (size_t)(dd ? dd : 1) * (size_t)count);
+        int64_t at = 0;
+        for (int64_t k = 0; k < n; ++k)
+            for (const AvgBucket &b : parts[k].pk->gbuckets) {
+                if (b.deg != dd) continue;
+                const int32_t *src = parts[k].pk->gslot.data() + b.base;
+                if (dd == 0) {
+                    const int64_t vo = P.ilp.inst_var[k];
+                    for (int32_t i = 0; i < b.count; ++i) O.gslot[nb.base + at + i] = (int32_t)(src[i] + vo);
+                } else {
+                    for (int kk = 0; kk < dd; ++kk)
+                        for (int32_t i = 0; i < b.count; ++i)
+                            O.gslot[nb.base + (int64_t)kk * count + at + i] =
+                                (int32_t)(src[(int64_t)kk * b.count + i] + slot_off[k]);
+                }
+                at += b.count;
+            }
+        blocks += (int32_t)((count + 255) / 256);
+        O.gbuckets.push_back(nb);
+    }
+    O.gblocks = blocks;
+    // every tile inside the merged tables
+    for (const TileDesc &d : O.tiles) {
+        const uint64_t n64 = (uint64_t)d.K * kLanes;
+        const uint64_t words = (uint64_t)d.nodes * ((d.flags & TILE_SHARED) ? 1u : (uint64_t)kLanes);
+        if ((uint64_t)d.pair_base + n64 > (uint64_t)S || (uint64_t)d.code_base + n64 > O.code.size() ||
+            (uint64_t)d.layer_base + d.K > O.layers.size() || (uint64_t)d.node_base + words > O.child.size() ||
+            (uint64_t)d.fast_base + words > O.child.size()) {
+            msg = "internal error: merged tile outside its tables";
+            return ST_INVALID;
+        }
+    }
+    if ((int64_t)O.vptr.size() != V + 1 || O.vptr.back() != PP || (int64_t)O.pair_var.size() != S) {
+        msg = "internal error: inconsistent merged slot tables";
+        return ST_INVALID;
+    }
+    return ST_OK;
+}
+
 }  // namespace bddmma

@@ -100,6 +100,19 @@ int build_problem(Problem &p, std::string &msg);
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
                  int64_t small_tiles, int wide_lds_elems, Packed &out, std::string &msg);
 
+// Batch of independent instances assembled from their own single-instance
+// results: the union problem is block-diagonal and every instance keeps the
+// tiles, classes and averaging codes it has when solved alone (tile, slot,
+// node, layer, code and scratch offsets are shifted; averaging buckets of equal
+// degree are merged).  Instance k's slots form the range
+// [slot_off[k], slot_off[k] + parts[k].pk->n_slots).  ST_OK / ST_INVALID.
+struct Part {
+    const Problem *p;
+    const Packed *pk;
+};
+int merge_instances(const std::vector<Part> &parts, Problem &out, Packed &opk, std::vector<int64_t> &slot_off,
+                    std::string &msg);
+
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.
 int compile_row(const int32_t *var, const int64_t *a, int k, int sense, int64_t b, BddSet &out,

@@ -193,3 +193,50 @@ def test_batch_with_an_infeasible_instance():
     with pytest.raises(B.BddmmaError) as e:
         B.Solver([good, infeasible])
     assert e.value.code == B.INFEASIBLE
+
+
+def test_pool_host_side_states_and_validation():
+    """serving pool without a device: option and argument checks, host
+    compilation into READY / FAILED, sizes, and which tickets can be released"""
+    with pytest.raises(B.BddmmaError) as e:
+        B.Pool(max_active=0)
+    assert e.value.code == B.INVALID_ARG
+    with pytest.raises(B.BddmmaError) as e:
+        B.Pool(omega=2.0)
+    assert e.value.code == B.INVALID_ARG
+    pool = B.Pool(max_active=2, host_threads=2, precision=64)
+    good = I.random_ilp(12, 8, seed=3)
+    with pytest.raises(B.BddmmaError) as e:
+        pool.submit(good, 0)
+    assert e.value.code == B.INVALID_ARG
+    t_good = pool.submit(good, 10)
+    t_inf = pool.submit(I.from_rows(2, [1.0, 1.0], [([0, 1], [1, 1], 0, 3)]), 10)   # x0 + x1 = 3
+    bad = I.from_rows(2, [1.0, 1.0], [([0, 1], [1, 1], -1, 1)])
+    bad.col = np.array([0, 5], dtype=np.int32)                                      # column out of range
+    t_bad = pool.submit(bad, 10)
+    t_batch = pool.submit_loaded(B.Solver([good, good], precision=64), 10)           # not a single ILP
+    t_prec = pool.submit_loaded(B.Solver(good, precision=32), 10)                    # other precision
+    t_own = pool.submit_loaded(B.Solver(good, precision=64), 10)
+    pool.wait_compiled()
+    g = pool.poll(t_good)
+    s = B.Solver(good, precision=64)
+    assert g["state"] == B.POOL_READY and g["n_pairs"] == s.n_pairs and g["n_vars"] == good.n_vars
+    assert g["workspace_bytes"] == s.workspace_bytes() and g["iters"] == 0 and np.isnan(g["lb_free"])
+    assert pool.poll(t_own)["state"] == B.POOL_READY
+    assert (pool.poll(t_inf)["state"], pool.poll(t_inf)["error"]) == (B.POOL_FAILED, B.INFEASIBLE)
+    for t in (t_bad, t_batch, t_prec):
+        assert (pool.poll(t)["state"], pool.poll(t)["error"]) == (B.POOL_FAILED, B.INVALID_ARG), t
+    with pytest.raises(B.BddmmaError) as e:
+        pool.step(5)                      # no arena bound
+    assert e.value.code == B.STATE
+    with pytest.raises(B.BddmmaError) as e:
+        pool.release(t_good)              # waiting, not retired
+    assert e.value.code == B.STATE
+    with pytest.raises(B.BddmmaError) as e:
+        pool.result(t_good)
+    assert e.value.code == B.STATE
+    pool.release(t_inf)
+    with pytest.raises(B.BddmmaError) as e:
+        pool.poll(t_inf)
+    assert e.value.code == B.INVALID_ARG
+    del pool

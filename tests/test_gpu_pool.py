@@ -1,0 +1,149 @@
+"""Serving pool (continuous batching) on the GPU, through the C ABI.
+
+Whatever joins or leaves the resident batch around it, every instance ends
+where a solver loaded with it alone ends after the same number of Alg. 1
+iterations: multipliers, deferred differences and per-instance bounds are
+compared bit for bit (the instance keeps its own tiles, and its state is
+copied unchanged when the batch is re-assembled).  Also: admission by
+workspace bytes and member count, retirement by tolerance, adopted solvers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_10270_amd import binding as B
+from paper_2111_10270_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    assert torch.cuda.get_device_properties(0).gcnArchName.startswith("gfx950")
+
+
+def members():
+    ms = [I.random_ilp(14, 10, max_row_len=6, seed=4200 + k) for k in range(4)]
+    ms += [I.mrf_grid(5, 6, 3, pairwise="potts", seed=3), I.mrf_grid(6, 5, 8, pairwise="trunc_linear", seed=8),
+           I.graph_matching(n_left=60, n_right=60, k=10, n_pairs=60, seed=11),
+           I.cell_tracking(frames=5, dets=40, conflicts_per_frame=10, seed=12),
+           I.random_ilp(40, 30, max_row_len=7, seed=4207), I.from_rows(3, [1.0, -1.0, 0.5], [])]
+    return [p for p in ms if O.Oracle(p).status == O.OK]
+
+
+def solo(ilp, n_iter, **kw):
+    s = B.Solver(ilp, **kw).bind()
+    s.run_dual(n_iter)
+    return s
+
+
+def assert_matches_solo(pool, t, ilp, **kw):
+    info = pool.poll(t)
+    assert info["state"] == B.POOL_DONE, info
+    lam, mm, pv, pr = pool.result(t)
+    a = solo(ilp, info["iters"], **kw)
+    la, ma = a.multipliers()
+    pa, ra = a.pairs()
+    assert np.array_equal(lam, la) and np.array_equal(mm, ma), ilp.name
+    assert np.array_equal(pv, pa) and np.array_equal(pr, ra), ilp.name
+    f, c, r = a.batch_bounds()
+    assert info["lb_free"] == f[0] and info["lb_cert"] == c[0] and info["max_residual"] == r[0], (ilp.name, info, f, c, r)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_pool_members_match_solo(prec):
+    """arrivals at different steps, different iteration counts, a member cap
+    of 4: each instance ends bitwise as it ends alone"""
+    ilps = members()
+    iters = [10, 20, 15, 5, 25, 10, 30, 5, 20, 15][:len(ilps)]
+    arrive = [0, 0, 0, 1, 1, 2, 3, 3, 5, 6][:len(ilps)]
+    note("pool of", len(ilps), "instances, prec", prec)
+    pool = B.Pool(max_active=4, precision=prec).bind(256 << 20)
+    tickets = {}
+    step = 0
+    while len(tickets) < len(ilps) or any(pool.poll(t)["state"] != B.POOL_DONE for t in tickets.values()):
+        for k, il in enumerate(ilps):
+            if arrive[k] == step and k not in tickets:
+                tickets[k] = pool.submit(il, iters[k])
+        pool.wait_compiled()
+        active, retired = pool.step(5)
+        states = [pool.poll(t)["state"] for t in tickets.values()]
+        assert active == states.count(B.POOL_ACTIVE) <= 4
+        step += 1
+        assert step < 100
+    note("pool steps", step)
+    for k, il in enumerate(ilps):
+        info = pool.poll(tickets[k])
+        assert info["iters"] == iters[k] and info["steps"] == iters[k] // 5
+        assert_matches_solo(pool, tickets[k], il, precision=prec)
+        pool.release(tickets[k])
+    assert pool.step(5) == (0, 0)
+
+
+def test_pool_admission_by_workspace():
+    """members' solo workspaces never exceed half the arena; an instance that
+    can never fit fails with NO_MEMORY; the cap on members holds"""
+    ilps = members()[:6]
+    sizes = [B.Solver(p, precision=64).workspace_bytes() for p in ilps]
+    half = max(sizes) + min(sizes)
+    pool = B.Pool(max_active=3, precision=64).bind(2 * half + 512)
+    big = I.mrf_grid(40, 40, 8, pairwise="trunc_linear", seed=1)
+    tb = pool.submit(big, 5)
+    ts = [pool.submit(p, 10) for p in ilps]
+    pool.wait_compiled()
+    assert pool.poll(tb)["workspace_bytes"] > half
+    seen = 0
+    for _ in range(40):
+        pool.step(5)
+        act = [t for t in ts if pool.poll(t)["state"] == B.POOL_ACTIVE]
+        assert len(act) <= 3
+        assert sum(pool.poll(t)["workspace_bytes"] for t in act) <= half
+        seen = max(seen, len(act))
+        if all(pool.poll(t)["state"] == B.POOL_DONE for t in ts):
+            break
+    info = pool.poll(tb)
+    assert info["state"] == B.POOL_FAILED and info["error"] == B.NO_MEMORY
+    assert seen >= 1
+    for p, t in zip(ilps, ts):
+        assert_matches_solo(pool, t, p, precision=64)
+
+
+def test_pool_tolerance_retirement():
+    """with rel_tol a member retires once lb_free stops moving over a step,
+    still on its solo trajectory"""
+    il = I.mrf_grid(8, 8, 3, pairwise="potts", seed=21)
+    tol = 1e-4
+    pool = B.Pool(max_active=2, precision=64, rel_tol=tol).bind(64 << 20)
+    t = pool.submit(il, 2000)
+    pool.wait_compiled()
+    lbs = []
+    while pool.poll(t)["state"] != B.POOL_DONE:
+        pool.step(10)
+        lbs.append(pool.poll(t)["lb_free"])
+        assert len(lbs) < 200
+    info = pool.poll(t)
+    assert info["iters"] < 2000 and len(lbs) >= 2
+    assert abs(lbs[-1] - lbs[-2]) <= tol * max(1.0, abs(lbs[-1]))
+    assert all(abs(lbs[k] - lbs[k - 1]) > tol * max(1.0, abs(lbs[k])) for k in range(1, len(lbs) - 1))
+    assert_matches_solo(pool, t, il, precision=64)
+
+
+def test_pool_adopts_loaded_solvers():
+    """an instance loaded by the caller joins like a submitted one"""
+    ilps = members()[:3]
+    pool = B.Pool(max_active=8, precision=32).bind(64 << 20)
+    ts = [pool.submit_loaded(B.Solver(p, precision=32), 10) for p in ilps]
+    assert all(pool.poll(t)["state"] == B.POOL_READY for t in ts)
+    assert pool.step(5) == (3, 0)
+    assert pool.step(5) == (0, 3)
+    for p, t in zip(ilps, ts):
+        assert_matches_solo(pool, t, p, precision=32)
