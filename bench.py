@@ -54,10 +54,14 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+# device code: the kernels and the headers they are compiled with
+KERNEL_FILES = ("device_common.hpp", "kernels.hip", "kernels.hpp", "layout.hpp", "sweep_reg.hip")
+
+
 def kernel_sha() -> str:
     """fingerprint of the kernel sources the counter summary was taken on"""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in KERNEL_FILES:
         h.update(f.encode())
         h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
