@@ -45,6 +45,9 @@ def parse():
                     help="batched serving measurement over N instances of the mixed stream (0 = skip)")
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--serve-iters", type=int, default=200)
+    ap.add_argument("--pool-max", type=int, default=16, help="serving pool: most members at once (0 = skip)")
+    ap.add_argument("--pool-step", type=int, default=25, help="serving pool: iterations per step")
+    ap.add_argument("--pool-arena-gib", type=int, default=16)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -109,7 +112,9 @@ def serve(a, B, I, torch):
     import numpy as np
 
     insts = I.serving_mix(a.serve, seed=5)
+    t = time.perf_counter()
     alone = [B.Solver(p, precision=a.precision) for p in insts]
+    compile_s = time.perf_counter() - t
     groups = [list(range(i, min(i + a.serve_batch, len(insts)))) for i in range(0, len(insts), a.serve_batch)]
     batches = [B.Solver([insts[k] for k in g], precision=a.precision) for g in groups]
     log(f"serving: {len(insts)} instances and {len(groups)} batches loaded")
@@ -156,13 +161,88 @@ def serve(a, B, I, torch):
         t = max(t, arrive[g[-1]]) + dt
         lat_b += [t - arrive[k] for k in g]
     pct = lambda v, q: float(np.percentile(np.asarray(v) * 1e3, q))
+    pool = serve_pool(a, B, insts, seq_lb, rate, pct) if a.pool_max > 0 else None
     return {"instances": n, "batch": a.serve_batch, "iterations": a.serve_iters,
+            "host_compile_ms_per_instance": compile_s / n * 1e3, "pool": pool,
             "vars": int(sum(p.n_vars for p in insts)),
             "seq_solves_per_s": seq_rate, "batched_solves_per_s": n / sum(bat_t),
             "speedup": (n / sum(bat_t)) / seq_rate, "arrival_rate_per_s": rate,
             "p50_ms": pct(lat_b, 50), "p99_ms": pct(lat_b, 99),
             "seq_p50_ms": pct(lat_seq, 50), "seq_p99_ms": pct(lat_seq, 99),
             "lb_max_rel_diff_vs_solo": diff}
+
+
+def serve_pool(a, B, insts, seq_lb, rate, pct):
+    """Continuous batching, live in wall-clock time: the same Poisson arrivals
+    (rate, seed 7) as the replayed servers; each instance arrives compiled
+    (host compilation is reported separately), joins the pool at a step
+    boundary once its table image is on the device, and retires after
+    serve_iters iterations.  Latency to target: arrival -> end of the first
+    step after which its lb_free is within 1e-3 (relative) of its solo final
+    lb_free; latency to done: arrival -> retirement.  Members follow their
+    solo trajectories exactly, so every final bound equals the solo one.  The
+    pool keeps bounds only (no multiplier copies at retirement).  The
+    saturated run submits every instance at time 0 (capacity)."""
+    import numpy as np
+
+    n = len(insts)
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    target = [lb - 1e-3 * max(1.0, abs(lb)) for lb in seq_lb]
+
+    def run(arrive):
+        solvers = [B.Solver(p, precision=a.precision) for p in insts]
+        pool = B.Pool(max_active=a.pool_max, keep_multipliers=False,
+                      precision=a.precision).bind(a.pool_arena_gib << 30)
+        tw = pool.submit_loaded(B.Solver(insts[0], precision=a.precision), a.pool_step)   # warm-up
+        pool.wait_compiled()
+        pool.step(a.pool_step)
+        pool.release(tw)
+        c0 = pool.counters()
+        tickets, reach, fin, final = [None] * n, [None] * n, [None] * n, [None] * n
+        nxt = done = member_steps = 0
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            while nxt < n and arrive[nxt] <= now:
+                tickets[nxt] = pool.submit_loaded(solvers[nxt], a.serve_iters)
+                solvers[nxt] = None
+                nxt += 1
+            if nxt == done:
+                time.sleep(max(0.0, arrive[nxt] - (time.perf_counter() - t0)))
+                continue
+            active, retired = pool.step(a.pool_step)
+            t = time.perf_counter() - t0
+            member_steps += active + retired
+            for k in range(nxt):
+                if fin[k] is not None:
+                    continue
+                info = pool.poll(tickets[k])
+                if info["steps"] and reach[k] is None and info["lb_free"] >= target[k]:
+                    reach[k] = t
+                if info["state"] == B.POOL_DONE:
+                    fin[k] = t
+                    final[k] = info["lb_free"]
+                    done += 1
+                    pool.release(tickets[k])
+        wall = time.perf_counter() - t0
+        c = pool.counters()
+        steps = c["steps"] - c0["steps"]
+        lat_t = [reach[k] - arrive[k] for k in range(n)]
+        lat_d = [fin[k] - arrive[k] for k in range(n)]
+        diff = max(abs(final[k] - seq_lb[k]) / max(1.0, abs(seq_lb[k])) for k in range(n))
+        return {"served_per_s": n / (max(fin) - arrive[0]), "steps": steps,
+                "mean_members_per_step": member_steps / max(1, steps),
+                "p50_ms_to_target": pct(lat_t, 50), "p99_ms_to_target": pct(lat_t, 99),
+                "p50_ms_to_done": pct(lat_d, 50), "p99_ms_to_done": pct(lat_d, 99),
+                "lb_max_rel_diff_vs_solo": diff, "wall_ms": wall * 1e3, "assemblies": c["assemblies"] - c0["assemblies"],
+                "host_ms": {k: round(c[k] - c0[k], 2) for k in ("image_ms", "merge_ms", "bind_ms", "run_ms",
+                                                                 "bounds_ms", "retire_ms")}}
+
+    live = run(arrivals)
+    sat = run(np.zeros(n))
+    return {"max_active": a.pool_max, "step_iters": a.pool_step, "arrival_rate_per_s": rate,
+            "live": live, "saturated": sat}
 
 
 def main():

@@ -264,9 +264,12 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * presolve, compile and pack each one alone (Sec. 5 construction, the tile
  * layout it has in a solver of its own).  Each bddmma_pool_step admits ready
  * instances in submission order while the resident batch fits its half of the
- * bound arena and holds at most max_active instances, re-assembles the batch
- * when its membership changed (tables of the members concatenated, lambda and
- * M of continuing members copied device to device), runs the given number of
+ * bound arena, their table images fit the image region and the batch holds
+ * at most max_active instances (an admitted instance's tables are uploaded
+ * once, as an image), re-assembles the batch on the device when its
+ * membership changed (member images copied into the batch tables with their
+ * index shifts, lambda and M of continuing members copied device to device),
+ * runs the given number of
  * Alg. 1 iterations on all members at once, computes every member's bounds
  * (as bddmma_batch_bounds) and retires the members that reached their
  * iteration count or, with options.rel_tol > 0, whose lb_free moved by less
@@ -274,8 +277,13 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * the trajectory of a solver loaded with it alone and run for the same
  * number of iterations (its iterations are counted in whole steps), so its
  * multipliers are bitwise those of the solo run.  Retiring copies the
- * member's terminated multipliers and M to the host.  Primal rounding is not
- * part of the pool (load the instance in a solver of its own for Alg. 2). */
+ * member's terminated multipliers and M to the host (keep_multipliers).  Once
+ * an instance is compiled, a worker thread uploads its image on a stream of
+ * its own if image space is free, overlapping the running batch; admission
+ * passes over an instance whose upload is still running (it joins at a
+ * later step), so a step never waits for one.  Primal
+ * rounding is not part of the pool (load the instance in a solver of its own
+ * for Alg. 2). */
 typedef struct bddmma_pool bddmma_pool;
 
 #define BDDMMA_POOL_QUEUED 0   /* submitted, host compilation pending or running */
@@ -297,14 +305,20 @@ typedef struct {
 } bddmma_pool_info;
 
 /* opt as for bddmma_create (rel_tol is applied per step as described above);
- * max_active >= 1; host_threads = compilation threads, 0 = min(8, cores). */
-int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, bddmma_pool **out);
+ * max_active >= 1; host_threads = worker threads (compilation, image
+ * uploads), 0 = min(8, cores); keep_multipliers = 1 copies a member's
+ * terminated multipliers to the host when it retires (bddmma_pool_result),
+ * 0 keeps bounds only. */
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t keep_multipliers,
+                       bddmma_pool **out);
 
-/* Device arena owned by the caller (256-byte aligned) and the stream every
- * pool launch is ordered on.  The resident batch lives in one half while the
- * next is assembled in the other, so an instance fits when the workspace
- * bytes of all members (each as if alone, an upper bound on the batch's)
- * stay within bytes / 2.  Once per pool. */
+/* Device arena owned by the caller (256-byte aligned, 8 MiB + 3 KiB at least) and
+ * the stream every pool launch is ordered on.  8 MiB hold the copy
+ * descriptors of an assembly; of the rest, a third holds member images and
+ * two equal halves the resident batch and the next one while it is
+ * assembled.  An instance fits when the workspace bytes of all members (each
+ * as if alone, an upper bound on the batch's) stay within one half and its
+ * image fits the free image space.  Once per pool. */
 int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stream);
 
 /* Queue one ILP (arguments as bddmma_load_ilp, copied during the call) for
@@ -316,7 +330,7 @@ int bddmma_pool_submit(bddmma_pool *p, int64_t n_vars, const double *costs, int6
 
 /* Queue an instance the caller has already loaded alone (bddmma_load_ilp,
  * not bound) with the pool's options; the pool takes ownership of s, also on
- * failure. */
+ * failure (a batch or another precision ends FAILED with INVALID_ARG). */
 int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, int64_t *ticket);
 
 /* One step: admission, re-assembly, iters >= 1 Alg. 1 iterations, bounds,
@@ -325,17 +339,32 @@ int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, 
  * ready instance the step returns at once.  Synchronises the stream. */
 int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *n_retired);
 
-/* Block until no submitted instance is still being compiled. */
+/* Block until no submitted instance is still being compiled or having its
+ * image uploaded by a worker. */
 int bddmma_pool_wait_compiled(bddmma_pool *p);
 
 int bddmma_pool_poll(bddmma_pool *p, int64_t ticket, bddmma_pool_info *info);
 
 /* DONE instances: terminated multipliers lambda + omega M and M in the
- * instance's own pair order, and the pairs (variable, row) as
- * bddmma_get_pairs gives them for the instance alone; every pointer may be
- * NULL, arrays hold n_pairs entries. */
+ * instance's own pair order (STATE unless the pool keeps multipliers), and
+ * the pairs (variable, row) as bddmma_get_pairs gives them for the instance
+ * alone; every pointer may be NULL, arrays hold n_pairs entries. */
 int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *mm, int32_t *pair_var,
                        int32_t *pair_row);
+
+/* Counters of the pool since creation: steps run, batch re-assemblies,
+ * instances admitted and retired; wall milliseconds spent writing and
+ * uploading the images of admitted instances, building the batch's host
+ * tables (merge), assembling it on the device and carrying the
+ * members' state (bind), running the iterations, computing bounds and
+ * retiring members; and the arena split: bytes of one batch half, of the
+ * member-image region and of its free part. */
+typedef struct {
+    int64_t steps, assemblies, admitted, retired;
+    double image_ms, merge_ms, bind_ms, run_ms, bounds_ms, retire_ms;
+    uint64_t batch_capacity, image_capacity, image_free;
+} bddmma_pool_counters;
+int bddmma_pool_get_counters(bddmma_pool *p, bddmma_pool_counters *out);
 
 /* Forget a DONE or FAILED instance (STATE otherwise). */
 int bddmma_pool_release(bddmma_pool *p, int64_t ticket);

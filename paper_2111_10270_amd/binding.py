@@ -27,7 +27,8 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_kernel_time", "bddmma_last_error", "bddmma_load_batch", "bddmma_num_instances",
            "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
-           "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy")
+           "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
+           "bddmma_pool_get_counters")
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 
@@ -84,11 +85,12 @@ def lib():
             "bddmma_profile": [P, C.c_int], "bddmma_kernel_time": [P, C.c_int, P, P], "bddmma_last_error": [],
             "bddmma_load_batch": [P, i64, P, P, i64, P, i64, P, P, P, P, P], "bddmma_num_instances": [P, P],
             "bddmma_batch_bounds": [P, P, P, P], "bddmma_batch_round": [P, P, P, P, P],
-            "bddmma_pool_create": [P, i32, i32, P], "bddmma_pool_bind": [P, P, C.c_size_t, P],
+            "bddmma_pool_create": [P, i32, i32, i32, P], "bddmma_pool_bind": [P, P, C.c_size_t, P],
             "bddmma_pool_submit": [P, i64, P, i64, P, P, P, P, P, i32, P],
             "bddmma_pool_submit_loaded": [P, P, i32, P], "bddmma_pool_step": [P, i32, P, P],
             "bddmma_pool_wait_compiled": [P], "bddmma_pool_poll": [P, i64, P],
             "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
+            "bddmma_pool_get_counters": [P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -284,15 +286,22 @@ class Solver:
         return n.value, ms.value
 
 
+class PoolCounters(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("assemblies", C.c_int64), ("admitted", C.c_int64), ("retired", C.c_int64),
+                ("image_ms", C.c_double), ("merge_ms", C.c_double), ("bind_ms", C.c_double), ("run_ms", C.c_double),
+                ("bounds_ms", C.c_double), ("retire_ms", C.c_double), ("batch_capacity", C.c_uint64),
+                ("image_capacity", C.c_uint64), ("image_free", C.c_uint64)]
+
+
 class Pool:
     """Serving pool (continuous batching): submit ILPs at any time, step the
     resident batch, poll each ticket; see bddmma_pool_* in the header."""
 
-    def __init__(self, max_active: int = 16, host_threads: int = 0, **options):
+    def __init__(self, max_active: int = 16, host_threads: int = 0, keep_multipliers: bool = True, **options):
         self._h = C.c_void_p()
         self.options = default_options(**options)
         _check(lib().bddmma_pool_create(C.byref(self.options), int(max_active), int(host_threads),
-                                        C.byref(self._h)))
+                                        int(bool(keep_multipliers)), C.byref(self._h)))
         self.arena = None
         self.stream = None
 
@@ -340,13 +349,19 @@ class Pool:
         _check(lib().bddmma_pool_poll(self._h, int(ticket), C.byref(i)))
         return {k: getattr(i, k) for k, _ in PoolInfo._fields_}
 
-    def result(self, ticket: int):
-        """-> (lambda + omega M, M, pair_var, pair_row) of a retired instance"""
+    def result(self, ticket: int, multipliers: bool = True):
+        """-> (lambda + omega M, M, pair_var, pair_row) of a retired instance
+        (lambda and M are None with multipliers=False)"""
         n = self.poll(ticket)["n_pairs"]
-        lam, mm = np.zeros(n), np.zeros(n)
+        lam, mm = (np.zeros(n), np.zeros(n)) if multipliers else (None, None)
         pv, pr = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
         _check(lib().bddmma_pool_result(self._h, int(ticket), _p(lam), _p(mm), _p(pv), _p(pr)))
         return lam, mm, pv, pr
 
     def release(self, ticket: int):
         _check(lib().bddmma_pool_release(self._h, int(ticket)))
+
+    def counters(self) -> dict:
+        c = PoolCounters()
+        _check(lib().bddmma_pool_get_counters(self._h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in PoolCounters._fields_}

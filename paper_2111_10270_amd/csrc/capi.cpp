@@ -12,10 +12,15 @@
 
 #include "bddmma.h"
 #include "kernels.hpp"
+#include "assemble.hpp"
 #include "problem.hpp"
 #include "solver_internal.hpp"
 
 using namespace bddmma;
+
+namespace bddmma {
+void launch_assemble(const Seg *segs, const int64_t *items, int64_t n_items, hipStream_t st);
+}
 
 namespace {
 
@@ -86,6 +91,12 @@ struct bddmma_solver {
     int prof_stride = 1;          // bracket every prof_stride-th sweep
     Events ev;
     double tau = 0.0;
+    // a batch assembled on the device from member images: its big tables
+    // exist only there (sizes in vsz), and its zero thresholds come from the
+    // members (virt_tau)
+    bool virt = false;
+    MergedSizes vsz{};
+    std::vector<double> virt_tau;
 
     template <typename T>
     T *ptr(size_t off) const { return reinterpret_cast<T *>(dev + off); }
@@ -109,8 +120,18 @@ int check_launch()
 Layout make_layout(const bddmma_solver &s)
 {
     const Packed &pk = s.pk;
-    const int64_t S = pk.n_slots, V = s.prob.ilp.n_vars, P = (int64_t)s.prob.pair_var.size();
+    const int64_t S = pk.n_slots, V = s.prob.ilp.n_vars;
     const int64_t T = (int64_t)pk.tiles.size();
+    const bool vt = s.virt;
+    const int64_t NI = s.prob.ilp.n_inst();
+    const size_t P = vt ? (size_t)s.vsz.pairs : s.prob.pair_var.size();
+    const size_t n_code = vt ? (size_t)s.vsz.code : pk.code.size();
+    const size_t n_gslot = vt ? (size_t)s.vsz.gslot : pk.gslot.size();
+    const size_t n_child = vt ? (size_t)s.vsz.child : pk.child.size();
+    const size_t n_layers = vt ? (size_t)s.vsz.layers : pk.layers.size();
+    const size_t nnz = vt ? (size_t)s.vsz.nnz : s.prob.ilp.col.size();
+    const size_t n_var_inst = vt ? (NI > 1 ? (size_t)V : 0) : pk.var_inst.size();
+    const size_t n_row_inst = vt ? (NI > 1 ? (size_t)s.prob.ilp.n_rows : 0) : pk.row_inst.size();
     const size_t e = (size_t)s.elem;
     Layout L{};
     size_t o = 0;
@@ -128,34 +149,33 @@ Layout make_layout(const bddmma_solver &s)
     L.pair_var = take(S * 4);
     L.vptr = take((V + 1) * 4);
     L.vslot = take(P * 4);
-    L.code = take(pk.code.size() * 2);
+    L.code = take(n_code * 2);
     L.gbuckets = take(pk.gbuckets.size() * sizeof(AvgBucket));
-    L.gslot = take(pk.gslot.size() * 4);
-    L.child = take(pk.child.size() * 4);
+    L.gslot = take(n_gslot * 4);
+    L.child = take(n_child * 4);
     L.tiles = take(T * sizeof(TileDesc));
     L.lists = take(pk.lists.size() * 4);
-    L.layers = take(pk.layers.size() * 4);
+    L.layers = take(n_layers * 4);
     L.cost = take(V * 8);
     L.lbpart = take((size_t)s.hist_chunk * T * 8);
     L.widepart = take((size_t)(pk.list_off[LIST_WIDE + 1] - pk.list_off[LIST_WIDE]) * kLanes * 8);
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
     L.lbh = take((size_t)kLbhCap * 8);
-    const int64_t NI = s.prob.ilp.n_inst();
     L.counter = take((size_t)(3 * NI + 16) * 4);
     L.flag = take(V + 1);
     L.x = take(V + 1);
     L.xfull = take(V + 1);
     const Ilp &ilp = s.prob.ilp;
     L.r_ptr = take((ilp.n_rows + 1) * 8);
-    L.r_col = take(ilp.col.size() * 4);
-    L.r_coef = take(ilp.coef.size() * 4);
+    L.r_col = take(nnz * 4);
+    L.r_coef = take(nnz * 4);
     L.r_sense = take(ilp.n_rows);
     L.r_rhs = take(ilp.n_rows * 8);
     L.preset = take(V);
-    L.var_inst = take(pk.var_inst.size() * 4);
+    L.var_inst = take(n_var_inst * 4);
     L.tile_inst = take(pk.tile_inst.size() * 4);
-    L.row_inst = take(pk.row_inst.size() * 4);
+    L.row_inst = take(n_row_inst * 4);
     L.inst_var = take((size_t)(NI + 1) * 8);
     L.inst_tile = take((size_t)(NI + 1) * 8);
     L.inst_off = take((size_t)NI * 8);
@@ -630,6 +650,164 @@ int check_ready(const bddmma_solver *s)
     catch (const std::exception &ex) { return fail(BDDMMA_ERR_INVALID_ARG, ex.what()); }            \
     catch (...) { return fail(BDDMMA_ERR_INVALID_ARG, "unexpected error"); }
 
+
+// member images of a batch assembled on the device (see assemble.hpp)
+struct Assembly {
+    const std::vector<const bddmma_solver *> *parts;
+    const std::vector<uint64_t> *images;       // device address of member k's image
+    const std::vector<uint64_t> *image_bytes;
+    void *scratch;                             // device area for the copy descriptors
+    size_t scratch_bytes;
+};
+
+int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, const Assembly *as)
+{
+    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
+    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
+    if (s->bound) return fail(BDDMMA_ERR_STATE, "workspace already bound");
+    if (!dev_ptr) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer is NULL");
+    if (((uintptr_t)dev_ptr) % kAlign) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer must be 256-byte aligned");
+    if (bytes < s->L.total) return fail(BDDMMA_ERR_NO_MEMORY, "workspace smaller than bddmma_workspace_bytes");
+    s->dev = (char *)dev_ptr;
+    s->st = (hipStream_t)hip_stream;
+    const Packed &pk = s->pk;
+    const Layout &L = s->L;
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
+    };
+    std::vector<Seg> segs;
+    std::vector<int64_t> items;
+    if (!as) {
+        HIPCHK(up(L.pair_var, pk.pair_var.data(), pk.pair_var.size() * 4));
+        HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
+        HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
+        HIPCHK(up(L.code, pk.code.data(), pk.code.size() * 2));
+        HIPCHK(up(L.gslot, pk.gslot.data(), pk.gslot.size() * 4));
+        HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
+        HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
+        HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
+        // original rows and presolved values, for the final exact check of a primal point
+        const Ilp &ilp = s->prob.ilp;
+        s->coef32.assign(ilp.coef.begin(), ilp.coef.end());
+        s->preset.assign((size_t)ilp.n_vars, -1);
+        for (int64_t i = 0; i < ilp.n_vars; ++i) {
+            if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
+            else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
+        }
+        HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
+        HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
+        HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
+        HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
+        HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
+        HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
+        HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
+        HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
+    } else {
+        // the big tables from the member images, on the device
+        TableSet dst{};
+        const size_t offs[kNumTables] = {L.pair_var, L.vptr, L.vslot, L.code, L.gslot, L.child, L.layers, L.cost,
+                                         L.r_ptr, L.r_col, L.r_coef, L.r_sense, L.r_rhs, L.preset, L.var_inst,
+                                         L.row_inst};
+        for (int t = 0; t < kNumTables; ++t) dst.off[t] = offs[t];
+        std::vector<Part> parts;
+        for (const bddmma_solver *q : *as->parts) parts.push_back(Part{&q->prob, &q->pk});
+        assembly_segments(parts, *as->images, (uint64_t)(uintptr_t)s->dev, dst, segs);
+        // every copy reads inside one member image and writes inside the workspace
+        const uint64_t lo = (uint64_t)(uintptr_t)s->dev, hi = lo + L.total;
+        for (const Seg &g : segs) {
+            const uint64_t nb = (uint64_t)g.n * (uint64_t)g.elem;
+            bool src_ok = g.op == SEG_FILL;
+            for (size_t k = 0; !src_ok && k < as->images->size(); ++k)
+                src_ok = g.src >= (*as->images)[k] && g.src + nb <= (*as->images)[k] + (*as->image_bytes)[k];
+            if (!src_ok || g.dst < lo || g.dst + nb > hi || g.n < 0)
+                return fail(BDDMMA_ERR_INVALID_ARG, "internal error: assembly copy out of range");
+        }
+        for (size_t q = 0; q < segs.size(); ++q)
+            for (int64_t b0 = 0; b0 < segs[q].n; b0 += kSegChunk) {
+                items.push_back((int64_t)q);
+                items.push_back(b0);
+            }
+        const size_t seg_bytes = segs.size() * sizeof(Seg), item_off = (seg_bytes + 255) & ~(size_t)255;
+        if (item_off + items.size() * 8 > as->scratch_bytes)
+            return fail(BDDMMA_ERR_NO_MEMORY, "assembly descriptors exceed the pool's descriptor area");
+        char *sc = (char *)as->scratch;
+        if (!segs.empty()) HIPCHK(hipMemcpyAsync(sc, segs.data(), seg_bytes, hipMemcpyHostToDevice, s->st));
+        if (!items.empty())
+            HIPCHK(hipMemcpyAsync(sc + item_off, items.data(), items.size() * 8, hipMemcpyHostToDevice, s->st));
+        launch_assemble(reinterpret_cast<const Seg *>(sc), reinterpret_cast<const int64_t *>(sc + item_off),
+                        (int64_t)items.size() / 2, s->st);
+        int rc = check_launch();
+        if (rc) return rc;
+    }
+    HIPCHK(up(L.gbuckets, pk.gbuckets.data(), pk.gbuckets.size() * sizeof(AvgBucket)));
+    HIPCHK(up(L.tiles, pk.tiles.data(), pk.tiles.size() * sizeof(TileDesc)));
+    HIPCHK(up(L.lists, pk.lists.data(), pk.lists.size() * 4));
+    {
+        const Ilp &ilp = s->prob.ilp;
+        DevRows &r = s->rows;
+        r.row_ptr = s->ptr<int64_t>(L.r_ptr);
+        r.col = s->ptr<int32_t>(L.r_col);
+        r.coef = s->ptr<int32_t>(L.r_coef);
+        r.sense = s->ptr<int8_t>(L.r_sense);
+        r.rhs = s->ptr<int64_t>(L.r_rhs);
+        r.n_rows = ilp.n_rows;
+        r.preset = s->ptr<int8_t>(L.preset);
+        // instances (batches)
+        HIPCHK(up(L.tile_inst, pk.tile_inst.data(), pk.tile_inst.size() * 4));
+        HIPCHK(up(L.inst_var, ilp.inst_var.data(), ilp.inst_var.size() * 8));
+        HIPCHK(up(L.inst_tile, pk.inst_tile.data(), pk.inst_tile.size() * 8));
+        HIPCHK(up(L.inst_off, s->prob.inst_offset.data(), s->prob.inst_offset.size() * 8));
+        HIPCHK(up(L.inst_tau, s->inst_tau.data(), s->inst_tau.size() * 8));
+        HIPCHK(up(L.ochunk, s->ochunk.data(), s->ochunk.size() * 8));
+        HIPCHK(up(L.oseg, s->oseg.data(), s->oseg.size() * 8));
+        r.row_inst = s->n_inst() > 1 ? s->ptr<int32_t>(L.row_inst) : nullptr;
+    }
+    DevProblem &d = s->dp;
+    d.tiles = s->ptr<TileDesc>(L.tiles);
+    d.n_tiles = (int64_t)pk.tiles.size();
+    d.lists = s->ptr<int32_t>(L.lists);
+    for (int l = 0; l <= kNumLists; ++l) d.list_off[l] = pk.list_off[l];
+    d.layers = s->ptr<uint32_t>(L.layers);
+    d.child = s->ptr<uint32_t>(L.child);
+    d.pair_var = s->ptr<int32_t>(L.pair_var);
+    d.vptr = s->ptr<int32_t>(L.vptr);
+    d.vslot = s->ptr<int32_t>(L.vslot);
+    d.code = s->ptr<uint16_t>(L.code);
+    d.gbuckets = s->ptr<AvgBucket>(L.gbuckets);
+    d.n_gbuckets = (int32_t)pk.gbuckets.size();
+    d.gblocks = pk.gblocks;
+    d.gslot = s->ptr<int32_t>(L.gslot);
+    d.cost = s->ptr<double>(L.cost);
+    d.n_vars = s->prob.ilp.n_vars;
+    d.n_slots = pk.n_slots;
+    d.scratch = s->dev + L.scratch;
+    d.lds_lane_elems = pk.max_lds_lane_elems;
+    d.wide_elems = pk.max_wide_elems;
+    d.wide_part = s->ptr<double>(L.widepart);
+    const bool batch = s->n_inst() > 1;
+    d.var_inst = batch ? s->ptr<int32_t>(L.var_inst) : nullptr;
+    d.tile_inst = batch ? s->ptr<int32_t>(L.tile_inst) : nullptr;
+    d.inst_var = batch ? s->ptr<int64_t>(L.inst_var) : nullptr;
+    d.inst_tau = batch ? s->ptr<double>(L.inst_tau) : nullptr;
+    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
+    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
+    launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
+    launch_fill<uint8_t>(s->ptr<uint8_t>(L.x), 0, s->prob.ilp.n_vars + 1, s->st);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->bound = true;
+    s->sweeps = 0;
+    s->hist_synced = 0;
+    s->lbh_n = 0;
+    s->part_n = 0;
+    s->last_row = -1;
+    s->hist.clear();
+    return BDDMMA_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -742,7 +920,8 @@ int finish_load(bddmma_solver *s)
     }
     // zero threshold of Alg. 2 per instance (from that instance's costs)
     s->inst_tau.assign((size_t)il.n_inst(), 0.0);
-    for (int64_t k = 0; k < il.n_inst(); ++k) {
+    if (s->virt) s->inst_tau = s->virt_tau;
+    for (int64_t k = 0; !s->virt && k < il.n_inst(); ++k) {
         double cmax = 1.0;
         for (int64_t i = il.inst_var[k]; i < il.inst_var[k + 1]; ++i) cmax = std::max(cmax, std::fabs(il.cost[i]));
         s->inst_tau[k] = s->opt.tau >= 0.0 ? s->opt.tau : (s->opt.precision == 64 ? 0.0 : 1e-6 * cmax);
@@ -810,108 +989,8 @@ int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream)
 {
     GUARD_BEGIN
     Range rg(true, "bddmma bind");
-    if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
-    if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
-    if (s->bound) return fail(BDDMMA_ERR_STATE, "workspace already bound");
-    if (!dev_ptr) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer is NULL");
-    if (((uintptr_t)dev_ptr) % kAlign) return fail(BDDMMA_ERR_INVALID_ARG, "device pointer must be 256-byte aligned");
-    if (bytes < s->L.total) return fail(BDDMMA_ERR_NO_MEMORY, "workspace smaller than bddmma_workspace_bytes");
-    s->dev = (char *)dev_ptr;
-    s->st = (hipStream_t)hip_stream;
-    const Packed &pk = s->pk;
-    const Layout &L = s->L;
-    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
-        if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
-    };
-    HIPCHK(up(L.pair_var, pk.pair_var.data(), pk.pair_var.size() * 4));
-    HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
-    HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
-    HIPCHK(up(L.code, pk.code.data(), pk.code.size() * 2));
-    HIPCHK(up(L.gbuckets, pk.gbuckets.data(), pk.gbuckets.size() * sizeof(AvgBucket)));
-    HIPCHK(up(L.gslot, pk.gslot.data(), pk.gslot.size() * 4));
-    HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
-    HIPCHK(up(L.tiles, pk.tiles.data(), pk.tiles.size() * sizeof(TileDesc)));
-    HIPCHK(up(L.lists, pk.lists.data(), pk.lists.size() * 4));
-    HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
-    HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
-    {
-        // original rows and presolved values, for the final exact check of a primal point
-        const Ilp &ilp = s->prob.ilp;
-        s->coef32.assign(ilp.coef.begin(), ilp.coef.end());
-        s->preset.assign((size_t)ilp.n_vars, -1);
-        for (int64_t i = 0; i < ilp.n_vars; ++i) {
-            if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
-            else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
-        }
-        HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
-        HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
-        HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
-        HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
-        HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
-        HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
-        DevRows &r = s->rows;
-        r.row_ptr = s->ptr<int64_t>(L.r_ptr);
-        r.col = s->ptr<int32_t>(L.r_col);
-        r.coef = s->ptr<int32_t>(L.r_coef);
-        r.sense = s->ptr<int8_t>(L.r_sense);
-        r.rhs = s->ptr<int64_t>(L.r_rhs);
-        r.n_rows = ilp.n_rows;
-        r.preset = s->ptr<int8_t>(L.preset);
-        // instances (batches)
-        HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
-        HIPCHK(up(L.tile_inst, pk.tile_inst.data(), pk.tile_inst.size() * 4));
-        HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
-        HIPCHK(up(L.inst_var, ilp.inst_var.data(), ilp.inst_var.size() * 8));
-        HIPCHK(up(L.inst_tile, pk.inst_tile.data(), pk.inst_tile.size() * 8));
-        HIPCHK(up(L.inst_off, s->prob.inst_offset.data(), s->prob.inst_offset.size() * 8));
-        HIPCHK(up(L.inst_tau, s->inst_tau.data(), s->inst_tau.size() * 8));
-        HIPCHK(up(L.ochunk, s->ochunk.data(), s->ochunk.size() * 8));
-        HIPCHK(up(L.oseg, s->oseg.data(), s->oseg.size() * 8));
-        r.row_inst = pk.row_inst.empty() ? nullptr : s->ptr<int32_t>(L.row_inst);
-    }
-    DevProblem &d = s->dp;
-    d.tiles = s->ptr<TileDesc>(L.tiles);
-    d.n_tiles = (int64_t)pk.tiles.size();
-    d.lists = s->ptr<int32_t>(L.lists);
-    for (int l = 0; l <= kNumLists; ++l) d.list_off[l] = pk.list_off[l];
-    d.layers = s->ptr<uint32_t>(L.layers);
-    d.child = s->ptr<uint32_t>(L.child);
-    d.pair_var = s->ptr<int32_t>(L.pair_var);
-    d.vptr = s->ptr<int32_t>(L.vptr);
-    d.vslot = s->ptr<int32_t>(L.vslot);
-    d.code = s->ptr<uint16_t>(L.code);
-    d.gbuckets = s->ptr<AvgBucket>(L.gbuckets);
-    d.n_gbuckets = (int32_t)pk.gbuckets.size();
-    d.gblocks = pk.gblocks;
-    d.gslot = s->ptr<int32_t>(L.gslot);
-    d.cost = s->ptr<double>(L.cost);
-    d.n_vars = s->prob.ilp.n_vars;
-    d.n_slots = pk.n_slots;
-    d.scratch = s->dev + L.scratch;
-    d.lds_lane_elems = pk.max_lds_lane_elems;
-    d.wide_elems = pk.max_wide_elems;
-    d.wide_part = s->ptr<double>(L.widepart);
-    const bool batch = s->n_inst() > 1;
-    d.var_inst = batch ? s->ptr<int32_t>(L.var_inst) : nullptr;
-    d.tile_inst = batch ? s->ptr<int32_t>(L.tile_inst) : nullptr;
-    d.inst_var = batch ? s->ptr<int64_t>(L.inst_var) : nullptr;
-    d.inst_tau = batch ? s->ptr<double>(L.inst_tau) : nullptr;
-    if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
-    else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
-    launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
-    launch_fill<uint8_t>(s->ptr<uint8_t>(L.x), 0, s->prob.ilp.n_vars + 1, s->st);
-    int rc = check_launch();
-    if (rc) return rc;
-    HIPCHK(hipStreamSynchronize(s->st));
-    s->bound = true;
-    s->sweeps = 0;
-    s->hist_synced = 0;
-    s->lbh_n = 0;
-    s->part_n = 0;
-    s->last_row = -1;
-    s->hist.clear();
-    return BDDMMA_OK;
+    if (s && s->virt) return fail(BDDMMA_ERR_STATE, "an assembled batch is bound by its pool");
+    return bind_impl(s, dev_ptr, bytes, hip_stream, nullptr);
     GUARD_END
 }
 
@@ -1250,26 +1329,59 @@ namespace bddmma {
 
 int set_error(int code, const std::string &msg) { return fail(code, msg); }
 
-int solver_load_merged(bddmma_solver *s, const std::vector<const bddmma_solver *> &parts,
-                       std::vector<int64_t> &slot_off)
+int solver_load_virtual(bddmma_solver *s, const std::vector<const bddmma_solver *> &parts,
+                        std::vector<int64_t> &slot_off)
 {
     GUARD_BEGIN
-    if (!s || s->loaded) return fail(BDDMMA_ERR_STATE, "merged load needs a fresh solver");
+    if (!s || s->loaded) return fail(BDDMMA_ERR_STATE, "assembled load needs a fresh solver");
     std::vector<Part> pv;
     for (const bddmma_solver *q : parts) {
-        if (!q || !q->loaded || q->n_inst() != 1 || q->elem != s->elem)
-            return fail(BDDMMA_ERR_INVALID_ARG, "merged load: parts must be loaded single instances of one precision");
+        if (!q || !q->loaded || q->virt || q->n_inst() != 1 || q->elem != s->elem)
+            return fail(BDDMMA_ERR_INVALID_ARG, "assembled load: parts must be loaded single instances of one precision");
         pv.push_back(Part{&q->prob, &q->pk});
     }
     std::string msg;
-    int rc = merge_instances(pv, s->prob, s->pk, slot_off, msg);
+    int rc = merge_small(pv, s->prob, s->pk, slot_off, s->vsz, msg);
     if (rc != ST_OK) {
         s->prob = Problem();
         s->pk = Packed();
         return fail(rc, msg);
     }
+    s->virt = true;
+    s->virt_tau.clear();
+    for (const bddmma_solver *q : parts) s->virt_tau.push_back(q->inst_tau[0]);
     return finish_load(s);
     GUARD_END
+}
+
+int solver_bind_assembled(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream,
+                          const std::vector<const bddmma_solver *> &parts, const std::vector<uint64_t> &images,
+                          const std::vector<uint64_t> &image_bytes, void *scratch, size_t scratch_bytes)
+{
+    GUARD_BEGIN
+    Range rg(true, "bddmma pool assemble");
+    if (!s || !s->virt || parts.size() != images.size() || images.size() != image_bytes.size() ||
+        (int64_t)parts.size() != s->n_inst())
+        return fail(BDDMMA_ERR_INVALID_ARG, "assembled bind: inconsistent members");
+    Assembly as{&parts, &images, &image_bytes, scratch, scratch_bytes};
+    return bind_impl(s, dev_ptr, bytes, hip_stream, &as);
+    GUARD_END
+}
+
+int solver_image(const bddmma_solver *s, std::vector<uint8_t> &buf)
+{
+    GUARD_BEGIN
+    if (!s || !s->loaded || s->virt || s->n_inst() != 1) return fail(BDDMMA_ERR_STATE, "image of a loaded instance only");
+    const TableSet ts = image_layout(s->prob, s->pk);
+    buf.resize((size_t)ts.bytes);   // padding between tables is never read
+    write_image(s->prob, s->pk, ts, buf.data());
+    return BDDMMA_OK;
+    GUARD_END
+}
+
+uint64_t solver_image_bytes(const bddmma_solver *s)
+{
+    return s && s->loaded && !s->virt ? image_layout(s->prob, s->pk).bytes : 0;
 }
 
 int64_t solver_slots(const bddmma_solver *s) { return s && s->loaded ? s->pk.n_slots : 0; }

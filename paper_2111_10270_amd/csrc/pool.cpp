@@ -1,14 +1,23 @@
-// Serving pool: continuous batching of independent instances.  Host side
-// only: instances are compiled on worker threads, the resident batch is the
-// solver's batch (every step of the method runs in its kernels), and
-// membership changes re-assemble it from the members' own packed tables
-// with their dual state carried over device to device.
+// Serving pool: continuous batching of independent instances.  Instances are
+// compiled on host worker threads, which then write each instance's table
+// image and upload it into the pool's arena, each on a stream of its own,
+// while the resident batch keeps running (when image space is free;
+// otherwise the image goes up at admission); an instance whose upload is
+// still running joins at a later step instead of holding the batch up.  The
+// resident batch is the solver's batch (every step of the method runs in its
+// kernels), re-assembled on the device from the member images whenever
+// membership changes, with the members' dual state carried over device to
+// device.
+//
+// Arena: [copy descriptors | member images | batch half A | batch half B].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <iterator>
 #include <limits>
 #include <map>
 #include <memory>
@@ -24,6 +33,8 @@ using namespace bddmma;
 
 namespace {
 
+enum ImgState { IMG_NONE = 0, IMG_UPLOADING = 1, IMG_RESIDENT = 2 };
+
 struct Inst {
     int32_t state = BDDMMA_POOL_QUEUED;
     int32_t error = 0;
@@ -33,7 +44,11 @@ struct Inst {
     size_t bytes = 0;
     int64_t n_vars = 0, n_pairs = 0;
     bddmma_solver *s = nullptr;     // the instance alone: loaded, never bound
+    bddmma_solver *pre = nullptr;   // handed over loaded by the caller, not yet checked
     int64_t slot_off = -1;          // first slot in the resident batch (-1: not in it)
+    uint64_t img_size = 0;          // bytes of its table image
+    int64_t img_off = -1;           // image offset in the image region (-1: none)
+    int img = IMG_NONE;
     std::vector<double> lam, mm;    // terminated multipliers and M at retirement
     // input, until compiled
     int64_t nv = 0, nr = 0;
@@ -44,16 +59,23 @@ struct Inst {
 };
 
 constexpr double kNaN = std::numeric_limits<double>::quiet_NaN();
+constexpr size_t kAsmBytes = 8u << 20;   // copy descriptors of one assembly
+
+double ms_since(std::chrono::steady_clock::time_point t)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
 
 }  // namespace
 
 struct bddmma_pool {
     bddmma_options opt{};
     int32_t max_active = 1;
+    bool keep_multipliers = true;
     std::mutex mu;
-    std::condition_variable cv_job, cv_idle;
+    std::condition_variable cv_job, cv_idle, cv_img;
     std::deque<Inst *> jobs;
-    int64_t compiling = 0;          // submitted and not yet READY / FAILED
+    int64_t pending = 0;            // jobs queued or running (compilations and image uploads)
     bool stop = false;
     std::vector<std::thread> workers;
     std::map<int64_t, std::unique_ptr<Inst>> inst;   // by ticket (submission order)
@@ -61,11 +83,17 @@ struct bddmma_pool {
     std::vector<int64_t> members;   // tickets of the resident batch, in batch order
     bool changed = false;           // membership differs from the assembled batch
     char *arena = nullptr;
+    char *asm_area = nullptr;       // copy descriptors
+    char *img_area = nullptr;       // member images
+    size_t img_cap = 0;
+    std::map<uint64_t, uint64_t> img_free;   // free image blocks: offset -> bytes
+    char *halves = nullptr;
     size_t half = 0;
     int side = 0;                   // arena half holding the assembled batch
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;       // the caller's stream: every batch launch
     bddmma_solver *batch = nullptr;
     bool bound = false;
+    bddmma_pool_counters cnt{};
 };
 
 namespace {
@@ -77,8 +105,46 @@ namespace {
     catch (const std::exception &ex) { return set_error(BDDMMA_ERR_INVALID_ARG, ex.what()); }            \
     catch (...) { return set_error(BDDMMA_ERR_INVALID_ARG, "unexpected error"); }
 
-// finish a compiled (or failed) instance; called with the lock held
-void settle(bddmma_pool *p, Inst *in, int rc, bddmma_solver *s)
+uint64_t img_blocks(uint64_t bytes) { return (std::max<uint64_t>(bytes, 1) + 255) & ~uint64_t(255); }
+
+// first fit in the image region; -1 when nothing fits (lock held)
+int64_t img_alloc(bddmma_pool *p, uint64_t bytes)
+{
+    bytes = img_blocks(bytes);
+    for (auto it = p->img_free.begin(); it != p->img_free.end(); ++it)
+        if (it->second >= bytes) {
+            const uint64_t at = it->first, left = it->second - bytes;
+            p->img_free.erase(it);
+            if (left) p->img_free.emplace(at + bytes, left);
+            return (int64_t)at;
+        }
+    return -1;
+}
+
+// return an instance's image space, merging free neighbours (lock held)
+void img_release(bddmma_pool *p, Inst *in)
+{
+    in->img = IMG_NONE;
+    if (in->img_off < 0) return;
+    uint64_t at = (uint64_t)in->img_off, bytes = img_blocks(in->img_size);
+    in->img_off = -1;
+    auto nx = p->img_free.lower_bound(at);
+    if (nx != p->img_free.end() && at + bytes == nx->first) {
+        bytes += nx->second;
+        nx = p->img_free.erase(nx);
+    }
+    if (nx != p->img_free.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == at) {
+            pv->second += bytes;
+            return;
+        }
+    }
+    p->img_free.emplace(at, bytes);
+}
+
+// a compiled (or failed) instance becomes READY (FAILED); lock held
+void settle(Inst *in, int rc, bddmma_solver *s)
 {
     if (rc == BDDMMA_OK) {
         size_t bytes = 0;
@@ -90,6 +156,7 @@ void settle(bddmma_pool *p, Inst *in, int rc, bddmma_solver *s)
             in->bytes = bytes;
             in->n_vars = stt.n_vars;
             in->n_pairs = stt.n_pairs;
+            in->img_size = solver_image_bytes(s);
             in->state = BDDMMA_POOL_READY;
         }
     }
@@ -105,29 +172,104 @@ void settle(bddmma_pool *p, Inst *in, int rc, bddmma_solver *s)
     in->col = {};
     in->coef = {};
     in->sense = {};
-    if (--p->compiling == 0) p->cv_idle.notify_all();
+}
+
+// image space for a READY instance without one, if it fits now (lock held):
+// the caller then uploads it
+bool claim_image(bddmma_pool *p, Inst *in)
+{
+    if (!p->bound || in->state != BDDMMA_POOL_READY || in->img != IMG_NONE || in->img_size > p->img_cap) return false;
+    const int64_t at = img_alloc(p, in->img_size);
+    if (at < 0) return false;
+    in->img_off = at;
+    in->img = IMG_UPLOADING;
+    return true;
+}
+
+// write the image of `in` into buf and upload it on `st` (no lock; the
+// instance is UPLOADING, which keeps it and its image space in place)
+int upload_image(bddmma_pool *p, Inst *in, hipStream_t st, std::vector<uint8_t> &buf)
+{
+    int rc = solver_image(in->s, buf);
+    if (rc) return rc;
+    if (!buf.empty() &&
+        hipMemcpyAsync(p->img_area + in->img_off, buf.data(), buf.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        return set_error(BDDMMA_ERR_HIP, "image upload failed");
+    if (hipStreamSynchronize(st) != hipSuccess) return set_error(BDDMMA_ERR_HIP, "image upload failed");
+    return BDDMMA_OK;
 }
 
 void worker(bddmma_pool *p)
 {
+    hipStream_t up_st = nullptr;   // this worker's upload stream (default priority)
+    std::vector<uint8_t> buf;      // image staging, reused
     for (;;) {
         Inst *in;
         {
             std::unique_lock<std::mutex> lk(p->mu);
             p->cv_job.wait(lk, [&] { return p->stop || !p->jobs.empty(); });
-            if (p->stop) return;
+            if (p->stop) {
+                lk.unlock();
+                if (up_st) (void)hipStreamDestroy(up_st);
+                return;
+            }
             in = p->jobs.front();
             p->jobs.pop_front();
         }
-        // a queued instance cannot be released and the pool joins its workers
-        // before freeing anything, so `in` stays valid without the lock
-        bddmma_solver *s = nullptr;
-        int rc = bddmma_create(&p->opt, &s);
-        if (rc == BDDMMA_OK)
-            rc = bddmma_load_ilp(s, in->nv, in->cost.data(), in->nr, in->row_ptr.data(), in->col.data(),
-                                 in->coef.data(), in->sense.data(), in->rhs.data());
+        // a queued or uploading instance is neither released nor admitted,
+        // and the pool joins its workers before freeing anything, so `in`
+        // stays valid without the lock
+        bool up = false;
+        if (in->state == BDDMMA_POOL_QUEUED) {
+            bddmma_solver *s = in->pre;
+            int rc = BDDMMA_OK;
+            if (s) {
+                in->pre = nullptr;
+                int64_t ni = 0;
+                rc = bddmma_num_instances(s, &ni);
+                if (!rc && ni != 1) rc = set_error(BDDMMA_ERR_INVALID_ARG, "a pool instance must be a single ILP");
+                if (!rc && solver_precision(s) != p->opt.precision)
+                    rc = set_error(BDDMMA_ERR_INVALID_ARG, "instance precision differs from the pool's");
+            } else {
+                rc = bddmma_create(&p->opt, &s);
+                if (rc == BDDMMA_OK)
+                    rc = bddmma_load_ilp(s, in->nv, in->cost.data(), in->nr, in->row_ptr.data(), in->col.data(),
+                                         in->coef.data(), in->sense.data(), in->rhs.data());
+            }
+            std::lock_guard<std::mutex> lk(p->mu);
+            settle(in, rc, s);
+            up = claim_image(p, in);
+        } else {
+            up = true;   // an upload job: image space already claimed
+        }
+        if (up) {
+            int rc = BDDMMA_OK;
+            if (!up_st && hipStreamCreateWithFlags(&up_st, hipStreamNonBlocking) != hipSuccess) {
+                up_st = nullptr;
+                rc = set_error(BDDMMA_ERR_HIP, "upload stream creation failed");
+            }
+            if (!rc) rc = upload_image(p, in, up_st, buf);
+            std::lock_guard<std::mutex> lk(p->mu);
+            if (rc) img_release(p, in);   // admission uploads it again
+            else in->img = IMG_RESIDENT;
+            p->cv_img.notify_all();
+        }
         std::lock_guard<std::mutex> lk(p->mu);
-        settle(p, in, rc, s);
+        if (--p->pending == 0) p->cv_idle.notify_all();
+    }
+}
+
+// hand image uploads of READY instances to the workers while space is free
+// (lock held)
+void prefetch_images(bddmma_pool *p)
+{
+    for (auto &kv : p->inst) {
+        Inst *in = kv.second.get();
+        if (in->state != BDDMMA_POOL_READY || in->img != IMG_NONE) continue;
+        if (!claim_image(p, in)) break;
+        p->jobs.push_back(in);
+        p->pending++;
+        p->cv_job.notify_one();
     }
 }
 
@@ -137,11 +279,15 @@ int reassemble(bddmma_pool *p)
 {
     std::vector<const bddmma_solver *> parts;
     std::vector<Inst *> mem;
+    std::vector<uint64_t> img, img_bytes;
     {
         std::lock_guard<std::mutex> lk(p->mu);
         for (int64_t t : p->members) {
-            mem.push_back(p->inst.at(t).get());
-            parts.push_back(mem.back()->s);
+            Inst *in = p->inst.at(t).get();
+            mem.push_back(in);
+            parts.push_back(in->s);
+            img.push_back((uint64_t)(uintptr_t)(p->img_area + in->img_off));
+            img_bytes.push_back(in->img_size);
         }
     }
     bddmma_options o = p->opt;
@@ -151,10 +297,15 @@ int reassemble(bddmma_pool *p)
     if (rc) return rc;
     std::vector<int64_t> off;
     size_t need = 0;
-    rc = solver_load_merged(nb, parts, off);
+    auto t0 = std::chrono::steady_clock::now();
+    rc = solver_load_virtual(nb, parts, off);
+    p->cnt.merge_ms += ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     if (!rc) rc = bddmma_workspace_bytes(nb, &need);
     if (!rc && need > p->half) rc = set_error(BDDMMA_ERR_NO_MEMORY, "resident batch exceeds its half of the pool arena");
-    if (!rc) rc = bddmma_bind(nb, p->arena + (size_t)(p->side ^ 1) * p->half, p->half, p->st);
+    if (!rc)
+        rc = solver_bind_assembled(nb, p->halves + (size_t)(p->side ^ 1) * p->half, p->half, p->st, parts, img,
+                                   img_bytes, p->asm_area, kAsmBytes);
     for (size_t k = 0; !rc && k < mem.size(); ++k)
         if (p->batch && mem[k]->slot_off >= 0)
             rc = solver_copy_slots(nb, off[k], p->batch, mem[k]->slot_off, solver_slots(mem[k]->s));
@@ -166,9 +317,23 @@ int reassemble(bddmma_pool *p)
     bddmma_destroy(p->batch);
     p->batch = nb;
     p->side ^= 1;
+    p->cnt.bind_ms += ms_since(t0);
+    p->cnt.assemblies++;
     std::lock_guard<std::mutex> lk(p->mu);
     for (size_t k = 0; k < mem.size(); ++k) mem[k]->slot_off = off[k];
     p->changed = false;
+    return BDDMMA_OK;
+}
+
+int enqueue(bddmma_pool *p, std::unique_ptr<Inst> in, int64_t *ticket)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int64_t t = p->next_ticket++;
+    p->jobs.push_back(in.get());
+    p->pending++;
+    p->inst.emplace(t, std::move(in));
+    *ticket = t;
+    p->cv_job.notify_one();
     return BDDMMA_OK;
 }
 
@@ -176,13 +341,16 @@ int reassemble(bddmma_pool *p)
 
 extern "C" {
 
-int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, bddmma_pool **out)
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t keep_multipliers,
+                       bddmma_pool **out)
 {
     POOL_GUARD_BEGIN
     if (!out) return set_error(BDDMMA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (max_active < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "max_active must be >= 1");
     if (host_threads < 0) return set_error(BDDMMA_ERR_INVALID_ARG, "host_threads must be >= 0");
+    if (keep_multipliers != 0 && keep_multipliers != 1)
+        return set_error(BDDMMA_ERR_INVALID_ARG, "keep_multipliers must be 0 or 1");
     bddmma_options o;
     if (opt) o = *opt;
     else bddmma_options_default(&o);
@@ -194,6 +362,7 @@ int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t ho
     std::unique_ptr<bddmma_pool> p(new bddmma_pool());
     p->opt = o;
     p->max_active = max_active;
+    p->keep_multipliers = keep_multipliers != 0;
     unsigned hw = std::thread::hardware_concurrency();
     int n = host_threads > 0 ? host_threads : (int)std::max(1u, std::min(hw ? hw : 1u, 8u));
     for (int i = 0; i < n; ++i) p->workers.emplace_back(worker, p.get());
@@ -205,15 +374,25 @@ int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t ho
 int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stream)
 {
     if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
     if (p->bound) return set_error(BDDMMA_ERR_STATE, "pool arena already bound");
     if (!dev_ptr) return set_error(BDDMMA_ERR_INVALID_ARG, "device pointer is NULL");
     if (((uintptr_t)dev_ptr) % 256) return set_error(BDDMMA_ERR_INVALID_ARG, "device pointer must be 256-byte aligned");
-    const size_t half = (bytes / 2) & ~(size_t)255;
-    if (half == 0) return set_error(BDDMMA_ERR_NO_MEMORY, "pool arena too small");
+    if (bytes < kAsmBytes + 3 * 1024) return set_error(BDDMMA_ERR_NO_MEMORY, "pool arena too small");
+    const size_t rest = bytes - kAsmBytes;
+    const size_t img_cap = (rest / 3) & ~(size_t)255;
+    const size_t half = ((rest - img_cap) / 2) & ~(size_t)255;
     p->arena = (char *)dev_ptr;
+    p->asm_area = p->arena;
+    p->img_area = p->arena + kAsmBytes;
+    p->img_cap = img_cap;
+    p->img_free.clear();
+    p->img_free.emplace(0, img_cap);
+    p->halves = p->img_area + img_cap;
     p->half = half;
     p->st = (hipStream_t)hip_stream;
     p->bound = true;
+    prefetch_images(p);
     return BDDMMA_OK;
 }
 
@@ -238,14 +417,7 @@ int bddmma_pool_submit(bddmma_pool *p, int64_t n_vars, const double *costs, int6
     in->coef.assign(coef, coef + nnz);
     in->sense.assign(sense, sense + n_rows);
     in->rhs.assign(rhs, rhs + n_rows);
-    std::lock_guard<std::mutex> lk(p->mu);
-    const int64_t t = p->next_ticket++;
-    p->jobs.push_back(in.get());
-    p->compiling++;
-    p->inst.emplace(t, std::move(in));
-    *ticket = t;
-    p->cv_job.notify_one();
-    return BDDMMA_OK;
+    return enqueue(p, std::move(in), ticket);
     POOL_GUARD_END
 }
 
@@ -260,20 +432,10 @@ int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, 
         bddmma_destroy(s);
         return set_error(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 1");
     }
-    int64_t ni = 0;
-    int rc = bddmma_num_instances(s, &ni);
-    if (!rc && ni != 1) rc = set_error(BDDMMA_ERR_INVALID_ARG, "a pool instance must be a single ILP");
-    if (!rc && solver_precision(s) != p->opt.precision)
-        rc = set_error(BDDMMA_ERR_INVALID_ARG, "instance precision differs from the pool's");
     std::unique_ptr<Inst> in(new Inst());
     in->n_iter = n_iter;
-    std::lock_guard<std::mutex> lk(p->mu);
-    const int64_t t = p->next_ticket++;
-    p->compiling++;
-    settle(p, in.get(), rc, s);
-    p->inst.emplace(t, std::move(in));
-    *ticket = t;
-    return BDDMMA_OK;
+    in->pre = s;
+    return enqueue(p, std::move(in), ticket);
     POOL_GUARD_END
 }
 
@@ -281,7 +443,7 @@ int bddmma_pool_wait_compiled(bddmma_pool *p)
 {
     if (!p) return set_error(BDDMMA_ERR_INVALID_ARG, "pool is NULL");
     std::unique_lock<std::mutex> lk(p->mu);
-    p->cv_idle.wait(lk, [&] { return p->compiling == 0; });
+    p->cv_idle.wait(lk, [&] { return p->pending == 0; });
     return BDDMMA_OK;
 }
 
@@ -293,15 +455,19 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
     if (iters < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "iters must be >= 1");
     if (n_active) *n_active = 0;
     if (n_retired) *n_retired = 0;
+    std::vector<Inst *> fresh;   // admitted without an uploaded image: it goes up now
+    auto ti = std::chrono::steady_clock::now();
     {
         // admission in submission order while the batch fits
-        std::lock_guard<std::mutex> lk(p->mu);
+        std::unique_lock<std::mutex> lk(p->mu);
         size_t used = 0;
         for (int64_t t : p->members) used += p->inst.at(t)->bytes;
         for (auto &kv : p->inst) {
             Inst *in = kv.second.get();
             if (in->state != BDDMMA_POOL_READY) continue;
-            if (in->bytes > p->half) {
+            if (in->bytes > p->half || in->img_size > p->img_cap) {
+                p->cv_img.wait(lk, [&] { return in->img != IMG_UPLOADING; });
+                img_release(p, in);
                 bddmma_destroy(in->s);
                 in->s = nullptr;
                 in->state = BDDMMA_POOL_FAILED;
@@ -309,8 +475,14 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
                 continue;
             }
             if ((int32_t)p->members.size() >= p->max_active || used + in->bytes > p->half) break;
+            if (in->img == IMG_UPLOADING) continue;   // joins once its image is up
+            if (in->img == IMG_NONE) {
+                if (!claim_image(p, in)) break;
+                fresh.push_back(in);
+            }
             in->state = BDDMMA_POOL_ACTIVE;
             in->slot_off = -1;
+            p->cnt.admitted++;
             used += in->bytes;
             p->members.push_back(kv.first);
             p->changed = true;
@@ -323,11 +495,24 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         }
     }
     int rc;
+    std::vector<uint8_t> buf;
+    for (Inst *in : fresh) {
+        if ((rc = upload_image(p, in, p->st, buf))) return rc;
+        std::lock_guard<std::mutex> lk(p->mu);
+        in->img = IMG_RESIDENT;
+    }
+    p->cnt.image_ms += ms_since(ti);
     if ((p->changed || !p->batch) && (rc = reassemble(p))) return rc;
+    auto t0 = std::chrono::steady_clock::now();
     if ((rc = bddmma_run_dual(p->batch, iters, nullptr))) return rc;
+    p->cnt.run_ms += ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     const size_t n = p->members.size();
     std::vector<double> lbf(n), lbc(n), res(n);
     if ((rc = bddmma_batch_bounds(p->batch, lbf.data(), lbc.data(), res.data()))) return rc;
+    p->cnt.bounds_ms += ms_since(t0);
+    p->cnt.steps++;
+    t0 = std::chrono::steady_clock::now();
     std::vector<Inst *> mem;
     {
         std::lock_guard<std::mutex> lk(p->mu);
@@ -339,7 +524,7 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         const bool flat = p->opt.rel_tol > 0.0 && in->steps >= 1 &&
                           std::fabs(lbf[k] - in->lb_free) <= p->opt.rel_tol * std::max(1.0, std::fabs(lbf[k]));
         done[k] = in->iters + iters >= in->n_iter || flat;
-        if (done[k]) {
+        if (done[k] && p->keep_multipliers) {
             std::vector<double> lam((size_t)in->n_pairs), mm((size_t)in->n_pairs);
             if ((rc = solver_instance_multipliers(p->batch, in->slot_off, in->s, lam.data(), mm.data()))) return rc;
             std::lock_guard<std::mutex> lk(p->mu);
@@ -360,6 +545,7 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         if (done[k]) {
             in->state = BDDMMA_POOL_DONE;
             in->slot_off = -1;
+            img_release(p, in);
             ++retired;
             p->changed = true;
         } else {
@@ -367,6 +553,10 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         }
     }
     p->members.swap(keep);
+    p->cnt.retired += retired;
+    p->cnt.retire_ms += ms_since(t0);
+    // freed image space goes to the next instances waiting for admission
+    if (retired) prefetch_images(p);
     if (n_active) *n_active = (int32_t)p->members.size();
     if (n_retired) *n_retired = retired;
     return BDDMMA_OK;
@@ -405,6 +595,8 @@ int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *m
     if (it == p->inst.end()) return set_error(BDDMMA_ERR_INVALID_ARG, "unknown ticket");
     const Inst &in = *it->second;
     if (in.state != BDDMMA_POOL_DONE) return set_error(BDDMMA_ERR_STATE, "instance not retired");
+    if ((lambda || mm) && !p->keep_multipliers)
+        return set_error(BDDMMA_ERR_STATE, "the pool keeps no multipliers (keep_multipliers = 0)");
     if (lambda) std::copy(in.lam.begin(), in.lam.end(), lambda);
     if (mm) std::copy(in.mm.begin(), in.mm.end(), mm);
     if (pair_var || pair_row) {
@@ -416,6 +608,18 @@ int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *m
     }
     return BDDMMA_OK;
     POOL_GUARD_END
+}
+
+int bddmma_pool_get_counters(bddmma_pool *p, bddmma_pool_counters *out)
+{
+    if (!p || !out) return set_error(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    *out = p->cnt;
+    out->batch_capacity = p->half;
+    out->image_capacity = p->img_cap;
+    out->image_free = 0;
+    for (auto &kv : p->img_free) out->image_free += kv.second;
+    return BDDMMA_OK;
 }
 
 int bddmma_pool_release(bddmma_pool *p, int64_t ticket)
@@ -443,7 +647,10 @@ void bddmma_pool_destroy(bddmma_pool *p)
     for (auto &w : p->workers) w.join();
     if (p->bound && p->st) (void)hipStreamSynchronize(p->st);
     bddmma_destroy(p->batch);
-    for (auto &kv : p->inst) bddmma_destroy(kv.second->s);
+    for (auto &kv : p->inst) {
+        bddmma_destroy(kv.second->s);
+        bddmma_destroy(kv.second->pre);
+    }
     delete p;
 }
 

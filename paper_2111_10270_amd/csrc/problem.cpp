@@ -9,8 +9,10 @@
 // pairs, which gives the reduced (canonical) quasi-reduced BDD.  The paper only
 // needs Def. "BDD"; reduction keeps the tiles small.
 #include "problem.hpp"
+#include "assemble.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <thread>
 #include <unordered_map>
@@ -946,140 +948,79 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     return ST_OK;
 }
 
-int merge_instances(const std::vector<Part> &parts, Problem &P, Packed &O, std::vector<int64_t> &slot_off,
-                    std::string &msg)
+namespace {
+
+// offsets of every instance in each merged table (prefix sums)
+struct MergeOff {
+    int64_t v, r, nnz, p, s, t, c, l, k, sc, b;
+};
+
+int merge_offsets(const std::vector<Part> &parts, std::vector<MergeOff> &off, std::string &msg)
 {
-    P = Problem();
-    O = Packed();
     const int64_t n = (int64_t)parts.size();
-    slot_off.assign((size_t)n, 0);
-    int64_t V = 0, R = 0, PP = 0, S = 0, T = 0, NODES = 0, LAY = 0, CODE = 0, SCR = 0;
-    for (const Part &pt : parts) {
+    off.assign((size_t)n + 1, MergeOff{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
+    for (int64_t k = 0; k < n; ++k) {
+        const Part &pt = parts[k];
         if (!pt.p || !pt.pk || pt.p->ilp.n_inst() != 1) {
             msg = "merge_instances: every part must be one compiled and packed instance";
             return ST_INVALID;
         }
-        V += pt.p->ilp.n_vars;
-        R += pt.p->ilp.n_rows;
-        PP += (int64_t)pt.p->pair_var.size();
-        S += pt.pk->n_slots;
-        T += (int64_t)pt.pk->tiles.size();
-        NODES += (int64_t)pt.pk->child.size();
-        LAY += (int64_t)pt.pk->layers.size();
-        CODE += (int64_t)pt.pk->code.size();
-        SCR += pt.pk->scratch_elems;
+        const Problem &p = *pt.p;
+        const Packed &pk = *pt.pk;
+        MergeOff o = off[k];
+        o.v += p.ilp.n_vars;
+        o.r += p.ilp.n_rows;
+        o.nnz += (int64_t)p.ilp.col.size();
+        o.p += (int64_t)p.pair_var.size();
+        o.s += pk.n_slots;
+        o.t += (int64_t)pk.tiles.size();
+        o.c += (int64_t)pk.child.size();
+        o.l += (int64_t)pk.layers.size();
+        o.k += (int64_t)pk.code.size();
+        o.sc += pk.scratch_elems;
+        o.b += p.bdds.n_bdds();
+        off[k + 1] = o;
     }
-    if (V >= INT32_MAX || PP >= INT32_MAX || S >= INT32_MAX || T >= INT32_MAX || NODES >= (int64_t)UINT32_MAX ||
-        LAY >= (int64_t)UINT32_MAX || CODE >= (int64_t)UINT32_MAX || SCR >= (int64_t)UINT32_MAX) {
+    const MergeOff &tot = off[n];
+    if (tot.v >= INT32_MAX || tot.p >= INT32_MAX || tot.s >= INT32_MAX || tot.t >= INT32_MAX || tot.r >= INT32_MAX ||
+        tot.c >= (int64_t)UINT32_MAX || tot.l >= (int64_t)UINT32_MAX || tot.k >= (int64_t)UINT32_MAX ||
+        tot.sc >= (int64_t)UINT32_MAX) {
         msg = "batch too large for 32-bit indices";
         return ST_INVALID;
     }
-    const bool batch = n > 1;
-    Ilp &U = P.ilp;
-    U.n_vars = V;
-    U.n_rows = R;
-    U.row_ptr.assign(1, 0);
-    U.inst_var.assign(1, 0);
-    U.inst_row.assign(1, 0);
-    BddSet &B = P.bdds;
-    B.lay_off.assign(1, 0);
-    B.node_off.assign(1, 0);
-    O.vptr.assign(1, 0);
-    O.inst_tile.assign(1, 0);
-    O.list_off.assign(kNumLists + 1, 0);
-    std::vector<std::vector<int32_t>> lists(kNumLists);
-    int64_t voff = 0, roff = 0, poff = 0, soff = 0, toff = 0, coff = 0, loff = 0, kodeoff = 0, scroff = 0;
-    for (int64_t k = 0; k < n; ++k) {
-        const Problem &p = *parts[k].p;
-        const Packed &pk = *parts[k].pk;
-        const Ilp &il = p.ilp;
-        slot_off[k] = soff;
-        // problem
-        const int64_t nnz0 = U.row_ptr.back();
-        U.cost.insert(U.cost.end(), il.cost.begin(), il.cost.end());
-        for (int64_t r = 0; r < il.n_rows; ++r) U.row_ptr.push_back(nnz0 + il.row_ptr[r + 1]);
-        for (int32_t c : il.col) U.col.push_back((int32_t)(c + voff));
-        U.coef.insert(U.coef.end(), il.coef.begin(), il.coef.end());
-        U.sense.insert(U.sense.end(), il.sense.begin(), il.sense.end());
-        U.rhs.insert(U.rhs.end(), il.rhs.begin(), il.rhs.end());
-        U.inst_var.push_back(voff + il.n_vars);
-        U.inst_row.push_back(roff + il.n_rows);
-        P.fixed.insert(P.fixed.end(), p.fixed.begin(), p.fixed.end());
-        P.deg.insert(P.deg.end(), p.deg.begin(), p.deg.end());
-        const int64_t blo = (int64_t)B.lay_var.size(), bno = (int64_t)B.child.size();
-        for (int32_t r : p.bdds.row) B.row.push_back((int32_t)(r + roff));
-        for (size_t j = 1; j < p.bdds.lay_off.size(); ++j) B.lay_off.push_back(blo + p.bdds.lay_off[j]);
-        for (size_t j = 1; j < p.bdds.node_off.size(); ++j) B.node_off.push_back(bno + p.bdds.node_off[j]);
-        for (int32_t v : p.bdds.lay_var) B.lay_var.push_back((int32_t)(v + voff));
-        B.lay_width.insert(B.lay_width.end(), p.bdds.lay_width.begin(), p.bdds.lay_width.end());
-        B.child.insert(B.child.end(), p.bdds.child.begin(), p.bdds.child.end());
-        for (int32_t v : p.pair_var) P.pair_var.push_back((int32_t)(v + voff));
-        for (int32_t r : p.pair_row) P.pair_row.push_back((int32_t)(r + roff));
-        P.lb_offset += p.lb_offset;
-        P.inst_offset.push_back(p.lb_offset);
-        P.n_nodes += p.n_nodes;
-        P.n_fixed += p.n_fixed;
-        P.n_free += p.n_free;
-        // tiles and their tables
-        std::vector<char> glob(pk.tiles.size(), 0);
-        for (int64_t q = pk.list_off[LIST_GEN_GLOB_ALL]; q < pk.list_off[LIST_GEN_GLOB_ALL + 1]; ++q)
-            glob[(size_t)pk.lists[q]] = 1;
-        for (size_t t = 0; t < pk.tiles.size(); ++t) {
-            TileDesc d = pk.tiles[t];
-            d.pair_base += (uint32_t)soff;
-            d.node_base += (uint32_t)coff;
-            d.fast_base += (uint32_t)coff;
-            d.layer_base += (uint32_t)loff;
-            d.code_base += (uint32_t)kodeoff;
-            if (glob[t]) d.scratch_base += (uint32_t)scroff;
-            O.tiles.push_back(d);
-            if (batch) O.tile_inst.push_back((int32_t)k);
-        }
-        for (int l = 0; l < kNumLists; ++l)
-            for (int64_t q = pk.list_off[l]; q < pk.list_off[l + 1]; ++q)
-                lists[l].push_back((int32_t)(pk.lists[q] + toff));
-        O.layers.insert(O.layers.end(), pk.layers.begin(), pk.layers.end());
-        O.child.insert(O.child.end(), pk.child.begin(), pk.child.end());
-        O.code.insert(O.code.end(), pk.code.begin(), pk.code.end());
-        for (int32_t v : pk.pair_var) O.pair_var.push_back(v == (int32_t)il.n_vars ? (int32_t)V : (int32_t)(v + voff));
-        for (int64_t s : pk.slot_of_pair) O.slot_of_pair.push_back(s + soff);
-        for (int64_t i = 0; i < il.n_vars; ++i) O.vptr.push_back((int32_t)(poff + pk.vptr[i + 1]));
-        for (int32_t s : pk.vslot) O.vslot.push_back((int32_t)(s + soff));
-        for (int32_t v : pk.gvars) O.gvars.push_back((int32_t)(v + voff));
-        O.max_lds_lane_elems = std::max(O.max_lds_lane_elems, pk.max_lds_lane_elems);
-        O.max_wide_elems = std::max(O.max_wide_elems, pk.max_wide_elems);
-        O.max_layers = std::max(O.max_layers, pk.max_layers);
-        O.max_width = std::max(O.max_width, pk.max_width);
-        if (batch) {
-            O.var_inst.insert(O.var_inst.end(), (size_t)il.n_vars, (int32_t)k);
-            O.row_inst.insert(O.row_inst.end(), (size_t)il.n_rows, (int32_t)k);
-        }
-        voff += il.n_vars;
-        roff += il.n_rows;
-        poff += (int64_t)p.pair_var.size();
-        soff += pk.n_slots;
-        toff += (int64_t)pk.tiles.size();
-        coff += (int64_t)pk.child.size();
-        loff += (int64_t)pk.layers.size();
-        kodeoff += (int64_t)pk.code.size();
-        scroff += pk.scratch_elems;
-        O.inst_tile.push_back(toff);
-    }
-    for (int l = 0; l < kNumLists; ++l) {
-        O.list_off[l + 1] = O.list_off[l] + (int64_t)lists[l].size();
-        O.lists.insert(O.lists.end(), lists[l].begin(), lists[l].end());
-    }
-    O.n_slots = S;
-    O.scratch_elems = SCR;
-    // averaging buckets: one per degree over all instances (variables in
-    // instance order), the CSR bucket last, as the packer orders them
+    return ST_OK;
+}
+
+// averaging buckets of the batch: one per degree over all instances
+// (variables in instance order), the CSR bucket last, as the packer orders
+// them; at[d][k] = first entry of instance k in the merged bucket of degree d
+struct BucketPlan {
+    std::vector<AvgBucket> mb;
+    std::vector<int64_t> of_deg;             // merged bucket of degree d, -1 if none
+    std::vector<std::vector<int64_t>> at;
+    int64_t gslot = 0;
     int32_t blocks = 0;
+};
+
+int bucket_plan(const std::vector<Part> &parts, BucketPlan &bp, std::string &msg)
+{
+    const int64_t n = (int64_t)parts.size();
+    constexpr int kDegs = kEllMaxDeg + 1;
+    bp.at.assign((size_t)kDegs, std::vector<int64_t>((size_t)n + 1, 0));
+    for (int d = 0; d < kDegs; ++d)
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t c = 0;
+            for (const AvgBucket &bk : parts[k].pk->gbuckets)
+                if (bk.deg == d) c += bk.count;
+            bp.at[d][k + 1] = bp.at[d][k] + c;
+        }
+    bp.mb.clear();
+    bp.of_deg.assign((size_t)kDegs, -1);
+    bp.blocks = 0;
+    bp.gslot = 0;
     for (int d = 1; d <= kEllMaxDeg + 1; ++d) {
         const int dd = d <= kEllMaxDeg ? d : 0;
-        int64_t count = 0;
-        for (const Part &pt : parts)
-            for (const AvgBucket &b : pt.pk->gbuckets)
-                if (b.deg == dd) count += b.count;
+        const int64_t count = bp.at[dd][n];
         if (count == 0) continue;
         if (count >= INT32_MAX) {
             msg = "batch too large for 32-bit indices";
@@ -1088,45 +1029,354 @@ int merge_instances(const std::vector<Part> &parts, Problem &P, Packed &O, std::
         AvgBucket nb{};
         nb.deg = dd;
         nb.count = (int32_t)count;
-        nb.block_begin = blocks;
-        nb.base = (int64_t)O.gslot.size();
-        O.gslot.resize(O.gslot.size() + (size_t)(dd ? dd : 1) * (size_t)count);
-        int64_t at = 0;
-        for (int64_t k = 0; k < n; ++k)
-            for (const AvgBucket &b : parts[k].pk->gbuckets) {
-                if (b.deg != dd) continue;
-                const int32_t *src = parts[k].pk->gslot.data() + b.base;
-                if (dd == 0) {
-                    const int64_t vo = P.ilp.inst_var[k];
-                    for (int32_t i = 0; i < b.count; ++i) O.gslot[nb.base + at + i] = (int32_t)(src[i] + vo);
-                } else {
-                    for (int kk = 0; kk < dd; ++kk)
-                        for (int32_t i = 0; i < b.count; ++i)
-                            O.gslot[nb.base + (int64_t)kk * count + at + i] =
-                                (int32_t)(src[(int64_t)kk * b.count + i] + slot_off[k]);
-                }
-                at += b.count;
-            }
-        blocks += (int32_t)((count + 255) / 256);
-        O.gbuckets.push_back(nb);
+        nb.block_begin = bp.blocks;
+        nb.base = bp.gslot;
+        bp.gslot += (int64_t)(dd ? dd : 1) * count;
+        bp.blocks += (int32_t)((count + 255) / 256);
+        bp.of_deg[dd] = (int64_t)bp.mb.size();
+        bp.mb.push_back(nb);
     }
-    O.gblocks = blocks;
+    return ST_OK;
+}
+
+int merge_impl(const std::vector<Part> &parts, Problem &P, Packed &O, std::vector<int64_t> &slot_off, bool big,
+               MergedSizes *sz, std::string &msg)
+{
+    P = Problem();
+    O = Packed();
+    const int64_t n = (int64_t)parts.size();
+    std::vector<MergeOff> off;
+    int rc = merge_offsets(parts, off, msg);
+    if (rc != ST_OK) return rc;
+    const MergeOff &tot = off[n];
+    const int64_t V = tot.v, S = tot.s;
+    slot_off.resize((size_t)n);
+    for (int64_t k = 0; k < n; ++k) slot_off[k] = off[k].s;
+    const bool batch = n > 1;
+    BucketPlan bp;
+    if ((rc = bucket_plan(parts, bp, msg)) != ST_OK) return rc;
+    const std::vector<AvgBucket> &mb = bp.mb;
+    const std::vector<int64_t> &bucket_of_deg = bp.of_deg;
+    const std::vector<std::vector<int64_t>> &at = bp.at;
+    O.gblocks = bp.blocks;
+    if (big) O.gslot.resize((size_t)bp.gslot);
+    O.gbuckets = mb;
+    // sizes
+    Ilp &U = P.ilp;
+    U.n_vars = V;
+    U.n_rows = tot.r;
+    if (big) {
+        U.cost.resize((size_t)V);
+        U.row_ptr.resize((size_t)tot.r + 1);
+        U.row_ptr[0] = 0;
+        U.col.resize((size_t)tot.nnz);
+        U.coef.resize((size_t)tot.nnz);
+        U.sense.resize((size_t)tot.r);
+        U.rhs.resize((size_t)tot.r);
+    }
+    U.inst_var.resize((size_t)n + 1);
+    U.inst_row.resize((size_t)n + 1);
+    for (int64_t k = 0; k <= n; ++k) {
+        U.inst_var[k] = off[k].v;
+        U.inst_row[k] = off[k].r;
+    }
+    // the merged problem carries the row ids of its BDDs only: the diagrams
+    // themselves live in the tiles' node words
+    P.bdds.lay_off.assign(1, 0);
+    P.bdds.node_off.assign(1, 0);
+    P.inst_offset.resize((size_t)n);
+    O.tiles.resize((size_t)tot.t);
+    O.inst_tile.resize((size_t)n + 1);
+    for (int64_t k = 0; k <= n; ++k) O.inst_tile[k] = off[k].t;
+    if (batch) O.tile_inst.resize((size_t)tot.t);
+    std::vector<int64_t> gv_off((size_t)n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) gv_off[k + 1] = gv_off[k] + (int64_t)parts[k].pk->gvars.size();
+    if (big) {
+        P.fixed.resize((size_t)V);
+        P.deg.resize((size_t)V);
+        P.bdds.row.resize((size_t)tot.b);
+        P.pair_var.resize((size_t)tot.p);
+        P.pair_row.resize((size_t)tot.p);
+        O.layers.resize((size_t)tot.l);
+        O.child.resize((size_t)tot.c);
+        O.code.resize((size_t)tot.k);
+        O.pair_var.resize((size_t)S);
+        O.slot_of_pair.resize((size_t)tot.p);
+        O.vptr.resize((size_t)V + 1);
+        O.vptr[0] = 0;
+        O.vslot.resize((size_t)tot.p);
+        O.gvars.resize((size_t)gv_off[n]);
+        if (batch) {
+            O.var_inst.resize((size_t)V);
+            O.row_inst.resize((size_t)tot.r);
+        }
+    } else if (sz) {
+        sz->pairs = tot.p;
+        sz->code = tot.k;
+        sz->gslot = bp.gslot;
+        sz->child = tot.c;
+        sz->layers = tot.l;
+        sz->nnz = tot.nnz;
+    }
+    // fill: every instance writes its own disjoint ranges
+    auto fill = [&](int64_t k) {
+        const Problem &p = *parts[k].p;
+        const Packed &pk = *parts[k].pk;
+        const Ilp &il = p.ilp;
+        const MergeOff &o = off[k];
+        const int32_t nv = (int32_t)il.n_vars;
+        P.inst_offset[k] = p.lb_offset;
+        std::vector<char> glob(pk.tiles.size(), 0);
+        for (int64_t q = pk.list_off[LIST_GEN_GLOB_ALL]; q < pk.list_off[LIST_GEN_GLOB_ALL + 1]; ++q)
+            glob[(size_t)pk.lists[q]] = 1;
+        for (size_t t = 0; t < pk.tiles.size(); ++t) {
+            TileDesc d = pk.tiles[t];
+            d.pair_base += (uint32_t)o.s;
+            d.node_base += (uint32_t)o.c;
+            d.fast_base += (uint32_t)o.c;
+            d.layer_base += (uint32_t)o.l;
+            d.code_base += (uint32_t)o.k;
+            if (glob[t]) d.scratch_base += (uint32_t)o.sc;
+            O.tiles[o.t + t] = d;
+        }
+        if (batch) std::fill(O.tile_inst.begin() + o.t, O.tile_inst.begin() + off[k + 1].t, (int32_t)k);
+        if (!big) return;
+        std::copy(il.cost.begin(), il.cost.end(), U.cost.begin() + o.v);
+        for (int64_t r = 0; r < il.n_rows; ++r) U.row_ptr[o.r + r + 1] = o.nnz + il.row_ptr[r + 1];
+        std::transform(il.col.begin(), il.col.end(), U.col.begin() + o.nnz,
+                       [&](int32_t c) { return (int32_t)(c + o.v); });
+        std::copy(il.coef.begin(), il.coef.end(), U.coef.begin() + o.nnz);
+        std::copy(il.sense.begin(), il.sense.end(), U.sense.begin() + o.r);
+        std::copy(il.rhs.begin(), il.rhs.end(), U.rhs.begin() + o.r);
+        std::copy(p.fixed.begin(), p.fixed.end(), P.fixed.begin() + o.v);
+        std::copy(p.deg.begin(), p.deg.end(), P.deg.begin() + o.v);
+        std::transform(p.bdds.row.begin(), p.bdds.row.end(), P.bdds.row.begin() + o.b,
+                       [&](int32_t r) { return (int32_t)(r + o.r); });
+        std::transform(p.pair_var.begin(), p.pair_var.end(), P.pair_var.begin() + o.p,
+                       [&](int32_t v) { return (int32_t)(v + o.v); });
+        std::transform(p.pair_row.begin(), p.pair_row.end(), P.pair_row.begin() + o.p,
+                       [&](int32_t r) { return (int32_t)(r + o.r); });
+        std::copy(pk.layers.begin(), pk.layers.end(), O.layers.begin() + o.l);
+        std::copy(pk.child.begin(), pk.child.end(), O.child.begin() + o.c);
+        std::copy(pk.code.begin(), pk.code.end(), O.code.begin() + o.k);
+        std::transform(pk.pair_var.begin(), pk.pair_var.end(), O.pair_var.begin() + o.s,
+                       [&](int32_t v) { return v == nv ? (int32_t)V : (int32_t)(v + o.v); });
+        std::transform(pk.slot_of_pair.begin(), pk.slot_of_pair.end(), O.slot_of_pair.begin() + o.p,
+                       [&](int64_t sl) { return sl + o.s; });
+        for (int64_t i = 0; i < il.n_vars; ++i) O.vptr[o.v + i + 1] = (int32_t)(o.p + pk.vptr[i + 1]);
+        std::transform(pk.vslot.begin(), pk.vslot.end(), O.vslot.begin() + o.p,
+                       [&](int32_t sl) { return (int32_t)(sl + o.s); });
+        std::transform(pk.gvars.begin(), pk.gvars.end(), O.gvars.begin() + gv_off[k],
+                       [&](int32_t v) { return (int32_t)(v + o.v); });
+        for (const AvgBucket &bk : pk.gbuckets) {
+            const AvgBucket &m = mb[(size_t)bucket_of_deg[bk.deg]];
+            const int32_t *src = pk.gslot.data() + bk.base;
+            const int64_t a0 = at[bk.deg][k];
+            if (bk.deg == 0) {
+                for (int32_t i = 0; i < bk.count; ++i) O.gslot[m.base + a0 + i] = (int32_t)(src[i] + o.v);
+            } else {
+                for (int kk = 0; kk < bk.deg; ++kk)
+                    for (int32_t i = 0; i < bk.count; ++i)
+                        O.gslot[m.base + (int64_t)kk * m.count + a0 + i] =
+                            (int32_t)(src[(int64_t)kk * bk.count + i] + o.s);
+            }
+        }
+        if (batch) {
+            std::fill(O.var_inst.begin() + o.v, O.var_inst.begin() + off[k + 1].v, (int32_t)k);
+            std::fill(O.row_inst.begin() + o.r, O.row_inst.begin() + off[k + 1].r, (int32_t)k);
+        }
+    };
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int64_t nth = std::min<int64_t>(n, (int64_t)std::max(1u, std::min(hw ? hw : 1u, 16u)));
+        if (nth <= 1 || !big || tot.s < (1 << 16)) {
+            for (int64_t k = 0; k < n; ++k) fill(k);
+        } else {
+            // instances in descending size order over the threads
+            std::vector<int64_t> order((size_t)n);
+            for (int64_t k = 0; k < n; ++k) order[k] = k;
+            std::sort(order.begin(), order.end(),
+                      [&](int64_t x, int64_t y) { return off[x + 1].s - off[x].s > off[y + 1].s - off[y].s; });
+            std::atomic<int64_t> next{0};
+            std::vector<std::thread> th;
+            for (int64_t t = 0; t < nth; ++t)
+                th.emplace_back([&] {
+                    for (int64_t q; (q = next.fetch_add(1)) < n;) fill(order[q]);
+                });
+            for (auto &t : th) t.join();
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        const Problem &p = *parts[k].p;
+        const Packed &pk = *parts[k].pk;
+        P.lb_offset += p.lb_offset;
+        P.n_nodes += p.n_nodes;
+        P.n_fixed += p.n_fixed;
+        P.n_free += p.n_free;
+        O.max_lds_lane_elems = std::max(O.max_lds_lane_elems, pk.max_lds_lane_elems);
+        O.max_wide_elems = std::max(O.max_wide_elems, pk.max_wide_elems);
+        O.max_layers = std::max(O.max_layers, pk.max_layers);
+        O.max_width = std::max(O.max_width, pk.max_width);
+    }
+    // lists: each class's tiles, instance by instance
+    O.list_off.assign(kNumLists + 1, 0);
+    for (int l = 0; l < kNumLists; ++l) {
+        for (int64_t k = 0; k < n; ++k) {
+            const Packed &pk = *parts[k].pk;
+            for (int64_t q = pk.list_off[l]; q < pk.list_off[l + 1]; ++q)
+                O.lists.push_back((int32_t)(pk.lists[q] + off[k].t));
+        }
+        O.list_off[l + 1] = (int64_t)O.lists.size();
+    }
+    O.n_slots = S;
+    O.scratch_elems = tot.sc;
     // every tile inside the merged tables
     for (const TileDesc &d : O.tiles) {
         const uint64_t n64 = (uint64_t)d.K * kLanes;
         const uint64_t words = (uint64_t)d.nodes * ((d.flags & TILE_SHARED) ? 1u : (uint64_t)kLanes);
-        if ((uint64_t)d.pair_base + n64 > (uint64_t)S || (uint64_t)d.code_base + n64 > O.code.size() ||
-            (uint64_t)d.layer_base + d.K > O.layers.size() || (uint64_t)d.node_base + words > O.child.size() ||
-            (uint64_t)d.fast_base + words > O.child.size()) {
+        if ((uint64_t)d.pair_base + n64 > (uint64_t)S || (uint64_t)d.code_base + n64 > (uint64_t)tot.k ||
+            (uint64_t)d.layer_base + d.K > (uint64_t)tot.l || (uint64_t)d.node_base + words > (uint64_t)tot.c ||
+            (uint64_t)d.fast_base + words > (uint64_t)tot.c) {
             msg = "internal error: merged tile outside its tables";
             return ST_INVALID;
         }
     }
-    if ((int64_t)O.vptr.size() != V + 1 || O.vptr.back() != PP || (int64_t)O.pair_var.size() != S) {
+    if (big && O.vptr.back() != tot.p) {
         msg = "internal error: inconsistent merged slot tables";
         return ST_INVALID;
     }
     return ST_OK;
+}
+
+}  // namespace
+
+int merge_instances(const std::vector<Part> &parts, Problem &P, Packed &O, std::vector<int64_t> &slot_off,
+                    std::string &msg)
+{
+    return merge_impl(parts, P, O, slot_off, true, nullptr, msg);
+}
+
+int merge_small(const std::vector<Part> &parts, Problem &P, Packed &O, std::vector<int64_t> &slot_off,
+                MergedSizes &sz, std::string &msg)
+{
+    return merge_impl(parts, P, O, slot_off, false, &sz, msg);
+}
+
+TableSet image_layout(const Problem &p, const Packed &pk)
+{
+    TableSet t{};
+    uint64_t o = 0;
+    auto take = [&](int id, uint64_t bytes) {
+        t.off[id] = o;
+        o = (o + std::max<uint64_t>(bytes, 1) + 255) & ~uint64_t(255);
+    };
+    const Ilp &il = p.ilp;
+    take(TB_PAIR_VAR, (uint64_t)pk.n_slots * 4);
+    take(TB_VPTR, (uint64_t)(il.n_vars + 1) * 4);
+    take(TB_VSLOT, pk.vslot.size() * 4);
+    take(TB_CODE, pk.code.size() * 2);
+    take(TB_GSLOT, pk.gslot.size() * 4);
+    take(TB_CHILD, pk.child.size() * 4);
+    take(TB_LAYERS, pk.layers.size() * 4);
+    take(TB_COST, (uint64_t)il.n_vars * 8);
+    take(TB_RPTR, (uint64_t)(il.n_rows + 1) * 8);
+    take(TB_RCOL, il.col.size() * 4);
+    take(TB_RCOEF, il.coef.size() * 4);
+    take(TB_RSENSE, (uint64_t)il.n_rows);
+    take(TB_RRHS, (uint64_t)il.n_rows * 8);
+    take(TB_PRESET, (uint64_t)il.n_vars);
+    t.off[TB_VAR_INST] = t.off[TB_ROW_INST] = o;   // instance ids are not part of an image
+    t.bytes = o;
+    return t;
+}
+
+void write_image(const Problem &p, const Packed &pk, const TableSet &ts, uint8_t *buf)
+{
+    const Ilp &il = p.ilp;
+    auto put = [&](int id, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(buf + ts.off[id], src, bytes);
+    };
+    put(TB_PAIR_VAR, pk.pair_var.data(), pk.pair_var.size() * 4);
+    put(TB_VPTR, pk.vptr.data(), pk.vptr.size() * 4);
+    put(TB_VSLOT, pk.vslot.data(), pk.vslot.size() * 4);
+    put(TB_CODE, pk.code.data(), pk.code.size() * 2);
+    put(TB_GSLOT, pk.gslot.data(), pk.gslot.size() * 4);
+    put(TB_CHILD, pk.child.data(), pk.child.size() * 4);
+    put(TB_LAYERS, pk.layers.data(), pk.layers.size() * 4);
+    put(TB_COST, il.cost.data(), il.cost.size() * 8);
+    put(TB_RPTR, il.row_ptr.data(), il.row_ptr.size() * 8);
+    put(TB_RCOL, il.col.data(), il.col.size() * 4);
+    int32_t *coef = reinterpret_cast<int32_t *>(buf + ts.off[TB_RCOEF]);
+    for (size_t e = 0; e < il.coef.size(); ++e) coef[e] = (int32_t)il.coef[e];
+    put(TB_RSENSE, il.sense.data(), il.sense.size());
+    put(TB_RRHS, il.rhs.data(), il.rhs.size() * 8);
+    int8_t *pre = reinterpret_cast<int8_t *>(buf + ts.off[TB_PRESET]);
+    for (int64_t i = 0; i < il.n_vars; ++i)
+        pre[i] = p.fixed[i] >= 0 ? p.fixed[i] : p.deg[i] == 0 ? (int8_t)(il.cost[i] < 0.0 ? 1 : 0) : (int8_t)-1;
+}
+
+void assembly_segments(const std::vector<Part> &parts, const std::vector<uint64_t> &img, uint64_t dst_base,
+                       const TableSet &dst, std::vector<Seg> &out)
+{
+    out.clear();
+    std::vector<MergeOff> off;
+    std::string msg;
+    BucketPlan bp;
+    if (merge_offsets(parts, off, msg) != ST_OK || bucket_plan(parts, bp, msg) != ST_OK) return;
+    const int64_t n = (int64_t)parts.size();
+    const int64_t V = off[n].v;
+    auto seg = [&](uint64_t src, int id, int64_t at_elem, int64_t cnt, int32_t op, int32_t elem, int64_t a = 0,
+                   int64_t b = 0, int64_t c = 0) {
+        if (cnt <= 0) return;
+        Seg g{};
+        g.src = src;
+        g.dst = dst_base + dst.off[id] + (uint64_t)at_elem * (uint64_t)elem;
+        g.n = cnt;
+        g.op = op;
+        g.elem = elem;
+        g.a = a;
+        g.b = b;
+        g.c = c;
+        out.push_back(g);
+    };
+    seg(0, TB_VPTR, 0, 1, SEG_FILL, 4, 0);
+    seg(0, TB_RPTR, 0, 1, SEG_FILL, 8, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        const Problem &p = *parts[k].p;
+        const Packed &pk = *parts[k].pk;
+        const Ilp &il = p.ilp;
+        const TableSet ts = image_layout(p, pk);
+        const uint64_t b = img[k];
+        const MergeOff &o = off[k];
+        seg(b + ts.off[TB_PAIR_VAR], TB_PAIR_VAR, o.s, pk.n_slots, SEG_PADVAR, 4, o.v, il.n_vars, V);
+        seg(b + ts.off[TB_VPTR] + 4, TB_VPTR, o.v + 1, il.n_vars, SEG_ADD, 4, o.p);
+        seg(b + ts.off[TB_VSLOT], TB_VSLOT, o.p, (int64_t)pk.vslot.size(), SEG_ADD, 4, o.s);
+        seg(b + ts.off[TB_CODE], TB_CODE, o.k, (int64_t)pk.code.size(), SEG_COPY, 2);
+        for (const AvgBucket &bk : pk.gbuckets) {
+            const AvgBucket &m = bp.mb[(size_t)bp.of_deg[bk.deg]];
+            const int64_t a0 = bp.at[bk.deg][k];
+            const uint64_t src = b + ts.off[TB_GSLOT] + (uint64_t)bk.base * 4;
+            if (bk.deg == 0)
+                seg(src, TB_GSLOT, m.base + a0, bk.count, SEG_ADD, 4, o.v);
+            else
+                for (int kk = 0; kk < bk.deg; ++kk)
+                    seg(src + (uint64_t)kk * bk.count * 4, TB_GSLOT, m.base + (int64_t)kk * m.count + a0, bk.count,
+                        SEG_ADD, 4, o.s);
+        }
+        seg(b + ts.off[TB_CHILD], TB_CHILD, o.c, (int64_t)pk.child.size(), SEG_COPY, 4);
+        seg(b + ts.off[TB_LAYERS], TB_LAYERS, o.l, (int64_t)pk.layers.size(), SEG_COPY, 4);
+        seg(b + ts.off[TB_COST], TB_COST, o.v, il.n_vars, SEG_COPY, 8);
+        seg(b + ts.off[TB_RPTR] + 8, TB_RPTR, o.r + 1, il.n_rows, SEG_ADD, 8, o.nnz);
+        seg(b + ts.off[TB_RCOL], TB_RCOL, o.nnz, (int64_t)il.col.size(), SEG_ADD, 4, o.v);
+        seg(b + ts.off[TB_RCOEF], TB_RCOEF, o.nnz, (int64_t)il.coef.size(), SEG_COPY, 4);
+        seg(b + ts.off[TB_RSENSE], TB_RSENSE, o.r, il.n_rows, SEG_COPY, 1);
+        seg(b + ts.off[TB_RRHS], TB_RRHS, o.r, il.n_rows, SEG_COPY, 8);
+        seg(b + ts.off[TB_PRESET], TB_PRESET, o.v, il.n_vars, SEG_COPY, 1);
+        if (n > 1) {
+            seg(0, TB_VAR_INST, o.v, il.n_vars, SEG_FILL, 4, k);
+            seg(0, TB_ROW_INST, o.r, il.n_rows, SEG_FILL, 4, k);
+        }
+    }
 }
 
 }  // namespace bddmma

@@ -113,6 +113,41 @@ struct Part {
 int merge_instances(const std::vector<Part> &parts, Problem &out, Packed &opk, std::vector<int64_t> &slot_off,
                     std::string &msg);
 
+// ---- the same batch assembled on the device -----------------------------------
+// Tables a solver uploads for its problem, in the order of the layout.
+enum TableId {
+    TB_PAIR_VAR, TB_VPTR, TB_VSLOT, TB_CODE, TB_GSLOT, TB_CHILD, TB_LAYERS, TB_COST,
+    TB_RPTR, TB_RCOL, TB_RCOEF, TB_RSENSE, TB_RRHS, TB_PRESET, TB_VAR_INST, TB_ROW_INST, kNumTables
+};
+struct TableSet {
+    uint64_t off[kNumTables];   // byte offsets from the base
+    uint64_t bytes;             // total (images) / end of the last table
+};
+
+// Image of one instance's tables (what bind uploads for it alone; presolved
+// values as the check kernel reads them, coefficients as int32), 256-byte
+// aligned tables; no instance ids.
+TableSet image_layout(const Problem &p, const Packed &pk);
+void write_image(const Problem &p, const Packed &pk, const TableSet &ts, uint8_t *buf);
+
+// Sizes of the big tables of a merged batch.
+struct MergedSizes {
+    int64_t pairs = 0, code = 0, gslot = 0, child = 0, layers = 0, nnz = 0;
+};
+
+// merge_instances without the big tables: tiles, lists, buckets, instance
+// ranges and scalars exactly as merge_instances fills them; the tables listed
+// in TableId (and the host-only pair maps) are left empty, their sizes in sz.
+int merge_small(const std::vector<Part> &parts, Problem &out, Packed &opk, std::vector<int64_t> &slot_off,
+                MergedSizes &sz, std::string &msg);
+
+// Copy steps that write every TableId table of the merged batch (byte offsets
+// dst.off from dst_base) from the instance images at img[k] (laid out by
+// image_layout), giving exactly the tables merge_instances builds.
+struct Seg;
+void assembly_segments(const std::vector<Part> &parts, const std::vector<uint64_t> &img, uint64_t dst_base,
+                       const TableSet &dst, std::vector<Seg> &out);
+
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.
 int compile_row(const int32_t *var, const int64_t *a, int k, int sense, int64_t b, BddSet &out,

@@ -13,9 +13,23 @@ int set_error(int code, const std::string &msg);
 
 // Load into the fresh solver s (created, nothing loaded) the batch of the
 // loaded single-instance solvers `parts` (same precision as s), each instance
-// keeping the tiles it has alone.  slot_off[k]: first slot of instance k.
-int solver_load_merged(bddmma_solver *s, const std::vector<const bddmma_solver *> &parts,
-                       std::vector<int64_t> &slot_off);
+// keeping the tiles it has alone.  Only the small tables are built on the
+// host; the big ones are assembled on the device when the batch is bound with
+// solver_bind_assembled.  slot_off[k]: first slot of instance k.
+int solver_load_virtual(bddmma_solver *s, const std::vector<const bddmma_solver *> &parts,
+                        std::vector<int64_t> &slot_off);
+
+// Bind such a batch: its big tables are copied (with their index shifts) on
+// the device from the member images (images[k]: device address of the image
+// of parts[k], image_bytes[k] its size, as solver_image wrote it); scratch
+// holds the copy descriptors.  Ordered on hip_stream; synchronises it.
+int solver_bind_assembled(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream,
+                          const std::vector<const bddmma_solver *> &parts, const std::vector<uint64_t> &images,
+                          const std::vector<uint64_t> &image_bytes, void *scratch, size_t scratch_bytes);
+
+// Host image of a loaded single instance's tables, and its size.
+int solver_image(const bddmma_solver *s, std::vector<uint8_t> &buf);
+uint64_t solver_image_bytes(const bddmma_solver *s);
 
 int64_t solver_slots(const bddmma_solver *s);
 

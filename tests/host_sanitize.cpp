@@ -2,14 +2,17 @@
 // solver's host code: ingestion, instance boundaries, presolve, BDD
 // compilation and tile packing, on generated ILPs (random rows around a
 // hidden point, wide knapsack rows, long rows, empty rows, batches) under
-// every packing option, and batches assembled from instances packed alone.
+// every packing option, and batches assembled from instances packed alone
+// (on the host, and through the device assembly's copy segments).
 // Exits non-zero on the first inconsistency; the
 // sanitizers abort on memory or undefined-behaviour errors.
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
+#include "assemble.hpp"
 #include "problem.hpp"
 
 using namespace bddmma;
@@ -129,6 +132,134 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
     }
 }
 
+// host model of the device copy kernel (same semantics per segment)
+void apply_segments(const std::vector<Seg> &segs)
+{
+    for (const Seg &g : segs)
+        for (int64_t i = 0; i < g.n; ++i) switch (g.elem) {
+            case 1:
+                reinterpret_cast<uint8_t *>(g.dst)[i] =
+                    g.op == SEG_FILL ? (uint8_t)g.a : reinterpret_cast<const uint8_t *>(g.src)[i];
+                break;
+            case 2:
+                reinterpret_cast<uint16_t *>(g.dst)[i] =
+                    g.op == SEG_FILL ? (uint16_t)g.a : reinterpret_cast<const uint16_t *>(g.src)[i];
+                break;
+            case 4: {
+                int32_t v = g.op == SEG_FILL ? (int32_t)g.a : reinterpret_cast<const int32_t *>(g.src)[i];
+                if (g.op == SEG_ADD) v += (int32_t)g.a;
+                else if (g.op == SEG_PADVAR) v = v == (int32_t)g.b ? (int32_t)g.c : v + (int32_t)g.a;
+                reinterpret_cast<int32_t *>(g.dst)[i] = v;
+                break;
+            }
+            case 8: {
+                int64_t v = g.op == SEG_FILL ? g.a : reinterpret_cast<const int64_t *>(g.src)[i];
+                if (g.op == SEG_ADD) v += g.a;
+                reinterpret_cast<int64_t *>(g.dst)[i] = v;
+                break;
+            }
+            default: break;
+            }
+}
+
+// The device assembly path: small tables from merge_small, big tables from
+// the instances' images through the copy segments; both must equal what
+// merge_instances builds on the host (the big tables are compared in a
+// buffer poisoned beforehand, so every element must have been written).
+void check_assembly(const std::vector<Part> &parts, const Problem &u, const Packed &o,
+                    const std::vector<int64_t> &soff, int64_t seed)
+{
+    Problem us;
+    Packed os;
+    std::vector<int64_t> so;
+    MergedSizes sz;
+    std::string msg;
+    int rc = merge_small(parts, us, os, so, sz, msg);
+    check(rc == ST_OK, "assembly: merge_small", seed);
+    if (rc != ST_OK) return;
+    check(so == soff, "assembly: slot offsets", seed);
+    auto eq = [](const void *a, const void *b, size_t n) { return n == 0 || std::memcmp(a, b, n) == 0; };
+    check(os.tiles.size() == o.tiles.size() && eq(os.tiles.data(), o.tiles.data(), o.tiles.size() * sizeof(TileDesc)),
+          "assembly: tiles", seed);
+    check(os.lists == o.lists && os.list_off == o.list_off && os.inst_tile == o.inst_tile &&
+              os.tile_inst == o.tile_inst && os.gblocks == o.gblocks && os.n_slots == o.n_slots &&
+              os.scratch_elems == o.scratch_elems && os.max_lds_lane_elems == o.max_lds_lane_elems &&
+              os.max_wide_elems == o.max_wide_elems,
+          "assembly: small tables", seed);
+    check(os.gbuckets.size() == o.gbuckets.size() &&
+              eq(os.gbuckets.data(), o.gbuckets.data(), o.gbuckets.size() * sizeof(AvgBucket)),
+          "assembly: buckets", seed);
+    check(us.ilp.inst_var == u.ilp.inst_var && us.ilp.inst_row == u.ilp.inst_row &&
+              us.inst_offset == u.inst_offset && us.lb_offset == u.lb_offset,
+          "assembly: instance ranges", seed);
+    check(sz.pairs == (int64_t)u.pair_var.size() && sz.code == (int64_t)o.code.size() &&
+              sz.gslot == (int64_t)o.gslot.size() && sz.child == (int64_t)o.child.size() &&
+              sz.layers == (int64_t)o.layers.size() && sz.nnz == (int64_t)u.ilp.col.size(),
+          "assembly: sizes", seed);
+    // images
+    std::vector<std::vector<uint64_t>> img(parts.size());
+    std::vector<uint64_t> base;
+    for (size_t k = 0; k < parts.size(); ++k) {
+        const TableSet ts = image_layout(*parts[k].p, *parts[k].pk);
+        img[k].assign(ts.bytes / 8 + 1, 0);
+        write_image(*parts[k].p, *parts[k].pk, ts, reinterpret_cast<uint8_t *>(img[k].data()));
+        base.push_back((uint64_t)(uintptr_t)img[k].data());
+    }
+    // batch tables
+    const int64_t V = u.ilp.n_vars, R = u.ilp.n_rows, nnz = (int64_t)u.ilp.col.size();
+    const uint64_t bytes[kNumTables] = {(uint64_t)o.n_slots * 4, (uint64_t)(V + 1) * 4, u.pair_var.size() * 4,
+                                        o.code.size() * 2, o.gslot.size() * 4, o.child.size() * 4,
+                                        o.layers.size() * 4, (uint64_t)V * 8, (uint64_t)(R + 1) * 8,
+                                        (uint64_t)nnz * 4, (uint64_t)nnz * 4, (uint64_t)R, (uint64_t)R * 8,
+                                        (uint64_t)V, parts.size() > 1 ? (uint64_t)V * 4 : 0,
+                                        parts.size() > 1 ? (uint64_t)R * 4 : 0};
+    TableSet dst{};
+    uint64_t at = 0;
+    for (int t = 0; t < kNumTables; ++t) {
+        dst.off[t] = at;
+        at = (at + bytes[t] + 8 + 255) & ~uint64_t(255);
+    }
+    std::vector<uint64_t> buf(at / 8 + 1, 0xA5A5A5A5A5A5A5A5ull);
+    uint8_t *b = reinterpret_cast<uint8_t *>(buf.data());
+    std::vector<Seg> segs;
+    assembly_segments(parts, base, (uint64_t)(uintptr_t)b, dst, segs);
+    // every segment inside its table
+    for (const Seg &g : segs) {
+        bool in = false;
+        for (int t = 0; t < kNumTables; ++t)
+            in |= g.dst >= (uint64_t)(uintptr_t)(b + dst.off[t]) &&
+                  g.dst + (uint64_t)g.n * g.elem <= (uint64_t)(uintptr_t)(b + dst.off[t]) + bytes[t];
+        check(in, "assembly: segment inside one table", seed);
+        if (!in) return;
+    }
+    apply_segments(segs);
+    auto same = [&](int t, const void *ref, uint64_t n) {
+        return n == bytes[t] && (n == 0 || std::memcmp(b + dst.off[t], ref, n) == 0);
+    };
+    std::vector<int32_t> coef32(u.ilp.coef.begin(), u.ilp.coef.end());
+    std::vector<int8_t> pre((size_t)V);
+    for (int64_t i = 0; i < V; ++i)
+        pre[i] = u.fixed[i] >= 0 ? u.fixed[i] : u.deg[i] == 0 ? (int8_t)(u.ilp.cost[i] < 0.0 ? 1 : 0) : (int8_t)-1;
+    check(same(TB_PAIR_VAR, o.pair_var.data(), o.pair_var.size() * 4), "assembly: pair_var", seed);
+    check(same(TB_VPTR, o.vptr.data(), o.vptr.size() * 4), "assembly: vptr", seed);
+    check(same(TB_VSLOT, o.vslot.data(), o.vslot.size() * 4), "assembly: vslot", seed);
+    check(same(TB_CODE, o.code.data(), o.code.size() * 2), "assembly: code", seed);
+    check(same(TB_GSLOT, o.gslot.data(), o.gslot.size() * 4), "assembly: gslot", seed);
+    check(same(TB_CHILD, o.child.data(), o.child.size() * 4), "assembly: child", seed);
+    check(same(TB_LAYERS, o.layers.data(), o.layers.size() * 4), "assembly: layers", seed);
+    check(same(TB_COST, u.ilp.cost.data(), u.ilp.cost.size() * 8), "assembly: cost", seed);
+    check(same(TB_RPTR, u.ilp.row_ptr.data(), u.ilp.row_ptr.size() * 8), "assembly: row_ptr", seed);
+    check(same(TB_RCOL, u.ilp.col.data(), u.ilp.col.size() * 4), "assembly: col", seed);
+    check(same(TB_RCOEF, coef32.data(), coef32.size() * 4), "assembly: coef", seed);
+    check(same(TB_RSENSE, u.ilp.sense.data(), u.ilp.sense.size()), "assembly: sense", seed);
+    check(same(TB_RRHS, u.ilp.rhs.data(), u.ilp.rhs.size() * 8), "assembly: rhs", seed);
+    check(same(TB_PRESET, pre.data(), pre.size()), "assembly: preset", seed);
+    if (parts.size() > 1) {
+        check(same(TB_VAR_INST, o.var_inst.data(), o.var_inst.size() * 4), "assembly: var_inst", seed);
+        check(same(TB_ROW_INST, o.row_inst.data(), o.row_inst.size() * 4), "assembly: row_inst", seed);
+    }
+}
+
 // Batch assembled from instances packed alone (the serving pool's path):
 // every instance keeps its tiles, slots and codes at shifted offsets, and the
 // merged averaging buckets hold every kernel-averaged variable once with its
@@ -227,6 +358,7 @@ void run_merge(const std::vector<Csr> &cs, int variant, int64_t seed)
     std::vector<int> want((size_t)V, 0);
     for (int32_t v : o.gvars) want[v] = 1;
     for (int64_t v = 0; v < V; ++v) check(hits[v] == want[v], "merge: averaged variables", seed);
+    check_assembly(parts, u, o, soff, seed);
 }
 
 }  // namespace
@@ -265,6 +397,16 @@ int main()
             insts.push_back(random_ilp(h, nk, nk ? h.range(0, 2 * nk) : 0, seed % 6 == 0 ? 40 : (int)h.range(1, 22), 3));
         }
         run_merge(insts, (int)(seed % 5), seed);
+    }
+    {
+        // large enough for the threaded merge
+        std::vector<Csr> big;
+        for (int k = 0; k < 5; ++k) {
+            Rng h{(uint64_t)(977 + k)};
+            big.push_back(random_ilp(h, 2500 + 300 * k, 3500, 8, 3));
+        }
+        run_merge(big, 0, 977);
+        run_merge(big, 4, 978);
     }
     std::printf("host checks: %d failures\n", fails);
     return fails ? 1 : 0;

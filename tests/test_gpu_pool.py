@@ -3,7 +3,8 @@
 Whatever joins or leaves the resident batch around it, every instance ends
 where a solver loaded with it alone ends after the same number of Alg. 1
 iterations: multipliers, deferred differences and per-instance bounds are
-compared bit for bit (the instance keeps its own tiles, and its state is
+compared bit for bit (the instance keeps its own tiles, the batch tables are
+assembled on the device from the members' images, and a member's state is
 copied unchanged when the batch is re-assembled).  Also: admission by
 workspace bytes and member count, retirement by tolerance, adopted solvers.
 """
@@ -94,8 +95,11 @@ def test_pool_admission_by_workspace():
     can never fit fails with NO_MEMORY; the cap on members holds"""
     ilps = members()[:6]
     sizes = [B.Solver(p, precision=64).workspace_bytes() for p in ilps]
-    half = max(sizes) + min(sizes)
-    pool = B.Pool(max_active=3, precision=64).bind(2 * half + 512)
+    want = max(sizes) + min(sizes)
+    pool = B.Pool(max_active=3, precision=64).bind((8 << 20) + 3 * want + 4096)   # descriptors + 3 thirds
+    cnt = pool.counters()
+    half = cnt["batch_capacity"]
+    assert want <= half < want + 4096 and cnt["image_free"] == cnt["image_capacity"]
     big = I.mrf_grid(40, 40, 8, pairwise="trunc_linear", seed=1)
     tb = pool.submit(big, 5)
     ts = [pool.submit(p, 10) for p in ilps]
@@ -115,6 +119,9 @@ def test_pool_admission_by_workspace():
     assert seen >= 1
     for p, t in zip(ilps, ts):
         assert_matches_solo(pool, t, p, precision=64)
+    cnt = pool.counters()
+    assert cnt["image_free"] == cnt["image_capacity"]          # every image released at retirement
+    assert cnt["admitted"] == cnt["retired"] == len(ilps) and cnt["assemblies"] >= 2
 
 
 def test_pool_tolerance_retirement():
@@ -142,8 +149,34 @@ def test_pool_adopts_loaded_solvers():
     ilps = members()[:3]
     pool = B.Pool(max_active=8, precision=32).bind(64 << 20)
     ts = [pool.submit_loaded(B.Solver(p, precision=32), 10) for p in ilps]
+    pool.wait_compiled()                      # checked and uploaded by the workers
     assert all(pool.poll(t)["state"] == B.POOL_READY for t in ts)
     assert pool.step(5) == (3, 0)
     assert pool.step(5) == (0, 3)
     for p, t in zip(ilps, ts):
         assert_matches_solo(pool, t, p, precision=32)
+
+
+def test_pool_bounds_only_and_prefetched_images():
+    """keep_multipliers=0 keeps bounds (still equal to the solo ones) and no
+    multipliers; images of compiled instances are uploaded by the workers
+    before admission"""
+    ilps = members()[:4]
+    pool = B.Pool(max_active=2, keep_multipliers=False, precision=64).bind(64 << 20)
+    ts = [pool.submit(p, 10) for p in ilps]
+    pool.wait_compiled()                      # compiled and uploaded
+    cnt = pool.counters()
+    assert cnt["image_free"] < cnt["image_capacity"]
+    while any(pool.poll(t)["state"] != B.POOL_DONE for t in ts):
+        pool.step(5)
+    assert pool.counters()["image_ms"] >= 0.0
+    for p, t in zip(ilps, ts):
+        info = pool.poll(t)
+        a = solo(p, 10, precision=64)
+        f, c, r = a.batch_bounds()
+        assert (info["lb_free"], info["lb_cert"], info["max_residual"]) == (f[0], c[0], r[0])
+        with pytest.raises(B.BddmmaError) as e:
+            pool.result(t)
+        assert e.value.code == B.STATE
+        _, _, pv, _ = pool.result(t, multipliers=False)
+        assert np.array_equal(pv, a.pairs()[0])
