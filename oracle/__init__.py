@@ -63,6 +63,7 @@ def lib():
         L.or_lb_cert.argtypes = [P, P]
         L.or_terminate.argtypes = [P]
         L.or_run_dual.argtypes = [P, i, P]
+        L.or_run_serial.argtypes = [P, i, P]
         L.or_rng_u01.restype = d
         L.or_rng_u01.argtypes = [ull, ull, ull]
         L.or_perturb.argtypes = [P, i, d, d, ull, P, i]
@@ -181,6 +182,13 @@ class Oracle:
     def run_dual(self, n_iter: int):
         hist = np.zeros(2 * max(n_iter, 0))
         lib().or_run_dual(self.h, int(n_iter), _p(hist) if n_iter > 0 else None)
+        return hist
+
+    def run_serial(self, n_iter: int):
+        """serial min-marginal averaging from the terminated multipliers; sum_j E^j
+        + offset after every sweep"""
+        hist = np.zeros(2 * max(n_iter, 0))
+        lib().or_run_serial(self.h, int(n_iter), _p(hist) if n_iter > 0 else None)
         return hist
 
     def full_mm(self):

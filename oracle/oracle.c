@@ -30,6 +30,9 @@
  *    sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0) with the multiplier
  *    residual r_i = sum_j (lambda_i^j + omega M_ij) - c_i.
  *  - Termination step of Alg. 1: lambda += omega * M-bar.
+ *  - Serial averaging (ablation): the sequential update of Sec. 3 applied
+ *    variable by variable in id order, full averaging, no damping, from the
+ *    terminated multipliers (see or_run_serial).
  *  - Presolve: a variable that a single row allows only one value for is
  *    fixed and substituted until nothing changes (keeps all min-marginals
  *    finite); variables in no row take x_i = [c_i < 0].
@@ -675,6 +678,110 @@ void or_run_dual(OSolver *s, int n_iter, double *lb_hist)
         or_average(s);
         if (lb_hist) lb_hist[2 * it + 1] = or_lb_free(s);
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Serial min-marginal averaging (ablation of the deferred scheme)     */
+/* ------------------------------------------------------------------ */
+
+/* One sweep of the sequential scheme the paper compares against (Sec. 3,
+ * update (dual_update_serial)): variables in ascending (dir 0) or descending
+ * (dir 1) id order; for variable i, the min-marginal differences M_ik of
+ * every subproblem k in J_i at the current multipliers, then
+ *     lambda_i^k <- (lambda_i^k - M_ik) + (1/|J_i|) * sum_{k in J_i} M_ik
+ * (sum in ascending row order) before the next variable is visited.  A
+ * subproblem's layers come in variable order, so each sweep visits them in
+ * order: dir 0 keeps SP(r, .) up to the current layer and uses SP(., top)
+ * computed at the start of the sweep for the layers not yet visited (their
+ * multipliers are unchanged), dir 1 the mirror image.  The update keeps
+ * sum_k lambda_i^k unchanged, so multipliers that start dual feasible stay
+ * feasible, and E^j after the sweep is the energy at the final multipliers. */
+static void serial_sweep(OSolver *s, int dir, long long *noff, int *pb, double *F, double *Bk, double *cost)
+{
+    for (int j = 0; j < s->nb; ++j) {
+        const OBdd *d = &s->bdd[j];
+        for (int h = 0; h < d->k; ++h) cost[h] = s->lam[s->pstart[j] + h];
+        if (dir == 0) {
+            sp_to_top(d, cost, Bk + noff[j]);
+            for (int v = 0; v < d->n; ++v) F[noff[j] + v] = INFINITY;
+            if (d->n > 0) F[noff[j]] = 0.0;
+            s->E[j] = INFINITY;
+        } else {
+            sp_from_root(d, cost, F + noff[j]);
+        }
+    }
+    for (long long idx = 0; idx < s->n_vars; ++idx) {
+        const long long i = dir == 0 ? idx : s->n_vars - 1 - idx;
+        if (s->deg[i] == 0) continue;
+        double sum = 0.0;
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) {
+            const long long p = s->vpair[q];
+            const int j = pb[p];
+            const int h = (int)(p - s->pstart[j]);
+            double m0, m1;
+            layer_min_marginals(&s->bdd[j], h, s->lam[p], F + noff[j], Bk + noff[j], &m0, &m1);
+            s->mm[p] = m1 - m0;
+            sum += s->mm[p];
+        }
+        const double a = (1.0 / (double)s->deg[i]) * sum;
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) {
+            const long long p = s->vpair[q];
+            const int j = pb[p];
+            const OBdd *d = &s->bdd[j];
+            const int h = (int)(p - s->pstart[j]);
+            s->lam[p] = (s->lam[p] - s->mm[p]) + a;
+            double *Fj = F + noff[j], *Bj = Bk + noff[j];
+            if (dir == 0) {
+                for (int v = d->lstart[h]; v < d->lstart[h + 1]; ++v)
+                    for (int t = 0; t < 2; ++t) {
+                        int c = t ? d->hi[v] : d->lo[v];
+                        double val = t ? Fj[v] + s->lam[p] : Fj[v];
+                        if (c == OR_BOT) continue;
+                        if (c == OR_TOP) { if (val < s->E[j]) s->E[j] = val; }
+                        else if (val < Fj[c]) Fj[c] = val;
+                    }
+            } else {
+                for (int v = d->lstart[h]; v < d->lstart[h + 1]; ++v) {
+                    double b0 = child_val(d->lo[v], Bj);
+                    double b1 = child_val(d->hi[v], Bj) + s->lam[p];
+                    Bj[v] = b0 < b1 ? b0 : b1;
+                }
+                if (h == 0) s->E[j] = Bj[0];
+            }
+        }
+    }
+}
+
+/* n_iter iterations (forward + backward sweep) of the serial scheme, starting
+ * from the terminated multipliers (termination step of Alg. 1 first, so they
+ * are dual feasible); lb_hist gets sum_j E^j + offset after every sweep when
+ * non-NULL.  Afterwards M-bar = 0 and a_i = 0: lambda alone is the dual point. */
+void or_run_serial(OSolver *s, int n_iter, double *lb_hist)
+{
+    long long *noff = malloc(sizeof(long long) * (size_t)(s->nb + 1));
+    int *pb = malloc(sizeof(int) * (size_t)(s->np > 0 ? s->np : 1));
+    double *cost = malloc(sizeof(double) * (size_t)(s->maxk > 0 ? s->maxk : 1));
+    noff[0] = 0;
+    for (int j = 0; j < s->nb; ++j) {
+        noff[j + 1] = noff[j] + s->bdd[j].n;
+        for (long long p = s->pstart[j]; p < s->pstart[j + 1]; ++p) pb[p] = j;
+    }
+    double *F = malloc(sizeof(double) * (size_t)(noff[s->nb] > 0 ? noff[s->nb] : 1));
+    double *Bk = malloc(sizeof(double) * (size_t)(noff[s->nb] > 0 ? noff[s->nb] : 1));
+    or_terminate(s);
+    for (long long p = 0; p < s->np; ++p) s->mm[p] = 0.0;
+    for (int it = 0; it < n_iter; ++it)
+        for (int dir = 0; dir < 2; ++dir) {
+            serial_sweep(s, dir, noff, pb, F, Bk, cost);
+            if (lb_hist) {
+                double e = 0.0;
+                for (int j = 0; j < s->nb; ++j) e += s->E[j];
+                lb_hist[2 * it + dir] = e + s->lb_offset;
+            }
+        }
+    for (long long p = 0; p < s->np; ++p) s->mm[p] = 0.0;
+    for (long long i = 0; i < s->n_vars; ++i) s->avg[i] = 0.0;
+    free(noff); free(pb); free(cost); free(F); free(Bk);
 }
 
 /* ------------------------------------------------------------------ */
