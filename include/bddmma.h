@@ -90,7 +90,11 @@ typedef struct {
                               kernel, so a sweep is one launch per layer class: the
                               launches of small problems are latency-bound.  0 = never.
                               2048 */
-    int32_t  reserved[2];  /* must be zero */
+    int32_t  serial_mma;   /* 1: also build the tables of the serial min-marginal averaging
+                              (bddmma_run_serial; BDDs in their own order plus a level
+                              schedule, about 4 B per node and 40 B per pair more device
+                              memory); 0: none.  0 */
+    int32_t  reserved[1];  /* must be zero */
 } bddmma_options;
 
 typedef struct {
@@ -377,6 +381,23 @@ void bddmma_pool_destroy(bddmma_pool *p);
  * resuming from it is bitwise identical to not stopping. */
 int bddmma_save_state(const bddmma_solver *s, void *buf, size_t *bytes);
 int bddmma_load_state(bddmma_solver *s, const void *buf, size_t bytes);
+
+/* Ablation of the deferred scheme: the serial min-marginal averaging it
+ * replaces (Sec. 3, update (dual_update_serial)).  Needs options.serial_mma =
+ * 1 (STATE otherwise).  Starts from the terminated multipliers lambda + omega
+ * M-bar of the current state and runs n_iter iterations, each a sweep over
+ * the variables in ascending and then in descending id order; for each
+ * variable i the min-marginal differences M_ik of all subproblems k in J_i are
+ * taken at the current multipliers and lambda_i^k <- (lambda_i^k - M_ik) +
+ * (1/|J_i|) sum_k M_ik (ascending row order) before the next variable.  The
+ * device runs the variables level by level (a variable's level follows its
+ * predecessors in every subproblem containing it), one launch per level.
+ * After every sweep sum_j E^j + constant is a lower bound; these bounds are
+ * appended to the bound history and, when lb_hist is not NULL, written to
+ * lb_hist[2 * n_iter].  Afterwards the state is the serial multipliers with
+ * M-bar = 0, so lower_bound, round_primal and further run_dual calls continue
+ * from them.  Synchronises the stream. */
+int bddmma_run_serial(bddmma_solver *s, int32_t n_iter, double *lb_hist);
 
 /* Per-kernel timing with HIP events recorded on the bound stream around the
  * sweeps of run_dual / run_sweeps.  enable = n > 0 starts a new collection

@@ -28,7 +28,7 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
-           "bddmma_pool_get_counters")
+           "bddmma_pool_get_counters", "bddmma_run_serial")
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 
@@ -45,7 +45,8 @@ class Options(C.Structure):
                 ("reopt_iters", C.c_int32), ("max_rounds", C.c_int32), ("tau", C.c_double),
                 ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("fast_path", C.c_int32),
                 ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32),
-                ("class_merge_kib", C.c_int32), ("small_tiles", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("class_merge_kib", C.c_int32), ("small_tiles", C.c_int32), ("serial_mma", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Stats(C.Structure):
@@ -90,7 +91,7 @@ def lib():
             "bddmma_pool_submit_loaded": [P, P, i32, P], "bddmma_pool_step": [P, i32, P, P],
             "bddmma_pool_wait_compiled": [P], "bddmma_pool_poll": [P, i64, P],
             "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
-            "bddmma_pool_get_counters": [P, P],
+            "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -185,6 +186,12 @@ class Solver:
         done = C.c_int32()
         _check(lib().bddmma_run_dual(self._h, int(n_iter), C.byref(done)))
         return done.value
+
+    def run_serial(self, n_iter: int) -> np.ndarray:
+        """serial min-marginal averaging (ablation); bound after every sweep"""
+        out = np.zeros(2 * max(int(n_iter), 0))
+        _check(lib().bddmma_run_serial(self._h, int(n_iter), _p(out) if n_iter > 0 else None))
+        return out
 
     def run_sweeps(self, n: int):
         _check(lib().bddmma_run_sweeps(self._h, int(n)))

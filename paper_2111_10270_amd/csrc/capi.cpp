@@ -20,6 +20,17 @@ using namespace bddmma;
 
 namespace bddmma {
 void launch_assemble(const Seg *segs, const int64_t *items, int64_t n_items, hipStream_t st);
+template <typename T>
+void launch_ser_gather(int64_t n, const int32_t *slot, const T *lam, const T *mm, T w, T *lam_p, hipStream_t st);
+template <typename T>
+void launch_ser_scatter(int64_t n, const int32_t *slot, const T *lam_p, T *lam, hipStream_t st);
+template <typename T>
+void launch_ser_prep(int dir, int64_t nb, const int32_t *bpair, const int32_t *pinfo, const uint32_t *child,
+                     const T *lam_p, T *F, T *Bk, double *E, hipStream_t st);
+template <typename T>
+void launch_ser_level(int dir, int64_t n, const int32_t *vars, const int32_t *vptr, const int32_t *vpair,
+                      const int32_t *bpair, const int32_t *pinfo, const uint32_t *child, T *lam_p, T *mm_p, T *F,
+                      T *Bk, double *E, hipStream_t st);
 }
 
 namespace {
@@ -35,6 +46,7 @@ int fail(int code, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int64_t kHistBytes = 64ll << 20;  // device budget for per-tile bound partials of pending sweeps
 constexpr int64_t kLbhCap = 4096;           // reduced bounds kept on the device before a copy to the host
+constexpr int64_t kSerChunk = 256;          // serial iterations whose bounds stay on the device before a copy
 constexpr int kWideLdsBytes = 64 << 10;     // LDS of one wide-kernel block (one BDD)
 constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
 
@@ -47,6 +59,9 @@ struct Layout {
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
     size_t var_inst, tile_inst, row_inst, inst_var, inst_tile, inst_off, inst_tau, ochunk, oseg, opart, imask, xbest,
         ires;
+    // serial min-marginal averaging (when built)
+    size_t sr_child, sr_F, sr_B, sr_lam, sr_mm, sr_E, sr_pinfo, sr_bpair, sr_vptr, sr_vpair, sr_lf, sr_lb, sr_slot,
+        sr_seg, sr_off, sr_lbh;
     size_t total;
 };
 
@@ -97,6 +112,9 @@ struct bddmma_solver {
     bool virt = false;
     MergedSizes vsz{};
     std::vector<double> virt_tau;
+    bool has_ser = false;         // serial min-marginal averaging tables built
+    SerialTables ser;
+    int64_t ser_seg[2] = {0, 0};  // host staging of the energy segment
 
     template <typename T>
     T *ptr(size_t off) const { return reinterpret_cast<T *>(dev + off); }
@@ -187,6 +205,26 @@ Layout make_layout(const bddmma_solver &s)
     L.xbest = take(V + 1);
     L.ires = take((size_t)NI * 4 * 8);   // per instance: lb_free, cert, residual pos, residual max / ub
     L.scratch = take((size_t)pk.scratch_elems * e);
+    if (s.has_ser) {
+        const SerialTables &q = s.ser;
+        const size_t N = q.child.size(), nb = q.bpair.size() - 1;
+        L.sr_child = take(N * 4);
+        L.sr_F = take(N * e);
+        L.sr_B = take(N * e);
+        L.sr_lam = take(P * e);
+        L.sr_mm = take(P * e);
+        L.sr_E = take(nb * 8);
+        L.sr_pinfo = take(q.pinfo.size() * 4);
+        L.sr_bpair = take(q.bpair.size() * 4);
+        L.sr_vptr = take(q.vptr.size() * 4);
+        L.sr_vpair = take(q.vpair.size() * 4);
+        L.sr_lf = take(q.lf_var.size() * 4);
+        L.sr_lb = take(q.lb_var.size() * 4);
+        L.sr_slot = take(q.slot.size() * 4);
+        L.sr_seg = take(2 * 8);
+        L.sr_off = take(8);
+        L.sr_lbh = take((size_t)kSerChunk * 2 * 8);
+    }
     L.total = o;
     return L;
 }
@@ -373,6 +411,56 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
     }
     if ((rc = check_launch())) return rc;
     return flush_history(s);
+}
+
+// Serial min-marginal averaging from the terminated multipliers (see the
+// header); bounds after every sweep go to the history and to lb_hist.
+template <typename T>
+int run_serial_T(bddmma_solver *s, int64_t n_iter, double *lb_hist)
+{
+    const Layout &L = s->L;
+    const SerialTables &q = s->ser;
+    const int64_t P = (int64_t)q.slot.size(), nb = (int64_t)q.bpair.size() - 1;
+    int rc = flush_history(s);
+    if (rc) return rc;
+    T *lam = s->ptr<T>(L.lam), *mm = s->ptr<T>(L.mm);
+    T *lam_p = s->ptr<T>(L.sr_lam), *mm_p = s->ptr<T>(L.sr_mm), *F = s->ptr<T>(L.sr_F), *Bk = s->ptr<T>(L.sr_B);
+    double *E = s->ptr<double>(L.sr_E), *lbh = s->ptr<double>(L.sr_lbh);
+    const int32_t *slot = s->ptr<int32_t>(L.sr_slot), *bpair = s->ptr<int32_t>(L.sr_bpair);
+    const int32_t *pinfo = s->ptr<int32_t>(L.sr_pinfo), *vptr = s->ptr<int32_t>(L.sr_vptr);
+    const int32_t *vpair = s->ptr<int32_t>(L.sr_vpair);
+    const int32_t *lvars[2] = {s->ptr<int32_t>(L.sr_lf), s->ptr<int32_t>(L.sr_lb)};
+    const std::vector<int32_t> *lptr[2] = {&q.lf_ptr, &q.lb_ptr};
+    const uint32_t *child = s->ptr<uint32_t>(L.sr_child);
+    launch_ser_gather<T>(P, slot, lam, mm, (T)s->opt.omega, lam_p, s->st);
+    std::vector<double> got;
+    for (int64_t it0 = 0; it0 < n_iter; it0 += kSerChunk) {
+        const int64_t n = std::min<int64_t>(kSerChunk, n_iter - it0);
+        for (int64_t it = 0; it < n; ++it)
+            for (int dir = 0; dir < 2; ++dir) {
+                launch_ser_prep<T>(dir, nb, bpair, pinfo, child, lam_p, F, Bk, E, s->st);
+                const std::vector<int32_t> &ptr = *lptr[dir];
+                for (size_t l = 0; l + 1 < ptr.size(); ++l)
+                    launch_ser_level<T>(dir, ptr[l + 1] - ptr[l], lvars[dir] + ptr[l], vptr, vpair, bpair, pinfo, child,
+                                        lam_p, mm_p, F, Bk, E, s->st);
+                launch_seg_sum(E, s->ptr<int64_t>(L.sr_seg), 1, s->ptr<double>(L.sr_off), lbh + 2 * it + dir, s->st);
+            }
+        if ((rc = check_launch())) return rc;
+        const size_t at = got.size();
+        got.resize(at + (size_t)(2 * n));
+        HIPCHK(hipMemcpyAsync(got.data() + at, lbh, (size_t)(2 * n) * 8, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+    }
+    launch_ser_scatter<T>(P, slot, lam_p, lam, s->st);
+    launch_fill<T>(mm, T(0), s->pk.n_slots, s->st);
+    if ((rc = check_launch())) return rc;
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->hist.insert(s->hist.end(), got.begin(), got.end());
+    s->hist_synced = (int64_t)s->hist.size();
+    s->sweeps += 2 * n_iter;
+    s->last_row = -1;
+    if (lb_hist) std::copy(got.begin(), got.end(), lb_hist);
+    return BDDMMA_OK;
 }
 
 template <typename T>
@@ -703,6 +791,21 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
         HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
         HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
         HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
+        if (s->has_ser) {
+            const SerialTables &q = s->ser;
+            HIPCHK(up(L.sr_child, q.child.data(), q.child.size() * 4));
+            HIPCHK(up(L.sr_pinfo, q.pinfo.data(), q.pinfo.size() * 4));
+            HIPCHK(up(L.sr_bpair, q.bpair.data(), q.bpair.size() * 4));
+            HIPCHK(up(L.sr_vptr, q.vptr.data(), q.vptr.size() * 4));
+            HIPCHK(up(L.sr_vpair, q.vpair.data(), q.vpair.size() * 4));
+            HIPCHK(up(L.sr_lf, q.lf_var.data(), q.lf_var.size() * 4));
+            HIPCHK(up(L.sr_lb, q.lb_var.data(), q.lb_var.size() * 4));
+            HIPCHK(up(L.sr_slot, q.slot.data(), q.slot.size() * 4));
+            s->ser_seg[0] = 0;
+            s->ser_seg[1] = (int64_t)q.bpair.size() - 1;
+            HIPCHK(up(L.sr_seg, s->ser_seg, 16));
+            HIPCHK(up(L.sr_off, &s->prob.lb_offset, 8));
+        }
     } else {
         // the big tables from the member images, on the device
         TableSet dst{};
@@ -854,8 +957,8 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.graph_sweeps < 0) return fail(BDDMMA_ERR_INVALID_ARG, "graph_sweeps must be >= 0");
     if (o.class_merge_kib < 0) return fail(BDDMMA_ERR_INVALID_ARG, "class_merge_kib must be >= 0");
     if (o.small_tiles < 0) return fail(BDDMMA_ERR_INVALID_ARG, "small_tiles must be >= 0");
-    for (int i = 0; i < 2; ++i)
-        if (o.reserved[i] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
+    if (o.serial_mma != 0 && o.serial_mma != 1) return fail(BDDMMA_ERR_INVALID_ARG, "serial_mma must be 0 or 1");
+    if (o.reserved[0] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
     s->elem = o.precision == 64 ? 8 : 4;
@@ -927,6 +1030,13 @@ int finish_load(bddmma_solver *s)
         s->inst_tau[k] = s->opt.tau >= 0.0 ? s->opt.tau : (s->opt.precision == 64 ? 0.0 : 1e-6 * cmax);
     }
     s->tau = s->inst_tau.empty() ? 0.0 : s->inst_tau[0];
+    s->has_ser = false;
+    if (s->opt.serial_mma && !s->virt) {
+        std::string msg;
+        int rc = build_serial(s->prob, s->pk, s->ser, msg);
+        if (rc != ST_OK) return fail(rc, msg);
+        s->has_ser = true;
+    }
     s->L = make_layout(*s);
     s->loaded = true;
     return BDDMMA_OK;
@@ -1051,6 +1161,18 @@ int bddmma_run_dual(bddmma_solver *s, int32_t n_iter, int32_t *iters_done)
     }
     if (iters_done) *iters_done = done;
     return BDDMMA_OK;
+    GUARD_END
+}
+
+int bddmma_run_serial(bddmma_solver *s, int32_t n_iter, double *lb_hist)
+{
+    GUARD_BEGIN
+    Range rg(true, "bddmma run_serial");
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (n_iter < 0) return fail(BDDMMA_ERR_INVALID_ARG, "n_iter must be >= 0");
+    if (!s->has_ser) return fail(BDDMMA_ERR_STATE, "serial tables not built (options.serial_mma = 0)");
+    return s->elem == 8 ? run_serial_T<double>(s, n_iter, lb_hist) : run_serial_T<float>(s, n_iter, lb_hist);
     GUARD_END
 }
 

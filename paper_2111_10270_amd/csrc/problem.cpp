@@ -1379,4 +1379,74 @@ void assembly_segments(const std::vector<Part> &parts, const std::vector<uint64_
     }
 }
 
+int build_serial(const Problem &p, const Packed &pk, SerialTables &o, std::string &msg)
+{
+    const BddSet &B = p.bdds;
+    const int64_t nb = B.n_bdds(), P = (int64_t)B.lay_var.size(), N = (int64_t)B.child.size();
+    const int64_t V = p.ilp.n_vars;
+    if (N >= INT32_MAX || P >= INT32_MAX || (int64_t)pk.slot_of_pair.size() != P) {
+        msg = "serial tables: problem too large or not packed";
+        return ST_INVALID;
+    }
+    o = SerialTables();
+    o.child = B.child;
+    o.pinfo.resize((size_t)(4 * P));
+    o.bpair.resize((size_t)nb + 1);
+    for (int64_t b = 0; b < nb; ++b) {
+        o.bpair[b] = (int32_t)B.lay_off[b];
+        int64_t node = B.node_off[b];
+        for (int64_t q = B.lay_off[b]; q < B.lay_off[b + 1]; ++q) {
+            const int64_t w = B.lay_width[q];
+            o.pinfo[4 * q + 0] = (int32_t)node;
+            o.pinfo[4 * q + 1] = (int32_t)w;
+            o.pinfo[4 * q + 2] = q + 1 < B.lay_off[b + 1] ? (int32_t)(node + w) : -1;
+            o.pinfo[4 * q + 3] = (int32_t)b;
+            node += w;
+        }
+        if (node != B.node_off[b + 1]) {
+            msg = "serial tables: inconsistent layer widths";
+            return ST_INVALID;
+        }
+    }
+    o.bpair[nb] = (int32_t)P;
+    o.vptr.assign((size_t)V + 1, 0);
+    for (int64_t q = 0; q < P; ++q) o.vptr[B.lay_var[q] + 1]++;
+    for (int64_t i = 0; i < V; ++i) o.vptr[i + 1] += o.vptr[i];
+    o.vpair.resize((size_t)P);
+    {
+        std::vector<int32_t> fill(o.vptr.begin(), o.vptr.end() - 1);
+        for (int64_t q = 0; q < P; ++q) o.vpair[fill[B.lay_var[q]]++] = (int32_t)q;   // pairs ascend in row order
+    }
+    // levels: predecessors have smaller ids (forward), successors larger ones
+    std::vector<int32_t> lf((size_t)V, -1), lb((size_t)V, -1);
+    auto first = [&](int64_t q) { return q == (int64_t)o.bpair[o.pinfo[4 * q + 3]]; };
+    for (int64_t i = 0; i < V; ++i)
+        for (int32_t t = o.vptr[i]; t < o.vptr[i + 1]; ++t) {
+            const int64_t q = o.vpair[t];
+            lf[i] = std::max(lf[i], first(q) ? 0 : lf[B.lay_var[q - 1]] + 1);
+        }
+    for (int64_t i = V - 1; i >= 0; --i)
+        for (int32_t t = o.vptr[i]; t < o.vptr[i + 1]; ++t) {
+            const int64_t q = o.vpair[t];
+            lb[i] = std::max(lb[i], o.pinfo[4 * q + 2] < 0 ? 0 : lb[B.lay_var[q + 1]] + 1);
+        }
+    auto csr = [&](const std::vector<int32_t> &lev, std::vector<int32_t> &ptr, std::vector<int32_t> &var) {
+        int32_t nl = 0;
+        for (int32_t l : lev) nl = std::max(nl, l + 1);
+        ptr.assign((size_t)nl + 1, 0);
+        for (int32_t l : lev)
+            if (l >= 0) ptr[l + 1]++;
+        for (int32_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+        var.resize((size_t)ptr[nl]);
+        std::vector<int32_t> f(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < V; ++i)
+            if (lev[i] >= 0) var[f[lev[i]]++] = (int32_t)i;
+    };
+    csr(lf, o.lf_ptr, o.lf_var);
+    csr(lb, o.lb_ptr, o.lb_var);
+    o.slot.resize((size_t)P);
+    for (int64_t q = 0; q < P; ++q) o.slot[q] = (int32_t)pk.slot_of_pair[q];
+    return ST_OK;
+}
+
 }  // namespace bddmma

@@ -148,6 +148,26 @@ struct Seg;
 void assembly_segments(const std::vector<Part> &parts, const std::vector<uint64_t> &img, uint64_t dst_base,
                        const TableSet &dst, std::vector<Seg> &out);
 
+// ---- serial min-marginal averaging (ablation) ---------------------------------
+// Tables of the variable-by-variable scheme: the compiled BDDs in their own
+// order (not tiled), and a level schedule.  A variable's forward level is
+// one more than the largest forward level of its predecessors in the BDDs
+// that contain it (0 without predecessors); backward levels mirror this with
+// successors.  Variables of one level share no BDD, so a level is one
+// parallel step, and visiting levels in order visits every BDD's layers in
+// order, as the sequential scheme does.
+struct SerialTables {
+    std::vector<uint32_t> child;     // [N] node words (next-layer index | index << 16, or kTop / kBot)
+    std::vector<int32_t> pinfo;      // [4P] per pair: first node of its layer, layer width,
+                                     //      first node of the next layer (-1: last layer), BDD
+    std::vector<int32_t> bpair;      // [B+1] pair range of each BDD
+    std::vector<int32_t> vptr, vpair;            // variable -> its pairs, ascending row order
+    std::vector<int32_t> lf_ptr, lf_var;         // forward levels (CSR)
+    std::vector<int32_t> lb_ptr, lb_var;         // backward levels (CSR)
+    std::vector<int32_t> slot;       // [P] slot of each pair in the tile layout
+};
+int build_serial(const Problem &p, const Packed &pk, SerialTables &out, std::string &msg);
+
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.
 int compile_row(const int32_t *var, const int64_t *a, int k, int sense, int64_t b, BddSet &out,
