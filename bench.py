@@ -48,6 +48,12 @@ def parse():
     ap.add_argument("--pool-max", type=int, default=16, help="serving pool: most members at once (0 = skip)")
     ap.add_argument("--pool-step", type=int, default=25, help="serving pool: iterations per step")
     ap.add_argument("--pool-arena-gib", type=int, default=16)
+    ap.add_argument("--ablation", action="store_true",
+                    help="only compare deferred (Alg. 1) with serial min-marginal averaging: iterations to the "
+                         "same bound and time per iteration")
+    ap.add_argument("--abl-workloads", default="mrf10x10L3,gm1000k10,track20x500,mrf256x256L8")
+    ap.add_argument("--abl-serial", type=int, default=100)
+    ap.add_argument("--abl-deferred", type=int, default=1500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -245,6 +251,56 @@ def serve_pool(a, B, insts, seq_lb, rate, pct):
             "live": live, "saturated": sat}
 
 
+def ablation(a, B, I, torch):
+    """Deferred parallel averaging (Alg. 1) against the serial averaging it
+    replaces (Sec. 3, sequential update), both on the GPU from the same start
+    (lambda = c/|J|): at checkpoints k of the serial run, the number of
+    deferred iterations whose bound (LB_free after the iteration) first
+    reaches the serial bound after k iterations (Sec. 6 reports about three
+    times as many for the deferred scheme), and the wall time each needs."""
+    import numpy as np
+
+    out = {}
+    for wl in a.abl_workloads.split(","):
+        ilp = I.workload(wl)
+        d = B.Solver(ilp, precision=a.precision, graph_sweeps=64).bind()
+        d.run_dual(2)
+        d.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        d.run_dual(a.abl_deferred)
+        torch.cuda.synchronize()
+        td = (time.perf_counter() - t) / a.abl_deferred
+        ld = d.lb_history()[1::2]
+        d = None
+        torch.cuda.empty_cache()
+        s = B.Solver(ilp, precision=a.precision, serial_mma=1).bind()
+        s.run_serial(1)
+        s.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ls = s.run_serial(a.abl_serial)[1::2]
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t) / a.abl_serial
+        s = None
+        torch.cuda.empty_cache()
+        at = {}
+        for k in (1, 5, 10, 20, 50, 100):
+            if k > len(ls):
+                continue
+            hit = np.nonzero(ld >= ls[k - 1])[0]
+            n = int(hit[0]) + 1 if hit.size else None
+            at[str(k)] = {"serial_lb": float(ls[k - 1]), "deferred_iters": n,
+                          "iter_ratio": n / k if n else None,
+                          "time_ratio": (n * td) / (k * ts) if n else None}
+        out[wl] = {"deferred_ms_per_iter": td * 1e3, "serial_ms_per_iter": ts * 1e3,
+                   "deferred_final_lb": float(ld[-1]), "serial_final_lb": float(ls[-1]),
+                   "deferred_iters": a.abl_deferred, "serial_iters": a.abl_serial, "at_serial_iter": at}
+        log(f"ablation {wl} done")
+    return {"ablation": "deferred vs serial min-marginal averaging", "dtype": "f64" if a.precision == 64 else "f32",
+            "data": "synthetic", "workloads": out}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -271,6 +327,10 @@ def main():
 
     from paper_2111_10270_amd import binding as B
     from paper_2111_10270_amd import instances as I
+
+    if a.ablation:
+        print(json.dumps(ablation(a, B, I, torch)), flush=True)
+        return
 
     ilp = I.workload(a.workload)
     s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps)
