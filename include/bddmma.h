@@ -415,6 +415,26 @@ int bddmma_run_serial(bddmma_solver *s, int32_t n_iter, double *lb_hist);
 int bddmma_profile(bddmma_solver *s, int enable);
 int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *total_ms);
 
+/* Autotuner for the launch schedule: which kernels sweep which tiles
+ * (register-resident fast path or general kernels; mixed per-lane tiles for
+ * small problems; layer-class merging; shortest paths in LDS or device
+ * memory) and whether sweeps are replayed from HIP graphs.  The ILP (as for
+ * bddmma_load_ilp) is compiled once; a greedy search then changes one option
+ * at a time among fast_path {1, 0}, small_tiles {2048, 0, 2^30},
+ * class_merge_kib {32768, 0, 4096, 262144}, sp_in_lds_max_nodes {0, -1} and
+ * graph_sweeps {64, 0}, starting from base (NULL: defaults) and keeping a
+ * change that is at least 2 % faster.  Each candidate is packed, bound to
+ * dev_ptr (bytes of caller-owned device memory; candidates that need more are
+ * skipped) and timed over `sweeps` (>= 2) Alg. 1 sweeps with HIP events on
+ * hip_stream after as many warm-up sweeps (the faster of two timed runs).  The options only choose kernels
+ * and layouts, never the arithmetic, so every candidate follows the same
+ * trajectory.  *best gets the fastest options (other fields as in base),
+ * *us_per_sweep (may be NULL) their time.  NO_MEMORY if no candidate fits. */
+int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *costs, int64_t n_rows,
+                    const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                    const int64_t *rhs, void *dev_ptr, size_t bytes, void *hip_stream, int32_t sweeps,
+                    bddmma_options *best, double *us_per_sweep);
+
 const char *bddmma_last_error(void);
 
 #ifdef __cplusplus

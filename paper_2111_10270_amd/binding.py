@@ -28,7 +28,7 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
-           "bddmma_pool_get_counters", "bddmma_run_serial")
+           "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune")
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 
@@ -92,6 +92,7 @@ def lib():
             "bddmma_pool_wait_compiled": [P], "bddmma_pool_poll": [P, i64, P],
             "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
             "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P],
+            "bddmma_autotune": [P, i64, P, i64, P, P, P, P, P, P, C.c_size_t, P, i32, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -122,6 +123,24 @@ def default_options(**kw) -> Options:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def autotune(ilp, sweeps: int = 64, slack: float = 2.0, device="cuda", stream=None, **options):
+    """fastest launch-schedule options for this ILP (bddmma_autotune), timed in
+    a device buffer of slack x the default workspace; -> (Options, us per sweep)"""
+    import torch
+    base = default_options(**options)
+    nbytes = int(Solver(ilp, **options).workspace_bytes() * slack) + (1 << 20)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    st = stream if stream is not None else torch.cuda.current_stream(buf.device)
+    arrs = [np.ascontiguousarray(ilp.costs, dtype=np.float64), np.ascontiguousarray(ilp.row_ptr, dtype=np.int64),
+            np.ascontiguousarray(ilp.col, dtype=np.int32), np.ascontiguousarray(ilp.coef, dtype=np.int32),
+            np.ascontiguousarray(ilp.sense, dtype=np.int8), np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
+    best, us = Options(), C.c_double()
+    _check(lib().bddmma_autotune(C.byref(base), ilp.n_vars, _p(arrs[0]), ilp.n_rows, *[_p(a) for a in arrs[1:]],
+                                 C.c_void_p(buf.data_ptr()), buf.numel(), C.c_void_p(st.cuda_stream), int(sweeps),
+                                 C.byref(best), C.byref(us)))
+    return best, us.value
 
 
 class Solver:

@@ -984,17 +984,28 @@ void bddmma_destroy(bddmma_solver *s)
 namespace {
 
 int finish_load(bddmma_solver *s);
+int pack_loaded(bddmma_solver *s);
 
 // presolve, compile, pack and lay out the ingested ILP (or batch)
 int load_compiled(bddmma_solver *s)
 {
     std::string msg;
     int rc = build_problem(s->prob, msg);
-    if (rc == ST_OK) {
-        int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
-        rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem, s->pk, msg);
+    if (rc != ST_OK) {
+        s->prob = Problem();
+        s->pk = Packed();
+        return fail(rc, msg);
     }
+    return pack_loaded(s);
+}
+
+// pack the compiled s->prob with s->opt, then host tables and layout
+int pack_loaded(bddmma_solver *s)
+{
+    std::string msg;
+    int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
+    int rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
+                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem, s->pk, msg);
     if (rc != ST_OK) {
         s->prob = Problem();
         s->pk = Packed();
@@ -1440,6 +1451,102 @@ int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *
     if (launches) *launches = (int64_t)s->ev.used[kernel].size();
     if (total_ms) *total_ms = t;
     return BDDMMA_OK;
+}
+
+int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *costs, int64_t n_rows,
+                    const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                    const int64_t *rhs, void *dev_ptr, size_t bytes, void *hip_stream, int32_t sweeps,
+                    bddmma_options *best, double *us_per_sweep)
+{
+    GUARD_BEGIN
+    Range rg(true, "bddmma autotune");
+    if (!best) return fail(BDDMMA_ERR_INVALID_ARG, "best is NULL");
+    if (sweeps < 2) return fail(BDDMMA_ERR_INVALID_ARG, "sweeps must be >= 2");
+    if (!dev_ptr || ((uintptr_t)dev_ptr) % kAlign) return fail(BDDMMA_ERR_INVALID_ARG, "bad device pointer");
+    bddmma_options o;
+    if (base) o = *base;
+    else bddmma_options_default(&o);
+    bddmma_solver *probe = nullptr;
+    int rc = bddmma_create(&o, &probe);
+    if (rc) return rc;
+    // compile once; every candidate re-packs the same BDDs
+    std::string msg;
+    rc = ingest_ilp(probe->prob.ilp, n_vars, costs, n_rows, row_ptr, col, coef, sense, rhs, msg);
+    if (rc == ST_OK) rc = build_problem(probe->prob, msg);
+    if (rc != ST_OK) {
+        bddmma_destroy(probe);
+        return fail(rc, msg);
+    }
+    const Problem compiled = probe->prob;
+    bddmma_destroy(probe);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(BDDMMA_ERR_HIP, "event creation failed");
+    }
+    // microseconds per sweep of one candidate (+inf when its workspace does not fit)
+    auto eval = [&](const bddmma_options &c, double &us) -> int {
+        us = INFINITY;
+        bddmma_solver *s = nullptr;
+        int r = bddmma_create(&c, &s);
+        if (r) return r;
+        s->prob = compiled;
+        r = pack_loaded(s);
+        if (!r && s->L.total <= bytes) {
+            r = bddmma_bind(s, dev_ptr, bytes, hip_stream);
+            if (!r) r = bddmma_run_sweeps(s, sweeps);   // warm-up: code objects, graph capture
+            for (int rep = 0; rep < 2 && !r; ++rep) {    // the faster of two timed runs
+                if (hipEventRecord(e0, st) != hipSuccess) r = fail(BDDMMA_ERR_HIP, "event record failed");
+                if (!r) r = bddmma_run_sweeps(s, sweeps);
+                if (!r && hipEventRecord(e1, st) != hipSuccess) r = fail(BDDMMA_ERR_HIP, "event record failed");
+                float ms = 0.f;
+                if (!r && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    r = fail(BDDMMA_ERR_HIP, "event timing failed");
+                if (!r) us = std::min(us, 1e3 * (double)ms / sweeps);
+            }
+        }
+        bddmma_destroy(s);
+        return r;
+    };
+    // greedy search, one option at a time; a change must gain 2 %
+    struct Dim {
+        int32_t bddmma_options::*field;
+        std::vector<int32_t> values;
+    };
+    const Dim dims[] = {{&bddmma_options::fast_path, {1, 0}},
+                        {&bddmma_options::small_tiles, {2048, 0, 1 << 30}},
+                        {&bddmma_options::class_merge_kib, {32768, 0, 4096, 262144}},
+                        {&bddmma_options::sp_in_lds_max_nodes, {0, -1}},
+                        {&bddmma_options::graph_sweeps, {64, 0}}};
+    bddmma_options cur = o;
+    double cur_us = INFINITY;
+    rc = eval(cur, cur_us);
+    for (const Dim &d : dims) {
+        if (rc) break;
+        bddmma_options pick = cur;
+        for (int32_t v : d.values) {
+            if (v == cur.*d.field) continue;
+            bddmma_options c = cur;
+            c.*d.field = v;
+            double us = INFINITY;
+            if ((rc = eval(c, us))) break;
+            if (us < 0.98 * cur_us) {
+                cur_us = us;
+                pick = c;
+            }
+        }
+        cur = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (!std::isfinite(cur_us)) return fail(BDDMMA_ERR_NO_MEMORY, "no candidate fits the given device memory");
+    *best = cur;
+    if (us_per_sweep) *us_per_sweep = cur_us;
+    return BDDMMA_OK;
+    GUARD_END
 }
 
 const char *bddmma_last_error(void) { return g_err.c_str(); }
