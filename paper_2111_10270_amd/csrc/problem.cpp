@@ -51,32 +51,82 @@ int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, cons
             msg = "cost " + std::to_string(i) + " is not finite";
             return ST_INVALID;
         }
-    o.row_ptr.assign(1, 0);
-    o.col.clear();
-    o.coef.clear();
     o.sense.assign(sense, sense + n_rows);
     o.rhs.assign(rhs, rhs + n_rows);
-    std::vector<std::pair<int32_t, int64_t>> ent;
-    for (int64_t r = 0; r < n_rows; ++r) {
-        if (row_ptr[r + 1] < row_ptr[r]) { msg = "row_ptr decreases at row " + std::to_string(r); return ST_INVALID; }
-        if (sense[r] < -1 || sense[r] > 1) { msg = "sense must be -1, 0 or +1"; return ST_INVALID; }
-        ent.clear();
+    // rows are checked, cleaned (zero coefficients dropped) and sorted by
+    // column on several threads, in two passes over contiguous row ranges:
+    // checks and counts, then entries written at their final place (and
+    // repeated variables detected).  A range stops at its first bad row and
+    // the lowest failing range reports, so the error is the first row in
+    // order that fails the first pass, else the first with a repeated
+    // variable.
+    unsigned hw = std::thread::hardware_concurrency();
+    int nth = (int)std::max(1u, std::min(hw ? hw : 1u, 16u));
+    if (n_rows < 4096) nth = 1;
+    const int64_t chunk = (n_rows + nth - 1) / std::max(1, nth);
+    std::vector<std::string> err((size_t)nth);
+    std::vector<char> bad((size_t)nth, 0);
+    auto run = [&](auto &&body) {
+        std::fill(bad.begin(), bad.end(), 0);
+        auto one = [&](int t) {
+            const int64_t r0 = std::min<int64_t>(n_rows, t * chunk), r1 = std::min<int64_t>(n_rows, r0 + chunk);
+            for (int64_t r = r0; r < r1; ++r)
+                if (!body(r, err[(size_t)t])) {
+                    bad[(size_t)t] = 1;
+                    return;
+                }
+        };
+        if (nth == 1) {
+            one(0);
+        } else {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nth; ++t) th.emplace_back(one, t);
+            for (auto &t : th) t.join();
+        }
+        for (int t = 0; t < nth; ++t)
+            if (bad[(size_t)t]) {
+                msg = err[(size_t)t];
+                return false;
+            }
+        return true;
+    };
+    o.row_ptr.assign((size_t)n_rows + 1, 0);
+    const bool counted = run([&](int64_t r, std::string &m) {
+        if (row_ptr[r + 1] < row_ptr[r]) { m = "row_ptr decreases at row " + std::to_string(r); return false; }
+        if (sense[r] < -1 || sense[r] > 1) { m = "sense must be -1, 0 or +1"; return false; }
         __int128 mag = 0;
+        int64_t n = 0;
         for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-            if (col[e] < 0 || col[e] >= n_vars) { msg = "column out of range in row " + std::to_string(r); return ST_INVALID; }
+            if (col[e] < 0 || col[e] >= n_vars) { m = "column out of range in row " + std::to_string(r); return false; }
             if (coef[e] == 0) continue;
-            ent.emplace_back(col[e], (int64_t)coef[e]);
+            ++n;
             mag += coef[e] < 0 ? -(__int128)coef[e] : (__int128)coef[e];
         }
         __int128 rb = rhs[r] < 0 ? -(__int128)rhs[r] : (__int128)rhs[r];
-        if (mag + rb > ((__int128)1 << 62)) { msg = "row " + std::to_string(r) + ": coefficient sum too large"; return ST_INVALID; }
+        if (mag + rb > ((__int128)1 << 62)) { m = "row " + std::to_string(r) + ": coefficient sum too large"; return false; }
+        o.row_ptr[r + 1] = n;
+        return true;
+    });
+    if (!counted) return ST_INVALID;
+    for (int64_t r = 0; r < n_rows; ++r) o.row_ptr[r + 1] += o.row_ptr[r];
+    o.col.resize((size_t)o.row_ptr[n_rows]);
+    o.coef.resize((size_t)o.row_ptr[n_rows]);
+    const bool filled = run([&](int64_t r, std::string &m) {
+        std::vector<std::pair<int32_t, int64_t>> ent;
+        ent.reserve((size_t)(o.row_ptr[r + 1] - o.row_ptr[r]));
+        for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+            if (coef[e] != 0) ent.emplace_back(col[e], (int64_t)coef[e]);
         std::sort(ent.begin(), ent.end());
         for (size_t q = 1; q < ent.size(); ++q)
-            if (ent[q].first == ent[q - 1].first) { msg = "variable repeated in row " + std::to_string(r); return ST_INVALID; }
-        for (auto &pr : ent) { o.col.push_back(pr.first); o.coef.push_back(pr.second); }
-        o.row_ptr.push_back((int64_t)o.col.size());
-    }
-    return ST_OK;
+            if (ent[q].first == ent[q - 1].first) { m = "variable repeated in row " + std::to_string(r); return false; }
+        int64_t at = o.row_ptr[r];
+        for (auto &pr : ent) {
+            o.col[at] = pr.first;
+            o.coef[at++] = pr.second;
+        }
+        return true;
+    });
+    return filled ? ST_OK : ST_INVALID;
 }
 
 int set_instances(Ilp &ilp, int64_t n_inst, const int64_t *inst_vars, const int64_t *inst_rows, std::string &msg)

@@ -399,6 +399,11 @@ int main()
         run_merge(insts, (int)(seed % 5), seed);
     }
     {
+        // enough rows for the threaded ingestion and compilation
+        Rng h{4242};
+        run(random_ilp(h, 3000, 6000, 6, 3), {}, {}, 4242);
+    }
+    {
         // large enough for the threaded merge
         std::vector<Csr> big;
         for (int k = 0; k < 5; ++k) {
