@@ -64,6 +64,7 @@ def lib():
         L.or_terminate.argtypes = [P]
         L.or_run_dual.argtypes = [P, i, P]
         L.or_run_serial.argtypes = [P, i, P]
+        L.or_set_termination.argtypes = [P, i]
         L.or_rng_u01.restype = d
         L.or_rng_u01.argtypes = [ull, ull, ull]
         L.or_perturb.argtypes = [P, i, d, d, ull, P, i]
@@ -178,6 +179,10 @@ class Oracle:
 
     def terminate(self):
         lib().or_terminate(self.h)
+
+    def set_termination(self, mode: int):
+        """0: lambda + omega M-bar (default), 1: lambda + (omega/|J_i|) sum_k M-bar_ik"""
+        lib().or_set_termination(self.h, int(mode))
 
     def run_dual(self, n_iter: int):
         hist = np.zeros(2 * max(n_iter, 0))

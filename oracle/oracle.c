@@ -29,7 +29,10 @@
  *    + omega * sum_ij min(M_ij, 0) after each sweep; LB_cert =
  *    sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0) with the multiplier
  *    residual r_i = sum_j (lambda_i^j + omega M_ij) - c_i.
- *  - Termination step of Alg. 1: lambda += omega * M-bar.
+ *  - Termination step of Alg. 1: lambda += omega * M-bar (the algorithm's
+ *    last loop); optionally the text's "min-marginal averaging step"
+ *    lambda_i^j += (omega/|J_i|) sum_k M-bar_ik (or_set_termination).  Both
+ *    give sum_j lambda_i^j = c_i; the certified bound uses the same form.
  *  - Serial averaging (ablation): the sequential update of Sec. 3 applied
  *    variable by variable in id order, full averaging, no damping, from the
  *    terminated multipliers (see or_run_serial).
@@ -90,6 +93,7 @@ typedef struct {
     double *lam, *mm, *avg;
     double *E;               /* [nb] subproblem energy after the last sweep */
     int maxn, maxk;          /* largest node / layer count, for scratch */
+    int term_mode;           /* termination step: 0 lambda + omega M-bar, 1 lambda + a_i */
 } OSolver;
 
 /* ------------------------------------------------------------------ */
@@ -628,42 +632,63 @@ double or_lb_free(const OSolver *s)
     return (e + s->omega * t) + s->lb_offset;
 }
 
-/* LB_cert = sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0)  (+ offset) */
+void or_set_termination(OSolver *s, int mode) { s->term_mode = mode; }
+
+/* the terminated multipliers of the current state, per pair (into t):
+ * lambda + omega M-bar, or lambda_i^j + (omega/|J_i|) sum_k M-bar_ik with the
+ * sum in ascending row order */
+static void terminated(const OSolver *s, double *t)
+{
+    if (s->term_mode == 0) {
+        for (long long p = 0; p < s->np; ++p) t[p] = s->lam[p] + s->omega * s->mm[p];
+        return;
+    }
+    for (long long i = 0; i < s->n_vars; ++i) {
+        if (s->deg[i] == 0) continue;
+        double sum = 0.0;
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) sum += s->mm[s->vpair[q]];
+        const double a = (s->omega / (double)s->deg[i]) * sum;
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) t[s->vpair[q]] = s->lam[s->vpair[q]] + a;
+    }
+}
+
+/* LB_cert = sum_j E^j(t^j) - sum_i max(r_i, 0)  (+ offset), t the terminated
+ * multipliers (lambda + omega M-bar by default), r_i = sum_j t_i^j - c_i */
 double or_lb_cert(const OSolver *s, double *max_residual)
 {
     double *F = malloc(sizeof(double) * (size_t)s->maxn);
     double *cost = malloc(sizeof(double) * (size_t)s->maxk);
+    double *t = malloc(sizeof(double) * (size_t)(s->np > 0 ? s->np : 1));
+    terminated(s, t);
     double e = 0.0;
     for (int j = 0; j < s->nb; ++j) {
         const OBdd *d = &s->bdd[j];
-        for (int h = 0; h < d->k; ++h) {
-            long long p = s->pstart[j] + h;
-            cost[h] = s->lam[p] + s->omega * s->mm[p];
-        }
+        for (int h = 0; h < d->k; ++h) cost[h] = t[s->pstart[j] + h];
         e += sp_from_root(d, cost, F);
     }
     double corr = 0.0, mr = 0.0;
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) continue;
         double sum = 0.0;
-        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) {
-            long long p = s->vpair[q];
-            sum += s->lam[p] + s->omega * s->mm[p];
-        }
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) sum += t[s->vpair[q]];
         double r = sum - s->cost[i];
         if (r > 0.0) corr += r;
         if (fabs(r) > mr) mr = fabs(r);
     }
     free(F);
     free(cost);
+    free(t);
     if (max_residual) *max_residual = mr;
     return (e - corr) + s->lb_offset;
 }
 
-/* termination step of Alg. 1: lambda += omega * M-bar */
+/* termination step of Alg. 1: lambda <- the terminated multipliers */
 void or_terminate(OSolver *s)
 {
-    for (long long p = 0; p < s->np; ++p) s->lam[p] = s->lam[p] + s->omega * s->mm[p];
+    double *t = malloc(sizeof(double) * (size_t)(s->np > 0 ? s->np : 1));
+    terminated(s, t);
+    memcpy(s->lam, t, sizeof(double) * (size_t)s->np);
+    free(t);
 }
 
 /* full Alg. 1 iterations from the current state; lb_hist gets LB_free after
