@@ -94,7 +94,12 @@ typedef struct {
                               (bddmma_run_serial; BDDs in their own order plus a level
                               schedule, about 4 B per node and 40 B per pair more device
                               memory); 0: none.  0 */
-    int32_t  reserved[1];  /* must be zero */
+    int32_t  termination;  /* termination step of Alg. 1, used for the certified bound, the
+                              exported multipliers, rounding and the serial start:
+                              0: lambda_i^j + omega M-bar_ij (the algorithm's last loop);
+                              1: lambda_i^j + (omega/|J_i|) sum_k M-bar_ik (the text's
+                              "min-marginal averaging step").  Both sum to c_i over J_i.  0 */
+    int32_t  reserved[2];  /* must be zero */
 } bddmma_options;
 
 typedef struct {

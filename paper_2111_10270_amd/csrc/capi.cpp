@@ -21,6 +21,9 @@ using namespace bddmma;
 namespace bddmma {
 void launch_assemble(const Seg *segs, const int64_t *items, int64_t n_items, hipStream_t st);
 template <typename T>
+void launch_add_term(int64_t n_slots, int64_t n_vars, const int32_t *pair_var, const T *lam, const T *avg, T *dst,
+                     hipStream_t st);
+template <typename T>
 void launch_ser_gather(int64_t n, const int32_t *slot, const T *lam, const T *mm, T w, T *lam_p, hipStream_t st);
 template <typename T>
 void launch_ser_scatter(int64_t n, const int32_t *slot, const T *lam_p, T *lam, hipStream_t st);
@@ -413,6 +416,40 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
     return flush_history(s);
 }
 
+// The terminated multipliers of the current state as a pair (l, m) with
+// l + omega * m: (lambda, M-bar) for termination 0; for termination 1 the
+// averaged form lambda + a_i in mmx and zeros in lam_bak (both free outside
+// the rounding).  Stream-ordered.
+template <typename T>
+void terminated_pair(bddmma_solver *s, T *&l, T *&m)
+{
+    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    if (s->opt.termination == 0) {
+        l = lam;
+        m = mm;
+        return;
+    }
+    T *avg = s->ptr<T>(s->L.avg), *mmx = s->ptr<T>(s->L.mmx), *zero = s->ptr<T>(s->L.lam_bak);
+    launch_average_all<T>(s->dp, mm, avg, s->opt.omega, s->st);
+    launch_add_term<T>(s->pk.n_slots, s->dp.n_vars, s->dp.pair_var, lam, avg, mmx, s->st);
+    launch_fill<T>(zero, T(0), s->pk.n_slots, s->st);
+    l = mmx;
+    m = zero;
+}
+
+// termination step in place (rounding): lambda <- the terminated multipliers
+template <typename T>
+void terminate_in_place(bddmma_solver *s, T *lam, T *mm)
+{
+    if (s->opt.termination == 0) {
+        launch_terminate<T>(s->dp, lam, mm, (T)s->opt.omega, s->st);
+        return;
+    }
+    T *avg = s->ptr<T>(s->L.avg);
+    launch_average_all<T>(s->dp, mm, avg, s->opt.omega, s->st);
+    launch_add_term<T>(s->pk.n_slots, s->dp.n_vars, s->dp.pair_var, lam, avg, lam, s->st);
+}
+
 // Serial min-marginal averaging from the terminated multipliers (see the
 // header); bounds after every sweep go to the history and to lb_hist.
 template <typename T>
@@ -432,7 +469,11 @@ int run_serial_T(bddmma_solver *s, int64_t n_iter, double *lb_hist)
     const int32_t *lvars[2] = {s->ptr<int32_t>(L.sr_lf), s->ptr<int32_t>(L.sr_lb)};
     const std::vector<int32_t> *lptr[2] = {&q.lf_ptr, &q.lb_ptr};
     const uint32_t *child = s->ptr<uint32_t>(L.sr_child);
-    launch_ser_gather<T>(P, slot, lam, mm, (T)s->opt.omega, lam_p, s->st);
+    {
+        T *tl, *tm;
+        terminated_pair<T>(s, tl, tm);
+        launch_ser_gather<T>(P, slot, tl, tm, (T)s->opt.omega, lam_p, s->st);
+    }
     std::vector<double> got;
     for (int64_t it0 = 0; it0 < n_iter; it0 += kSerChunk) {
         const int64_t n = std::min<int64_t>(kSerChunk, n_iter - it0);
@@ -467,7 +508,8 @@ template <typename T>
 int lower_bound_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res)
 {
     const DevProblem &p = s->dp;
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    T *lam, *mm;
+    terminated_pair<T>(s, lam, mm);
     double *red = s->ptr<double>(s->L.red);
     double *tile_e = s->ptr<double>(s->L.tile_e);
     launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
@@ -549,11 +591,18 @@ int set_state_T(bddmma_solver *s, const double *lam, const double *mm)
 template <typename T>
 int multipliers_T(bddmma_solver *s, double *lam_out, double *mm_out)
 {
-    std::vector<double> l, m;
+    std::vector<double> l, m, z;
     int rc;
-    if ((rc = download_pairs<T>(s, s->L.lam, l))) return rc;
+    if (s->opt.termination == 0) {
+        if ((rc = download_pairs<T>(s, s->L.lam, l))) return rc;
+    } else {
+        // lambda + a_i, formed on the device
+        T *tl, *tm;
+        terminated_pair<T>(s, tl, tm);
+        if ((rc = download_pairs<T>(s, (size_t)((char *)tl - s->dev), l))) return rc;
+    }
     if ((rc = download_pairs<T>(s, s->L.mm, m))) return rc;
-    const T w = (T)s->opt.omega;
+    const T w = s->opt.termination == 0 ? (T)s->opt.omega : T(0);
     for (size_t q = 0; q < l.size(); ++q) {
         if (lam_out) lam_out[q] = (double)((T)l[q] + w * (T)m[q]);
         if (mm_out) mm_out[q] = m[q];
@@ -601,7 +650,7 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
     launch_copy<T>(mm_b, mm, S, s->st);
     launch_fill<uint8_t>(flag, 0, V, s->st);
     launch_fill<uint8_t>(xb, 0, V + 1, s->st);
-    launch_terminate<T>(p, lam, mm, omega, s->st);
+    terminate_in_place<T>(s, lam, mm);
     launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
 
     std::vector<int32_t> conf((size_t)n), bad((size_t)n), viol((size_t)n);
@@ -656,7 +705,7 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
             plain_sweep<T>(s, 0);
             plain_sweep<T>(s, 1);
         }
-        launch_terminate<T>(p, lam, mm, omega, s->st);
+        terminate_in_place<T>(s, lam, mm);
         launch_sweep<T>(p, lam, mm, nullptr, w, 0, MODE_FIXED, s->st);
     }
     launch_copy<T>(lam, lam_b, S, s->st);
@@ -691,7 +740,8 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
 {
     const DevProblem &p = s->dp;
     const int64_t n = s->n_inst(), nt = (int64_t)s->pk.tiles.size();
-    T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
+    T *lam, *mm;
+    terminated_pair<T>(s, lam, mm);
     double *res = s->ptr<double>(s->L.ires), *tile_e = s->ptr<double>(s->L.tile_e);
     const int64_t *seg = s->ptr<int64_t>(s->L.inst_tile);
     const double *off = s->ptr<double>(s->L.inst_off);
@@ -958,7 +1008,9 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.class_merge_kib < 0) return fail(BDDMMA_ERR_INVALID_ARG, "class_merge_kib must be >= 0");
     if (o.small_tiles < 0) return fail(BDDMMA_ERR_INVALID_ARG, "small_tiles must be >= 0");
     if (o.serial_mma != 0 && o.serial_mma != 1) return fail(BDDMMA_ERR_INVALID_ARG, "serial_mma must be 0 or 1");
-    if (o.reserved[0] != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
+    if (o.termination != 0 && o.termination != 1) return fail(BDDMMA_ERR_INVALID_ARG, "termination must be 0 or 1");
+    if (o.reserved[0] != 0 || o.reserved[1] != 0)
+        return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
     s->elem = o.precision == 64 ? 8 : 4;
@@ -1638,14 +1690,15 @@ int instance_multipliers_T(bddmma_solver *s, int64_t off, const bddmma_solver *p
 {
     const int64_t S = part->pk.n_slots, P = (int64_t)part->prob.pair_var.size();
     std::vector<T> l((size_t)std::max<int64_t>(S, 1)), m((size_t)std::max<int64_t>(S, 1));
+    T *tl, *tm;
+    terminated_pair<T>(s, tl, tm);
     if (S > 0) {
-        HIPCHK(hipMemcpyAsync(l.data(), s->dev + s->L.lam + (size_t)off * sizeof(T), (size_t)S * sizeof(T),
-                              hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipMemcpyAsync(l.data(), tl + off, (size_t)S * sizeof(T), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipMemcpyAsync(m.data(), s->dev + s->L.mm + (size_t)off * sizeof(T), (size_t)S * sizeof(T),
                               hipMemcpyDeviceToHost, s->st));
     }
     HIPCHK(hipStreamSynchronize(s->st));
-    const T w = (T)s->opt.omega;
+    const T w = s->opt.termination == 0 ? (T)s->opt.omega : T(0);
     for (int64_t q = 0; q < P; ++q) {
         const size_t at = (size_t)part->pk.slot_of_pair[q];
         if (lam) lam[q] = (double)(l[at] + w * m[at]);

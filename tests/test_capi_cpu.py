@@ -27,14 +27,14 @@ def test_default_options():
     assert (o.omega, o.precision, o.delta0, o.alpha, o.reopt_iters, o.max_rounds) == (0.5, 32, 1.0, 1.2, 5, 200)
     assert o.lb_every == 1 and o.rel_tol == 0.0 and o.tau < 0
     assert (o.fast_path, o.perturb_scale, o.sp_in_lds_max_nodes, o.graph_sweeps) == (1, 0, 0, 64)
-    assert o.class_merge_kib == 32768 and o.small_tiles == 2048 and o.serial_mma == 0
+    assert o.class_merge_kib == 32768 and o.small_tiles == 2048 and o.serial_mma == 0 and o.termination == 0
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=1.5), dict(precision=16), dict(lb_every=0),
                                  dict(alpha=0.5), dict(delta0=0.0), dict(max_rounds=-1),
                                  dict(sp_in_lds_max_nodes=-2), dict(fast_path=2), dict(perturb_scale=2),
                                  dict(graph_sweeps=-1), dict(class_merge_kib=-1), dict(small_tiles=-1),
-                                 dict(serial_mma=2)])
+                                 dict(serial_mma=2), dict(termination=2)])
 def test_invalid_options(bad):
     ilp = I.random_ilp(5, 3, seed=1)
     with pytest.raises(B.BddmmaError) as e:
