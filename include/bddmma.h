@@ -117,6 +117,9 @@ typedef struct {
     int64_t n_reg_mixed_tiles;    /* tiles swept by the register kernels (per-lane topologies) */
     int64_t n_reg_launches;       /* register-kernel launches per sweep (non-empty classes) */
     int64_t n_wide_tiles;         /* tiles swept one BDD per wave (layers of >= 16 nodes) */
+    int64_t node_words;           /* 32-bit node words on the device: tiles of one topology share
+                                     one copy (plus the register path's copy), other tiles hold
+                                     one word per node and lane */
 } bddmma_stats;
 
 /* Fill *opt with the defaults listed above.  INVALID_ARG if opt is NULL. */

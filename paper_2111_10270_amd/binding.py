@@ -54,7 +54,7 @@ class Stats(C.Structure):
                 ("n_nodes", C.c_int64), ("n_fixed", C.c_int64), ("n_free", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_slots", C.c_int64), ("max_layers", C.c_int64), ("max_width", C.c_int64),
                 ("lb_offset", C.c_double), ("n_reg_tiles", C.c_int64), ("n_reg_mixed_tiles", C.c_int64),
-                ("n_reg_launches", C.c_int64), ("n_wide_tiles", C.c_int64)]
+                ("n_reg_launches", C.c_int64), ("n_wide_tiles", C.c_int64), ("node_words", C.c_int64)]
 
 
 class PoolInfo(C.Structure):

@@ -1147,6 +1147,7 @@ int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
         o->n_reg_launches += n > 0;
     }
     o->n_wide_tiles = s->pk.list_off[LIST_WIDE + 1] - s->pk.list_off[LIST_WIDE];
+    o->node_words = s->virt ? s->vsz.child : (int64_t)s->pk.child.size();
     return BDDMMA_OK;
 }
 

@@ -253,3 +253,14 @@ def test_serial_tables_cost_workspace_only_when_asked():
     st = b.stats
     # node words, two distance arrays, per-pair tables: at least 4 B per node and 16 B per pair more
     assert b.workspace_bytes() - a.workspace_bytes() >= 4 * st.n_nodes + 16 * st.n_pairs
+
+
+def test_one_topology_tiles_share_their_node_words():
+    """grid MRFs repeat a handful of row shapes: the device keeps one copy of
+    the node words per shape, orders of magnitude fewer words than nodes"""
+    st = B.Solver(I.mrf_grid(48, 48, 8, pairwise="trunc_linear", seed=3)).stats
+    assert st.n_reg_mixed_tiles == 0 and st.n_tiles > 2048
+    assert st.node_words * 1000 < st.n_nodes
+    # per-lane layouts (mixed tiles of a small problem) hold a word per node and lane
+    small = B.Solver(I.graph_matching(n_left=100, n_right=100, k=10, n_pairs=100, seed=2)).stats
+    assert small.node_words >= small.n_nodes
