@@ -324,9 +324,10 @@ def test_gm_tracking_fp32(name):
 
 
 def test_mrf256_sampled_sweep_and_properties():
+    """the benchmark's instance and launch configuration (FP32, eager launches)"""
     ilp = I.workload("mrf256x256L8")
     note("mrf256x256L8: load")
-    s = solver(ilp, precision=32)
+    s = solver(ilp, precision=32, graph_sweeps=0)
     s.run_dual(20)
     lam, mm, avg = s.get_state()
     note("mrf256x256L8: reference")
@@ -350,6 +351,15 @@ def test_mrf256_sampled_sweep_and_properties():
     lf, lc, res = s.lower_bound()
     assert lf <= lc + 1e-4 * abs(lc)
     assert res <= 1e-4 * sc * 8
+    # Alg. 2 at full size: every original row holds for the decoded point
+    # (checked again by the reference, exactly), and UB >= the certified bound
+    note("mrf256x256L8: rounding")
+    s.run_dual(200)
+    lf, lc, res = s.lower_bound()
+    r = s.round_primal()
+    assert r["rc"] == 0
+    assert o.count_violated(r["x"]) == 0
+    assert r["ub"] >= lc
 
 
 # ---------------------------------------------------------------- Alg. 2
