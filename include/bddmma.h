@@ -289,13 +289,15 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * the trajectory of a solver loaded with it alone and run for the same
  * number of iterations (its iterations are counted in whole steps), so its
  * multipliers are bitwise those of the solo run.  Retiring copies the
- * member's terminated multipliers and M to the host (keep_multipliers).  Once
+ * member's terminated multipliers and M to the host (BDDMMA_POOL_KEEP_MULTIPLIERS)
+ * and, with BDDMMA_POOL_ROUND, runs Alg. 2 for the retiring members in a
+ * batch of their own (assembled from their images in the free arena half,
+ * their state copied over), which gives each the point, UB and round count
+ * it gets from bddmma_round_primal when solved alone.  Once
  * an instance is compiled, a worker thread uploads its image on a stream of
  * its own if image space is free, overlapping the running batch; admission
  * passes over an instance whose upload is still running (it joins at a
- * later step), so a step never waits for one.  Primal
- * rounding is not part of the pool (load the instance in a solver of its own
- * for Alg. 2). */
+ * later step), so a step never waits for one. */
 typedef struct bddmma_pool bddmma_pool;
 
 #define BDDMMA_POOL_QUEUED 0   /* submitted, host compilation pending or running */
@@ -314,14 +316,22 @@ typedef struct {
     int64_t steps;           /* pool steps it has been a member of */
     double lb_free, lb_cert, max_residual;   /* after its last step (NaN before) */
     uint64_t workspace_bytes; /* device bytes of the instance alone */
+    int32_t rounded;         /* 1 once Alg. 2 ran for it at retirement (BDDMMA_POOL_ROUND) */
+    int32_t round_status;    /* then: OK, NOT_CONVERGED or STATE (point violates a row) */
+    int32_t rounds;          /* rounds Alg. 2 used */
+    int32_t reserved_;
+    double ub;               /* c^T x of the rounded point (OK only) */
 } bddmma_pool_info;
 
-/* opt as for bddmma_create (rel_tol is applied per step as described above);
- * max_active >= 1; host_threads = worker threads (compilation, image
- * uploads), 0 = min(8, cores); keep_multipliers = 1 copies a member's
- * terminated multipliers to the host when it retires (bddmma_pool_result),
- * 0 keeps bounds only. */
-int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t keep_multipliers,
+#define BDDMMA_POOL_KEEP_MULTIPLIERS 1   /* copy terminated multipliers to the host at retirement */
+#define BDDMMA_POOL_ROUND            2   /* run Alg. 2 for members when they retire */
+
+/* opt as for bddmma_create (rel_tol is applied per step as described above;
+ * Alg. 2 uses its delta0, alpha, reopt_iters, max_rounds, tau, seed and
+ * perturb_scale); max_active >= 1; host_threads = worker threads
+ * (compilation, image uploads), 0 = min(8, cores); flags: a combination of
+ * BDDMMA_POOL_KEEP_MULTIPLIERS and BDDMMA_POOL_ROUND (0: bounds only). */
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t flags,
                        bddmma_pool **out);
 
 /* Device arena owned by the caller (256-byte aligned, 8 MiB + 3 KiB at least) and
@@ -368,15 +378,19 @@ int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *m
  * instances admitted and retired; wall milliseconds spent writing and
  * uploading the images of admitted instances, building the batch's host
  * tables (merge), assembling it on the device and carrying the
- * members' state (bind), running the iterations, computing bounds and
- * retiring members; and the arena split: bytes of one batch half, of the
- * member-image region and of its free part. */
+ * members' state (bind), running the iterations, computing bounds,
+ * retiring members and rounding them; and the arena split: bytes of one
+ * batch half, of the member-image region and of its free part. */
 typedef struct {
     int64_t steps, assemblies, admitted, retired;
-    double image_ms, merge_ms, bind_ms, run_ms, bounds_ms, retire_ms;
+    double image_ms, merge_ms, bind_ms, run_ms, bounds_ms, retire_ms, round_ms;
     uint64_t batch_capacity, image_capacity, image_free;
 } bddmma_pool_counters;
 int bddmma_pool_get_counters(bddmma_pool *p, bddmma_pool_counters *out);
+
+/* The rounded point x_out[n_vars] of a DONE instance whose Alg. 2 returned OK
+ * (presolved variables included); STATE otherwise. */
+int bddmma_pool_primal(bddmma_pool *p, int64_t ticket, uint8_t *x_out);
 
 /* Forget a DONE or FAILED instance (STATE otherwise). */
 int bddmma_pool_release(bddmma_pool *p, int64_t ticket);

@@ -28,9 +28,10 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
-           "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune")
+           "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune", "bddmma_pool_primal")
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
+POOL_KEEP_MULTIPLIERS, POOL_ROUND = 1, 2
 
 
 class BddmmaError(RuntimeError):
@@ -60,7 +61,9 @@ class Stats(C.Structure):
 class PoolInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("iters", C.c_int32), ("n_iter", C.c_int32),
                 ("n_vars", C.c_int64), ("n_pairs", C.c_int64), ("steps", C.c_int64), ("lb_free", C.c_double),
-                ("lb_cert", C.c_double), ("max_residual", C.c_double), ("workspace_bytes", C.c_uint64)]
+                ("lb_cert", C.c_double), ("max_residual", C.c_double), ("workspace_bytes", C.c_uint64),
+                ("rounded", C.c_int32), ("round_status", C.c_int32), ("rounds", C.c_int32), ("reserved_", C.c_int32),
+                ("ub", C.c_double)]
 
 
 _lib = None
@@ -91,7 +94,7 @@ def lib():
             "bddmma_pool_submit_loaded": [P, P, i32, P], "bddmma_pool_step": [P, i32, P, P],
             "bddmma_pool_wait_compiled": [P], "bddmma_pool_poll": [P, i64, P],
             "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
-            "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P],
+            "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P], "bddmma_pool_primal": [P, i64, P],
             "bddmma_autotune": [P, i64, P, i64, P, P, P, P, P, P, C.c_size_t, P, i32, P, P],
         }
         for name, args in sig.items():
@@ -315,7 +318,8 @@ class Solver:
 class PoolCounters(C.Structure):
     _fields_ = [("steps", C.c_int64), ("assemblies", C.c_int64), ("admitted", C.c_int64), ("retired", C.c_int64),
                 ("image_ms", C.c_double), ("merge_ms", C.c_double), ("bind_ms", C.c_double), ("run_ms", C.c_double),
-                ("bounds_ms", C.c_double), ("retire_ms", C.c_double), ("batch_capacity", C.c_uint64),
+                ("bounds_ms", C.c_double), ("retire_ms", C.c_double), ("round_ms", C.c_double),
+                ("batch_capacity", C.c_uint64),
                 ("image_capacity", C.c_uint64), ("image_free", C.c_uint64)]
 
 
@@ -323,11 +327,13 @@ class Pool:
     """Serving pool (continuous batching): submit ILPs at any time, step the
     resident batch, poll each ticket; see bddmma_pool_* in the header."""
 
-    def __init__(self, max_active: int = 16, host_threads: int = 0, keep_multipliers: bool = True, **options):
+    def __init__(self, max_active: int = 16, host_threads: int = 0, keep_multipliers: bool = True,
+                 round: bool = False, **options):
         self._h = C.c_void_p()
         self.options = default_options(**options)
-        _check(lib().bddmma_pool_create(C.byref(self.options), int(max_active), int(host_threads),
-                                        int(bool(keep_multipliers)), C.byref(self._h)))
+        flags = (POOL_KEEP_MULTIPLIERS if keep_multipliers else 0) | (POOL_ROUND if round else 0)
+        _check(lib().bddmma_pool_create(C.byref(self.options), int(max_active), int(host_threads), flags,
+                                        C.byref(self._h)))
         self.arena = None
         self.stream = None
 
@@ -383,6 +389,12 @@ class Pool:
         pv, pr = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
         _check(lib().bddmma_pool_result(self._h, int(ticket), _p(lam), _p(mm), _p(pv), _p(pr)))
         return lam, mm, pv, pr
+
+    def primal(self, ticket: int) -> np.ndarray:
+        """rounded point of a retired instance (pool created with round=True)"""
+        x = np.zeros(self.poll(ticket)["n_vars"], dtype=np.uint8)
+        _check(lib().bddmma_pool_primal(self._h, int(ticket), _p(x)))
+        return x
 
     def release(self, ticket: int):
         _check(lib().bddmma_pool_release(self._h, int(ticket)))

@@ -50,6 +50,9 @@ struct Inst {
     int64_t img_off = -1;           // image offset in the image region (-1: none)
     int img = IMG_NONE;
     std::vector<double> lam, mm;    // terminated multipliers and M at retirement
+    int32_t rounded = 0, round_status = 0, rounds = 0;   // Alg. 2 at retirement
+    double ub = NAN;
+    std::vector<uint8_t> x;         // its point (round_status OK)
     // input, until compiled
     int64_t nv = 0, nr = 0;
     std::vector<double> cost;
@@ -72,6 +75,7 @@ struct bddmma_pool {
     bddmma_options opt{};
     int32_t max_active = 1;
     bool keep_multipliers = true;
+    bool round = false;             // Alg. 2 for retiring members
     std::mutex mu;
     std::condition_variable cv_job, cv_idle, cv_img;
     std::deque<Inst *> jobs;
@@ -325,6 +329,57 @@ int reassemble(bddmma_pool *p)
     return BDDMMA_OK;
 }
 
+// Alg. 2 for the retiring members mem[ret[.]]: a batch of only them,
+// assembled from their images in the free arena half with their state copied
+// from the resident batch (which gives each the result of its solo run).
+int round_members(bddmma_pool *p, const std::vector<Inst *> &mem, const std::vector<size_t> &ret)
+{
+    std::vector<const bddmma_solver *> parts;
+    std::vector<uint64_t> img, img_bytes;
+    std::vector<int64_t> voff(1, 0);
+    for (size_t k : ret) {
+        const Inst *in = mem[k];
+        parts.push_back(in->s);
+        img.push_back((uint64_t)(uintptr_t)(p->img_area + in->img_off));
+        img_bytes.push_back(in->img_size);
+        voff.push_back(voff.back() + in->n_vars);
+    }
+    bddmma_options o = p->opt;
+    o.rel_tol = 0.0;
+    bddmma_solver *rb = nullptr;
+    int rc = bddmma_create(&o, &rb);
+    if (rc) return rc;
+    std::vector<int64_t> off;
+    size_t need = 0;
+    rc = solver_load_virtual(rb, parts, off);
+    if (!rc) rc = bddmma_workspace_bytes(rb, &need);
+    if (!rc && need > p->half) rc = set_error(BDDMMA_ERR_NO_MEMORY, "rounding batch exceeds half of the pool arena");
+    if (!rc)
+        rc = solver_bind_assembled(rb, p->halves + (size_t)(p->side ^ 1) * p->half, p->half, p->st, parts, img,
+                                   img_bytes, p->asm_area, kAsmBytes);
+    for (size_t q = 0; !rc && q < ret.size(); ++q)
+        rc = solver_copy_slots(rb, off[q], p->batch, mem[ret[q]]->slot_off, solver_slots(parts[q]));
+    const size_t n = ret.size();
+    std::vector<uint8_t> x((size_t)std::max<int64_t>(voff.back(), 1));
+    std::vector<double> ub(n);
+    std::vector<int32_t> rounds(n), status(n);
+    if (!rc) rc = bddmma_batch_round(rb, x.data(), ub.data(), rounds.data(), status.data());
+    bddmma_destroy(rb);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (size_t q = 0; q < n; ++q) {
+        Inst *in = mem[ret[q]];
+        in->rounded = 1;
+        in->round_status = status[q];
+        in->rounds = rounds[q];
+        if (status[q] == BDDMMA_OK) {
+            in->ub = ub[q];
+            in->x.assign(x.begin() + voff[q], x.begin() + voff[q + 1]);
+        }
+    }
+    return BDDMMA_OK;
+}
+
 int enqueue(bddmma_pool *p, std::unique_ptr<Inst> in, int64_t *ticket)
 {
     std::lock_guard<std::mutex> lk(p->mu);
@@ -341,7 +396,7 @@ int enqueue(bddmma_pool *p, std::unique_ptr<Inst> in, int64_t *ticket)
 
 extern "C" {
 
-int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t keep_multipliers,
+int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t host_threads, int32_t flags,
                        bddmma_pool **out)
 {
     POOL_GUARD_BEGIN
@@ -349,8 +404,8 @@ int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t ho
     *out = nullptr;
     if (max_active < 1) return set_error(BDDMMA_ERR_INVALID_ARG, "max_active must be >= 1");
     if (host_threads < 0) return set_error(BDDMMA_ERR_INVALID_ARG, "host_threads must be >= 0");
-    if (keep_multipliers != 0 && keep_multipliers != 1)
-        return set_error(BDDMMA_ERR_INVALID_ARG, "keep_multipliers must be 0 or 1");
+    if (flags & ~(BDDMMA_POOL_KEEP_MULTIPLIERS | BDDMMA_POOL_ROUND))
+        return set_error(BDDMMA_ERR_INVALID_ARG, "unknown pool flags");
     bddmma_options o;
     if (opt) o = *opt;
     else bddmma_options_default(&o);
@@ -362,7 +417,8 @@ int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t ho
     std::unique_ptr<bddmma_pool> p(new bddmma_pool());
     p->opt = o;
     p->max_active = max_active;
-    p->keep_multipliers = keep_multipliers != 0;
+    p->keep_multipliers = (flags & BDDMMA_POOL_KEEP_MULTIPLIERS) != 0;
+    p->round = (flags & BDDMMA_POOL_ROUND) != 0;
     unsigned hw = std::thread::hardware_concurrency();
     int n = host_threads > 0 ? host_threads : (int)std::max(1u, std::min(hw ? hw : 1u, 8u));
     for (int i = 0; i < n; ++i) p->workers.emplace_back(worker, p.get());
@@ -532,6 +588,16 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
             in->mm.swap(mm);
         }
     }
+    if (p->round) {
+        std::vector<size_t> ret;
+        for (size_t k = 0; k < n; ++k)
+            if (done[k]) ret.push_back(k);
+        if (!ret.empty()) {
+            auto tr = std::chrono::steady_clock::now();
+            if ((rc = round_members(p, mem, ret))) return rc;
+            p->cnt.round_ms += ms_since(tr);
+        }
+    }
     std::lock_guard<std::mutex> lk(p->mu);
     std::vector<int64_t> keep;
     int32_t retired = 0;
@@ -582,6 +648,23 @@ int bddmma_pool_poll(bddmma_pool *p, int64_t ticket, bddmma_pool_info *info)
     info->lb_cert = in.steps ? in.lb_cert : kNaN;
     info->max_residual = in.steps ? in.res : kNaN;
     info->workspace_bytes = in.bytes;
+    info->rounded = in.rounded;
+    info->round_status = in.round_status;
+    info->rounds = in.rounds;
+    info->ub = in.ub;
+    return BDDMMA_OK;
+}
+
+int bddmma_pool_primal(bddmma_pool *p, int64_t ticket, uint8_t *x_out)
+{
+    if (!p || !x_out) return set_error(BDDMMA_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->inst.find(ticket);
+    if (it == p->inst.end()) return set_error(BDDMMA_ERR_INVALID_ARG, "unknown ticket");
+    const Inst &in = *it->second;
+    if (in.state != BDDMMA_POOL_DONE || !in.rounded || in.round_status != BDDMMA_OK)
+        return set_error(BDDMMA_ERR_STATE, "no rounded point (retire with BDDMMA_POOL_ROUND and a converged Alg. 2)");
+    std::copy(in.x.begin(), in.x.end(), x_out);
     return BDDMMA_OK;
 }
 
@@ -596,7 +679,7 @@ int bddmma_pool_result(bddmma_pool *p, int64_t ticket, double *lambda, double *m
     const Inst &in = *it->second;
     if (in.state != BDDMMA_POOL_DONE) return set_error(BDDMMA_ERR_STATE, "instance not retired");
     if ((lambda || mm) && !p->keep_multipliers)
-        return set_error(BDDMMA_ERR_STATE, "the pool keeps no multipliers (keep_multipliers = 0)");
+        return set_error(BDDMMA_ERR_STATE, "the pool keeps no multipliers (no BDDMMA_POOL_KEEP_MULTIPLIERS)");
     if (lambda) std::copy(in.lam.begin(), in.lam.end(), lambda);
     if (mm) std::copy(in.mm.begin(), in.mm.end(), mm);
     if (pair_var || pair_row) {

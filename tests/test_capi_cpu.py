@@ -206,7 +206,7 @@ def test_pool_host_side_states_and_validation():
         B.Pool(omega=2.0)
     assert e.value.code == B.INVALID_ARG
     with pytest.raises(B.BddmmaError) as e:
-        B._check(B.lib().bddmma_pool_create(None, 2, 1, 7, B.C.byref(B.C.c_void_p())))
+        B._check(B.lib().bddmma_pool_create(None, 2, 1, 4, B.C.byref(B.C.c_void_p())))   # unknown flag
     assert e.value.code == B.INVALID_ARG
     pool = B.Pool(max_active=2, host_threads=2, precision=64)
     good = I.random_ilp(12, 8, seed=3)

@@ -180,3 +180,32 @@ def test_pool_bounds_only_and_prefetched_images():
         assert e.value.code == B.STATE
         _, _, pv, _ = pool.result(t, multipliers=False)
         assert np.array_equal(pv, a.pairs()[0])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_pool_rounds_members_as_alone(prec):
+    """with round=True each member is rounded at retirement in a batch of the
+    retiring members: same status, rounds and point as Alg. 2 on the instance
+    alone after the same iterations (UB to 1e-12: its sum runs per instance
+    chunk either way, in FP64)"""
+    ilps = members()[:6]
+    iters = [10, 15, 10, 20, 5, 15][:len(ilps)]
+    pool = B.Pool(max_active=3, round=True, precision=prec).bind(128 << 20)
+    ts = [pool.submit(p, n) for p, n in zip(ilps, iters)]
+    pool.wait_compiled()
+    while any(pool.poll(t)["state"] != B.POOL_DONE for t in ts):
+        pool.step(5)
+    assert pool.counters()["round_ms"] > 0.0
+    for p, t, n in zip(ilps, ts, iters):
+        info = pool.poll(t)
+        assert info["rounded"] == 1
+        a = solo(p, n, precision=prec)
+        r = a.round_primal()
+        assert info["round_status"] == r["rc"] and info["rounds"] == r["rounds"], (p.name, info, r["rc"], r["rounds"])
+        if r["rc"] == 0:
+            assert np.array_equal(pool.primal(t), r["x"])
+            assert abs(info["ub"] - r["ub"]) <= 1e-12 * max(1.0, abs(r["ub"]))
+        else:
+            with pytest.raises(B.BddmmaError) as e:
+                pool.primal(t)
+            assert e.value.code == B.STATE
