@@ -437,6 +437,32 @@ int bddmma_run_serial(bddmma_solver *s, int32_t n_iter, double *lb_hist);
 int bddmma_profile(bddmma_solver *s, int enable);
 int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *total_ms);
 
+/* Encoding of rows whose BDDs would be too wide (the paper leaves such rows to
+ * additional encodings, Sec. 7).  Reads an ILP in the bddmma_load_ilp format
+ * and writes an equivalent one in which every row whose partial sums can
+ * take more than max_states values (min(2^k, sum |a| + 1) over its k nonzero
+ * terms) is replaced by a binary adder network over auxiliary variables
+ * appended after the original n_vars:
+ *  - one complement variable per variable with a negative coefficient in
+ *    such a row, with the row x + xbar = 1;
+ *  - one equality row per bit column of the weights, summing the column's
+ *    inputs and the previous column's carry bits into a sum bit and new
+ *    carry bits;
+ *  - one comparison row sum_k 2^k s_k (sense) B.
+ * Every auxiliary value is determined by the original ones, so the feasible
+ * points of the output, restricted to the first n_vars entries, are those of
+ * the input.  Auxiliary variables cost 0; other rows are copied, normalised
+ * (zero coefficients dropped, columns ascending).  Two calls: with costs_out
+ * NULL only the sizes are written (n_vars_out, n_rows_out, nnz_out and
+ * n_encoded = rows replaced); then every output array with those sizes.
+ * INVALID_ARG on bad input, max_states < 2, or an encoded row whose weight
+ * sum reaches 2^30.  All arrays are host memory owned by the caller. */
+int bddmma_encode_rows(int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                       const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+                       int64_t max_states, int64_t *n_vars_out, int64_t *n_rows_out, int64_t *nnz_out,
+                       int64_t *n_encoded, double *costs_out, int64_t *row_ptr_out, int32_t *col_out,
+                       int32_t *coef_out, int8_t *sense_out, int64_t *rhs_out);
+
 /* Autotuner for the launch schedule: which kernels sweep which tiles
  * (register-resident fast path or general kernels; mixed per-lane tiles for
  * small problems; layer-class merging; shortest paths in LDS or device

@@ -28,7 +28,8 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_batch_bounds", "bddmma_batch_round", "bddmma_pool_create", "bddmma_pool_bind",
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
-           "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune", "bddmma_pool_primal")
+           "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune", "bddmma_pool_primal",
+           "bddmma_encode_rows")
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 POOL_KEEP_MULTIPLIERS, POOL_ROUND = 1, 2
@@ -96,6 +97,7 @@ def lib():
             "bddmma_pool_result": [P, i64, P, P, P, P], "bddmma_pool_release": [P, i64], "bddmma_pool_destroy": [P],
             "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P], "bddmma_pool_primal": [P, i64, P],
             "bddmma_autotune": [P, i64, P, i64, P, P, P, P, P, P, C.c_size_t, P, i32, P, P],
+            "bddmma_encode_rows": [i64, P, i64, P, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -126,6 +128,27 @@ def default_options(**kw) -> Options:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def encode_rows(ilp, max_states: int = 4096):
+    """ILP with every row of more than max_states partial-sum values replaced by
+    a binary adder network (bddmma_encode_rows); -> (ILP, rows replaced).  The
+    first ilp.n_vars variables are the original ones."""
+    from . import instances
+    arrs = [np.ascontiguousarray(ilp.costs, dtype=np.float64), np.ascontiguousarray(ilp.row_ptr, dtype=np.int64),
+            np.ascontiguousarray(ilp.col, dtype=np.int32), np.ascontiguousarray(ilp.coef, dtype=np.int32),
+            np.ascontiguousarray(ilp.sense, dtype=np.int8), np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
+    nv, nr, nnz, ne = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    args = [ilp.n_vars, _p(arrs[0]), ilp.n_rows] + [_p(a) for a in arrs[1:]] + [int(max_states)]
+    _check(lib().bddmma_encode_rows(*args, C.byref(nv), C.byref(nr), C.byref(nnz), C.byref(ne),
+                                    None, None, None, None, None, None))
+    out = [np.zeros(nv.value), np.zeros(nr.value + 1, dtype=np.int64), np.zeros(nnz.value, dtype=np.int32),
+           np.zeros(nnz.value, dtype=np.int32), np.zeros(nr.value, dtype=np.int8), np.zeros(nr.value, dtype=np.int64)]
+    _check(lib().bddmma_encode_rows(*args, C.byref(nv), C.byref(nr), C.byref(nnz), C.byref(ne),
+                                    *[_p(a) for a in out]))
+    enc = instances.ILP(nv.value, out[0], out[1], out[2], out[3], out[4], out[5], name=ilp.name + "_enc",
+                        meta={"n_original_vars": ilp.n_vars})
+    return enc, ne.value
 
 
 def autotune(ilp, sweeps: int = 64, slack: float = 2.0, device="cuda", stream=None, **options):

@@ -1506,6 +1506,37 @@ int bddmma_kernel_time(bddmma_solver *s, int kernel, int64_t *launches, double *
     return BDDMMA_OK;
 }
 
+int bddmma_encode_rows(int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
+                       const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
+                       int64_t max_states, int64_t *n_vars_out, int64_t *n_rows_out, int64_t *nnz_out,
+                       int64_t *n_encoded, double *costs_out, int64_t *row_ptr_out, int32_t *col_out,
+                       int32_t *coef_out, int8_t *sense_out, int64_t *rhs_out)
+{
+    GUARD_BEGIN
+    if (!n_vars_out || !n_rows_out || !nnz_out) return fail(BDDMMA_ERR_INVALID_ARG, "size outputs are NULL");
+    Ilp in, out;
+    std::string msg;
+    int rc = ingest_ilp(in, n_vars, costs, n_rows, row_ptr, col, coef, sense, rhs, msg);
+    int64_t ne = 0;
+    if (rc == ST_OK) rc = encode_wide_rows(in, max_states, out, ne, msg);
+    if (rc != ST_OK) return fail(rc, msg);
+    *n_vars_out = out.n_vars;
+    *n_rows_out = out.n_rows;
+    *nnz_out = (int64_t)out.col.size();
+    if (n_encoded) *n_encoded = ne;
+    if (!costs_out) return BDDMMA_OK;
+    if (!row_ptr_out || (out.n_rows > 0 && (!sense_out || !rhs_out)) || (!out.col.empty() && (!col_out || !coef_out)))
+        return fail(BDDMMA_ERR_INVALID_ARG, "output arrays are NULL");
+    std::copy(out.cost.begin(), out.cost.end(), costs_out);
+    std::copy(out.row_ptr.begin(), out.row_ptr.end(), row_ptr_out);
+    std::copy(out.col.begin(), out.col.end(), col_out);
+    for (size_t e = 0; e < out.coef.size(); ++e) coef_out[e] = (int32_t)out.coef[e];
+    std::copy(out.sense.begin(), out.sense.end(), sense_out);
+    std::copy(out.rhs.begin(), out.rhs.end(), rhs_out);
+    return BDDMMA_OK;
+    GUARD_END
+}
+
 int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *costs, int64_t n_rows,
                     const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
                     const int64_t *rhs, void *dev_ptr, size_t bytes, void *hip_stream, int32_t sweeps,

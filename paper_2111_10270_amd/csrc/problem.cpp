@@ -181,9 +181,18 @@ int compile_row(const int32_t *var, const int64_t *a_in, int k, int sense, int64
         if (sense < 0) return s + slo[h] <= b;
         return s + slo[h] <= b && b <= s + shi[h];
     };
+    // a <= row is certain once even the largest completion stays within b; all
+    // such partial sums of a layer have the same (all-accepting) future, so
+    // they share one state, b - shi[h] (the reduction below would merge them
+    // anyway; merging here keeps rows with huge weights, which have few
+    // undecided sums per layer, from growing before the reduction)
+    auto canon = [&](int64_t v, int h) {
+        if (sense < 0 && h < k && v + shi[h] <= b) return b - shi[h];
+        return v;
+    };
     if (!admissible(0, 0)) return ST_INFEASIBLE;
     if ((int)S.size() < k + 1) { S.resize(k + 1); W.resize(k + 1); alive.resize(k + 1); nid.resize(k + 1); }
-    S[0].assign(1, 0);
+    S[0].assign(1, canon(0, 0));
     for (int h = 0; h < k; ++h) {
         // successors of layer h: s (zero-arc) and s + a_h (one-arc); both lists sorted
         const auto &s = S[h];
@@ -195,6 +204,7 @@ int compile_row(const int32_t *var, const int64_t *a_in, int k, int sense, int64
             int64_t v;
             if (j >= s.size() || (i < s.size() && s[i] <= s[j] + d)) v = s[i++];
             else v = s[j++] + d;
+            v = canon(v, h + 1);
             if ((n.empty() || n.back() != v) && (h + 1 == k ? (sense < 0 ? v <= b : v == b) : admissible(v, h + 1)))
                 n.push_back(v);
         }
@@ -211,7 +221,7 @@ int compile_row(const int32_t *var, const int64_t *a_in, int k, int sense, int64
         for (size_t q = 0; q < s.size(); ++q) {
             uint32_t c[2];
             for (int t = 0; t < 2; ++t) {
-                int64_t v = s[q] + (t ? A[h] : 0);
+                int64_t v = canon(s[q] + (t ? A[h] : 0), h + 1);
                 if (h + 1 == k) {
                     c[t] = std::binary_search(S[k].begin(), S[k].end(), v) ? kTop : kBot;
                 } else {
@@ -1496,6 +1506,119 @@ int build_serial(const Problem &p, const Packed &pk, SerialTables &o, std::strin
     csr(lb, o.lb_ptr, o.lb_var);
     o.slot.resize((size_t)P);
     for (int64_t q = 0; q < P; ++q) o.slot[q] = (int32_t)pk.slot_of_pair[q];
+    return ST_OK;
+}
+
+int encode_wide_rows(const Ilp &in, int64_t max_states, Ilp &o, int64_t &n_encoded, std::string &msg)
+{
+    if (max_states < 2) {
+        msg = "max_states must be >= 2";
+        return ST_INVALID;
+    }
+    const int64_t n = in.n_vars;
+    n_encoded = 0;
+    // which rows need the encoding
+    std::vector<char> enc((size_t)in.n_rows, 0);
+    for (int64_t r = 0; r < in.n_rows; ++r) {
+        const int64_t k = in.row_ptr[r + 1] - in.row_ptr[r];
+        __int128 mag = 0;
+        for (int64_t e = in.row_ptr[r]; e < in.row_ptr[r + 1]; ++e) mag += in.coef[e] < 0 ? -in.coef[e] : in.coef[e];
+        const bool few = k < 62 && ((int64_t)1 << k) <= max_states;
+        enc[r] = !few && mag + 1 > (__int128)max_states;
+        n_encoded += enc[r];
+    }
+    o = Ilp();
+    o.cost = in.cost;
+    o.row_ptr.assign(1, 0);
+    int64_t nv = n;
+    auto add_row = [&](const std::vector<std::pair<int32_t, int64_t>> &t, int sense, int64_t b) {
+        std::vector<std::pair<int32_t, int64_t>> s(t);
+        std::sort(s.begin(), s.end());
+        for (auto &pr : s) {
+            o.col.push_back(pr.first);
+            o.coef.push_back(pr.second);
+        }
+        o.row_ptr.push_back((int64_t)o.col.size());
+        o.sense.push_back((int8_t)sense);
+        o.rhs.push_back(b);
+    };
+    auto new_var = [&]() {
+        o.cost.push_back(0.0);
+        return (int32_t)nv++;
+    };
+    std::vector<int32_t> comp((size_t)n, -1);   // complement of x_i, created on first use
+    for (int64_t r = 0; r < in.n_rows; ++r) {
+        std::vector<std::pair<int32_t, int64_t>> t;
+        for (int64_t e = in.row_ptr[r]; e < in.row_ptr[r + 1]; ++e) t.emplace_back(in.col[e], in.coef[e]);
+        if (!enc[r]) {
+            add_row(t, in.sense[r], in.rhs[r]);
+            continue;
+        }
+        // positive weights over x or its complement
+        std::vector<std::pair<int32_t, int64_t>> w;
+        int64_t B = in.rhs[r], total = 0;
+        for (auto &pr : t) {
+            if (pr.second > 0) {
+                w.push_back(pr);
+            } else {
+                int32_t &c = comp[pr.first];
+                if (c < 0) {
+                    c = new_var();
+                    add_row({{pr.first, 1}, {c, 1}}, 0, 1);
+                }
+                w.emplace_back(c, -pr.second);
+                B += -pr.second;
+            }
+            total += w.back().second;
+            if (total >= ((int64_t)1 << 30)) {
+                msg = "row " + std::to_string(r) + ": weight sum too large to encode";
+                return ST_INVALID;
+            }
+        }
+        // L columns cover the total weight; the carry out of column k is at
+        // most floor(sum_i (w_i mod 2^(k+1)) / 2^(k+1)), which is 0 after the
+        // last column since the total is below 2^L
+        int L = 1;
+        while (((int64_t)1 << L) <= total) ++L;
+        std::vector<int64_t> maxc((size_t)L);
+        for (int k = 0; k < L; ++k) {
+            int64_t low = 0;
+            for (auto &pr : w) low += pr.second & (((int64_t)1 << (k + 1)) - 1);
+            maxc[k] = low >> (k + 1);
+        }
+        // ids: sum bits from the most significant down, then carry bits
+        std::vector<int32_t> sbit((size_t)L);
+        for (int k = L - 1; k >= 0; --k) sbit[k] = new_var();
+        std::vector<std::vector<int32_t>> cbits((size_t)L);
+        for (int k = 0; k < L; ++k)
+            for (int j = 0; ((int64_t)1 << j) <= maxc[k]; ++j) cbits[k].push_back(new_var());
+        for (int k = 0; k < L; ++k) {
+            std::vector<std::pair<int32_t, int64_t>> row;
+            for (auto &pr : w)
+                if ((pr.second >> k) & 1) row.emplace_back(pr.first, 1);
+            if (k > 0)
+                for (size_t j = 0; j < cbits[k - 1].size(); ++j) row.emplace_back(cbits[k - 1][j], (int64_t)1 << j);
+            row.emplace_back(sbit[k], -1);
+            for (size_t j = 0; j < cbits[k].size(); ++j) row.emplace_back(cbits[k][j], -((int64_t)1 << (j + 1)));
+            add_row(row, 0, 0);
+        }
+        const int K = L;
+        std::vector<std::pair<int32_t, int64_t>> cmp;
+        for (int k = 0; k < K; ++k) cmp.emplace_back(sbit[k], (int64_t)1 << k);
+        add_row(cmp, in.sense[r], B);
+        if (maxc[K - 1] != 0) {
+            msg = "internal error: adder network leaves a carry";
+            return ST_INVALID;
+        }
+    }
+    o.n_vars = nv;
+    o.n_rows = (int64_t)o.sense.size();
+    o.inst_var = {0, nv};
+    o.inst_row = {0, o.n_rows};
+    if (nv >= INT32_MAX) {
+        msg = "encoding needs too many variables";
+        return ST_INVALID;
+    }
     return ST_OK;
 }
 

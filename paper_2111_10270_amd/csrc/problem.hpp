@@ -168,6 +168,27 @@ struct SerialTables {
 };
 int build_serial(const Problem &p, const Packed &pk, SerialTables &out, std::string &msg);
 
+// ---- encoding of rows whose BDDs would be too wide --------------------------------
+// A row  sum a_i x_i (sense) b  whose partial sums can take more than
+// max_states values (min(2^k, sum |a_i| + 1) over its k nonzero terms) is
+// replaced by a binary adder network over auxiliary variables appended after
+// the original ones:
+//  - a negative coefficient uses the complement xb_i of x_i (row x_i + xb_i = 1,
+//    one complement per variable), so all weights w_i are positive and the
+//    right-hand side becomes B = b + sum_{a_i < 0} |a_i|;
+//  - column k adds the inputs whose weight has bit k set and the carry of
+//    column k - 1 (its bits c_{k-1,j} with weights 2^j) into a sum bit s_k and
+//    a carry C_k = (sum bits) div 2 written in binary:
+//        sum inputs + sum_j 2^j c_{k-1,j} - s_k - sum_j 2^(j+1) c_{k,j} = 0,
+//    with as many columns as the total weight needs;
+//  - one row  sum_k 2^k s_k (sense) B  compares the sum with B; its most
+//    significant bit gets the smallest variable id, so this BDD stays narrow.
+// Every auxiliary value is determined by x, so the encoded rows admit exactly
+// the points of the original row (extended by those values).  Auxiliary
+// variables cost 0.  Rows within the limit are copied unchanged.  The weight
+// sum of an encoded row must stay below 2^30 (ST_INVALID otherwise).
+int encode_wide_rows(const Ilp &in, int64_t max_states, Ilp &out, int64_t &n_encoded, std::string &msg);
+
 // Compile one row  sum a_h x_h (sense) b  over ascending variables into a
 // reduced BDD appended to `out`.  Returns ST_OK, ST_INFEASIBLE or ST_INVALID.
 int compile_row(const int32_t *var, const int64_t *a, int k, int sense, int64_t b, BddSet &out,

@@ -175,3 +175,69 @@ class ExactAlg1:
     def flat(self, which):
         src = self.lam if which == "lam" else self.M
         return [v for row in src for v in row]
+
+
+def completions(ilp, fixed, limit=2):
+    """Number (capped at limit) of 0/1 completions of a partial assignment
+    (fixed[i] in {-1,0,1}) that satisfy every row: depth-first search with
+    interval propagation over the rows, generic in the rows' content."""
+    n = ilp.n_vars
+    rows = [ilp.row(r) for r in range(ilp.n_rows)]
+    rows = [([int(c) for c in cs], [int(a) for a in as_], int(s), int(b)) for cs, as_, s, b in rows]
+    by_var = [[] for _ in range(n)]
+    for r, (cs, _, _, _) in enumerate(rows):
+        for c in cs:
+            by_var[c].append(r)
+
+    def propagate(x, queue):
+        while queue:
+            r = queue.pop()
+            cs, as_, s, b = rows[r]
+            lo = hi = 0
+            for c, a in zip(cs, as_):
+                if x[c] >= 0:
+                    lo += a * x[c]
+                    hi += a * x[c]
+                elif a < 0:
+                    lo += a
+                else:
+                    hi += a
+            if (s <= 0 and lo > b) or (s >= 0 and hi < b):
+                return False
+            for c, a in zip(cs, as_):
+                if x[c] >= 0:
+                    continue
+                # the value of x_c that moves the sum to each end
+                v = None
+                if s <= 0 and lo + abs(a) > b:
+                    v = 0 if a > 0 else 1          # the other value would exceed b
+                if s >= 0 and hi - abs(a) < b:
+                    w = 1 if a > 0 else 0          # the other value would fall short of b
+                    if v is not None and v != w:
+                        return False
+                    v = w
+                if v is not None:
+                    x[c] = v
+                    queue.extend(by_var[c])   # r among them: its interval is recomputed
+                    break
+        return True
+
+    def dfs(x):
+        free = [i for i in range(n) if x[i] < 0]
+        if not free:
+            return 1
+        best = min(free, key=lambda i: min(sum(x[c] < 0 for c in rows[r][0]) for r in by_var[i]) if by_var[i] else n)
+        total = 0
+        for v in (0, 1):
+            y = list(x)
+            y[best] = v
+            if propagate(y, list(by_var[best])):
+                total += dfs(y)
+                if total >= limit:
+                    return total
+        return total
+
+    x = [int(v) for v in fixed]
+    if not propagate(x, list(range(len(rows)))):
+        return 0
+    return dfs(x)

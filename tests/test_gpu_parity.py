@@ -157,6 +157,33 @@ def test_long_and_wide_rows_fp64():
 
 
 @pytest.mark.parametrize("prec", [64, 32])
+def test_encoded_wide_rows(prec):
+    """an ILP whose knapsack rows are rewritten into binary adders
+    (encode_rows): sweep-by-sweep parity with the reference on the encoded
+    rows, certified bound below the enumerated optimum of the original ILP,
+    and a rounded point that satisfies the original rows"""
+    rng = np.random.default_rng(31)
+    n = 12
+    rows = [(list(range(n)), [int(v) for v in rng.integers(200, 5000, n)], -1, 12000),
+            ([1, 4, 7, 9, 10], [int(v) for v in rng.integers(-3000, 3000, 5)], 1, -500)]
+    for r in range(6):
+        rows.append((rng.choice(n, size=3, replace=False), [1, 1, 1], -1, 1))
+    ilp = I.from_rows(n, rng.standard_normal(n) - 0.5, rows, name="knap12")
+    enc, ne = B.encode_rows(ilp, max_states=24)
+    assert ne == 2
+    note("encoded", enc.n_vars, "vars", enc.n_rows, "rows")
+    s, o, _ = lockstep(enc, 8, precision=prec)
+    s.run_dual(200)
+    opt, _ = brute.ilp_opt(ilp)
+    lb = s.lower_bound()[1]
+    assert lb <= float(opt) + 1e-9 * max(1.0, abs(float(opt))), (lb, opt)
+    r = s.round_primal()
+    if r["rc"] == 0:
+        assert brute.check_rows(ilp, r["x"][:n]) == 0
+        assert brute.check_rows(enc, r["x"]) == 0
+
+
+@pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("merge", [0, 32768])
 def test_layer_classes(prec, merge):
     """many register classes (shared at widths 2 and 4, mixed), class merging
