@@ -29,7 +29,75 @@ uint64_t mix64(uint64_t h, uint64_t v)
 
 bool sense_holds(int64_t v, int sense, int64_t b) { return sense < 0 ? v <= b : sense > 0 ? v >= b : v == b; }
 
+std::atomic<int> g_thread_cap{16};
+
+// host threads for construction work over `items` independent items: up to
+// the cap (16 by default) and the hardware's threads, one below 4,096 items
+int host_threads(int64_t items)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    const unsigned cap = (unsigned)g_thread_cap.load(std::memory_order_relaxed);
+    int n = (int)std::max(1u, std::min(hw ? hw : 1u, cap));
+    return items < 4096 ? 1 : n;
+}
+
+// fn(t, begin, end) on nth contiguous ranges of [0, n), range t on thread t
+template <class F>
+void parallel_ranges(int64_t n, int nth, F &&fn)
+{
+    if (nth <= 1 || n < 2) {
+        fn(0, (int64_t)0, n);
+        return;
+    }
+    const int64_t chunk = (n + nth - 1) / nth;
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) {
+        const int64_t a = std::min<int64_t>(n, t * chunk), b = std::min<int64_t>(n, a + chunk);
+        th.emplace_back([&fn, t, a, b] { fn(t, a, b); });
+    }
+    fn(0, (int64_t)0, std::min<int64_t>(n, chunk));
+    for (auto &x : th) x.join();
+}
+
+// the result of std::sort(v, less) for a strict total order `less`: runs
+// sorted on nth threads, then merged pairwise in parallel
+template <class T, class L>
+void parallel_sort(std::vector<T> &v, int nth, L less)
+{
+    const int64_t n = (int64_t)v.size();
+    if (nth <= 1 || n < 16384) {
+        std::sort(v.begin(), v.end(), less);
+        return;
+    }
+    const int64_t chunk = (n + nth - 1) / nth;
+    std::vector<int64_t> cut;
+    for (int64_t a = 0; a < n; a += chunk) cut.push_back(a);
+    cut.push_back(n);
+    const int runs = (int)cut.size() - 1;
+    parallel_ranges(runs, runs, [&](int, int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) std::sort(v.begin() + cut[r], v.begin() + cut[r + 1], less);
+    });
+    std::vector<T> tmp((size_t)n);
+    while (cut.size() > 2) {
+        std::vector<int64_t> next;
+        const int pairs = ((int)cut.size() - 1 + 1) / 2;
+        parallel_ranges(pairs, pairs, [&](int, int64_t a, int64_t b) {
+            for (int64_t q = a; q < b; ++q) {
+                const int64_t x0 = cut[2 * q], x1 = cut[std::min<size_t>(2 * q + 1, cut.size() - 1)],
+                              x2 = cut[std::min<size_t>(2 * q + 2, cut.size() - 1)];
+                std::merge(v.begin() + x0, v.begin() + x1, v.begin() + x1, v.begin() + x2, tmp.begin() + x0, less);
+            }
+        });
+        for (size_t q = 0; q < cut.size(); q += 2) next.push_back(cut[q]);
+        if (next.back() != n) next.push_back(n);
+        cut.swap(next);
+        v.swap(tmp);
+    }
+}
+
 }  // namespace
+
+void set_host_thread_cap(int n) { g_thread_cap.store(std::max(1, std::min(n, 16)), std::memory_order_relaxed); }
 
 int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, const int64_t *row_ptr,
                const int32_t *col, const int32_t *coef, const int8_t *sense, const int64_t *rhs,
@@ -60,9 +128,7 @@ int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, cons
     // the lowest failing range reports, so the error is the first row in
     // order that fails the first pass, else the first with a repeated
     // variable.
-    unsigned hw = std::thread::hardware_concurrency();
-    int nth = (int)std::max(1u, std::min(hw ? hw : 1u, 16u));
-    if (n_rows < 4096) nth = 1;
+    const int nth = host_threads(n_rows);
     const int64_t chunk = (n_rows + nth - 1) / std::max(1, nth);
     std::vector<std::string> err((size_t)nth);
     std::vector<char> bad((size_t)nth, 0);
@@ -352,9 +418,7 @@ int build_problem(Problem &p, std::string &msg)
 {
     const Ilp &ilp = p.ilp;
     p.fixed.assign(ilp.n_vars, -1);
-    unsigned hw = std::thread::hardware_concurrency();
-    int nthreads = (int)std::max(1u, std::min(hw ? hw : 1u, 16u));
-    if (ilp.n_rows < 4096) nthreads = 1;
+    const int nthreads = host_threads(ilp.n_rows);
     std::vector<PassResult> res;
     // Presolve by rounds: compile every row against the fixings known at the
     // start of the round, then apply all forced values; repeat until a round
@@ -384,32 +448,64 @@ int build_problem(Problem &p, std::string &msg)
             }
         if (!any) break;
     }
-    // concatenate the per-thread stores (each already in ascending row order)
+    // concatenate the per-thread stores (each already in ascending row order),
+    // every store copied to its final place by its own thread
     BddSet &B = p.bdds;
     B = BddSet();
-    B.lay_off.assign(1, 0);
-    B.node_off.assign(1, 0);
-    for (auto &r : res) {
-        const BddSet &s = r.set;
-        int64_t lo = (int64_t)B.lay_var.size(), no = (int64_t)B.child.size();
-        B.row.insert(B.row.end(), s.row.begin(), s.row.end());
-        for (size_t j = 1; j < s.lay_off.size(); ++j) B.lay_off.push_back(lo + s.lay_off[j]);
-        for (size_t j = 1; j < s.node_off.size(); ++j) B.node_off.push_back(no + s.node_off[j]);
-        B.lay_var.insert(B.lay_var.end(), s.lay_var.begin(), s.lay_var.end());
-        B.lay_width.insert(B.lay_width.end(), s.lay_width.begin(), s.lay_width.end());
-        B.child.insert(B.child.end(), s.child.begin(), s.child.end());
+    const size_t nres = res.size();
+    std::vector<int64_t> bo(nres + 1, 0), lo(nres + 1, 0), no(nres + 1, 0);
+    for (size_t r = 0; r < nres; ++r) {
+        bo[r + 1] = bo[r] + (int64_t)res[r].set.row.size();
+        lo[r + 1] = lo[r] + (int64_t)res[r].set.lay_var.size();
+        no[r + 1] = no[r] + (int64_t)res[r].set.child.size();
     }
+    B.row.resize((size_t)bo[nres]);
+    B.lay_off.resize((size_t)bo[nres] + 1);
+    B.node_off.resize((size_t)bo[nres] + 1);
+    B.lay_var.resize((size_t)lo[nres]);
+    B.lay_width.resize((size_t)lo[nres]);
+    B.child.resize((size_t)no[nres]);
+    B.lay_off[0] = 0;
+    B.node_off[0] = 0;
+    parallel_ranges((int64_t)nres, (int)nres, [&](int, int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            BddSet &s = res[(size_t)r].set;
+            std::copy(s.row.begin(), s.row.end(), B.row.begin() + bo[r]);
+            for (size_t j = 1; j < s.lay_off.size(); ++j) B.lay_off[(size_t)bo[r] + j] = lo[r] + s.lay_off[j];
+            for (size_t j = 1; j < s.node_off.size(); ++j) B.node_off[(size_t)bo[r] + j] = no[r] + s.node_off[j];
+            std::copy(s.lay_var.begin(), s.lay_var.end(), B.lay_var.begin() + lo[r]);
+            std::copy(s.lay_width.begin(), s.lay_width.end(), B.lay_width.begin() + lo[r]);
+            std::copy(s.child.begin(), s.child.end(), B.child.begin() + no[r]);
+            s = BddSet();
+        }
+    });
     res.clear();
     const int64_t P = (int64_t)B.lay_var.size();
     p.deg.assign(ilp.n_vars, 0);
     p.pair_var.resize(P);
     p.pair_row.resize(P);
-    for (int64_t j = 0; j < B.n_bdds(); ++j)
-        for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) {
-            p.pair_var[q] = B.lay_var[q];
-            p.pair_row[q] = B.row[j];
-            p.deg[B.lay_var[q]]++;
-        }
+    parallel_ranges(B.n_bdds(), host_threads(B.n_bdds()), [&](int, int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j)
+            for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) {
+                p.pair_var[q] = B.lay_var[q];
+                p.pair_row[q] = B.row[j];
+            }
+    });
+    {
+        // |J_i|: each thread counts the pairs of its own variable range
+        const int dt = host_threads(P);
+        const int64_t V = ilp.n_vars, chunk = (V + dt - 1) / dt;
+        parallel_ranges(dt, dt, [&](int t, int64_t, int64_t) {
+            const int64_t v0 = std::min<int64_t>(V, t * chunk), v1 = std::min<int64_t>(V, v0 + chunk);
+            std::vector<int32_t> cnt((size_t)(v1 - v0) + 1, 0);   // last entry absorbs other ranges
+            const uint64_t span = (uint64_t)(v1 - v0);
+            for (int64_t q = 0; q < P; ++q) {
+                const uint64_t d = (uint64_t)((int64_t)B.lay_var[q] - v0);
+                cnt[d < span ? d : span]++;
+            }
+            std::copy(cnt.begin(), cnt.end() - 1, p.deg.begin() + v0);
+        });
+    }
     p.lb_offset = 0.0;
     p.n_fixed = p.n_free = 0;
     p.inst_offset.assign((size_t)ilp.n_inst(), 0.0);
@@ -455,13 +551,16 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     const int64_t V = p.ilp.n_vars;
     auto k_of = [&](int64_t j) { return (int)(B.lay_off[j + 1] - B.lay_off[j]); };
     auto n_of = [&](int64_t j) { return (int64_t)(B.node_off[j + 1] - B.node_off[j]); };
+    const int nth = host_threads(nb);
     std::vector<uint64_t> hash(nb);
-    for (int64_t j = 0; j < nb; ++j) {
-        uint64_t h = mix64(0, (uint64_t)k_of(j));
-        for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) h = mix64(h, (uint64_t)B.lay_width[q]);
-        for (int64_t q = B.node_off[j]; q < B.node_off[j + 1]; ++q) h = mix64(h, B.child[q]);
-        hash[j] = h;
-    }
+    parallel_ranges(nb, nth, [&](int, int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j) {
+            uint64_t h = mix64(0, (uint64_t)k_of(j));
+            for (int64_t q = B.lay_off[j]; q < B.lay_off[j + 1]; ++q) h = mix64(h, (uint64_t)B.lay_width[q]);
+            for (int64_t q = B.node_off[j]; q < B.node_off[j + 1]; ++q) h = mix64(h, B.child[q]);
+            hash[j] = h;
+        }
+    });
     // instance of every BDD (tiles never mix instances of a batch)
     const Ilp &ilp = p.ilp;
     const bool batch = ilp.n_inst() > 1;
@@ -482,7 +581,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     };
     std::vector<int64_t> order(nb);
     for (int64_t j = 0; j < nb; ++j) order[j] = j;
-    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    parallel_sort(order, nth, [&](int64_t x, int64_t y) {
         if (inst_of(x) != inst_of(y)) return inst_of(x) < inst_of(y);
         if (k_of(x) != k_of(y)) return k_of(x) < k_of(y);
         if (n_of(x) != n_of(y)) return n_of(x) < n_of(y);
@@ -895,52 +994,89 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     const int64_t P = (int64_t)B.lay_var.size();
     o.pair_var.assign(slots, (int32_t)V);
     o.slot_of_pair.assign(P, -1);
-    for (size_t t = 0; t < plans.size(); ++t) {
-        const TilePlan &tp = plans[t];
-        for (int l = 0; l < kLanes; ++l) {
-            int64_t j = tp.lanes[l];
-            if (j < 0) continue;
-            for (int h = 0; h < k_of(j); ++h) {
-                int64_t slot = (int64_t)o.tiles[t].pair_base + (int64_t)h * kLanes + l;
-                int64_t pq = B.lay_off[j] + h;
-                o.pair_var[slot] = B.lay_var[pq];
-                o.slot_of_pair[pq] = slot;
+    const int64_t n_plans = (int64_t)plans.size();
+    parallel_ranges(n_plans, host_threads(n_plans), [&](int, int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            const TilePlan &tp = plans[t];
+            for (int l = 0; l < kLanes; ++l) {
+                int64_t j = tp.lanes[l];
+                if (j < 0) continue;
+                for (int h = 0; h < k_of(j); ++h) {
+                    int64_t slot = (int64_t)o.tiles[t].pair_base + (int64_t)h * kLanes + l;
+                    int64_t pq = B.lay_off[j] + h;
+                    o.pair_var[slot] = B.lay_var[pq];
+                    o.slot_of_pair[pq] = slot;
+                }
             }
         }
-    }
-    // variable -> slots in ascending row order (pairs are already in row order)
+    });
+    // variable -> slots in ascending row order (pairs are already in row
+    // order): each thread owns a variable range and scans all pairs in order
     o.vptr.assign(V + 1, 0);
     for (int64_t i = 0; i < V; ++i) o.vptr[i + 1] = o.vptr[i] + p.deg[i];
     o.vslot.assign(P, 0);
-    std::vector<int32_t> fill(o.vptr.begin(), o.vptr.end() - 1);
-    for (int64_t q = 0; q < P; ++q) o.vslot[fill[B.lay_var[q]]++] = (int32_t)o.slot_of_pair[q];
+    {
+        const int vt = host_threads(P);
+        const int64_t chunk = (V + vt - 1) / vt;
+        parallel_ranges(vt, vt, [&](int t, int64_t, int64_t) {
+            const int64_t v0 = std::min<int64_t>(V, t * chunk), v1 = std::min<int64_t>(V, v0 + chunk);
+            const uint64_t span = (uint64_t)(v1 - v0);
+            // write positions of the range's variables, plus one entry whose
+            // writes (pairs of other ranges) land in a private dummy slot;
+            // no branch on the variable
+            std::vector<int64_t> fill((size_t)span + 1);
+            for (int64_t v = v0; v < v1; ++v) fill[(size_t)(v - v0)] = o.vptr[v];
+            int32_t dummy[1];
+            for (int64_t q = 0; q < P; ++q) {
+                const uint64_t d = (uint64_t)((int64_t)B.lay_var[q] - v0);
+                const bool mine = d < span;
+                int64_t &f = fill[mine ? d : span];
+                int32_t *dst = mine ? o.vslot.data() + f : dummy;
+                *dst = (int32_t)o.slot_of_pair[q];
+                f += mine;
+            }
+        });
+    }
     // source of every slot's averaged term
     std::vector<int32_t> tile_of_slot((size_t)slots);
-    for (size_t t = 0; t < o.tiles.size(); ++t)
-        for (int64_t s = o.tiles[t].pair_base; s < (int64_t)o.tiles[t].pair_base + (int64_t)o.tiles[t].K * kLanes; ++s)
-            tile_of_slot[s] = (int32_t)t;
+    const int64_t n_tiles = (int64_t)o.tiles.size();
+    parallel_ranges(n_tiles, host_threads(n_tiles), [&](int, int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t)
+            for (int64_t s = o.tiles[t].pair_base; s < (int64_t)o.tiles[t].pair_base + (int64_t)o.tiles[t].K * kLanes;
+                 ++s)
+                tile_of_slot[s] = (int32_t)t;
+    });
     std::vector<uint16_t> code((size_t)slots, kCodeSelf);
     // a wide tile's BDDs run in different blocks, so no in-tile partner there
     std::vector<char> wide_tile(o.tiles.size(), 0);
     for (int32_t t : lists[LIST_WIDE]) wide_tile[t] = 1;
     o.gvars.clear();
-    for (int64_t i = 0; i < V; ++i) {
-        const int32_t a = o.vptr[i], b = o.vptr[i + 1];
-        if (a == b) continue;
-        bool local = fast && b - a <= 2;
-        if (local) {
-            const int32_t t = tile_of_slot[o.vslot[a]];
-            local = o.tiles[t].K * kLanes < (int)kCodeSelf && tile_of_slot[o.vslot[b - 1]] == t &&
-                    (b - a == 1 || !wide_tile[t]);
-        }
-        if (!local) {
-            o.gvars.push_back((int32_t)i);
-            for (int32_t q = a; q < b; ++q) code[o.vslot[q]] = kCodeGlobal;
-        } else if (b - a == 2) {
-            const int32_t base = (int32_t)o.tiles[tile_of_slot[o.vslot[a]]].pair_base;
-            code[o.vslot[a]] = (uint16_t)(o.vslot[a + 1] - base);
-            code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
-        }
+    {
+        // each thread codes a variable range (its slots are its own) and
+        // lists its kernel-averaged variables; the lists join in order
+        const int ct = host_threads(V);
+        std::vector<std::vector<int32_t>> gv((size_t)ct);
+        parallel_ranges(V, ct, [&](int t, int64_t v0, int64_t v1) {
+            for (int64_t i = v0; i < v1; ++i) {
+                const int32_t a = o.vptr[i], b = o.vptr[i + 1];
+                if (a == b) continue;
+                bool local = fast && b - a <= 2;
+                if (local) {
+                    const int32_t t2 = tile_of_slot[o.vslot[a]];
+                    local = o.tiles[t2].K * kLanes < (int)kCodeSelf && tile_of_slot[o.vslot[b - 1]] == t2 &&
+                            (b - a == 1 || !wide_tile[t2]);
+                }
+                if (!local) {
+                    gv[(size_t)t].push_back((int32_t)i);
+                    for (int32_t q = a; q < b; ++q) code[o.vslot[q]] = kCodeGlobal;
+                } else if (b - a == 2) {
+                    const int32_t base = (int32_t)o.tiles[tile_of_slot[o.vslot[a]]].pair_base;
+                    code[o.vslot[a]] = (uint16_t)(o.vslot[a + 1] - base);
+                    code[o.vslot[a + 1]] = (uint16_t)(o.vslot[a] - base);
+                }
+            }
+        });
+        for (auto &g : gv) o.gvars.insert(o.gvars.end(), g.begin(), g.end());
     }
     // bucket the kernel-averaged variables by |J_i|
     {
@@ -977,11 +1113,21 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
     // tiles with the same code pattern share one copy of it
     o.code.clear();
     std::unordered_multimap<uint64_t, uint32_t> code_seen;
-    for (TileDesc &d : o.tiles) {
+    std::vector<uint64_t> code_hash((size_t)n_tiles);
+    parallel_ranges(n_tiles, host_threads(n_tiles), [&](int, int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            const size_t n = (size_t)o.tiles[t].K * kLanes;
+            const uint16_t *blk = code.data() + o.tiles[t].pair_base;
+            uint64_t h = mix64(0, n);
+            for (size_t q = 0; q < n; ++q) h = mix64(h, blk[q]);
+            code_hash[t] = h;
+        }
+    });
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        TileDesc &d = o.tiles[t];
         const size_t n = (size_t)d.K * kLanes;
         const uint16_t *blk = code.data() + d.pair_base;
-        uint64_t h = mix64(0, n);
-        for (size_t q = 0; q < n; ++q) h = mix64(h, blk[q]);
+        const uint64_t h = code_hash[t];
         int64_t found = -1;
         auto range = code_seen.equal_range(h);
         for (auto it = range.first; it != range.second; ++it)

@@ -87,6 +87,10 @@ int set_instances(Ilp &ilp, int64_t n_inst, const int64_t *inst_vars, const int6
 // Presolve + compile every remaining row.  ST_OK / ST_INFEASIBLE / ST_INVALID.
 int build_problem(Problem &p, std::string &msg);
 
+// Host threads of ingestion, presolve, compilation and packing: at most n
+// (clamped to 1..16, default 16), process-wide.  Results do not depend on it.
+void set_host_thread_cap(int n);
+
 // Pack the compiled BDDs into tiles.  lds_elem_budget: per-lane elements a tile
 // may keep in LDS (0 disables LDS); lds_max_nodes > 0 additionally caps the
 // nodes per lane of LDS tiles; fast selects the register-resident path for the

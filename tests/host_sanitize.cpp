@@ -77,6 +77,34 @@ Csr random_ilp(Rng &g, int64_t n, int64_t rows, int max_len, int max_coef)
     return c;
 }
 
+// <= rows of 2..6 variables with coefficients in [-3, 3] and slack 3..5 at a
+// hidden point: flipping one variable moves a row by at most 3, so no row
+// forces a variable and presolve keeps every row
+Csr loose_ilp(Rng &g, int64_t n, int64_t rows)
+{
+    Csr c;
+    c.n_vars = n;
+    std::vector<int> x(n);
+    for (auto &v : x) v = (int)g.range(0, 1);
+    for (int64_t i = 0; i < n; ++i) c.cost.push_back((double)g.range(-40, 40) / 8.0);
+    for (int64_t r = 0; r < rows; ++r) {
+        const int k = (int)g.range(2, 6);
+        std::vector<int32_t> vs, a;
+        while ((int)vs.size() < k) {
+            const int32_t v = (int32_t)g.range(0, n - 1);
+            bool dup = false;
+            for (int32_t u : vs) dup |= u == v;
+            if (dup) continue;
+            vs.push_back(v);
+            a.push_back((int32_t)(g.range(1, 3) * (g.range(0, 1) ? 1 : -1)));
+        }
+        int64_t lhs = 0;
+        for (int q = 0; q < k; ++q) lhs += (int64_t)a[q] * x[vs[q]];
+        c.row(vs, a, -1, lhs + g.range(3, 5));
+    }
+    return c;
+}
+
 int fails = 0;
 
 void check(bool ok, const char *what, int64_t seed)
@@ -130,6 +158,64 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
         }
         check((int64_t)pk.inst_tile.size() == p.ilp.n_inst() + 1, "instance tile ranges", seed);
     }
+}
+
+template <class T>
+bool same_vec(const std::vector<T> &a, const std::vector<T> &b)
+{
+    return a.size() == b.size() && (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(T)) == 0);
+}
+
+// ingestion, presolve, compilation and packing give the same tables on one
+// host thread and on several (every threaded phase is reached: more than
+// 16,384 BDDs for the parallel sort, more than 4,096 variables, rows and tiles)
+void run_threads(const Csr &c, int64_t seed)
+{
+    Problem p[2];
+    Packed pk[2];
+    for (int k = 0; k < 2; ++k) {
+        set_host_thread_cap(k == 0 ? 1 : 8);
+        std::string msg;
+        int rc = ingest_ilp(p[k].ilp, c.n_vars, c.cost.data(), c.n_rows(), c.row_ptr.data(), c.col.data(),
+                            c.coef.data(), c.sense.data(), c.rhs.data(), msg);
+        if (rc == ST_OK) rc = build_problem(p[k], msg);
+        if (rc == ST_OK) rc = pack_problem(p[k], 128, 0, true, 32.0 * (1 << 20), 2048, 16384, pk[k], msg);
+        check(rc == ST_OK, "threads: construction", seed);
+        if (rc != ST_OK) {
+            std::fprintf(stderr, "  %s\n", msg.c_str());
+            set_host_thread_cap(16);
+            return;
+        }
+    }
+    set_host_thread_cap(16);
+    const Ilp &a = p[0].ilp, &b = p[1].ilp;
+    check(same_vec(a.row_ptr, b.row_ptr) && same_vec(a.col, b.col) && same_vec(a.coef, b.coef), "threads: ingest",
+          seed);
+    const BddSet &x = p[0].bdds, &y = p[1].bdds;
+    check(same_vec(x.row, y.row) && same_vec(x.lay_off, y.lay_off) && same_vec(x.lay_var, y.lay_var) &&
+              same_vec(x.lay_width, y.lay_width) && same_vec(x.node_off, y.node_off) && same_vec(x.child, y.child),
+          "threads: BDDs", seed);
+    check(same_vec(p[0].fixed, p[1].fixed) && same_vec(p[0].deg, p[1].deg) && same_vec(p[0].pair_var, p[1].pair_var) &&
+              same_vec(p[0].pair_row, p[1].pair_row),
+          "threads: pairs", seed);
+    const Packed &u = pk[0], &v = pk[1];
+    check(u.tiles.size() == v.tiles.size() &&
+              (u.tiles.empty() || std::memcmp(u.tiles.data(), v.tiles.data(), u.tiles.size() * sizeof(TileDesc)) == 0),
+          "threads: tiles", seed);
+    check(same_vec(u.lists, v.lists) && same_vec(u.list_off, v.list_off) && same_vec(u.layers, v.layers) &&
+              same_vec(u.child, v.child),
+          "threads: lists, layers, node words", seed);
+    check(same_vec(u.pair_var, v.pair_var) && same_vec(u.slot_of_pair, v.slot_of_pair) && same_vec(u.vptr, v.vptr) &&
+              same_vec(u.vslot, v.vslot),
+          "threads: slots", seed);
+    check(same_vec(u.code, v.code) && same_vec(u.gvars, v.gvars) && same_vec(u.gslot, v.gslot) &&
+              u.gbuckets.size() == v.gbuckets.size() &&
+              (u.gbuckets.empty() ||
+               std::memcmp(u.gbuckets.data(), v.gbuckets.data(), u.gbuckets.size() * sizeof(AvgBucket)) == 0) &&
+              u.gblocks == v.gblocks && u.n_slots == v.n_slots,
+          "threads: averaging tables", seed);
+    check(x.n_bdds() > 16384 && p[0].ilp.n_vars > 4096 && (int64_t)u.tiles.size() > 4096 / 64,
+          "threads: the case reaches every threaded phase", seed);
 }
 
 // host model of the device copy kernel (same semantics per segment)
@@ -402,6 +488,11 @@ int main()
         // enough rows for the threaded ingestion and compilation
         Rng h{4242};
         run(random_ilp(h, 3000, 6000, 6, 3), {}, {}, 4242);
+    }
+    {
+        // one host thread against several
+        Rng h{5151};
+        run_threads(loose_ilp(h, 9000, 20000), 5151);
     }
     {
         // large enough for the threaded merge
