@@ -94,7 +94,12 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(ilp, n_iter):
+def cpu_baseline(ilp, n_iter, gpu=None):
+    """The FP64 reference timed on one host thread; with `gpu` (multipliers,
+    min-marginal differences and bounds of the GPU after the same iterations
+    from the same start) also the GPU's error against it."""
+    import numpy as np
+
     import oracle
 
     ref = oracle.Oracle(ilp)
@@ -102,9 +107,24 @@ def cpu_baseline(ilp, n_iter):
     t = time.perf_counter()
     ref.run_dual(n_iter)
     dt = time.perf_counter() - t
-    return dict(value=n_iter / dt, unit="dual iters/s", cores=1, kind="oracle",
+    base = dict(value=n_iter / dt, unit="dual iters/s", cores=1, kind="oracle",
                 sample=f"{n_iter} Alg. 1 iterations of the same instance, FP64, one thread "
                        f"({dt:.1f} s; BDD construction not timed)")
+    if gpu is None:
+        return base, None
+    lam, mm, lbf, lbc = gpu
+    rl, rm, _ = ref.get()
+    sc = max(1e-12, float(np.mean(np.abs(ilp.costs))))
+
+    def scaled(g, r):   # |d| / max(|ref|, mean|c|), the parity tests' measure
+        return float(np.max(np.abs(g - r) / np.maximum(np.abs(r), sc), initial=0.0))
+
+    rc, _ = ref.lb_cert()
+    err = {"iterations": n_iter, "scale_mean_abs_cost": sc,
+           "lambda_max_scaled": scaled(lam, rl), "min_marginal_max_scaled": scaled(mm, rm),
+           "lb_free_rel": abs(lbf - ref.lb_free()) / max(1.0, abs(ref.lb_free())),
+           "lb_cert_rel": abs(lbc - rc) / max(1.0, abs(rc))}
+    return base, err
 
 
 def serve(a, B, I, torch):
@@ -419,12 +439,20 @@ def main():
         "result": {"lb_free": lf, "lb_cert": lc, "max_residual": res, "ub": r["ub"] if r["rc"] == 0 else None,
                    "rounding_rc": r["rc"], "rounding_rounds": r["rounds"]},
     }
+    gpu_state = None
+    if not a.no_cpu_baseline:
+        # the GPU after the reference's iterations, for the error report (untimed)
+        s.reset()
+        s.run_dual(a.cpu_iters)
+        lam_g, mm_g, _ = s.get_state()
+        lbf_g, lbc_g, _ = s.lower_bound()
+        gpu_state = (lam_g.astype("float64"), mm_g.astype("float64"), lbf_g, lbc_g)
     if a.serve > 0:
         s = None
         torch.cuda.empty_cache()
         out["batched"] = serve(a, B, I, torch)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ilp, a.cpu_iters)
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(ilp, a.cpu_iters, gpu_state)
     print(json.dumps(out), flush=True)
 
 
