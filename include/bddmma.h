@@ -99,7 +99,11 @@ typedef struct {
                               0: lambda_i^j + omega M-bar_ij (the algorithm's last loop);
                               1: lambda_i^j + (omega/|J_i|) sum_k M-bar_ik (the text's
                               "min-marginal averaging step").  Both sum to c_i over J_i.  0 */
-    int32_t  reserved[2];  /* must be zero */
+    int32_t  wide_min_width; /* BDDs outside the register classes whose widest layer has at
+                              least this many nodes are swept one BDD per wave, the lanes
+                              spread over each layer's nodes, when their distances fit in
+                              LDS; narrower ones run one BDD per lane.  0 = never.  4 */
+    int32_t  reserved[1];  /* must be zero */
 } bddmma_options;
 
 typedef struct {

@@ -984,6 +984,7 @@ int bddmma_options_default(bddmma_options *o)
     o->graph_sweeps = 64;
     o->class_merge_kib = 32768;
     o->small_tiles = 2048;
+    o->wide_min_width = kWideMinWidth;
     return BDDMMA_OK;
 }
 
@@ -1009,7 +1010,9 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.small_tiles < 0) return fail(BDDMMA_ERR_INVALID_ARG, "small_tiles must be >= 0");
     if (o.serial_mma != 0 && o.serial_mma != 1) return fail(BDDMMA_ERR_INVALID_ARG, "serial_mma must be 0 or 1");
     if (o.termination != 0 && o.termination != 1) return fail(BDDMMA_ERR_INVALID_ARG, "termination must be 0 or 1");
-    if (o.reserved[0] != 0 || o.reserved[1] != 0)
+    if (o.wide_min_width < 0 || o.wide_min_width > 65535)
+        return fail(BDDMMA_ERR_INVALID_ARG, "wide_min_width must lie in [0, 65535]");
+    if (o.reserved[0] != 0)
         return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
@@ -1057,7 +1060,8 @@ int pack_loaded(bddmma_solver *s)
     std::string msg;
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
     int rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem, s->pk, msg);
+                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem,
+                          s->opt.wide_min_width, s->pk, msg);
     if (rc != ST_OK) {
         s->prob = Problem();
         s->pk = Packed();
@@ -1603,6 +1607,7 @@ int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *co
                         {&bddmma_options::small_tiles, {2048, 0, 1 << 30}},
                         {&bddmma_options::class_merge_kib, {32768, 0, 4096, 262144}},
                         {&bddmma_options::sp_in_lds_max_nodes, {0, -1}},
+                        {&bddmma_options::wide_min_width, {kWideMinWidth, 0, 2, 16, 64}},
                         {&bddmma_options::graph_sweeps, {64, 0}}};
     bddmma_options cur = o;
     double cur_us = INFINITY;

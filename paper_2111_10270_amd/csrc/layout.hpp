@@ -88,12 +88,13 @@ enum TileList {
     kNumLists = LIST_WIDE + 1
 };
 
-// Wide tiles (layers of at least kWideMinWidth nodes) are swept one BDD per
+// Wide tiles (a layer of at least wide_min_width nodes, kWideMinWidth by
+// default) are swept one BDD per
 // wave with the lanes spread over a layer's nodes; the BDD's distances to
 // root and to top, multipliers and averaged terms sit in LDS (2 * nodes + 2 * K
 // elements).  Mixed wide tiles carry a BDD-major copy of their node words at
 // fast_base (lane l's node n at fast_base + l * nodes + n).
-constexpr int kWideMinWidth = 16;
+constexpr int kWideMinWidth = 4;
 inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + ki; }
 inline int mix_list(int ki) { return LIST_MIX0 + ki; }
 

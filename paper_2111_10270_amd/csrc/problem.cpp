@@ -544,7 +544,7 @@ struct TilePlan {
 }  // namespace
 
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, int wide_lds_elems, Packed &o, std::string &msg)
+                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, Packed &o, std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -669,7 +669,7 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
         int64_t nodes = 0;
         for (int w : tp.width) nodes += w;
         if (K > 65535 || nodes > 65535) { msg = "a BDD has more than 65535 layers or nodes"; return ST_INVALID; }
-        tp.wide = fast && tp.wi < 0 && maxw >= kWideMinWidth && wide_lds_elems > 0 &&
+        tp.wide = fast && tp.wi < 0 && wide_min_width > 0 && maxw >= wide_min_width && wide_lds_elems > 0 &&
                   2 * nodes + 2 * (int64_t)K <= (int64_t)wide_lds_elems;
     }
     // Fewer launches: inside a width class, the tiles of a layer class join

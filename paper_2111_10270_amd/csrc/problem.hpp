@@ -97,12 +97,13 @@ void set_host_thread_cap(int n);
 // tiles it can take; merge_bytes is the padding traffic per sweep a layer
 // class may add to join a larger class (0: no merging); problems of at most
 // small_tiles tiles sweep their width-2 tiles of one topology as mixed tiles
-// (one launch per layer class); wide_lds_elems > 0 lets tiles with layers of
-// >= kWideMinWidth nodes whose per-BDD LDS need fits use the wide kernel.
+// (one launch per layer class); tiles outside the register classes with a
+// layer of >= wide_min_width nodes (> 0) whose per-BDD LDS need fits in
+// wide_lds_elems elements use the wide kernel (one wave per BDD).
 // ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, int wide_lds_elems, Packed &out, std::string &msg);
+                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, Packed &out, std::string &msg);
 
 // Batch of independent instances assembled from their own single-instance
 // results: the union problem is block-diagonal and every instance keeps the

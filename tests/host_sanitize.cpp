@@ -137,7 +137,7 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
         const int lds = variant == 3 ? 0 : 128;
         const double merge = variant == 1 ? 0.0 : 32.0 * (1 << 20);
         const int64_t small = variant == 2 ? 0 : 2048;
-        rc = pack_problem(p, lds, 0, fast, merge, small, variant == 0 ? 0 : 16384, pk, msg);
+        rc = pack_problem(p, lds, 0, fast, merge, small, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, pk, msg);
         check(rc == ST_OK, "pack", seed);
         if (rc != ST_OK) {
             std::fprintf(stderr, "  %s\n", msg.c_str());
@@ -179,7 +179,7 @@ void run_threads(const Csr &c, int64_t seed)
         int rc = ingest_ilp(p[k].ilp, c.n_vars, c.cost.data(), c.n_rows(), c.row_ptr.data(), c.col.data(),
                             c.coef.data(), c.sense.data(), c.rhs.data(), msg);
         if (rc == ST_OK) rc = build_problem(p[k], msg);
-        if (rc == ST_OK) rc = pack_problem(p[k], 128, 0, true, 32.0 * (1 << 20), 2048, 16384, pk[k], msg);
+        if (rc == ST_OK) rc = pack_problem(p[k], 128, 0, true, 32.0 * (1 << 20), 2048, 16384, 16, pk[k], msg);
         check(rc == ST_OK, "threads: construction", seed);
         if (rc != ST_OK) {
             std::fprintf(stderr, "  %s\n", msg.c_str());
@@ -363,7 +363,7 @@ void run_merge(const std::vector<Csr> &cs, int variant, int64_t seed)
         if (rc == ST_OK) rc = build_problem(ps[k], msg);
         if (rc == ST_OK)
             rc = pack_problem(ps[k], variant == 3 ? 0 : 128, 0, variant != 4, variant == 1 ? 0.0 : 32.0 * (1 << 20),
-                              variant == 2 ? 0 : 2048, variant == 0 ? 0 : 16384, pks[k], msg);
+                              variant == 2 ? 0 : 2048, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, pks[k], msg);
         check(rc == ST_OK, "merge: instance alone", seed);
         if (rc != ST_OK) return;
         parts.push_back(Part{&ps[k], &pks[k]});

@@ -28,18 +28,38 @@ def test_default_options():
     assert o.lb_every == 1 and o.rel_tol == 0.0 and o.tau < 0
     assert (o.fast_path, o.perturb_scale, o.sp_in_lds_max_nodes, o.graph_sweeps) == (1, 0, 0, 64)
     assert o.class_merge_kib == 32768 and o.small_tiles == 2048 and o.serial_mma == 0 and o.termination == 0
+    assert o.wide_min_width == 4 and o.reserved[0] == 0
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=1.5), dict(precision=16), dict(lb_every=0),
                                  dict(alpha=0.5), dict(delta0=0.0), dict(max_rounds=-1),
                                  dict(sp_in_lds_max_nodes=-2), dict(fast_path=2), dict(perturb_scale=2),
                                  dict(graph_sweeps=-1), dict(class_merge_kib=-1), dict(small_tiles=-1),
-                                 dict(serial_mma=2), dict(termination=2)])
+                                 dict(serial_mma=2), dict(termination=2), dict(wide_min_width=-1),
+                                 dict(wide_min_width=65536)])
 def test_invalid_options(bad):
     ilp = I.random_ilp(5, 3, seed=1)
     with pytest.raises(B.BddmmaError) as e:
         B.Solver(ilp, **bad)
     assert e.value.code == B.INVALID_ARG
+
+
+def test_wide_kernel_threshold_moves_tiles():
+    """wide_min_width decides which tiles outside the register classes run one
+    BDD per wave: 0 none, and a lower threshold takes at least the tiles a
+    higher one does"""
+    rng = np.random.default_rng(23)
+    n = 300
+    rows = []
+    for _ in range(80):
+        k = int(rng.integers(8, 15))
+        vs = rng.choice(n, size=k, replace=False)
+        a = rng.integers(1, 21, size=k)
+        rows.append((vs, a, -1, int(a.sum() // 2)))
+    ilp = I.from_rows(n, rng.standard_normal(n), rows)
+    counts = {w: B.Solver(ilp, wide_min_width=w).stats.n_wide_tiles for w in (0, 4, 16, 64, 65535)}
+    assert counts[0] == 0 and counts[65535] == 0
+    assert counts[4] >= counts[16] >= counts[64] and counts[16] > 0
 
 
 def _raw(ilp, **kw):

@@ -11,7 +11,20 @@ from paper_2111_10270_amd import binding as B
 from paper_2111_10270_amd import instances as I
 
 pytestmark = pytest.mark.gpu
-KEYS = ("fast_path", "small_tiles", "class_merge_kib", "sp_in_lds_max_nodes", "graph_sweeps")
+KEYS = ("fast_path", "small_tiles", "class_merge_kib", "sp_in_lds_max_nodes", "wide_min_width", "graph_sweeps")
+
+
+def knapsack_rows(seed=23, n=300, rows=80):
+    """rows with coefficients up to 20: layers of tens of nodes, the wide
+    kernel's candidates"""
+    rng = np.random.default_rng(seed)
+    rs = []
+    for _ in range(rows):
+        k = int(rng.integers(8, 15))
+        vs = rng.choice(n, size=k, replace=False)
+        a = rng.integers(1, 21, size=k)
+        rs.append((vs, a, -1, int(a.sum() // 2)))
+    return I.from_rows(n, rng.standard_normal(n), rs, name="knapsack_rows")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -21,10 +34,11 @@ def _cuda():
     assert torch.cuda.get_device_properties(0).gcnArchName.startswith("gfx950")
 
 
-@pytest.mark.parametrize("k", range(3))
+@pytest.mark.parametrize("k", range(4))
 def test_autotuned_options_keep_the_trajectory(k):
     ilp = [I.graph_matching(n_left=150, n_right=150, k=10, n_pairs=150, seed=3),
-           I.cell_tracking(frames=6, dets=80, seed=4), I.random_ilp(80, 60, max_row_len=8, seed=5)][k]
+           I.cell_tracking(frames=6, dets=80, seed=4), I.random_ilp(80, 60, max_row_len=8, seed=5),
+           knapsack_rows()][k]
     print("autotune", ilp.name, flush=True)
     best, us = B.autotune(ilp, sweeps=16, precision=64)
     assert us > 0 and np.isfinite(us)

@@ -220,15 +220,20 @@ def wide_ilp(seed=23):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-def test_wide_rows_node_parallel_kernel(prec):
+@pytest.mark.parametrize("wmin", [16, 4, 0])
+def test_wide_rows_node_parallel_kernel(prec, wmin):
     """BDDs with wide layers on the wave-per-BDD kernel (LDS scatter minima),
     sweep by sweep against the reference, and the rounding's fixed-multiplier
-    sweeps"""
+    sweeps; the width threshold of that kernel (wide_min_width, 0 = lane per
+    BDD throughout) moves tiles between schedules, never the results"""
     ilp = wide_ilp()
     if O.Oracle(ilp).status != O.OK:
         pytest.skip("generated instance infeasible")
-    s, o, _ = lockstep(ilp, 6, precision=prec)
-    assert s.stats.n_wide_tiles >= 2 and s.stats.max_width >= 16
+    s, o, _ = lockstep(ilp, 6, precision=prec, wide_min_width=wmin)
+    if wmin == 0:
+        assert s.stats.n_wide_tiles == 0
+    else:
+        assert s.stats.n_wide_tiles >= 2 and s.stats.max_width >= 16
     if prec == 64:
         assert np.array_equal(s.min_marginals(), o.full_mm())
 
