@@ -1060,7 +1060,7 @@ int pack_loaded(bddmma_solver *s)
     std::string msg;
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
     int rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
-                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / s->elem,
+                          1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / (s->elem + 2),
                           s->opt.wide_min_width, s->pk, msg);
     if (rc != ST_OK) {
         s->prob = Problem();

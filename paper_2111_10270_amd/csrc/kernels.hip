@@ -229,26 +229,12 @@ __device__ __forceinline__ T wave_min(T v)
     return v;
 }
 
-__device__ __forceinline__ void lds_min(float *p, float v)
+// *p = min(*p, v) in LDS with the native float / double min (ds_min_f32,
+// ds_min_f64): exact, so the result does not depend on the order of the lanes
+template <typename T>
+__device__ __forceinline__ void lds_min(T *p, T v)
 {
-    unsigned int *ip = reinterpret_cast<unsigned int *>(p);
-    unsigned int old = *ip;
-    while (v < __uint_as_float(old)) {
-        const unsigned int seen = atomicCAS(ip, old, __float_as_uint(v));
-        if (seen == old) break;
-        old = seen;
-    }
-}
-
-__device__ __forceinline__ void lds_min(double *p, double v)
-{
-    unsigned long long *ip = reinterpret_cast<unsigned long long *>(p);
-    unsigned long long old = *ip;
-    while (v < __longlong_as_double((long long)old)) {
-        const unsigned long long seen = atomicCAS(ip, old, (unsigned long long)__double_as_longlong(v));
-        if (seen == old) break;
-        old = seen;
-    }
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <typename T, int DIR, bool UPD>
@@ -277,10 +263,14 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
     T *const Bk = F + NN;                                // [NN] SP(v, top)
     T *const lamS = Bk + NN;                             // [K]
     T *const avS = lamS + K;                             // [K]
+    uint32_t *const Wd = reinterpret_cast<uint32_t *>(avS + K);   // [NN] node words
     auto head = [&](uint32_t c, uint32_t noffn) -> T {
         return c == kTop ? T(0) : (c == kBot ? INF : Bk[noffn + c]);
     };
 
+    // the BDD's node words are staged in LDS once, so no layer waits on a
+    // global load
+    for (int n = t; n < NN; n += kLanes) Wd[n] = words[n];
     for (int h = t; h < K; h += kLanes) {
         const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
         lamS[h] = lam[s];
@@ -299,7 +289,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
             const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
             const T l = lamS[h];
             for (uint32_t q = t; q < W; q += kLanes) {
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + l);
             }
             __syncthreads();
@@ -314,7 +304,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
             T m0 = INF, m1 = INF;
             for (uint32_t q = t; q < W; q += kLanes) {
                 const T f = F[noff + q];
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
                 if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
                 if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
@@ -335,7 +325,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
             __syncthreads();
             for (uint32_t q = t; q < W; q += kLanes) {
                 const T f = F[noff + q];
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
                 if (lo != kBot) {
                     if (lo == kTop) top = tmin(top, f);
@@ -362,7 +352,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
             __syncthreads();
             for (uint32_t q = t; q < W; q += kLanes) {
                 const T f = F[noff + q];
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
                 if (lo < kTop) lds_min(&F[noffn + lo], f);
                 if (hi < kTop) lds_min(&F[noffn + hi], f + l);
@@ -376,7 +366,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
             T m0 = INF, m1 = INF;
             for (uint32_t q = t; q < W; q += kLanes) {
                 const T f = F[noff + q];
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
                 if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
                 if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
@@ -394,7 +384,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
                 }
             }
             for (uint32_t q = t; q < W; q += kLanes) {
-                const uint32_t c = words[noff + q];
+                const uint32_t c = Wd[noff + q];
                 Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + lu);
             }
             __syncthreads();
@@ -951,7 +941,9 @@ void launch_wide(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w
     const int64_t n = p.list_off[LIST_WIDE + 1] - p.list_off[LIST_WIDE];
     if (n == 0) return;
     const int32_t *list = p.lists + p.list_off[LIST_WIDE];
-    const size_t lds = (size_t)p.wide_elems * sizeof(T);
+    // distances, multipliers and terms (wide_elems values), then the node
+    // words (4 B per node, at most wide_elems / 2 nodes)
+    const size_t lds = (size_t)p.wide_elems * (sizeof(T) + 2);
     hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD>), dim3((unsigned)(n * kLanes)), dim3(kLanes), lds, st, p, lam, mm, w,
                        list, n);
     if (UPD && tile_lb)
