@@ -301,7 +301,13 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * an instance is compiled, a worker thread uploads its image on a stream of
  * its own if image space is free, overlapping the running batch; admission
  * passes over an instance whose upload is still running (it joins at a
- * later step), so a step never waits for one. */
+ * later step), so a step never waits for one.
+ *
+ * Threads: bddmma_pool_submit, _submit_loaded, _wait_compiled, _poll,
+ * _result, _primal, _release and _get_counters may be called from any thread,
+ * also while another thread is inside bddmma_pool_step.  Calls of
+ * bddmma_pool_step must not overlap each other, bddmma_pool_bind comes before
+ * the first step, and bddmma_pool_destroy must not overlap any call. */
 typedef struct bddmma_pool bddmma_pool;
 
 #define BDDMMA_POOL_QUEUED 0   /* submitted, host compilation pending or running */

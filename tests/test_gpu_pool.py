@@ -9,6 +9,8 @@ copied unchanged when the batch is re-assembled).  Also: admission by
 workspace bytes and member count, retirement by tolerance, adopted solvers.
 """
 import sys
+import threading
+import time
 
 import numpy as np
 import pytest
@@ -209,3 +211,57 @@ def test_pool_rounds_members_as_alone(prec):
             with pytest.raises(B.BddmmaError) as e:
                 pool.primal(t)
             assert e.value.code == B.STATE
+
+
+def test_pool_submit_and_poll_from_other_threads():
+    """a submitter thread and a polling thread run beside the stepping thread
+    (the library releases the GIL in every call): each instance still ends
+    bitwise as it ends alone"""
+    ilps = members()
+    iters = [10, 20, 15, 5, 25, 10, 30, 5, 20, 15][:len(ilps)]
+    pool = B.Pool(max_active=3, precision=64).bind(256 << 20)
+    tickets = [None] * len(ilps)
+    submitted = threading.Event()
+    errors = []
+
+    def submitter():
+        try:
+            for k, il in enumerate(ilps):
+                tickets[k] = pool.submit(il, iters[k])
+                time.sleep(0.002)
+        except Exception as e:   # reported by the main thread
+            errors.append(e)
+        submitted.set()
+
+    def poller():
+        try:
+            while not submitted.is_set() or any(t is None for t in tickets):
+                for t in list(tickets):
+                    if t is not None:
+                        pool.poll(t)
+                pool.counters()
+            for _ in range(50):
+                for t in tickets:
+                    pool.poll(t)
+        except Exception as e:
+            errors.append(e)
+
+    ts = [threading.Thread(target=submitter), threading.Thread(target=poller)]
+    for t in ts:
+        t.start()
+    steps = 0
+    while not submitted.is_set() or any(pool.poll(t)["state"] != B.POOL_DONE for t in tickets if t is not None):
+        active, _ = pool.step(5)
+        assert active <= 3
+        steps += 1
+        assert steps < 400
+        if not active:
+            time.sleep(0.001)
+    for t in ts:
+        t.join()
+    assert not errors, errors
+    note("pool steps", steps)
+    for k, il in enumerate(ilps):
+        info = pool.poll(tickets[k])
+        assert info["iters"] == iters[k]
+        assert_matches_solo(pool, tickets[k], il, precision=64)
