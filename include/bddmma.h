@@ -103,6 +103,9 @@ typedef struct {
                               least this many nodes are swept one BDD per wave, the lanes
                               spread over each layer's nodes, when their distances fit in
                               LDS; narrower ones run one BDD per lane.  0 = never.  4 */
+    int32_t  wide_lanes;   /* lanes per BDD in that kernel: 16, 32 or 64 (a 64-lane wave
+                              then holds 4, 2 or 1 BDDs of a tile; more lanes are used
+                              when the BDDs' LDS regions would not fit one block).  32 */
     int32_t  reserved[1];  /* must be zero */
 } bddmma_options;
 

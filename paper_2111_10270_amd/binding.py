@@ -48,7 +48,8 @@ class Options(C.Structure):
                 ("seed", C.c_uint64), ("sp_in_lds_max_nodes", C.c_int32), ("fast_path", C.c_int32),
                 ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32),
                 ("class_merge_kib", C.c_int32), ("small_tiles", C.c_int32), ("serial_mma", C.c_int32),
-                ("termination", C.c_int32), ("wide_min_width", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("termination", C.c_int32), ("wide_min_width", C.c_int32), ("wide_lanes", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Stats(C.Structure):

@@ -937,6 +937,7 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     d.scratch = s->dev + L.scratch;
     d.lds_lane_elems = pk.max_lds_lane_elems;
     d.wide_elems = pk.max_wide_elems;
+    d.wide_lanes = s->opt.wide_lanes;
     d.wide_part = s->ptr<double>(L.widepart);
     const bool batch = s->n_inst() > 1;
     d.var_inst = batch ? s->ptr<int32_t>(L.var_inst) : nullptr;
@@ -985,6 +986,7 @@ int bddmma_options_default(bddmma_options *o)
     o->class_merge_kib = 32768;
     o->small_tiles = 2048;
     o->wide_min_width = kWideMinWidth;
+    o->wide_lanes = 32;
     return BDDMMA_OK;
 }
 
@@ -1012,6 +1014,8 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
     if (o.termination != 0 && o.termination != 1) return fail(BDDMMA_ERR_INVALID_ARG, "termination must be 0 or 1");
     if (o.wide_min_width < 0 || o.wide_min_width > 65535)
         return fail(BDDMMA_ERR_INVALID_ARG, "wide_min_width must lie in [0, 65535]");
+    if (o.wide_lanes != 16 && o.wide_lanes != 32 && o.wide_lanes != 64)
+        return fail(BDDMMA_ERR_INVALID_ARG, "wide_lanes must be 16, 32 or 64");
     if (o.reserved[0] != 0)
         return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
@@ -1608,6 +1612,7 @@ int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *co
                         {&bddmma_options::class_merge_kib, {32768, 0, 4096, 262144}},
                         {&bddmma_options::sp_in_lds_max_nodes, {0, -1}},
                         {&bddmma_options::wide_min_width, {kWideMinWidth, 0, 2, 16, 64}},
+                        {&bddmma_options::wide_lanes, {32, 16, 64}},
                         {&bddmma_options::graph_sweeps, {64, 0}}};
     bddmma_options cur = o;
     double cur_us = INFINITY;

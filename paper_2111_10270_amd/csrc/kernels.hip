@@ -222,13 +222,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep(DevProblem P, T *__restrict_
 // slot or the averaging kernel's term are read).  Blocks of dummy lanes (padding BDDs) return at once:
 // a padding BDD keeps lambda = 0 and M = 0.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_min(T v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = tmin(v, (T)__shfl_xor(v, off, kLanes));
-    return v;
-}
-
 // *p = min(*p, v) in LDS with the native float / double min (ds_min_f32,
 // ds_min_f64): exact, so the result does not depend on the order of the lanes
 template <typename T>
@@ -237,29 +230,42 @@ __device__ __forceinline__ void lds_min(T *p, T v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <typename T, int DIR, bool UPD>
+// min over the LPB lanes of a group (aligned groups of LPB lanes of one wave)
+template <int LPB, typename T>
+__device__ __forceinline__ T group_min(T v)
+{
+    for (int off = LPB / 2; off > 0; off >>= 1) v = tmin(v, (T)__shfl_xor(v, off, kLanes));
+    return v;
+}
+
+// One BDD per group of LPB lanes; a single-wave block holds G = 64 / LPB BDDs
+// of one tile, which share the tile's layer structure, so every group runs
+// the same loops and the block's barriers stay uniform.  Each group has its
+// own LDS region of region_bytes.  Padding BDDs take part in the barriers
+// only.
+template <typename T, int DIR, bool UPD, int LPB>
 __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restrict__ lam, T *mm,
                                                         Omega<T> w, const int32_t *__restrict__ list,
-                                                        int64_t count)
+                                                        int64_t count, uint32_t region_bytes)
 {
+    constexpr int G = kLanes / LPB;
     extern __shared__ unsigned char smem_raw[];
-    const int t = threadIdx.x;
-    const int64_t wt = (int64_t)blockIdx.x / kLanes;     // index in the wide list
-    const int j = (int)(blockIdx.x % kLanes);             // lane (BDD) of the tile
-    if (wt >= count) return;
+    const int t = (int)threadIdx.x % LPB;                // lane in the group
+    const int g = (int)threadIdx.x / LPB;                // group = BDD of the block
+    const int64_t wt = (int64_t)blockIdx.x / LPB;        // index in the wide list (LPB blocks per tile)
+    const int j = (int)(blockIdx.x % LPB) * G + g;       // lane (BDD) of the tile
+    if (wt >= count) return;                             // uniform over the block
     const int64_t tile = (int64_t)uni((uint32_t)list[wt]);
     const TileView tv = load_tile(P.tiles + tile);
     double *const part = P.wide_part + wt * kLanes + j;
-    if (P.pair_var[tv.pb + j] >= P.n_vars) {           // padding BDD
-        if (UPD && t == 0) *part = 0.0;
-        return;
-    }
+    const bool live = P.pair_var[tv.pb + j] < P.n_vars;  // false: padding BDD
     const T omega = w.w1;
     const int K = (int)tv.K, NN = (int)tv.NN;
     const T INF = inf_of<T>();
     const uint32_t *__restrict__ layers = P.layers + tv.lb;
     const uint32_t *__restrict__ words = tv.shared ? P.child + tv.nb : P.child + tv.fb + (size_t)j * NN;
-    T *const F = reinterpret_cast<T *>(smem_raw);       // [NN] SP(root, v)
+    unsigned char *const region = smem_raw + (size_t)g * region_bytes;
+    T *const F = reinterpret_cast<T *>(region);         // [NN] SP(root, v)
     T *const Bk = F + NN;                                // [NN] SP(v, top)
     T *const lamS = Bk + NN;                             // [K]
     T *const avS = lamS + K;                             // [K]
@@ -270,132 +276,144 @@ __global__ __launch_bounds__(kLanes) void k_sweep_wide(DevProblem P, T *__restri
 
     // the BDD's node words are staged in LDS once, so no layer waits on a
     // global load
-    for (int n = t; n < NN; n += kLanes) Wd[n] = words[n];
-    for (int h = t; h < K; h += kLanes) {
-        const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
-        lamS[h] = lam[s];
-        if (UPD) {
-            const uint32_t cd = P.code[tv.cb + (uint32_t)h * kLanes + j];
-            avS[h] = averaged_term(mm, tv.pb, cd, mm[s], w);
+    if (live) {
+        for (int n = t; n < NN; n += LPB) Wd[n] = words[n];
+        for (int h = t; h < K; h += LPB) {
+            const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+            lamS[h] = lam[s];
+            if (UPD) {
+                const uint32_t cd = P.code[tv.cb + (uint32_t)h * kLanes + j];
+                avS[h] = averaged_term(mm, tv.pb, cd, mm[s], w);
+            }
         }
     }
     __syncthreads();
 
-    double lbacc = 0.0;   // lane 0 only
-    T energy;
+    double lbacc = 0.0;   // lane 0 of the group only
+    T energy = INF;
     if (DIR == 0) {
         // SP(v, top) under the current multipliers
         for (int h = K - 1; h >= 0; --h) {
             const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
-            const T l = lamS[h];
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const uint32_t c = Wd[noff + q];
-                Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + l);
+            if (live) {
+                const T l = lamS[h];
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const uint32_t c = Wd[noff + q];
+                    Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + l);
+                }
             }
             __syncthreads();
         }
-        if (t == 0) F[0] = T(0);
+        if (live && t == 0) F[0] = T(0);
         __syncthreads();
         T top = INF;
         for (int h = 0; h < K; ++h) {
             const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
             const uint32_t Wn = h + 1 < K ? (uni(layers[h + 1]) >> 16) : 0u;
-            const T l = lamS[h];
-            T m0 = INF, m1 = INF;
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const T f = F[noff + q];
-                const uint32_t c = Wd[noff + q];
-                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-                if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
-                if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
-            }
-            m0 = wave_min(m0);
-            m1 = wave_min(m1);
-            const T M = m1 - m0;
-            const T lu = UPD ? (l - omega * M) + avS[h] : l;
-            if (t == 0) {
-                const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
-                mm[s] = M;
-                if (UPD) {
-                    lam[s] = lu;
-                    lbacc += (double)(M < T(0) ? M : T(0));
+            T lu = T(0);
+            if (live) {
+                const T l = lamS[h];
+                T m0 = INF, m1 = INF;
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const T f = F[noff + q];
+                    const uint32_t c = Wd[noff + q];
+                    const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                    if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
+                    if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
                 }
+                m0 = group_min<LPB>(m0);
+                m1 = group_min<LPB>(m1);
+                const T M = m1 - m0;
+                lu = UPD ? (l - omega * M) + avS[h] : l;
+                if (t == 0) {
+                    const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+                    mm[s] = M;
+                    if (UPD) {
+                        lam[s] = lu;
+                        lbacc += (double)(M < T(0) ? M : T(0));
+                    }
+                }
+                for (uint32_t q = t; q < Wn; q += LPB) F[noffn + q] = INF;
             }
-            for (uint32_t q = t; q < Wn; q += kLanes) F[noffn + q] = INF;
             __syncthreads();
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const T f = F[noff + q];
-                const uint32_t c = Wd[noff + q];
-                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-                if (lo != kBot) {
-                    if (lo == kTop) top = tmin(top, f);
-                    else lds_min(&F[noffn + lo], f);
-                }
-                if (hi != kBot) {
-                    const T v = f + lu;
-                    if (hi == kTop) top = tmin(top, v);
-                    else lds_min(&F[noffn + hi], v);
+            if (live) {
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const T f = F[noff + q];
+                    const uint32_t c = Wd[noff + q];
+                    const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                    if (lo != kBot) {
+                        if (lo == kTop) top = tmin(top, f);
+                        else lds_min(&F[noffn + lo], f);
+                    }
+                    if (hi != kBot) {
+                        const T v = f + lu;
+                        if (hi == kTop) top = tmin(top, v);
+                        else lds_min(&F[noffn + hi], v);
+                    }
                 }
             }
             __syncthreads();
         }
-        energy = wave_min(top);
+        energy = group_min<LPB>(top);
     } else {
         // SP(root, v) under the current multipliers
-        if (t == 0) F[0] = T(0);
+        if (live && t == 0) F[0] = T(0);
         __syncthreads();
         for (int h = 0; h + 1 < K; ++h) {
             const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
             const uint32_t Wn = uni(layers[h + 1]) >> 16;
-            const T l = lamS[h];
-            for (uint32_t q = t; q < Wn; q += kLanes) F[noffn + q] = INF;
+            if (live)
+                for (uint32_t q = t; q < Wn; q += LPB) F[noffn + q] = INF;
             __syncthreads();
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const T f = F[noff + q];
-                const uint32_t c = Wd[noff + q];
-                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-                if (lo < kTop) lds_min(&F[noffn + lo], f);
-                if (hi < kTop) lds_min(&F[noffn + hi], f + l);
+            if (live) {
+                const T l = lamS[h];
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const T f = F[noff + q];
+                    const uint32_t c = Wd[noff + q];
+                    const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                    if (lo < kTop) lds_min(&F[noffn + lo], f);
+                    if (hi < kTop) lds_min(&F[noffn + hi], f + l);
+                }
             }
             __syncthreads();
         }
         // backward sweep with updates
         for (int h = K - 1; h >= 0; --h) {
             const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
-            const T l = lamS[h];
-            T m0 = INF, m1 = INF;
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const T f = F[noff + q];
-                const uint32_t c = Wd[noff + q];
-                const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-                if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
-                if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
-            }
-            m0 = wave_min(m0);
-            m1 = wave_min(m1);
-            const T M = m1 - m0;
-            const T lu = UPD ? (l - omega * M) + avS[h] : l;
-            if (t == 0) {
-                const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
-                mm[s] = M;
-                if (UPD) {
-                    lam[s] = lu;
-                    lbacc += (double)(M < T(0) ? M : T(0));
+            if (live) {
+                const T l = lamS[h];
+                T m0 = INF, m1 = INF;
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const T f = F[noff + q];
+                    const uint32_t c = Wd[noff + q];
+                    const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+                    if (lo != kBot) m0 = tmin(m0, f + head(lo, noffn));
+                    if (hi != kBot) m1 = tmin(m1, (f + l) + head(hi, noffn));
                 }
-            }
-            for (uint32_t q = t; q < W; q += kLanes) {
-                const uint32_t c = Wd[noff + q];
-                Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + lu);
+                m0 = group_min<LPB>(m0);
+                m1 = group_min<LPB>(m1);
+                const T M = m1 - m0;
+                const T lu = UPD ? (l - omega * M) + avS[h] : l;
+                if (t == 0) {
+                    const uint32_t s = tv.pb + (uint32_t)h * kLanes + j;
+                    mm[s] = M;
+                    if (UPD) {
+                        lam[s] = lu;
+                        lbacc += (double)(M < T(0) ? M : T(0));
+                    }
+                }
+                for (uint32_t q = t; q < W; q += LPB) {
+                    const uint32_t c = Wd[noff + q];
+                    Bk[noff + q] = tmin(head(c & 0xFFFFu, noffn), head(c >> 16, noffn) + lu);
+                }
             }
             __syncthreads();
         }
         energy = Bk[0];
     }
-    if (UPD && t == 0) *part = (double)energy + (double)omega * lbacc;
+    if (UPD && t == 0) *part = live ? (double)energy + (double)omega * lbacc : 0.0;
 }
 
-// per-tile bound partial of the wide tiles: the 64 BDD partials of the tile
-// summed in the shuffle order of the other sweep kernels
 __global__ __launch_bounds__(kLanes) void k_wide_lb(const double *__restrict__ part,
                                                    const int32_t *__restrict__ list, double *__restrict__ tile_lb)
 {
@@ -941,11 +959,23 @@ void launch_wide(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w
     const int64_t n = p.list_off[LIST_WIDE + 1] - p.list_off[LIST_WIDE];
     if (n == 0) return;
     const int32_t *list = p.lists + p.list_off[LIST_WIDE];
-    // distances, multipliers and terms (wide_elems values), then the node
-    // words (4 B per node, at most wide_elems / 2 nodes)
-    const size_t lds = (size_t)p.wide_elems * (sizeof(T) + 2);
-    hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD>), dim3((unsigned)(n * kLanes)), dim3(kLanes), lds, st, p, lam, mm, w,
-                       list, n);
+    // a BDD's LDS region: distances, multipliers and terms (wide_elems
+    // values), then its node words (4 B per node, at most wide_elems / 2
+    // nodes); a block holds 64 / lanes regions within kWideBlockLds
+    const size_t region = ((size_t)p.wide_elems * (sizeof(T) + 2) + 15) & ~(size_t)15;
+    int lanes = p.wide_lanes;
+    while (lanes < kLanes && (size_t)(kLanes / lanes) * region > (size_t)kWideBlockLds) lanes *= 2;
+    const dim3 grid((unsigned)(n * lanes)), block(kLanes);
+    const size_t lds = (size_t)(kLanes / lanes) * region;
+    if (lanes == 16)
+        hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD, 16>), grid, block, lds, st, p, lam, mm, w, list, n,
+                           (uint32_t)region);
+    else if (lanes == 32)
+        hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD, 32>), grid, block, lds, st, p, lam, mm, w, list, n,
+                           (uint32_t)region);
+    else
+        hipLaunchKernelGGL((k_sweep_wide<T, DIR, UPD, 64>), grid, block, lds, st, p, lam, mm, w, list, n,
+                           (uint32_t)region);
     if (UPD && tile_lb)
         hipLaunchKernelGGL(k_wide_lb, dim3((unsigned)n), dim3(kLanes), 0, st, p.wide_part, list, tile_lb);
 }

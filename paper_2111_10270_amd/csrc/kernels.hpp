@@ -13,6 +13,9 @@ namespace bddmma {
 // sweeps; FIXED only records min-marginal differences at fixed multipliers.
 enum SweepMode { MODE_UPDATE = 0, MODE_FIXED = 1 };
 
+// LDS of one block of the wide kernel (all the BDD regions it holds)
+constexpr int kWideBlockLds = 64 << 10;
+
 struct DevProblem {
     const TileDesc *tiles;
     int64_t n_tiles;
@@ -33,6 +36,7 @@ struct DevProblem {
     void *scratch;          // per-tile scratch for tiles outside LDS (element type = precision)
     int lds_lane_elems;     // per-lane LDS elements of the largest LDS tile
     int wide_elems;         // LDS elements of the largest wide tile (2 * nodes + 2 * K)
+    int wide_lanes;         // lanes per BDD of the wide kernel: 16, 32 or 64
     double *wide_part;      // [wide tiles * 64] per-BDD bound partials of the wide kernel
     // batches of independent instances (nullptr for a single ILP): instance
     // of every variable and tile, and the first variable of every instance

@@ -28,7 +28,7 @@ def test_default_options():
     assert o.lb_every == 1 and o.rel_tol == 0.0 and o.tau < 0
     assert (o.fast_path, o.perturb_scale, o.sp_in_lds_max_nodes, o.graph_sweeps) == (1, 0, 0, 64)
     assert o.class_merge_kib == 32768 and o.small_tiles == 2048 and o.serial_mma == 0 and o.termination == 0
-    assert o.wide_min_width == 4 and o.reserved[0] == 0
+    assert o.wide_min_width == 4 and o.wide_lanes == 32 and o.reserved[0] == 0
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=1.5), dict(precision=16), dict(lb_every=0),
@@ -36,7 +36,7 @@ def test_default_options():
                                  dict(sp_in_lds_max_nodes=-2), dict(fast_path=2), dict(perturb_scale=2),
                                  dict(graph_sweeps=-1), dict(class_merge_kib=-1), dict(small_tiles=-1),
                                  dict(serial_mma=2), dict(termination=2), dict(wide_min_width=-1),
-                                 dict(wide_min_width=65536)])
+                                 dict(wide_min_width=65536), dict(wide_lanes=8), dict(wide_lanes=48)])
 def test_invalid_options(bad):
     ilp = I.random_ilp(5, 3, seed=1)
     with pytest.raises(B.BddmmaError) as e:

@@ -11,7 +11,8 @@ from paper_2111_10270_amd import binding as B
 from paper_2111_10270_amd import instances as I
 
 pytestmark = pytest.mark.gpu
-KEYS = ("fast_path", "small_tiles", "class_merge_kib", "sp_in_lds_max_nodes", "wide_min_width", "graph_sweeps")
+KEYS = ("fast_path", "small_tiles", "class_merge_kib", "sp_in_lds_max_nodes", "wide_min_width", "wide_lanes",
+        "graph_sweeps")
 
 
 def knapsack_rows(seed=23, n=300, rows=80):

@@ -220,16 +220,17 @@ def wide_ilp(seed=23):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("wmin", [16, 4, 0])
-def test_wide_rows_node_parallel_kernel(prec, wmin):
-    """BDDs with wide layers on the wave-per-BDD kernel (LDS scatter minima),
+@pytest.mark.parametrize("wmin,lanes", [(16, 16), (4, 16), (4, 32), (4, 64), (0, 16)])
+def test_wide_rows_node_parallel_kernel(prec, wmin, lanes):
+    """BDDs with wide layers on the node-parallel kernel (LDS scatter minima),
     sweep by sweep against the reference, and the rounding's fixed-multiplier
     sweeps; the width threshold of that kernel (wide_min_width, 0 = lane per
-    BDD throughout) moves tiles between schedules, never the results"""
+    BDD throughout) and its lanes per BDD (several BDDs of a tile per wave)
+    move tiles between schedules, never the results"""
     ilp = wide_ilp()
     if O.Oracle(ilp).status != O.OK:
         pytest.skip("generated instance infeasible")
-    s, o, _ = lockstep(ilp, 6, precision=prec, wide_min_width=wmin)
+    s, o, _ = lockstep(ilp, 6, precision=prec, wide_min_width=wmin, wide_lanes=lanes)
     if wmin == 0:
         assert s.stats.n_wide_tiles == 0
     else:
