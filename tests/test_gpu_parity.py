@@ -240,6 +240,26 @@ def test_wide_rows_node_parallel_kernel(prec, wmin, lanes):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
+def test_wide_large_bdds_lane_fallback(prec):
+    """BDDs of about 2,100 nodes (LDS regions of ~30 KB in FP32, ~50 KB in
+    FP64): 16 lanes per BDD are asked for, four regions do not fit a block,
+    so the launch takes 32 (FP32) or 64 (FP64) lanes per BDD; one tile, most
+    of its lanes padding BDDs.  Sweep by sweep against the reference."""
+    rng = np.random.default_rng(41)
+    n = 60
+    rows = []
+    for _ in range(6):
+        vs = rng.choice(n, size=20, replace=False)
+        a = rng.integers(50, 300, size=20)
+        rows.append((vs, a, -1, int(a.sum() // 2)))
+    ilp = I.from_rows(n, rng.standard_normal(n), rows, name="large_wide")
+    s, o, _ = lockstep(ilp, 6, precision=prec, wide_lanes=16)
+    assert s.stats.n_wide_tiles == 1 and s.stats.n_nodes / s.stats.n_bdds > 1500
+    if prec == 64:
+        assert np.array_equal(s.min_marginals(), o.full_mm())
+
+
+@pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("kw", [dict(), dict(small_tiles=0)])
 def test_long_rows_chunked_kernel(prec, kw):
     """width-2 BDDs longer than every register class (assignment-type rows of a
