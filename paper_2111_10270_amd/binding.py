@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -176,6 +177,7 @@ class Solver:
 
     def __init__(self, ilp, **options):
         L = lib()
+        self._destroy = L.bddmma_destroy   # kept for __del__, which may run after module teardown
         self._h = C.c_void_p()
         self.options = default_options(**options)
         _check(L.bddmma_create(C.byref(self.options), C.byref(self._h)))
@@ -203,11 +205,12 @@ class Solver:
         self.workspace = None
         self.stream = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().bddmma_destroy(h)
-            self._h = None
+        if h is None or not h.value or _finalizing():
+            return   # at interpreter exit the process releases everything
+        self._destroy(h)
+        self._h = None
 
     # ---- device binding ----
     def workspace_bytes(self) -> int:
@@ -353,6 +356,7 @@ class Pool:
 
     def __init__(self, max_active: int = 16, host_threads: int = 0, keep_multipliers: bool = True,
                  round: bool = False, **options):
+        self._destroy = lib().bddmma_pool_destroy   # kept for __del__
         self._h = C.c_void_p()
         self.options = default_options(**options)
         flags = (POOL_KEEP_MULTIPLIERS if keep_multipliers else 0) | (POOL_ROUND if round else 0)
@@ -361,11 +365,12 @@ class Pool:
         self.arena = None
         self.stream = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().bddmma_pool_destroy(h)
-            self._h = None
+        if h is None or not h.value or _finalizing():
+            return   # at interpreter exit the process releases everything
+        self._destroy(h)
+        self._h = None
 
     def bind(self, nbytes: int, device="cuda", stream=None):
         import torch
