@@ -318,7 +318,38 @@ def ablation(a, B, I, torch):
                    "deferred_iters": a.abl_deferred, "serial_iters": a.abl_serial, "at_serial_iter": at}
         log(f"ablation {wl} done")
     return {"ablation": "deferred vs serial min-marginal averaging", "dtype": "f64" if a.precision == 64 else "f32",
-            "data": "synthetic", "workloads": out}
+            "data": "synthetic", "workloads": out, "node_word_sharing": compression(a, B, I, torch)}
+
+
+def compression(a, B, I, torch):
+    """BDD compression by shared node words: the default layout (tiles of one
+    topology share one copy of their node words) against per-lane words for
+    every width-2 tile (small_tiles = 2^30) on mrf256x256L8, when it is among
+    the ablation workloads; us per sweep (sweep + averaging) from HIP events."""
+    wl = "mrf256x256L8"
+    if wl not in a.abl_workloads.split(","):
+        return None   # small problems keep per-lane words anyway (one launch per layer class)
+    ilp = I.workload(wl)
+    res = {"workload": wl}
+    for name, kw in (("shared", {}), ("per_lane", {"small_tiles": 1 << 30})):
+        s = B.Solver(ilp, precision=a.precision, graph_sweeps=0, **kw).bind()
+        s.run_sweeps(20)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.run_sweeps(100)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            best = min(best, 1e3 * e0.elapsed_time(e1) / 100)
+        res[name] = {"node_words": s.stats.node_words, "nodes": s.stats.n_nodes,
+                     "workspace_bytes": s.workspace_bytes(), "us_per_sweep": best}
+        s = None
+        torch.cuda.empty_cache()
+    log("node-word sharing done")
+    return res
 
 
 def main():
