@@ -98,7 +98,7 @@ typedef struct {
                               exported multipliers, rounding and the serial start:
                               0: lambda_i^j + omega M-bar_ij (the algorithm's last loop);
                               1: lambda_i^j + (omega/|J_i|) sum_k M-bar_ik (the text's
-                              "min-marginal averaging step").  Both sum to c_i over J_i.  0 */
+                              description: one more min-marginal averaging).  Both sum to c_i over J_i.  0 */
     int32_t  wide_min_width; /* BDDs outside the register classes whose widest layer has at
                               least this many nodes are swept one BDD per wave, the lanes
                               spread over each layer's nodes, when their distances fit in

@@ -30,8 +30,8 @@
  *    sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0) with the multiplier
  *    residual r_i = sum_j (lambda_i^j + omega M_ij) - c_i.
  *  - Termination step of Alg. 1: lambda += omega * M-bar (the algorithm's
- *    last loop); optionally the text's "min-marginal averaging step"
- *    lambda_i^j += (omega/|J_i|) sum_k M-bar_ik (or_set_termination).  Both
+ *    last loop); optionally the form the text describes, one more
+ *    min-marginal averaging: lambda_i^j += (omega/|J_i|) sum_k M-bar_ik (or_set_termination).  Both
  *    give sum_j lambda_i^j = c_i; the certified bound uses the same form.
  *  - Serial averaging (ablation): the sequential update of Sec. 3 applied
  *    variable by variable in id order, full averaging, no damping, from the

@@ -1,6 +1,6 @@
 """Pins of the averaging form of the termination step in the reference
-implementation (the text's "min-marginal averaging step" instead of the
-algorithm's last loop): exact dual feasibility, certified bounds below the
+implementation (the text's description, one more min-marginal averaging,
+instead of the algorithm's last loop): exact dual feasibility, certified bounds below the
 enumerated optimum, the paper's Example A, and the cases where both forms must
 coincide."""
 import numpy as np
