@@ -265,3 +265,36 @@ def test_pool_submit_and_poll_from_other_threads():
         info = pool.poll(tickets[k])
         assert info["iters"] == iters[k]
         assert_matches_solo(pool, tickets[k], il, precision=64)
+
+
+def knapsack_ilp(n, rows, seed, coef=20):
+    rng = np.random.default_rng(seed)
+    rs = []
+    for _ in range(rows):
+        k = int(rng.integers(6, 12))
+        vs = rng.choice(n, size=k, replace=False)
+        a = rng.integers(1, coef, size=k)
+        rs.append((vs, a, -1, int(a.sum() // 2)))
+    return I.from_rows(n, rng.standard_normal(n), rs, name=f"knap{n}x{rows}")
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_pool_members_with_wide_tiles_match_solo(prec):
+    """members whose BDDs run on the node-parallel kernel (wide tiles of
+    different sizes, several BDDs per wave) beside register-path members: the
+    batch's wide list and LDS regions come from the assembled images, and each
+    member still ends bitwise as it ends alone"""
+    ilps = [knapsack_ilp(40, 30, 1), knapsack_ilp(60, 50, 2, coef=60), I.mrf_grid(5, 6, 3, pairwise="potts", seed=3),
+            knapsack_ilp(30, 12, 3, coef=200)]
+    assert all(B.Solver(p, precision=prec).stats.n_wide_tiles > 0 for p in ilps if p.name.startswith("knap"))
+    iters = [10, 15, 10, 5]
+    pool = B.Pool(max_active=3, precision=prec).bind(256 << 20)
+    ts = [pool.submit(p, n) for p, n in zip(ilps, iters)]
+    pool.wait_compiled()
+    steps = 0
+    while any(pool.poll(t)["state"] != B.POOL_DONE for t in ts):
+        pool.step(5)
+        steps += 1
+        assert steps < 50
+    for p, t in zip(ilps, ts):
+        assert_matches_solo(pool, t, p, precision=prec)
