@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <exception>
 #include <thread>
 #include <unordered_map>
 
@@ -41,6 +42,38 @@ int host_threads(int64_t items)
     return items < 4096 ? 1 : n;
 }
 
+// fn(t) for t in [0, n): t = 0 on the calling thread, the others on threads
+// of their own.  An exception thrown on any of them (std::bad_alloc on a huge
+// problem) is rethrown here once every thread has joined, so it reaches the
+// caller's error handling instead of ending the process.
+template <class F>
+void run_threads(int n, F &&fn)
+{
+    if (n <= 1) {
+        fn(0);
+        return;
+    }
+    std::vector<std::exception_ptr> err((size_t)n);
+    std::vector<std::thread> th;
+    th.reserve((size_t)n - 1);
+    try {
+        for (int t = 1; t < n; ++t)
+            th.emplace_back([&fn, &err, t] {
+                try {
+                    fn(t);
+                } catch (...) {
+                    err[(size_t)t] = std::current_exception();
+                }
+            });
+        fn(0);
+    } catch (...) {
+        err[0] = std::current_exception();
+    }
+    for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 // fn(t, begin, end) on nth contiguous ranges of [0, n), range t on thread t
 template <class F>
 void parallel_ranges(int64_t n, int nth, F &&fn)
@@ -50,13 +83,10 @@ void parallel_ranges(int64_t n, int nth, F &&fn)
         return;
     }
     const int64_t chunk = (n + nth - 1) / nth;
-    std::vector<std::thread> th;
-    for (int t = 1; t < nth; ++t) {
+    run_threads(nth, [&](int t) {
         const int64_t a = std::min<int64_t>(n, t * chunk), b = std::min<int64_t>(n, a + chunk);
-        th.emplace_back([&fn, t, a, b] { fn(t, a, b); });
-    }
-    fn(0, (int64_t)0, std::min<int64_t>(n, chunk));
-    for (auto &x : th) x.join();
+        fn(t, a, b);
+    });
 }
 
 // the result of std::sort(v, less) for a strict total order `less`: runs
@@ -142,13 +172,7 @@ int ingest_ilp(Ilp &o, int64_t n_vars, const double *costs, int64_t n_rows, cons
                     return;
                 }
         };
-        if (nth == 1) {
-            one(0);
-        } else {
-            std::vector<std::thread> th;
-            for (int t = 0; t < nth; ++t) th.emplace_back(one, t);
-            for (auto &t : th) t.join();
-        }
+        run_threads(nth, one);
         for (int t = 0; t < nth; ++t)
             if (bad[(size_t)t]) {
                 msg = err[(size_t)t];
@@ -426,14 +450,11 @@ int build_problem(Problem &p, std::string &msg)
     // so the order of rounds does not change it.
     for (;;) {
         res.assign(nthreads, PassResult());
-        std::vector<std::thread> th;
-        int64_t chunk = (ilp.n_rows + nthreads - 1) / nthreads;
-        for (int t = 0; t < nthreads; ++t) {
-            int64_t r0 = std::min<int64_t>(ilp.n_rows, t * chunk), r1 = std::min<int64_t>(ilp.n_rows, r0 + chunk);
-            if (nthreads == 1) compile_rows(ilp, p.fixed, r0, r1, res[t]);
-            else th.emplace_back(compile_rows, std::cref(ilp), std::cref(p.fixed), r0, r1, std::ref(res[t]));
-        }
-        for (auto &t : th) t.join();
+        const int64_t chunk = (ilp.n_rows + nthreads - 1) / nthreads;
+        run_threads(nthreads, [&](int t) {
+            const int64_t r0 = std::min<int64_t>(ilp.n_rows, t * chunk), r1 = std::min<int64_t>(ilp.n_rows, r0 + chunk);
+            compile_rows(ilp, p.fixed, r0, r1, res[(size_t)t]);
+        });
         for (auto &r : res)
             if (r.status != ST_OK) { msg = r.msg; return r.status; }
         bool any = false;
@@ -1404,12 +1425,9 @@ int merge_impl(const std::vector<Part> &parts, Problem &P, Packed &O, std::vecto
             std::sort(order.begin(), order.end(),
                       [&](int64_t x, int64_t y) { return off[x + 1].s - off[x].s > off[y + 1].s - off[y].s; });
             std::atomic<int64_t> next{0};
-            std::vector<std::thread> th;
-            for (int64_t t = 0; t < nth; ++t)
-                th.emplace_back([&] {
-                    for (int64_t q; (q = next.fetch_add(1)) < n;) fill(order[q]);
-                });
-            for (auto &t : th) t.join();
+            run_threads((int)nth, [&](int) {
+                for (int64_t q; (q = next.fetch_add(1)) < n;) fill(order[q]);
+            });
         }
     }
     for (int64_t k = 0; k < n; ++k) {
