@@ -262,7 +262,8 @@ int bddmma_num_instances(const bddmma_solver *s, int64_t *n_inst);
  * lb_free of the most recent recorded sweep (STATE if there is none since
  * bind / reset / load_state), lb_cert with its residual correction and the
  * largest multiplier residual, as bddmma_lower_bound computes them for the
- * whole problem.  Synchronises the stream. */
+ * whole problem.  With lb_cert and max_res both NULL the certificate pass and
+ * the residuals are skipped.  Synchronises the stream. */
 int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res);
 
 /* Alg. 2 for every instance of the loaded problem (dual state restored
@@ -289,8 +290,9 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * membership changed (member images copied into the batch tables with their
  * index shifts, lambda and M of continuing members copied device to device),
  * runs the given number of
- * Alg. 1 iterations on all members at once, computes every member's bounds
- * (as bddmma_batch_bounds) and retires the members that reached their
+ * Alg. 1 iterations on all members at once, computes every member's lb_free
+ * (as bddmma_batch_bounds; lb_cert and the residual for the members that
+ * retire) and retires the members that reached their
  * iteration count or, with options.rel_tol > 0, whose lb_free moved by less
  * than rel_tol * max(1, |lb_free|) over the step.  A member follows exactly
  * the trajectory of a solver loaded with it alone and run for the same
@@ -327,7 +329,8 @@ typedef struct {
     int32_t n_iter;          /* iterations requested at submission */
     int64_t n_vars, n_pairs; /* of the instance (valid from READY on) */
     int64_t steps;           /* pool steps it has been a member of */
-    double lb_free, lb_cert, max_residual;   /* after its last step (NaN before) */
+    double lb_free;          /* after its last step (NaN before) */
+    double lb_cert, max_residual;   /* at retirement (NaN before) */
     uint64_t workspace_bytes; /* device bytes of the instance alone */
     int32_t rounded;         /* 1 once Alg. 2 ran for it at retirement (BDDMMA_POOL_ROUND) */
     int32_t round_status;    /* then: OK, NOT_CONVERGED or STATE (point violates a row) */

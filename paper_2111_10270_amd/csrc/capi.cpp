@@ -740,8 +740,6 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
 {
     const DevProblem &p = s->dp;
     const int64_t n = s->n_inst(), nt = (int64_t)s->pk.tiles.size();
-    T *lam, *mm;
-    terminated_pair<T>(s, lam, mm);
     double *res = s->ptr<double>(s->L.ires), *tile_e = s->ptr<double>(s->L.tile_e);
     const int64_t *seg = s->ptr<int64_t>(s->L.inst_tile);
     const double *off = s->ptr<double>(s->L.inst_off);
@@ -749,12 +747,16 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
         if (s->last_row < 0) return fail(BDDMMA_ERR_STATE, "no sweep recorded since bind / reset / load");
         launch_seg_sum(s->ptr<double>(s->L.lbpart) + (size_t)s->last_row * nt, seg, n, off, res, s->st);
     }
-    launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
-    launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
-    const int64_t nc = (int64_t)s->ochunk.size() - 1;
-    double *opart = s->ptr<double>(s->L.opart);
-    launch_residual_seg<T>(p, lam, mm, s->opt.omega, s->ptr<int64_t>(s->L.ochunk), nc, s->ptr<int64_t>(s->L.oseg), n,
-                           opart, opart + nc + 1, res + 2 * n, res + 3 * n, s->st);
+    if (lb_cert || max_res) {   // the certificate pass and the residuals only when asked for
+        T *lam, *mm;
+        terminated_pair<T>(s, lam, mm);
+        launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
+        launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
+        const int64_t nc = (int64_t)s->ochunk.size() - 1;
+        double *opart = s->ptr<double>(s->L.opart);
+        launch_residual_seg<T>(p, lam, mm, s->opt.omega, s->ptr<int64_t>(s->L.ochunk), nc,
+                               s->ptr<int64_t>(s->L.oseg), n, opart, opart + nc + 1, res + 2 * n, res + 3 * n, s->st);
+    }
     int rc = check_launch();
     if (rc) return rc;
     std::vector<double> h((size_t)(4 * n));

@@ -564,11 +564,10 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
     p->cnt.run_ms += ms_since(t0);
     t0 = std::chrono::steady_clock::now();
     const size_t n = p->members.size();
-    std::vector<double> lbf(n), lbc(n), res(n);
-    if ((rc = bddmma_batch_bounds(p->batch, lbf.data(), lbc.data(), res.data()))) return rc;
+    std::vector<double> lbf(n), lbc(n, NAN), res(n, NAN);
+    if ((rc = bddmma_batch_bounds(p->batch, lbf.data(), nullptr, nullptr))) return rc;   // lb_free only
     p->cnt.bounds_ms += ms_since(t0);
     p->cnt.steps++;
-    t0 = std::chrono::steady_clock::now();
     std::vector<Inst *> mem;
     {
         std::lock_guard<std::mutex> lk(p->mu);
@@ -580,6 +579,17 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         const bool flat = p->opt.rel_tol > 0.0 && in->steps >= 1 &&
                           std::fabs(lbf[k] - in->lb_free) <= p->opt.rel_tol * std::max(1.0, std::fabs(lbf[k]));
         done[k] = in->iters + iters >= in->n_iter || flat;
+    }
+    // the certified bound and the residual of the retiring members (one
+    // certificate pass over the batch, only on steps where someone retires)
+    if (std::find(done.begin(), done.end(), 1) != done.end()) {
+        const auto tc = std::chrono::steady_clock::now();
+        if ((rc = bddmma_batch_bounds(p->batch, nullptr, lbc.data(), res.data()))) return rc;
+        p->cnt.bounds_ms += ms_since(tc);
+    }
+    t0 = std::chrono::steady_clock::now();
+    for (size_t k = 0; k < n; ++k) {
+        Inst *in = mem[k];
         if (done[k] && p->keep_multipliers) {
             std::vector<double> lam((size_t)in->n_pairs), mm((size_t)in->n_pairs);
             if ((rc = solver_instance_multipliers(p->batch, in->slot_off, in->s, lam.data(), mm.data()))) return rc;
@@ -606,8 +616,10 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
         in->iters += iters;
         in->steps++;
         in->lb_free = lbf[k];
-        in->lb_cert = lbc[k];
-        in->res = res[k];
+        if (done[k]) {
+            in->lb_cert = lbc[k];
+            in->res = res[k];
+        }
         if (done[k]) {
             in->state = BDDMMA_POOL_DONE;
             in->slot_off = -1;

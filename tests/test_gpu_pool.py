@@ -81,6 +81,10 @@ def test_pool_members_match_solo(prec):
         active, retired = pool.step(5)
         states = [pool.poll(t)["state"] for t in tickets.values()]
         assert active == states.count(B.POOL_ACTIVE) <= 4
+        for t in tickets.values():   # lb_free after every step, lb_cert at retirement
+            info = pool.poll(t)
+            if info["state"] == B.POOL_ACTIVE:
+                assert np.isfinite(info["lb_free"]) and np.isnan(info["lb_cert"]) and np.isnan(info["max_residual"])
         step += 1
         assert step < 100
     note("pool steps", step)
