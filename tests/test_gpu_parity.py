@@ -282,6 +282,22 @@ def test_long_rows_chunked_kernel(prec, kw):
         assert st.max_layers > 32 and st.n_reg_tiles + st.n_reg_mixed_tiles == st.n_tiles
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_very_long_rows(prec):
+    """a 6,000-variable at-most-one row (width 2: the chunked register kernel,
+    18,000 scratch values per lane) and a 5,000-variable cardinality row
+    (width 4, too large for LDS: the general kernel with device scratch),
+    linked by short rows; sweep by sweep against the reference"""
+    rng = np.random.default_rng(5)
+    n = 8000
+    rows = [(list(range(6000)), [1] * 6000, -1, 1), (list(range(2000, 7000)), [1] * 5000, -1, 3)]
+    for _ in range(300):
+        rows.append((rng.choice(n, size=3, replace=False), [1, 1, -1], -1, 1))
+    ilp = I.from_rows(n, rng.standard_normal(n), rows, name="very_long")
+    s, o, _ = lockstep(ilp, 4, precision=prec)
+    assert s.stats.max_layers == 6000 and s.stats.n_tiles > s.stats.n_reg_tiles + s.stats.n_reg_mixed_tiles
+
+
 @pytest.mark.parametrize("path", PATHS[:3])
 @pytest.mark.parametrize("n_rows", [1, 63, 64, 65, 130])
 def test_ragged_tile_counts_fp64(n_rows, path):
