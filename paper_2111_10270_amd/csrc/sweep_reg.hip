@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, 
 {
     const T omega = w.w1;
     const int lane = threadIdx.x & (kLanes - 1);
-    const int64_t lt = xcd_block() * kRegWaves + uni(threadIdx.x >> 6);
+    const int64_t lt = xcd_block() * (int64_t)(blockDim.x >> 6) + uni(threadIdx.x >> 6);
     if (lt >= tile_count) return;
     const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
     const TileView tv = load_tile(P.tiles + tile);
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_long(DevProblem P,
     constexpr int W = 2;
     const T omega = w.w1;
     const int lane = threadIdx.x & (kLanes - 1);
-    const int64_t lt = xcd_block() * kRegWaves + uni(threadIdx.x >> 6);
+    const int64_t lt = xcd_block() * (int64_t)(blockDim.x >> 6) + uni(threadIdx.x >> 6);
     if (lt >= tile_count) return;
     const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
     const TileView tv = load_tile(P.tiles + tile);
@@ -579,6 +579,11 @@ inline unsigned grid8(int64_t tiles, int per_block)
     return (unsigned)((((tiles + per_block - 1) / per_block) + 7) & ~int64_t(7));
 }
 
+// waves per block of a register-kernel launch: small launches (a few tiles per
+// compute unit, latency-bound) spread one wave per block over more compute
+// units; large ones keep kRegWaves
+inline int reg_waves(int64_t tiles) { return tiles <= 4096 ? 1 : kRegWaves; }
+
 template <typename T, int DIR, int W, bool UPD, int KI>
 void launch_class(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st)
 {
@@ -586,15 +591,15 @@ void launch_class(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, O
         const int l = fast_list(wi, KI);
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
         if (n > 0)
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, true>), dim3(grid8(n, kRegWaves)),
-                               dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, true>), dim3(grid8(n, reg_waves(n))),
+                               dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
     }
     if constexpr (W == 2 && mix_class_ok(KI)) {
         const int l = mix_list(KI);
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
         if (n > 0)
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false>), dim3(grid8(n, kRegWaves)),
-                               dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false>), dim3(grid8(n, reg_waves(n))),
+                               dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
     }
 }
 
@@ -616,11 +621,11 @@ void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Ome
             const int64_t n = p.list_off[l + 1] - p.list_off[l];
             if (n == 0) continue;
             if (l == LIST_LONG_SH)
-                hipLaunchKernelGGL((k_sweep_long<T, DIR, UPD, true>), dim3(grid8(n, kRegWaves)),
-                                   dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+                hipLaunchKernelGGL((k_sweep_long<T, DIR, UPD, true>), dim3(grid8(n, reg_waves(n))),
+                                   dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
             else
-                hipLaunchKernelGGL((k_sweep_long<T, DIR, UPD, false>), dim3(grid8(n, kRegWaves)),
-                                   dim3(kRegWaves * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+                hipLaunchKernelGGL((k_sweep_long<T, DIR, UPD, false>), dim3(grid8(n, reg_waves(n))),
+                                   dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
         }
     }
 }
