@@ -100,9 +100,10 @@ typedef struct {
                               1: lambda_i^j + (omega/|J_i|) sum_k M-bar_ik (the text's
                               description: one more min-marginal averaging).  Both sum to c_i over J_i.  0 */
     int32_t  wide_min_width; /* BDDs outside the register classes whose widest layer has at
-                              least this many nodes are swept one BDD per wave, the lanes
-                              spread over each layer's nodes, when their distances fit in
-                              LDS; narrower ones run one BDD per lane.  0 = never.  4 */
+                              least this many nodes are swept by a group of wide_lanes
+                              lanes each, spread over each layer's nodes, when their
+                              distances fit in LDS; narrower ones run one BDD per lane.
+                              0 = never.  4 */
     int32_t  wide_lanes;   /* lanes per BDD in that kernel: 16, 32 or 64 (a 64-lane wave
                               then holds 4, 2 or 1 BDDs of a tile; more lanes are used
                               when the BDDs' LDS regions would not fit one block).  32 */
@@ -123,7 +124,7 @@ typedef struct {
     int64_t n_reg_tiles;          /* tiles swept by the register kernels (one topology) */
     int64_t n_reg_mixed_tiles;    /* tiles swept by the register kernels (per-lane topologies) */
     int64_t n_reg_launches;       /* register-kernel launches per sweep (non-empty classes) */
-    int64_t n_wide_tiles;         /* tiles swept one BDD per wave (layers of >= 16 nodes) */
+    int64_t n_wide_tiles;         /* tiles on the node-parallel kernel (layers of >= wide_min_width nodes) */
     int64_t node_words;           /* 32-bit node words on the device: tiles of one topology share
                                      one copy (plus the register path's copy), other tiles hold
                                      one word per node and lane */

@@ -84,16 +84,16 @@ enum TileList {
     LIST_MIX0 = LIST_FAST0 + kNumKClasses * kNumWClasses,
     LIST_LONG_SH = LIST_MIX0 + kNumKClasses,   // width-2 tiles longer than every class, one topology
     LIST_LONG_MIX = LIST_LONG_SH + 1,          // the same, per-lane topologies
-    LIST_WIDE = LIST_LONG_MIX + 1,             // wide tiles: one wave per BDD, lanes over nodes
+    LIST_WIDE = LIST_LONG_MIX + 1,             // wide tiles: a group of lanes per BDD, over its nodes
     kNumLists = LIST_WIDE + 1
 };
 
 // Wide tiles (a layer of at least wide_min_width nodes, kWideMinWidth by
-// default) are swept one BDD per
-// wave with the lanes spread over a layer's nodes; the BDD's distances to
-// root and to top, multipliers and averaged terms sit in LDS (2 * nodes + 2 * K
-// elements).  Mixed wide tiles carry a BDD-major copy of their node words at
-// fast_base (lane l's node n at fast_base + l * nodes + n).
+// default) are swept by a group of 16, 32 or 64 lanes per BDD, spread over a
+// layer's nodes; the BDD's distances to root and to top, multipliers and
+// averaged terms (2 * nodes + 2 * K elements) and its node words sit in LDS.
+// Mixed wide tiles carry a BDD-major copy of their node words at fast_base
+// (lane l's node n at fast_base + l * nodes + n).
 constexpr int kWideMinWidth = 4;
 inline int fast_list(int wi, int ki) { return LIST_FAST0 + wi * kNumKClasses + ki; }
 inline int mix_list(int ki) { return LIST_MIX0 + ki; }

@@ -559,7 +559,7 @@ struct TilePlan {
     int wi = -1, ki = -1;         // fast-path class, -1 = general kernels only
     bool mix = false;             // fast path with per-lane topologies
     bool lng = false;             // chunked register kernel (width 2, K beyond the classes)
-    bool wide = false;            // wide kernel (one wave per BDD)
+    bool wide = false;            // wide kernel (a group of lanes per BDD)
 };
 
 }  // namespace

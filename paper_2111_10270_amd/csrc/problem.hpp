@@ -99,7 +99,7 @@ void set_host_thread_cap(int n);
 // small_tiles tiles sweep their width-2 tiles of one topology as mixed tiles
 // (one launch per layer class); tiles outside the register classes with a
 // layer of >= wide_min_width nodes (> 0) whose per-BDD LDS need fits in
-// wide_lds_elems elements use the wide kernel (one wave per BDD).
+// wide_lds_elems elements use the wide kernel (a group of lanes per BDD).
 // ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
