@@ -291,13 +291,14 @@ int bddmma_batch_round(bddmma_solver *s, uint8_t *x_out, double *ub, int32_t *ro
  * membership changed (member images copied into the batch tables with their
  * index shifts, lambda and M of continuing members copied device to device),
  * runs the given number of
- * Alg. 1 iterations on all members at once, computes every member's lb_free
+ * Alg. 1 iterations on all members at once (fewer when a member has fewer
+ * left: no member runs past its n_iter), computes every member's lb_free
  * (as bddmma_batch_bounds; lb_cert and the residual for the members that
  * retire) and retires the members that reached their
  * iteration count or, with options.rel_tol > 0, whose lb_free moved by less
  * than rel_tol * max(1, |lb_free|) over the step.  A member follows exactly
  * the trajectory of a solver loaded with it alone and run for the same
- * number of iterations (its iterations are counted in whole steps), so its
+ * number of iterations (exactly its n_iter unless it retires by rel_tol), so its
  * multipliers are bitwise those of the solo run.  Retiring copies the
  * member's terminated multipliers and M to the host (BDDMMA_POOL_KEEP_MULTIPLIERS)
  * and, with BDDMMA_POOL_ROUND, runs Alg. 2 for the retiring members in a
@@ -372,7 +373,8 @@ int bddmma_pool_submit(bddmma_pool *p, int64_t n_vars, const double *costs, int6
  * failure (a batch or another precision ends FAILED with INVALID_ARG). */
 int bddmma_pool_submit_loaded(bddmma_pool *p, bddmma_solver *s, int32_t n_iter, int64_t *ticket);
 
-/* One step: admission, re-assembly, iters >= 1 Alg. 1 iterations, bounds,
+/* One step: admission, re-assembly, at most iters >= 1 Alg. 1 iterations
+ * (the smallest count a member has left, if that is less), bounds,
  * retirement (see above).  *n_active = members after retirement, *n_retired =
  * instances retired by this step (either may be NULL).  With no member and no
  * ready instance the step returns at once.  Synchronises the stream. */

@@ -22,7 +22,7 @@ def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc (FP64, no contraction)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fPIC", "-fopenmp",
                                "-shared", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -54,6 +54,7 @@ def lib():
         L.or_bdd_nodes.argtypes = [P, i, P, P, P, P]
         L.or_bdd_sp.argtypes = [P, i, P, P, P, P]
         L.or_init.argtypes = [P]
+        L.or_set_threads.argtypes = [P, i]
         L.or_sweep.argtypes = [P, i, i]
         L.or_sweep_subset.argtypes = [P, i, i, ll, P]
         L.or_average.argtypes = [P]
@@ -82,7 +83,7 @@ def _p(a):
 class Oracle:
     """One ILP loaded into the reference implementation (presolve + BDDs)."""
 
-    def __init__(self, ilp, omega: float = 0.5):
+    def __init__(self, ilp, omega: float = 0.5, threads: int = 1):
         L = lib()
         self.ilp = ilp
         self.omega = float(omega)
@@ -93,18 +94,28 @@ class Oracle:
                       np.ascontiguousarray(ilp.sense, dtype=np.int8),
                       np.ascontiguousarray(ilp.rhs, dtype=np.int64)]
         c, rp, col, coef, sense, rhs = self._keep
+        self._destroy = L.or_destroy
         self.h = L.or_create(ilp.n_vars, _p(c), ilp.n_rows, _p(rp), _p(col), _p(coef), _p(sense),
                              _p(rhs), self.omega)
         self.status = L.or_status(self.h)
+        self.set_threads(threads)
         nb, np_, nn = C.c_longlong(), C.c_longlong(), C.c_longlong()
         if self.status == OK:
             L.or_sizes(self.h, C.byref(nb), C.byref(np_), C.byref(nn))
         self.n_bdds, self.n_pairs, self.n_nodes = nb.value, np_.value, nn.value
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_destroy(self.h)
+        # the destroy function is kept on the object: at interpreter exit the
+        # module globals may already be gone
+        if getattr(self, "h", None) and getattr(self, "_destroy", None):
+            self._destroy(self.h)
             self.h = None
+
+    def set_threads(self, n: int):
+        """host threads of the loops over BDDs and variables (results do not
+        depend on it)"""
+        self.threads = max(1, int(n))
+        lib().or_set_threads(self.h, self.threads)
 
     # ---- structure ----
     def pairs(self):

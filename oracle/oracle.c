@@ -4,8 +4,12 @@
  * suite, the smoke check and the benchmark's CPU-baseline leg load this file's
  * library; the solver product never does.  It shares no code with the HIP path.
  *
- * Plain and slow on purpose: one BDD at a time, every quantity recomputed from
- * its definition, all arithmetic in double, compiled with -ffp-contract=off.
+ * Plain and slow on purpose: every BDD is processed on its own, every quantity
+ * recomputed from its definition, all arithmetic in double, compiled with
+ * -ffp-contract=off.  The loops over independent BDDs (the "for j in parallel"
+ * of Alg. 1) and over variables may run on several host threads (OpenMP,
+ * or_set_threads); every sum still runs on one thread in a fixed order, so
+ * the thread count never changes a result.
  *
  * Readings of the paper adopted here (each also listed in the design notes):
  *  - BDD of a row (Sec. 5, Def. "BDD" and "Constraint Set Correspondence"):
@@ -94,6 +98,7 @@ typedef struct {
     double *E;               /* [nb] subproblem energy after the last sweep */
     int maxn, maxk;          /* largest node / layer count, for scratch */
     int term_mode;           /* termination step: 0 lambda + omega M-bar, 1 lambda + a_i */
+    int nthreads;            /* host threads of the parallel loops (1 = serial) */
 } OSolver;
 
 /* ------------------------------------------------------------------ */
@@ -331,6 +336,7 @@ OSolver *or_create(long long n_vars, const double *cost, long long n_rows, const
 {
     OSolver *s = calloc(1, sizeof(OSolver));
     s->omega = omega;
+    s->nthreads = 1;
     s->n_vars = n_vars;
     s->n_rows = n_rows;
     long long nnz = row_ptr[n_rows];
@@ -594,27 +600,40 @@ static void scratch3(const OSolver *s, double **F, double **Bk, double **cost)
     *cost = malloc(sizeof(double) * (size_t)s->maxk);
 }
 
+/* host threads for the parallel loops; subproblems of one sweep touch
+ * disjoint pairs, so any thread count gives the same result */
+void or_set_threads(OSolver *s, int n) { s->nthreads = n > 0 ? n : 1; }
+
 /* sweep over every subproblem (the "for j in parallel" loop of Alg. 1) */
 void or_sweep(OSolver *s, int dir, int update)
 {
-    double *F, *Bk, *cost;
-    scratch3(s, &F, &Bk, &cost);
-    for (int j = 0; j < s->nb; ++j) sweep_one(s, j, dir, update, F, Bk, cost);
-    free(F); free(Bk); free(cost);
+#pragma omp parallel num_threads(s->nthreads)
+    {
+        double *F, *Bk, *cost;
+        scratch3(s, &F, &Bk, &cost);
+#pragma omp for schedule(dynamic, 256)
+        for (int j = 0; j < s->nb; ++j) sweep_one(s, j, dir, update, F, Bk, cost);
+        free(F); free(Bk); free(cost);
+    }
 }
 
-/* sweep over a chosen list of subproblems only (they are independent) */
+/* sweep over a chosen list of distinct subproblems only (they are independent) */
 void or_sweep_subset(OSolver *s, int dir, int update, long long nsel, const long long *sel)
 {
-    double *F, *Bk, *cost;
-    scratch3(s, &F, &Bk, &cost);
-    for (long long q = 0; q < nsel; ++q) sweep_one(s, (int)sel[q], dir, update, F, Bk, cost);
-    free(F); free(Bk); free(cost);
+#pragma omp parallel num_threads(s->nthreads)
+    {
+        double *F, *Bk, *cost;
+        scratch3(s, &F, &Bk, &cost);
+#pragma omp for schedule(dynamic, 256)
+        for (long long q = 0; q < nsel; ++q) sweep_one(s, (int)sel[q], dir, update, F, Bk, cost);
+        free(F); free(Bk); free(cost);
+    }
 }
 
 /* a_i = (omega / |J_i|) * sum_{k in J_i} M_ik, ascending row order (deferred M-bar <- M) */
 void or_average(OSolver *s)
 {
+#pragma omp parallel for num_threads(s->nthreads) schedule(static)
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) { s->avg[i] = 0.0; continue; }
         double sum = 0.0;
@@ -643,6 +662,7 @@ static void terminated(const OSolver *s, double *t)
         for (long long p = 0; p < s->np; ++p) t[p] = s->lam[p] + s->omega * s->mm[p];
         return;
     }
+#pragma omp parallel for num_threads(s->nthreads) schedule(static)
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) continue;
         double sum = 0.0;
@@ -656,16 +676,25 @@ static void terminated(const OSolver *s, double *t)
  * multipliers (lambda + omega M-bar by default), r_i = sum_j t_i^j - c_i */
 double or_lb_cert(const OSolver *s, double *max_residual)
 {
-    double *F = malloc(sizeof(double) * (size_t)s->maxn);
-    double *cost = malloc(sizeof(double) * (size_t)s->maxk);
     double *t = malloc(sizeof(double) * (size_t)(s->np > 0 ? s->np : 1));
+    double *Ej = malloc(sizeof(double) * (size_t)(s->nb > 0 ? s->nb : 1));
     terminated(s, t);
-    double e = 0.0;
-    for (int j = 0; j < s->nb; ++j) {
-        const OBdd *d = &s->bdd[j];
-        for (int h = 0; h < d->k; ++h) cost[h] = t[s->pstart[j] + h];
-        e += sp_from_root(d, cost, F);
+#pragma omp parallel num_threads(s->nthreads)
+    {
+        double *F = malloc(sizeof(double) * (size_t)s->maxn);
+        double *cost = malloc(sizeof(double) * (size_t)s->maxk);
+#pragma omp for schedule(dynamic, 256)
+        for (int j = 0; j < s->nb; ++j) {
+            const OBdd *d = &s->bdd[j];
+            for (int h = 0; h < d->k; ++h) cost[h] = t[s->pstart[j] + h];
+            Ej[j] = sp_from_root(d, cost, F);
+        }
+        free(F);
+        free(cost);
     }
+    double e = 0.0;
+    for (int j = 0; j < s->nb; ++j) e += Ej[j];
+    free(Ej);
     double corr = 0.0, mr = 0.0;
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) continue;
@@ -675,8 +704,6 @@ double or_lb_cert(const OSolver *s, double *max_residual)
         if (r > 0.0) corr += r;
         if (fabs(r) > mr) mr = fabs(r);
     }
-    free(F);
-    free(cost);
     free(t);
     if (max_residual) *max_residual = mr;
     return (e - corr) + s->lb_offset;
@@ -856,6 +883,7 @@ static long long count_conflicts(const OSolver *s, double tau, const unsigned ch
 void or_perturb(OSolver *s, int round, double delta, double tau, unsigned long long seed,
                 const unsigned char *flag, int scale)
 {
+#pragma omp parallel for num_threads(s->nthreads) schedule(static)
     for (long long i = 0; i < s->n_vars; ++i) {
         if (s->deg[i] == 0) continue;
         double r = 2.0 * or_rng_u01(seed, (unsigned long long)round, (unsigned long long)i) - 1.0;

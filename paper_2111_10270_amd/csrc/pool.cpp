@@ -559,8 +559,16 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
     }
     p->cnt.image_ms += ms_since(ti);
     if ((p->changed || !p->batch) && (rc = reassemble(p))) return rc;
+    std::vector<Inst *> mem;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (int64_t t : p->members) mem.push_back(p->inst.at(t).get());
+    }
+    // a step ends early where a member would otherwise run past its count
+    int32_t run = iters;
+    for (Inst *in : mem) run = std::min(run, in->n_iter - in->iters);
     auto t0 = std::chrono::steady_clock::now();
-    if ((rc = bddmma_run_dual(p->batch, iters, nullptr))) return rc;
+    if ((rc = bddmma_run_dual(p->batch, run, nullptr))) return rc;
     p->cnt.run_ms += ms_since(t0);
     t0 = std::chrono::steady_clock::now();
     const size_t n = p->members.size();
@@ -568,17 +576,12 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
     if ((rc = bddmma_batch_bounds(p->batch, lbf.data(), nullptr, nullptr))) return rc;   // lb_free only
     p->cnt.bounds_ms += ms_since(t0);
     p->cnt.steps++;
-    std::vector<Inst *> mem;
-    {
-        std::lock_guard<std::mutex> lk(p->mu);
-        for (int64_t t : p->members) mem.push_back(p->inst.at(t).get());
-    }
     std::vector<char> done(n, 0);
     for (size_t k = 0; k < n; ++k) {
         Inst *in = mem[k];
         const bool flat = p->opt.rel_tol > 0.0 && in->steps >= 1 &&
                           std::fabs(lbf[k] - in->lb_free) <= p->opt.rel_tol * std::max(1.0, std::fabs(lbf[k]));
-        done[k] = in->iters + iters >= in->n_iter || flat;
+        done[k] = in->iters + run >= in->n_iter || flat;
     }
     // the certified bound and the residual of the retiring members (one
     // certificate pass over the batch, only on steps where someone retires)
@@ -613,7 +616,7 @@ int bddmma_pool_step(bddmma_pool *p, int32_t iters, int32_t *n_active, int32_t *
     int32_t retired = 0;
     for (size_t k = 0; k < n; ++k) {
         Inst *in = mem[k];
-        in->iters += iters;
+        in->iters += run;
         in->steps++;
         in->lb_free = lbf[k];
         if (done[k]) {

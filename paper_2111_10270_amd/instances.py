@@ -350,28 +350,41 @@ def concat(ilps) -> ILP:
     )
 
 
-def serving_mix(n: int, seed: int = 5):
-    """A seeded stream of small instances for batched serving: the family is
-    uniform over {Potts MRF with 3 labels, truncated-linear MRF with 8 labels,
-    graph matching, cell tracking}; MRF side U{16..128}, matching points
-    U{50..1000}, tracking frames U{5..20} x detections U{50..500}."""
+def serving_specs(n: int, seed: int = 5):
+    """The instance descriptions of serving_mix(n, seed): (family, size
+    parameters, instance seed) per instance, drawn in stream order."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
         fam = int(rng.integers(0, 4))
         sd = int(rng.integers(0, 2**31 - 1))
-        if fam == 0:
-            side = int(rng.integers(16, 129))
-            out.append(mrf_grid(side, side, 3, pairwise="potts", potts_weight=0.5, seed=sd))
-        elif fam == 1:
-            side = int(rng.integers(16, 129))
-            out.append(mrf_grid(side, side, 8, pairwise="trunc_linear", trunc=2, seed=sd))
+        if fam in (0, 1):
+            out.append((fam, (int(rng.integers(16, 129)),), sd))
         elif fam == 2:
-            m = int(rng.integers(50, 1001))
-            out.append(graph_matching(n_left=m, n_right=m, k=10, n_pairs=m, seed=sd))
+            out.append((fam, (int(rng.integers(50, 1001)),), sd))
         else:
-            out.append(cell_tracking(frames=int(rng.integers(5, 21)), dets=int(rng.integers(50, 501)), seed=sd))
+            out.append((fam, (int(rng.integers(5, 21)), int(rng.integers(50, 501))), sd))
     return out
+
+
+def serving_instance(spec) -> ILP:
+    """One instance of the serving stream from its description."""
+    fam, size, sd = spec
+    if fam == 0:
+        return mrf_grid(size[0], size[0], 3, pairwise="potts", potts_weight=0.5, seed=sd)
+    if fam == 1:
+        return mrf_grid(size[0], size[0], 8, pairwise="trunc_linear", trunc=2, seed=sd)
+    if fam == 2:
+        return graph_matching(n_left=size[0], n_right=size[0], k=10, n_pairs=size[0], seed=sd)
+    return cell_tracking(frames=size[0], dets=size[1], seed=sd)
+
+
+def serving_mix(n: int, seed: int = 5):
+    """A seeded stream of small instances for batched serving: the family is
+    uniform over {Potts MRF with 3 labels, truncated-linear MRF with 8 labels,
+    graph matching, cell tracking}; MRF side U{16..128}, matching points
+    U{50..1000}, tracking frames U{5..20} x detections U{50..500}."""
+    return [serving_instance(sp) for sp in serving_specs(n, seed)]
 
 
 # --------------------------------------------------------------------------
@@ -383,6 +396,10 @@ def workload(name: str) -> ILP:
         return mrf_grid(10, 10, 3, pairwise="potts", potts_weight=0.5, seed=1)
     if name == "mrf256x256L8":
         return mrf_grid(256, 256, 8, pairwise="trunc_linear", trunc=2, seed=2)
+    if name == "mrf512x512L8":
+        # the same generator at four times the size: its FP32 multipliers and
+        # differences (about 620 MB) exceed the GPU's 256 MB last-level cache
+        return mrf_grid(512, 512, 8, pairwise="trunc_linear", trunc=2, seed=2)
     if name == "gm1000k10":
         return graph_matching(1000, 1000, 10, 1000, seed=3)
     if name == "track20x500":
@@ -390,4 +407,4 @@ def workload(name: str) -> ILP:
     raise KeyError(name)
 
 
-WORKLOADS = ("mrf10x10L3", "mrf256x256L8", "gm1000k10", "track20x500")
+WORKLOADS = ("mrf10x10L3", "mrf256x256L8", "gm1000k10", "track20x500", "mrf512x512L8")

@@ -49,7 +49,38 @@ def solo(ilp, n_iter, **kw):
     return s
 
 
-def assert_matches_solo(pool, t, ilp, **kw):
+def assert_matches_oracle(ilp, n_iter, lam, mm, pv, pr, info, prec):
+    """a retired member against the FP64 reference run alone from the start
+    for the same iterations: terminated multipliers and differences bitwise
+    in FP64 (within the scaled 1e-4 tolerance in FP32), bounds to 1e-12
+    (1e-4)"""
+    o = O.Oracle(ilp)
+    o.init()
+    hist = o.run_dual(n_iter)
+    lbc, res = o.lb_cert()
+    o.terminate()
+    rl, rm, _ = o.get()
+    opv, opr = o.pairs()
+    assert np.array_equal(pv, opv) and np.array_equal(pr, opr), ilp.name
+    sc = max(1e-12, float(np.mean(np.abs(ilp.costs)))) if ilp.n_vars else 1.0
+    if prec == 64:
+        assert np.array_equal(lam, rl) and np.array_equal(mm, rm), ilp.name
+        tol_f = tol_c = 1e-12 * max(1.0, abs(lbc))
+        tol_r = 1e-12 * max(1.0, float(np.max(np.abs(ilp.costs), initial=0.0)))
+    else:
+        for g, r in ((lam, rl), (mm, rm)):
+            err = np.abs(g - r) / np.maximum(np.abs(r), sc)
+            assert np.all(err <= 1e-4), (ilp.name, float(np.max(err, initial=0)))
+        tol_f = tol_c = 1e-4 * max(abs(lbc), sc * max(1, o.n_bdds))
+        tol_r = 1e-4 * sc * 8
+    assert abs(info["lb_free"] - hist[-1]) <= tol_f, (ilp.name, info["lb_free"], hist[-1])
+    assert abs(info["lb_cert"] - lbc) <= tol_c, (ilp.name, info["lb_cert"], lbc)
+    assert abs(info["max_residual"] - res) <= tol_r, (ilp.name, info["max_residual"], res)
+
+
+def assert_matches_solo(pool, t, ilp, oracle_check=True, **kw):
+    """bitwise equal to the instance solved alone on the GPU, and (FP64
+    bitwise, FP32 within tolerance) to the reference run alone"""
     info = pool.poll(t)
     assert info["state"] == B.POOL_DONE, info
     lam, mm, pv, pr = pool.result(t)
@@ -60,6 +91,8 @@ def assert_matches_solo(pool, t, ilp, **kw):
     assert np.array_equal(pv, pa) and np.array_equal(pr, ra), ilp.name
     f, c, r = a.batch_bounds()
     assert info["lb_free"] == f[0] and info["lb_cert"] == c[0] and info["max_residual"] == r[0], (ilp.name, info, f, c, r)
+    if oracle_check and O.Oracle(ilp).n_bdds > 0:
+        assert_matches_oracle(ilp, info["iters"], lam, mm, pv, pr, info, kw.get("precision", 32))
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -94,6 +127,30 @@ def test_pool_members_match_solo(prec):
         assert_matches_solo(pool, tickets[k], il, precision=prec)
         pool.release(tickets[k])
     assert pool.step(5) == (0, 0)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_pool_iteration_counts_not_multiple_of_step(prec):
+    """n_iter = 7, 3 and 12 with steps of 5: a step stops where a member
+    would run past its count, so each member runs exactly its n_iter and
+    ends as it ends alone (GPU bitwise, reference)"""
+    ilps = members()[:3]
+    n_iters = [7, 3, 12]
+    pool = B.Pool(max_active=8, precision=prec).bind(128 << 20)
+    tickets = [pool.submit(p, n) for p, n in zip(ilps, n_iters)]
+    pool.wait_compiled()
+    runs = []
+    for _ in range(20):
+        active, retired = pool.step(5)
+        runs.append(pool.poll(tickets[-1])["iters"])
+        if active == 0:
+            break
+    assert runs == [3, 7, 12], runs   # steps of 3 (the second member retires), 4 (the first), 5
+    for t, p, n in zip(tickets, ilps, n_iters):
+        info = pool.poll(t)
+        assert info["iters"] == n
+        assert_matches_solo(pool, t, p, precision=prec)
+        pool.release(t)
 
 
 def test_pool_admission_by_workspace():

@@ -461,3 +461,122 @@ def test_workload_sizes():
     assert hist[-1] <= lbc + 1e-9 and res < 1e-12
     r = o.round()
     assert r["rc"] == 0 and brute.check_rows(ilp, r["x"]) == 0 and r["ub"] >= lbc - 1e-9
+
+
+# ---------------------------------------------------------------- certified bound off the feasible set
+def residual_point():
+    """hand-derived point of tests/golden/lb_cert_residual_example_a.txt:
+    (lambda, M-bar) with lambda + M-bar/2 = t, and the golden values"""
+    g = _read("lb_cert_residual_example_a.txt")
+    t = np.array([float(v) for v in g["t1"][0] + g["t2"][0]])
+    mbar = np.array([float(v) for v in g["mbar"][0]])
+    return t, mbar, g
+
+
+@pytest.mark.parametrize("with_mbar", [False, True])
+def test_lb_cert_residual_correction_hand_value(with_mbar):
+    """LB_cert subtracts sum_i max(r_i, 0) when the terminated multipliers do
+    not sum to c (the FP32 path always leaves such a residual): the hand
+    value of Example A at a point with r = (1, 0, -0.5, 0) is OPT = -5"""
+    ilp, _ = example_a()
+    t, mbar, g = residual_point()
+    o = O.Oracle(ilp)
+    o.init()
+    if with_mbar:
+        o.set(lam=t - 0.5 * mbar, mm=mbar, avg=np.zeros(4))   # dyadic: exact
+    else:
+        o.set(lam=t, mm=np.zeros(6), avg=np.zeros(4))
+    lbc, res = o.lb_cert()
+    assert lbc == float(g["lb_cert"][0][0]) and res == float(g["max_residual"][0][0])
+    # the energies of the derivation, by enumeration of each row's points
+    pts1 = brute.row_points([1, 1, 1], -1, 2)
+    pts2 = brute.row_points([1, 1, -1], 0, 0)
+    e = [brute.ExactAlg1.energy(pts1, [Fraction(v) for v in t[:3]]),
+         brute.ExactAlg1.energy(pts2, [Fraction(v) for v in t[3:]])]
+    assert [float(v) for v in e] == [float(v) for v in g["energies"][0]]
+    opt, _ = brute.ilp_opt(ilp)
+    assert lbc <= float(opt)
+
+
+def _exact_cert(ilp, o, t):
+    """sum_j min over the enumerated points of row j of t^j . x (exact) and
+    the residuals r_i = sum_j t_i^j - c_i (exact)"""
+    pv, pr = o.pairs()
+    e = Fraction(0)
+    start = 0
+    while start < pv.size:
+        end = start
+        while end < pv.size and pr[end] == pr[start]:
+            end += 1
+        vs = [int(v) for v in pv[start:end]]
+        c, a, s, b = ilp.row(int(pr[start]))
+        coef = dict(zip((int(v) for v in c), (int(v) for v in a)))
+        fixed = o.fixed()
+        rhs = int(b) - sum(coef[v] * int(fixed[v]) for v in coef if fixed[v] >= 0)
+        pts = brute.row_points([coef[v] for v in vs], s, rhs)
+        e += brute.ExactAlg1.energy(pts, [Fraction(float(x)) for x in t[start:end]])
+        start = end
+    acc = [Fraction(0)] * ilp.n_vars
+    for p, v in enumerate(pv):
+        acc[v] += Fraction(float(t[p]))
+    used = np.bincount(pv, minlength=ilp.n_vars) > 0
+    r = [acc[i] - Fraction(float(ilp.costs[i])) for i in range(ilp.n_vars) if used[i]]
+    return e, r
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_lb_cert_is_a_bound_at_any_multipliers(seed):
+    """weak duality with the residual correction (Sec. 3, dual (D)): at
+    multipliers moved off the feasible set in both directions, from a point
+    near the dual optimum and from the start, LB_cert stays <= the enumerated
+    optimum and equals the exact enumerated energies minus sum max(r, 0)
+    up to rounding"""
+    ilp = I.random_ilp(9, 6, max_row_len=5, seed=900 + seed)
+    o = O.Oracle(ilp)
+    if o.status != O.OK:
+        return
+    opt, _ = brute.ilp_opt(ilp)
+    rng = np.random.default_rng(seed)
+    scale = max(1.0, float(np.max(np.abs(ilp.costs))))
+    for iters in (0, 40):
+        o.init()
+        o.run_dual(iters)
+        lam, mm, avg = o.get()
+        for amp in (0.0, 0.25, 1.0, 3.0):
+            d = rng.uniform(-amp, amp, size=lam.size)
+            o.set(lam=lam + d, mm=mm, avg=avg)
+            lbc, res = o.lb_cert()
+            assert lbc <= float(opt) + 1e-12 * scale, (iters, amp, lbc, opt)
+            t = (lam + d) + 0.5 * mm
+            e, r = _exact_cert(ilp, o, t)
+            exact = e - sum(max(v, Fraction(0)) for v in r) + Fraction(o.lb_offset())
+            assert abs(lbc - float(exact)) <= 1e-12 * scale * max(1, o.n_pairs)
+            assert abs(res - float(max((abs(v) for v in r), default=0))) <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------- host threads
+@pytest.mark.parametrize("name", ["random", "mrf", "gm"])
+def test_thread_count_does_not_change_results(name):
+    """the OpenMP loops over BDDs and variables give bitwise the same
+    trajectory, bounds and rounding as one thread"""
+    ilp = {"random": lambda: I.random_ilp(400, 300, max_row_len=8, seed=77),
+           "mrf": lambda: I.mrf_grid(12, 12, 3, pairwise="potts", seed=3),
+           "gm": lambda: I.graph_matching(n_left=40, n_right=40, k=5, n_pairs=40, seed=9)}[name]()
+    a = O.Oracle(ilp, threads=1)
+    b = O.Oracle(ilp, threads=4)
+    if a.status != O.OK:
+        pytest.skip("generated instance infeasible")
+    for o in (a, b):
+        o.init()
+    assert np.array_equal(a.run_dual(15), b.run_dual(15))
+    for x, y in zip(a.get(), b.get()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.energies(), b.energies())
+    assert a.lb_cert() == b.lb_cert()
+    ra, rb = a.round(max_rounds=40), b.round(max_rounds=40)
+    assert ra["rc"] == rb["rc"] and ra["rounds"] == rb["rounds"]
+    assert np.array_equal(ra["x"], rb["x"]) and np.array_equal(ra["conflicts"], rb["conflicts"])
+    for o in (a, b):
+        o.set_termination(1)
+    assert a.lb_cert() == b.lb_cert()
+    assert np.array_equal(a.full_mm(), b.full_mm())
