@@ -78,6 +78,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2111_10270_amd.build.build()")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (same soname), so both work on one runtime instance; loaded
+        # the other way round, torch's device allocations are invisible to
+        # the library's runtime
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
