@@ -172,6 +172,26 @@ int bddmma_workspace_bytes(const bddmma_solver *s, size_t *bytes);
  * STATE (not loaded or already bound), HIP. */
 int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bddmma_bind with the library's own workspace instead of caller memory.
+ * The workspace is a static device array of BDDMMA_STATIC_WORKSPACE_BYTES
+ * (64 MiB) that every GPU the library runs on holds until the process ends;
+ * this call allocates nothing (no hipMalloc, no torch allocation).  It binds
+ * the current HIP device's copy and the given stream, then behaves exactly as
+ * bddmma_bind (same tables, same initial state, same results of every later
+ * call).
+ * All solvers bound this way on one GPU share that GPU's array, which keeps
+ * the contents the last solver left: binding a solver hands the array over
+ * to it, and every later call on the solver that held it before fails with
+ * STATE.  Calls that overlap in time on one GPU (a bind while the previous
+ * holder's work is still running, or two threads) race; order them.
+ * Errors: NO_MEMORY (workspace bytes above BDDMMA_STATIC_WORKSPACE_BYTES;
+ * checked before any device call), STATE (not loaded or already bound),
+ * HIP. */
+#define BDDMMA_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int bddmma_bind_static(bddmma_solver *s, void *hip_stream);
+
 /* Re-initialise the dual state of a bound solver (lambda_i^j = c_i / |J_i|,
  * M-bar = 0, empty bound history, sweep counter 0) without re-copying the
  * problem.  STATE if not bound. */

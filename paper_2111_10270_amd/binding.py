@@ -30,7 +30,8 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
            "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune", "bddmma_pool_primal",
-           "bddmma_encode_rows")
+           "bddmma_encode_rows", "bddmma_bind_static")
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
 POOL_KEEP_MULTIPLIERS, POOL_ROUND = 1, 2
@@ -88,7 +89,8 @@ def lib():
         sig = {
             "bddmma_options_default": [P], "bddmma_create": [P, P], "bddmma_destroy": [P],
             "bddmma_load_ilp": [P, i64, P, i64, P, P, P, P, P], "bddmma_get_stats": [P, P],
-            "bddmma_workspace_bytes": [P, P], "bddmma_bind": [P, P, C.c_size_t, P], "bddmma_reset": [P],
+            "bddmma_workspace_bytes": [P, P], "bddmma_bind": [P, P, C.c_size_t, P], "bddmma_bind_static": [P, P],
+            "bddmma_reset": [P],
             "bddmma_run_dual": [P, i32, P], "bddmma_run_sweeps": [P, i32], "bddmma_lower_bound": [P, P, P, P],
             "bddmma_lb_history": [P, P, i64, P], "bddmma_num_pairs": [P, P], "bddmma_get_pairs": [P, P, P],
             "bddmma_get_fixed": [P, P], "bddmma_get_multipliers": [P, P, P], "bddmma_get_state": [P, P, P, P],
@@ -230,6 +232,17 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         _check(lib().bddmma_bind(self._h, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                  C.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def bind_static(self, device="cuda", stream=None):
+        """bind to the library's static device workspace (no allocation);
+        the current device of `device` is the one whose copy is bound"""
+        import torch
+        dev = torch.device(device)
+        torch.cuda.set_device(dev)
+        self.workspace = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib().bddmma_bind_static(self._h, C.c_void_p(self.stream.cuda_stream)))
         return self
 
     # ---- Alg. 1 ----

@@ -78,6 +78,7 @@ struct Events {
 struct bddmma_solver {
     bddmma_options opt{};
     bool loaded = false, bound = false;
+    int static_dev = -1;          // HIP device whose static workspace is bound (bddmma_bind_static), else -1
     Problem prob;
     Packed pk;
     int elem = 4;
@@ -780,6 +781,8 @@ int check_ready(const bddmma_solver *s)
     if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
     if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
     if (!s->bound) return fail(BDDMMA_ERR_STATE, "no device workspace bound");
+    if (s->static_dev >= 0 && !bddmma::static_workspace_held(s, s->static_dev))
+        return fail(BDDMMA_ERR_STATE, "the static workspace of this GPU is now bound to another solver");
     return BDDMMA_OK;
 }
 
@@ -1039,6 +1042,7 @@ void bddmma_destroy(bddmma_solver *s)
     for (auto e : s->ev.pool) (void)hipEventDestroy(e);
     drop_graph(s);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
+    if (s->static_dev >= 0) bddmma::static_workspace_forget(s, s->static_dev);
     delete s;
 }
 
@@ -1676,6 +1680,17 @@ int solver_load_virtual(bddmma_solver *s, const std::vector<const bddmma_solver 
     s->virt_tau.clear();
     for (const bddmma_solver *q : parts) s->virt_tau.push_back(q->inst_tau[0]);
     return finish_load(s);
+    GUARD_END
+}
+
+int solver_bind_static(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, int device)
+{
+    GUARD_BEGIN
+    Range rg(true, "bddmma bind_static");
+    if (s && s->virt) return fail(BDDMMA_ERR_STATE, "an assembled batch is bound by its pool");
+    int rc = bind_impl(s, dev_ptr, bytes, hip_stream, nullptr);
+    if (rc == BDDMMA_OK) s->static_dev = device;
+    return rc;
     GUARD_END
 }
 

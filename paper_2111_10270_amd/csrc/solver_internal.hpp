@@ -46,4 +46,14 @@ int solver_copy_slots(bddmma_solver *dst, int64_t dst_off, const bddmma_solver *
 int solver_instance_multipliers(bddmma_solver *s, int64_t slot_off, const bddmma_solver *part, double *lam,
                                 double *mm);
 
+// Bind s to the library's static workspace (dev_ptr, bytes) on HIP device
+// `device`; as bddmma_bind, and the solver remembers the device so that its
+// later calls fail once another solver holds that device's array.
+int solver_bind_static(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, int device);
+
+// Whether s holds the static workspace of `device` (static_workspace.hip),
+// and its release when s is destroyed.
+bool static_workspace_held(const bddmma_solver *s, int device);
+void static_workspace_forget(const bddmma_solver *s, int device);
+
 }  // namespace bddmma

@@ -284,3 +284,21 @@ def test_one_topology_tiles_share_their_node_words():
     # per-lane layouts (mixed tiles of a small problem) hold a word per node and lane
     small = B.Solver(I.graph_matching(n_left=100, n_right=100, k=10, n_pairs=100, seed=2)).stats
     assert small.node_words >= small.n_nodes
+
+
+def test_bind_static_rejects_problems_above_its_size():
+    """the static workspace (64 MiB) refuses a larger problem before any
+    device call, so this runs without a GPU"""
+    s = B.Solver(I.mrf_grid(64, 64, 8, pairwise="trunc_linear", trunc=2, seed=2), precision=64)
+    assert s.workspace_bytes() > B.STATIC_WORKSPACE_BYTES
+    rc = B.lib().bddmma_bind_static(s._h, None)
+    assert rc == B.NO_MEMORY
+    msg = B.lib().bddmma_last_error().decode()
+    assert "static workspace" in msg and str(B.STATIC_WORKSPACE_BYTES) in msg
+    # and a solver with nothing loaded is refused as out of order
+    t = B.lib()
+    h = __import__("ctypes").c_void_p()
+    assert t.bddmma_create(None, __import__("ctypes").byref(h)) == B.OK
+    assert t.bddmma_bind_static(h, None) == B.STATE
+    t.bddmma_destroy(h)
+
