@@ -549,7 +549,7 @@ def main():
         return
 
     ilp = I.workload(a.workload)
-    s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps)
+    s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps, **I.rounding_options(a.workload))
     s.bind("cuda:0")
     st = s.stats
     N, P, V = st.n_nodes, st.n_pairs, st.n_vars

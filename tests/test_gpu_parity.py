@@ -353,7 +353,7 @@ def test_mrf10_fp64_200_iterations(path):
 def test_gm_tracking_fp32(name):
     ilp = I.workload(name)
     note(name, "fp32")
-    s = solver(ilp, precision=32)
+    s = solver(ilp, precision=32, **I.rounding_options(name))
     o = O.Oracle(ilp)
     o.init()
     sc = scale_of(ilp)
@@ -386,19 +386,16 @@ def test_gm_tracking_fp32(name):
     assert abs(lc - rc_) <= 1e-4 * abs(rc_)
     # LB_free <= LB_cert holds exactly; FP32 path sums move LB_free by ~1e-5 relative
     assert lf <= lc + 1e-4 * abs(lc)
-    # Alg. 2 with the default options: the tracking instance terminates with
-    # a feasible point; the graph-matching instance does not (Sec. 4 does not
-    # guarantee termination): pairs of left points keep claiming one right
-    # point and the mixed case pushes both towards 1
+    # Alg. 2 with the workload's options terminates with a feasible point
+    # (exact row check by the reference) whose cost is above the bound, within
+    # the paper's "fewer than 100" rounds; the dual state is left as it was
     before = s.get_state()
     r = s.round_primal()
-    if name == "track20x500":
-        assert r["rc"] == 0
-        assert o.count_violated(r["x"]) == 0
-        assert r["ub"] >= lc - 1e-6 * abs(lc)
-    else:
-        assert r["rc"] == B.NOT_CONVERGED and r["rounds"] == s.options.max_rounds
-        assert all(np.array_equal(a, b) for a, b in zip(before, s.get_state()))
+    note(f"  {name} rounding: rc {r['rc']} rounds {r['rounds']} ub {r['ub']}")
+    assert r["rc"] == 0 and r["rounds"] < 100
+    assert o.count_violated(r["x"]) == 0
+    assert r["ub"] >= lc - 1e-6 * abs(lc)
+    assert all(np.array_equal(a, b) for a, b in zip(before, s.get_state()))
 
 
 def oracle_threads():
@@ -491,14 +488,14 @@ def test_rounding_fp64_matches_reference():
         assert np.array_equal(s.get_state()[0], o.get()[0])
 
 
-@pytest.mark.parametrize("reopt,seed,converges", [(5, 0, False), (100, 1, True)])
+@pytest.mark.parametrize("reopt,seed,converges", [(5, 0, False), (50, 0, True)])
 def test_gm1000_rounding_fp64_matches_reference(reopt, seed, converges):
     """Alg. 2 on the full graph-matching instance in FP64, from the same
     500-iteration dual point: the GPU takes the reference's rounds exactly.
     With 5 re-optimisation iterations per round neither terminates within 60
-    rounds (the left points that collide on one right point keep being pushed
-    towards it); with 100 iterations and seed 1 both terminate in the same
-    round with the same feasible point."""
+    rounds (the perturbation runs ahead of the dual and a few dozen variables
+    keep disagreeing); with 50 (the workload's setting) both terminate in the
+    same round with the same feasible point."""
     ilp = I.workload("gm1000k10")
     cap = 60 if not converges else 150
     note("gm1000k10 rounding fp64 reopt", reopt, "seed", seed)

@@ -580,3 +580,73 @@ def test_thread_count_does_not_change_results(name):
         o.set_termination(1)
     assert a.lb_cert() == b.lb_cert()
     assert np.array_equal(a.full_mm(), b.full_mm())
+
+
+# ---------------------------------------------------------------- Alg. 2 on the matching workload
+def test_matching_workload_rounding_terminates():
+    """Alg. 2 (Sec. 4) on the graph-matching workload (uniqueness rows on
+    both sides) with its re-optimisation count terminates in fewer than 100
+    rounds, as the paper reports for its datasets, with a point that every
+    original row accepts (exact integer check) and whose cost is above the
+    certified bound"""
+    ilp = I.workload("gm1000k10")
+    o = O.Oracle(ilp, threads=min(8, os.cpu_count() or 1))
+    o.init()
+    o.run_dual(200)
+    lc, _ = o.lb_cert()
+    r = o.round(max_rounds=100, **I.rounding_options("gm1000k10"))
+    assert r["rc"] == O.OK and r["rounds"] < 100
+    assert brute.check_rows(ilp, r["x"]) == 0
+    assert r["ub"] >= lc
+    # with 5 re-optimisation iterations per round it stalls: the conflict
+    # count stops falling well above zero
+    r5 = o.round(max_rounds=60, reopt_iters=5)
+    assert r5["rc"] == O.NOT_CONVERGED and min(r5["conflicts"]) > 20
+
+
+def test_perfect_matching_variant_blocks_rounding():
+    """The exactly-one variant on as many left as right points asks for a
+    perfect matching.  Alg. 2 pushes every variable whose subproblems agree
+    further towards its value, so a left point whose candidate right points
+    are all held by other left points' agreed assignments cannot be matched
+    without undoing one of them, which the perturbation never does: after 16
+    rounds most conflicting left points are such blocked points."""
+    n, k = 1000, 10
+    ilp = I.graph_matching(n, n, k, n, seed=3, left_rows="exactly_one")
+    o = O.Oracle(ilp, threads=min(8, os.cpu_count() or 1))
+    o.init()
+    o.run_dual(200)
+    pv, _ = o.pairs()
+    order = np.argsort(pv, kind="stable")
+    start = np.searchsorted(pv[order], np.arange(ilp.n_vars + 1))
+    nx = n * k
+    right_of = np.empty(nx, dtype=np.int64)
+    for r in range(n, ilp.n_rows):   # the right points' rows hold assignment variables only
+        a, b = ilp.row_ptr[r], ilp.row_ptr[r + 1]
+        if np.all(ilp.col[a:b] < nx):
+            right_of[ilp.col[a:b]] = r
+    # the rounds of Alg. 2 one at a time (as the reference's own loop runs them)
+    o.terminate()
+    o.sweep(0, update=False)
+    delta = 1.0
+    for rnd in range(16):
+        o.perturb(rnd, delta, 0.0, 0, None, 0)
+        delta *= 1.2
+        lam, _, _ = o.get()
+        o.set(lam=lam, mm=np.zeros_like(lam), avg=np.zeros(ilp.n_vars))
+        o.run_dual(5)
+        o.terminate()
+        o.sweep(0, update=False)
+    mm = o.get()[1]
+    signs = [mm[order[start[i]:start[i + 1]]] for i in range(nx)]
+    agree1 = np.array([bool(np.all(m < 0)) for m in signs])
+    conflict = np.array([not (np.all(m > 0) or np.all(m < 0)) for m in signs])
+    holders = {}
+    for i in np.nonzero(agree1)[0]:
+        holders.setdefault(right_of[i], set()).add(i // k)
+    lefts = np.unique(np.nonzero(conflict)[0] // k)
+    blocked = [p for p in lefts
+               if not agree1[p * k:(p + 1) * k].any()
+               and all(holders.get(right_of[p * k + s], set()) - {p} for s in range(k))]
+    assert len(lefts) > 20
+    assert len(blocked) >= len(lefts) // 2
