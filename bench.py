@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default="mrf256x256L8")
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
+                    help="extra solver option of the headline solver (integer value), e.g. fused_average=0")
     ap.add_argument("--cpu-iters", type=int, default=10,
                     help="iterations of the single-thread reference sample")
     ap.add_argument("--cpu-all-iters", type=int, default=20,
@@ -549,7 +551,9 @@ def main():
         return
 
     ilp = I.workload(a.workload)
-    s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps, **I.rounding_options(a.workload))
+    extra = {k: int(v) for k, v in (o.split("=", 1) for o in a.opt)}
+    s = B.Solver(ilp, precision=a.precision, graph_sweeps=a.graph_sweeps,
+                 **{**I.rounding_options(a.workload), **extra})
     s.bind("cuda:0")
     st = s.stats
     N, P, V = st.n_nodes, st.n_pairs, st.n_vars
@@ -616,7 +620,8 @@ def main():
         "dtype": "f32" if a.precision == 32 else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "iterations_per_solve": a.iters, "vars": V, "bdds": st.n_bdds,
-                   "pairs": P, "nodes": N, "precision_bound_sums": "f64", "graph_sweeps": a.graph_sweeps},
+                   "pairs": P, "nodes": N, "precision_bound_sums": "f64", "graph_sweeps": a.graph_sweeps,
+                   "fused_average_vars": st.n_fused_vars, **({"options": extra} if extra else {})},
         "arcs_per_s": 2.0 * N * iters / wall,
         "dual_phase_iters_per_s": a.iters * a.steps / (dual_ms * 1e-3),
         "dual_phase_arcs_per_s": 2.0 * N * a.iters * a.steps / (dual_ms * 1e-3),

@@ -107,7 +107,19 @@ typedef struct {
     int32_t  wide_lanes;   /* lanes per BDD in that kernel: 16, 32 or 64 (a 64-lane wave
                               then holds 4, 2 or 1 BDDs of a tile; more lanes are used
                               when the BDDs' LDS regions would not fit one block).  32 */
-    int32_t  reserved[1];  /* must be zero */
+    int32_t  fused_average;/* 1: when every variable that is not averaged inside one tile lies
+                              in tiles of different BDDs on the register kernels (small
+                              problems) and in at most 16 subproblems, the sweep averages
+                              it itself from a per-variable copy of the previous
+                              differences instead of a separate averaging launch per sweep
+                              (same operations in the same order, so the same results);
+                              0: always the averaging kernel.  1 */
+    int32_t  persistent;   /* 1: when every tile is a mixed register tile of one layer class
+                              and the averaging is fused (or not needed), run_sweeps /
+                              run_dual run blocks of sweeps in one cooperative launch with a
+                              grid-wide barrier between sweeps (same results) instead of
+                              one launch per sweep or graph replay; 0: off.  0 */
+    int32_t  reserved;     /* must be zero */
 } bddmma_options;
 
 typedef struct {
@@ -128,6 +140,10 @@ typedef struct {
     int64_t node_words;           /* 32-bit node words on the device: tiles of one topology share
                                      one copy (plus the register path's copy), other tiles hold
                                      one word per node and lane */
+    int64_t n_fused_vars;         /* variables averaged by the sweep from the per-variable copy
+                                     (options.fused_average); 0 = the averaging kernel runs */
+    int64_t persist_tiles;        /* tiles the persistent kernel sweeps when options.persistent
+                                     is set (all of them), 0 when the problem does not qualify */
 } bddmma_stats;
 
 /* Fill *opt with the defaults listed above.  INVALID_ARG if opt is NULL. */
@@ -505,11 +521,14 @@ int bddmma_encode_rows(int64_t n_vars, const double *costs, int64_t n_rows, cons
 /* Autotuner for the launch schedule: which kernels sweep which tiles
  * (register-resident fast path or general kernels; mixed per-lane tiles for
  * small problems; layer-class merging; shortest paths in LDS or device
- * memory) and whether sweeps are replayed from HIP graphs.  The ILP (as for
+ * memory; node-parallel kernel for wide BDDs; averaging inside the sweep) and
+ * whether sweeps are replayed from HIP graphs.  The ILP (as for
  * bddmma_load_ilp) is compiled once; a greedy search then changes one option
  * at a time among fast_path {1, 0}, small_tiles {2048, 0, 2^30},
- * class_merge_kib {32768, 0, 4096, 262144}, sp_in_lds_max_nodes {0, -1} and
- * graph_sweeps {64, 0}, starting from base (NULL: defaults) and keeping a
+ * class_merge_kib {32768, 0, 4096, 262144}, sp_in_lds_max_nodes {0, -1},
+ * wide_min_width {4, 0, 2, 16, 64}, wide_lanes {32, 16, 64}, fused_average
+ * {1, 0}, graph_sweeps {64, 0} and persistent {0, 1}, starting from base
+ * (NULL: defaults) and keeping a
  * change that is at least 2 % faster.  Each candidate is packed, bound to
  * dev_ptr (bytes of caller-owned device memory; candidates that need more are
  * skipped) and timed over `sweeps` (>= 2) Alg. 1 sweeps with HIP events on

@@ -51,7 +51,7 @@ class Options(C.Structure):
                 ("perturb_scale", C.c_int32), ("graph_sweeps", C.c_int32),
                 ("class_merge_kib", C.c_int32), ("small_tiles", C.c_int32), ("serial_mma", C.c_int32),
                 ("termination", C.c_int32), ("wide_min_width", C.c_int32), ("wide_lanes", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("fused_average", C.c_int32), ("persistent", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("n_nodes", C.c_int64), ("n_fixed", C.c_int64), ("n_free", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_slots", C.c_int64), ("max_layers", C.c_int64), ("max_width", C.c_int64),
                 ("lb_offset", C.c_double), ("n_reg_tiles", C.c_int64), ("n_reg_mixed_tiles", C.c_int64),
-                ("n_reg_launches", C.c_int64), ("n_wide_tiles", C.c_int64), ("node_words", C.c_int64)]
+                ("n_reg_launches", C.c_int64), ("n_wide_tiles", C.c_int64), ("node_words", C.c_int64),
+                ("n_fused_vars", C.c_int64), ("persist_tiles", C.c_int64)]
 
 
 class PoolInfo(C.Structure):

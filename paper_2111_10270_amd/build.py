@@ -14,6 +14,7 @@ LIB = os.path.join(PKG, "libbddmma.so")
 UNITS = [("kernels.hip", "kernels", []), ("problem.cpp", "problem", []), ("capi.cpp", "capi", []), ("pool.cpp", "pool", []),
          ("assemble.hip", "assemble", []), ("serial.hip", "serial", []),
          ("termination.hip", "termination", []), ("static_workspace.hip", "static_workspace", [])] + [
+    ("persist.hip", f"persist_{t}", [f"-DBDDMMA_PERSIST_T={t}"]) for t in ("float", "double")] + [
     ("sweep_reg.hip", f"sweep_reg_{t}_{d}_{u}",
      [f"-DBDDMMA_REG_T={t}", f"-DBDDMMA_REG_DIR={d}", f"-DBDDMMA_REG_UPD={u}"])
     for t in ("float", "double") for d in (0, 1) for u in ("true", "false")]

@@ -58,6 +58,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     size_t lam, mm, lam_bak, mm_bak, mmx, avg;
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
+    size_t gmeta, gsrc, gbuf;   // fused averaging (single instances and static batches)
     size_t lbpart, widepart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
     size_t var_inst, tile_inst, row_inst, inst_var, inst_tile, inst_off, inst_tau, ochunk, oseg, opart, imask, xbest,
@@ -209,6 +210,11 @@ Layout make_layout(const bddmma_solver &s)
     L.xbest = take(V + 1);
     L.ires = take((size_t)NI * 4 * 8);   // per instance: lb_free, cert, residual pos, residual max / ub
     L.scratch = take((size_t)pk.scratch_elems * e);
+    if (!vt && !pk.gmeta.empty()) {
+        L.gmeta = take(S * 4);
+        L.gsrc = take(pk.gsrc.size() * 4);
+        L.gbuf = take(2 * pk.gsrc.size() * e);
+    }
     if (s.has_ser) {
         const SerialTables &q = s.ser;
         const size_t N = q.child.size(), nb = q.bpair.size() - 1;
@@ -285,7 +291,7 @@ struct Scope {
 template <typename T>
 Omega<T> weights(const bddmma_solver *s)
 {
-    return Omega<T>{(T)s->opt.omega, (T)(s->opt.omega / 2.0)};
+    return Omega<T>{(T)s->opt.omega, (T)(s->opt.omega / 2.0), s->opt.omega};
 }
 
 // One Alg. 1 sweep with its deferred averaging.  Between sweeps mm holds the
@@ -384,6 +390,27 @@ int capture_graph(bddmma_solver *s, int64_t len)
     return BDDMMA_OK;
 }
 
+// layer class of the persistent kernel (options.persistent): every tile is a
+// mixed register tile of that class and no averaging launch is needed
+// between sweeps; else -1
+int persist_eligible_class(const bddmma_solver *s)
+{
+    const Packed &pk = s->pk;
+    if (s->virt || (pk.gblocks > 0 && pk.gmeta.empty())) return -1;
+    const int64_t nt = (int64_t)pk.tiles.size();
+    for (int ki = 0; ki < kNumKClasses; ++ki) {
+        const int l = mix_list(ki);
+        const int64_t n = pk.list_off[l + 1] - pk.list_off[l];
+        if (n > 0) return n == nt ? ki : -1;
+    }
+    return -1;
+}
+
+int persist_class(const bddmma_solver *s)
+{
+    return s->opt.persistent && !s->prof ? persist_eligible_class(s) : -1;
+}
+
 template <typename T>
 int run_sweeps_T(bddmma_solver *s, int64_t n)
 {
@@ -391,6 +418,26 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
     int64_t len = std::min<int64_t>(s->opt.graph_sweeps, s->hist_chunk) & ~int64_t(1);
     const bool graphs = len >= 2 && !s->prof;
     int64_t k = 0;
+    // the differences may have changed since the last sweep (state load,
+    // reset, rounding): fused averaging reads its copy of them
+    if (n > 0) launch_gather_refresh<T>(s->dp, s->ptr<T>(s->L.mm), (int)(s->sweeps & 1), s->st);
+    const int pki = persist_class(s);
+    while (pki >= 0 && k < n) {
+        // blocks of sweeps in one cooperative launch each
+        const int64_t chunk = std::min<int64_t>(n - k, s->hist_chunk);
+        if ((rc = make_room(s, chunk))) return rc;
+        const int64_t nt = (int64_t)s->pk.tiles.size();
+        double *rows = s->ptr<double>(s->L.lbpart) + (size_t)s->part_n * (size_t)nt;
+        if (launch_persist<T>(s->dp, pki, s->ptr<T>(s->L.lam), s->ptr<T>(s->L.mm), rows, nt, weights<T>(s),
+                              (int32_t)chunk, (int32_t)(s->sweeps & 1), s->st)) {
+            (void)hipGetLastError();
+            return fail(BDDMMA_ERR_HIP, "persistent kernel: cooperative launch failed");
+        }
+        s->part_n += chunk;
+        s->last_row = s->part_n - 1;
+        s->sweeps += chunk;
+        k += chunk;
+    }
     while (k < n) {
         if (graphs && (s->sweeps & 1) == 0 && n - k >= len) {
             if (s->graph_len != len) {
@@ -702,6 +749,7 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
         delta = delta * s->opt.alpha;
         // Alg. 1 restarts with M-bar = 0
         launch_fill<T>(mm, T(0), S, s->st);
+        launch_gather_refresh<T>(p, mm, 0, s->st);
         for (int t = 0; t < s->opt.reopt_iters; ++t) {
             plain_sweep<T>(s, 0);
             plain_sweep<T>(s, 1);
@@ -838,6 +886,8 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
             if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
             else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
         }
+        HIPCHK(up(L.gmeta, pk.gmeta.data(), pk.gmeta.size() * 4));
+        HIPCHK(up(L.gsrc, pk.gsrc.data(), pk.gsrc.size() * 4));
         HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
         HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
         HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
@@ -926,6 +976,13 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     d.n_tiles = (int64_t)pk.tiles.size();
     d.lists = s->ptr<int32_t>(L.lists);
     for (int l = 0; l <= kNumLists; ++l) d.list_off[l] = pk.list_off[l];
+    // lists of consecutive tile ids: kernels compute the id instead of loading it
+    for (int l = 0; l < kNumLists; ++l) {
+        const int64_t a = pk.list_off[l], b = pk.list_off[l + 1];
+        bool run = b > a;
+        for (int64_t q = a + 1; run && q < b; ++q) run = pk.lists[q] == pk.lists[q - 1] + 1;
+        d.list_first[l] = run ? pk.lists[a] : -1;
+    }
     d.layers = s->ptr<uint32_t>(L.layers);
     d.child = s->ptr<uint32_t>(L.child);
     d.pair_var = s->ptr<int32_t>(L.pair_var);
@@ -934,6 +991,10 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     d.code = s->ptr<uint16_t>(L.code);
     d.gbuckets = s->ptr<AvgBucket>(L.gbuckets);
     d.n_gbuckets = (int32_t)pk.gbuckets.size();
+    if (pk.gbuckets.size() > (size_t)kEllMaxDeg + 1) return fail(BDDMMA_ERR_INVALID_ARG, "internal error: bucket count");
+    d.gbucket_set = AvgBucketSet{};
+    for (size_t k = 0; k < pk.gbuckets.size(); ++k) d.gbucket_set.b[k] = pk.gbuckets[k];
+    d.gbucket_set.n = (int32_t)pk.gbuckets.size();
     d.gblocks = pk.gblocks;
     d.gslot = s->ptr<int32_t>(L.gslot);
     d.cost = s->ptr<double>(L.cost);
@@ -949,6 +1010,11 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     d.tile_inst = batch ? s->ptr<int32_t>(L.tile_inst) : nullptr;
     d.inst_var = batch ? s->ptr<int64_t>(L.inst_var) : nullptr;
     d.inst_tau = batch ? s->ptr<double>(L.inst_tau) : nullptr;
+    const bool fused = !as && !pk.gmeta.empty();
+    d.gmeta = fused ? s->ptr<uint32_t>(L.gmeta) : nullptr;
+    d.gsrc = fused ? s->ptr<int32_t>(L.gsrc) : nullptr;
+    d.gbuf = fused ? (void *)(s->dev + L.gbuf) : nullptr;
+    d.n_g = fused ? (int64_t)pk.gsrc.size() : 0;
     if (s->elem == 8) launch_init<double>(d, s->ptr<double>(L.lam), s->ptr<double>(L.mm), s->st);
     else launch_init<float>(d, s->ptr<float>(L.lam), s->ptr<float>(L.mm), s->st);
     launch_fill<uint8_t>(s->ptr<uint8_t>(L.flag), 0, s->prob.ilp.n_vars + 1, s->st);
@@ -991,6 +1057,7 @@ int bddmma_options_default(bddmma_options *o)
     o->class_merge_kib = 32768;
     o->small_tiles = 2048;
     o->wide_min_width = kWideMinWidth;
+    o->fused_average = 1;
     o->wide_lanes = 32;
     return BDDMMA_OK;
 }
@@ -1021,8 +1088,11 @@ int bddmma_create(const bddmma_options *opt, bddmma_solver **out)
         return fail(BDDMMA_ERR_INVALID_ARG, "wide_min_width must lie in [0, 65535]");
     if (o.wide_lanes != 16 && o.wide_lanes != 32 && o.wide_lanes != 64)
         return fail(BDDMMA_ERR_INVALID_ARG, "wide_lanes must be 16, 32 or 64");
-    if (o.reserved[0] != 0)
-        return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
+    if (o.fused_average != 0 && o.fused_average != 1)
+        return fail(BDDMMA_ERR_INVALID_ARG, "fused_average must be 0 or 1");
+    if (o.persistent != 0 && o.persistent != 1)
+        return fail(BDDMMA_ERR_INVALID_ARG, "persistent must be 0 or 1");
+    if (o.reserved != 0) return fail(BDDMMA_ERR_INVALID_ARG, "reserved option fields must be zero");
     bddmma_solver *s = new bddmma_solver();
     s->opt = o;
     s->elem = o.precision == 64 ? 8 : 4;
@@ -1071,7 +1141,7 @@ int pack_loaded(bddmma_solver *s)
     int budget = s->opt.sp_in_lds_max_nodes < 0 ? 0 : kLdsBytesPerLane / s->elem;
     int rc = pack_problem(s->prob, budget, std::max(0, s->opt.sp_in_lds_max_nodes), s->opt.fast_path != 0,
                           1024.0 * s->opt.class_merge_kib, s->opt.small_tiles, kWideLdsBytes / (s->elem + 2),
-                          s->opt.wide_min_width, s->pk, msg);
+                          s->opt.wide_min_width, s->opt.fused_average ? s->elem : 0, s->pk, msg);
     if (rc != ST_OK) {
         s->prob = Problem();
         s->pk = Packed();
@@ -1162,6 +1232,8 @@ int bddmma_get_stats(const bddmma_solver *s, bddmma_stats *o)
     }
     o->n_wide_tiles = s->pk.list_off[LIST_WIDE + 1] - s->pk.list_off[LIST_WIDE];
     o->node_words = s->virt ? s->vsz.child : (int64_t)s->pk.child.size();
+    o->n_fused_vars = s->pk.gmeta.empty() ? 0 : (int64_t)s->pk.gvars.size();
+    o->persist_tiles = persist_eligible_class(s) >= 0 ? (int64_t)s->pk.tiles.size() : 0;
     return BDDMMA_OK;
 }
 
@@ -1619,7 +1691,9 @@ int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *co
                         {&bddmma_options::sp_in_lds_max_nodes, {0, -1}},
                         {&bddmma_options::wide_min_width, {kWideMinWidth, 0, 2, 16, 64}},
                         {&bddmma_options::wide_lanes, {32, 16, 64}},
-                        {&bddmma_options::graph_sweeps, {64, 0}}};
+                        {&bddmma_options::fused_average, {1, 0}},
+                        {&bddmma_options::graph_sweeps, {64, 0}},
+                        {&bddmma_options::persistent, {0, 1}}};
     bddmma_options cur = o;
     double cur_us = INFINITY;
     rc = eval(cur, cur_us);

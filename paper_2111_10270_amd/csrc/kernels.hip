@@ -528,18 +528,17 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_stage2(const double *__rest
 // at every slot of i (each thread owns the slots of its variable).  Blocks are
 // assigned to degree buckets (layout.hpp).
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_average(const AvgBucket *__restrict__ buckets, int nbuckets,
-                                                         const int32_t *__restrict__ gslot,
+__global__ __launch_bounds__(kRedThreads) void k_average(AvgBucketSet bs, const int32_t *__restrict__ gslot,
                                                          const int32_t *__restrict__ vptr,
                                                          const int32_t *__restrict__ vslot, T *__restrict__ mm,
                                                          double omega)
 {
-    // bucket of this block (uniform)
+    // bucket of this block (uniform; the descriptors are kernel arguments)
     int bi = -1;
-    for (int j = 0; j < nbuckets; ++j)
-        if ((int)blockIdx.x >= buckets[j].block_begin) bi = j;
+    for (int j = 0; j < bs.n; ++j)
+        if ((int)blockIdx.x >= bs.b[j].block_begin) bi = j;
     if (bi >= 0) {
-        const AvgBucket bk = buckets[bi];
+        const AvgBucket bk = bs.b[bi];
         const int64_t i = (int64_t)((int)blockIdx.x - bk.block_begin) * kRedThreads + threadIdx.x;
         if (i < bk.count) {
             if (bk.deg > 0) {
@@ -607,6 +606,15 @@ __global__ __launch_bounds__(256) void k_average_all(const int32_t *__restrict__
     T s = T(0);
     for (int32_t q = a; q < b; ++q) s += mm[vslot[q]];
     avg[v] = (T)(omega / (double)(b - a)) * s;
+}
+
+// per-variable copy of the differences for the fused averaging
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_refresh(const int32_t *__restrict__ gsrc, const T *__restrict__ mm,
+                                                        T *__restrict__ g, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) g[e] = mm[gsrc[e]];
 }
 
 template <typename T>
@@ -1031,9 +1039,17 @@ void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, d
 template <typename T>
 void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st)
 {
-    if (p.gblocks == 0) return;
-    hipLaunchKernelGGL((k_average<T>), dim3((unsigned)p.gblocks), dim3(kRedThreads), 0, st, p.gbuckets, p.n_gbuckets,
+    if (p.gblocks == 0 || p.gmeta) return;
+    hipLaunchKernelGGL((k_average<T>), dim3((unsigned)p.gblocks), dim3(kRedThreads), 0, st, p.gbucket_set,
                        p.gslot, p.vptr, p.vslot, mm, omega);
+}
+
+template <typename T>
+void launch_gather_refresh(const DevProblem &p, const T *mm, int dir, hipStream_t st)
+{
+    if (!p.gmeta || p.n_g == 0) return;
+    T *g = static_cast<T *>(p.gbuf) + (dir ? p.n_g : 0);
+    hipLaunchKernelGGL((k_gather_refresh<T>), dim3(blocks_for(p.n_g, 256)), dim3(256), 0, st, p.gsrc, mm, g, p.n_g);
 }
 
 void launch_lb_many(const double *part, int64_t n_tiles, int64_t n, double offset, double *out, hipStream_t st)
@@ -1183,6 +1199,7 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
     template void launch_sweep<T>(const DevProblem &, T *, T *, double *, Omega<T>, int, int, hipStream_t);         \
     template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
     template void launch_average<T>(const DevProblem &, T *, double, hipStream_t);                                  \
+    template void launch_gather_refresh<T>(const DevProblem &, const T *, int, hipStream_t);                        \
     template void launch_average_all<T>(const DevProblem &, const T *, T *, double, hipStream_t);                   \
     template void launch_init<T>(const DevProblem &, T *, T *, hipStream_t);                                        \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \

@@ -21,6 +21,7 @@ struct DevProblem {
     int64_t n_tiles;
     const int32_t *lists;              // tile ids of every TileList
     int64_t list_off[kNumLists + 1];
+    int32_t list_first[kNumLists];     // first id of a list of consecutive ascending tile ids, else -1
     const uint32_t *layers;
     const uint32_t *child;
     const int32_t *pair_var;
@@ -29,6 +30,7 @@ struct DevProblem {
     const uint16_t *code;              // [n_slots] source of each slot's averaged term
     const AvgBucket *gbuckets;         // variables averaged by the averaging kernel
     int32_t n_gbuckets;
+    AvgBucketSet gbucket_set;          // the same descriptors, passed to the averaging kernel by value
     int64_t gblocks;
     const int32_t *gslot;
     const double *cost;
@@ -44,6 +46,11 @@ struct DevProblem {
     const int32_t *tile_inst;
     const int64_t *inst_var;
     const double *inst_tau;   // Alg. 2 zero threshold per instance (replaces tau)
+    // fused averaging (layout.hpp; nullptr / 0 when the averaging kernel runs)
+    const uint32_t *gmeta;    // [n_slots] entry, rank and |J_i| of slots of such variables
+    const int32_t *gsrc;      // [n_g] slot of every entry
+    void *gbuf;               // 2 x n_g values (element type = precision)
+    int64_t n_g;
 };
 
 constexpr int kRedBlocks = 512;
@@ -52,6 +59,7 @@ constexpr int kRedBlocks = 512;
 template <typename T>
 struct Omega {
     T w1, w2;
+    double w64;   // omega itself (the averaged terms' weight omega/|J_i| is formed in FP64)
 };
 
 // One sweep over every tile.  dir 0 = ascending variables (Alg. 3), 1 =
@@ -64,14 +72,31 @@ struct Omega {
 template <typename T>
 void launch_sweep(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> w, int dir, int mode, hipStream_t st);
 
+// Persistent kernel: n_sweeps updating sweeps (directions dir0, dir0^1, ...)
+// over the mixed register tiles of layer class ki in one cooperative launch,
+// a grid-wide barrier between sweeps; sweep s writes its per-tile bound
+// partials to lbpart + s * lb_stride.  Only for problems whose tiles all lie
+// in that class and whose averaging is fused (or absent).  Returns 0, or -1
+// when the launch is not possible (then nothing ran).
+template <typename T>
+int launch_persist(const DevProblem &p, int ki, T *lam, T *mm, double *lbpart, int64_t lb_stride, Omega<T> w,
+                   int32_t n_sweeps, int32_t dir0, hipStream_t st);
+
 // register-resident sweeps of the fast-path tiles of width class wi
 template <typename T, int DIR, int W, bool UPD>
 void launch_reg(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, Omega<T> w, hipStream_t st);
 
 // a_i = omega/|J_i| * sum_k M_ik (ascending row order) for the variables the
 // sweep does not average itself; the term replaces M_ik at every slot of i.
+// Nothing to do with fused averaging.
 template <typename T>
 void launch_average(const DevProblem &p, T *mm, double omega, hipStream_t st);
+
+// fused averaging: the per-variable copy read by the next sweep (direction
+// dir) from the differences in mm; needed before a run of sweeps whenever mm
+// may have changed outside the sweeps (initialisation, state loads, rounding)
+template <typename T>
+void launch_gather_refresh(const DevProblem &p, const T *mm, int dir, hipStream_t st);
 
 // bounds of n sweeps from their per-tile partials (row r of part, n_tiles
 // each): out[r] = offset + sum of row r, in a fixed order

@@ -27,6 +27,8 @@ constexpr uint32_t kTop = 0xFFFEu;   // arc into the accepting terminal
 constexpr int kMaxWidth = 65533;     // largest layer width encodable in 16 bits
 
 constexpr uint16_t TILE_SHARED = 1;  // all lanes use the same node words
+constexpr uint16_t TILE_GATHER = 2;  // some slot's variable is averaged inside the sweep from
+                                     // the per-variable copy of the previous differences
 
 struct TileDesc {
     uint32_t pair_base;     // first pair slot of the tile
@@ -113,6 +115,27 @@ inline int mix_list(int ki) { return LIST_MIX0 + ki; }
 constexpr uint16_t kCodeSelf = 0xFFFEu;
 constexpr uint16_t kCodeGlobal = 0xFFFFu;
 
+// Fused averaging of the variables with code kCodeGlobal (used when all of
+// them lie in mixed register tiles, at most kGatherMaxDeg subproblems each, so
+// that a slot reads at most kGatherOthers entries besides its own in one trip):
+// instead of the averaging kernel, each sweep reads the previous sweep's
+// differences of all slots of such a variable from a variable-major array
+// (entries base .. base+|J_i|-1 in ascending row order) and writes its own
+// difference into the other of two such arrays (forward sweeps read the
+// first and write the second, backward sweeps the reverse).  Per slot of such
+// a variable: gmeta = entry | rank << 24 | (|J_i| - 1) << 28, entry = base +
+// rank, so one 32-bit word locates the whole block.
+constexpr int kGatherOthers = 4;
+constexpr int kGatherMaxDeg = kGatherOthers + 1;
+// layer classes whose mixed tiles may use it: all in FP32; up to 24 layers in
+// FP64, where the extra registers of the deeper classes would spill
+constexpr bool fuse_class_ok(int elem, int layers) { return elem == 4 || layers <= 24; }
+constexpr int64_t kGatherMaxEntries = int64_t(1) << 24;
+inline uint32_t gather_meta(uint32_t entry, uint32_t rank, uint32_t deg)
+{
+    return entry | (rank << 24) | ((deg - 1u) << 28);
+}
+
 // Variables averaged by the averaging kernel are bucketed by |J_i|.  Buckets
 // with deg <= kEllMaxDeg store the slots column-major (slot k of the bucket's
 // variable i at base + k * count + i) so a thread reads its slots coalesced
@@ -127,5 +150,12 @@ struct AvgBucket {
     int64_t base;           // first entry in the bucket slot / id array
 };
 static_assert(sizeof(AvgBucket) == 24, "AvgBucket is 24 bytes");
+
+// all buckets of a problem (at most one per degree up to kEllMaxDeg, plus the
+// CSR bucket), small enough to travel as a kernel argument
+struct AvgBucketSet {
+    AvgBucket b[kEllMaxDeg + 1];
+    int32_t n;
+};
 
 }  // namespace bddmma

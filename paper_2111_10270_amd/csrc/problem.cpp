@@ -565,7 +565,8 @@ struct TilePlan {
 }  // namespace
 
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, Packed &o, std::string &msg)
+                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, int fuse_elem, Packed &o,
+                 std::string &msg)
 {
     const BddSet &B = p.bdds;
     const int64_t nb = B.n_bdds();
@@ -1130,6 +1131,40 @@ int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool 
             o.gbuckets.push_back(b);
         }
         o.gblocks = blocks;
+    }
+    // fused averaging (layout.hpp) when every kernel-averaged variable lies in
+    // mixed register tiles of classes that support it at the value size
+    // fuse_elem (0 = off) and has at most kGatherMaxDeg subproblems
+    o.gmeta.clear();
+    o.gsrc.clear();
+    if (fuse_elem > 0 && !o.gvars.empty()) {
+        std::vector<char> mixed(o.tiles.size(), 0);
+        for (int ki = 0; ki < kNumKClasses; ++ki)
+            if (fuse_class_ok(fuse_elem, kKClass[ki]))
+                for (int32_t t : lists[mix_list(ki)]) mixed[t] = 1;
+        bool ok = true;
+        int64_t ne = 0;
+        for (size_t k = 0; ok && k < o.gvars.size(); ++k) {
+            const int32_t v = o.gvars[k], a = o.vptr[v], b = o.vptr[v + 1];
+            ok = b - a <= kGatherMaxDeg;
+            for (int32_t q = a; ok && q < b; ++q) ok = mixed[tile_of_slot[o.vslot[q]]] != 0;
+            ne += b - a;
+        }
+        if (ok && ne < kGatherMaxEntries) {
+            o.gmeta.assign((size_t)slots, 0u);
+            o.gsrc.resize((size_t)ne);
+            int64_t e = 0;
+            for (int32_t v : o.gvars) {
+                const int32_t a = o.vptr[v], deg = o.vptr[v + 1] - a;
+                for (int32_t r = 0; r < deg; ++r) {
+                    const int32_t sl = o.vslot[a + r];
+                    o.gsrc[(size_t)(e + r)] = sl;
+                    o.gmeta[(size_t)sl] = gather_meta((uint32_t)(e + r), (uint32_t)r, (uint32_t)deg);
+                    o.tiles[tile_of_slot[sl]].flags |= TILE_GATHER;
+                }
+                e += deg;
+            }
+        }
     }
     // tiles with the same code pattern share one copy of it
     o.code.clear();

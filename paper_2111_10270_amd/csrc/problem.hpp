@@ -50,6 +50,8 @@ struct Packed {
     std::vector<AvgBucket> gbuckets;  // the same variables bucketed by |J_i| (layout.hpp)
     std::vector<int32_t> gslot;       // bucket slot lists (ELL) / variable ids (CSR bucket)
     int64_t gblocks = 0;              // averaging blocks covering all buckets
+    std::vector<uint32_t> gmeta;      // [S] fused averaging (layout.hpp); empty when the averaging kernel runs
+    std::vector<int32_t> gsrc;        // slot of every entry of the per-variable copies
     int64_t n_slots = 0;
     int64_t scratch_elems = 0;        // device scratch elements for non-LDS tiles
     int max_lds_lane_elems = 0;       // per-lane LDS elements of the largest LDS tile
@@ -103,7 +105,8 @@ void set_host_thread_cap(int n);
 // ST_OK / ST_INVALID.
 // fast also enables the in-tile averaging of variables with |J_i| <= 2.
 int pack_problem(const Problem &p, int lds_elem_budget, int lds_max_nodes, bool fast, double merge_bytes,
-                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, Packed &out, std::string &msg);
+                 int64_t small_tiles, int wide_lds_elems, int wide_min_width, int fuse_elem, Packed &out,
+                 std::string &msg);
 
 // Batch of independent instances assembled from their own single-instance
 // results: the union problem is block-diagonal and every instance keeps the

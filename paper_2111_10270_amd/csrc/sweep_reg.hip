@@ -8,6 +8,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "sweep_tile.hpp"
 
 #ifndef BDDMMA_REG_T
 #define BDDMMA_REG_T float
@@ -23,269 +24,20 @@ namespace bddmma {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// Register-resident sweep for tiles of the fast path (64 BDDs of one topology
-// if SH, else of any topologies; fixed layer stride W, exactly KMAX layers).  The layer loops are unrolled,
-// so every per-lane array below lives in VGPRs: the multipliers and averaged terms of all layers and the opposite
-// direction's distances.  With SH the node words are uniform across the wave
-// and live in SGPRs, and each arc test becomes a scalar penalty (see pen);
-// otherwise each lane holds its own words in VGPRs and selects per lane.  All loads are
-// issued before the first use.  The arithmetic is the same as in k_sweep
-// (same operations, same order).
-// ---------------------------------------------------------------------------
-// Uniform arc penalty: 0 when the arc's head is `target`, +inf otherwise.
-// Adding it to a value and taking a min routes the value along the arc with
-// one v_add and one v_min, without branches or per-lane selects.
-template <typename T>
-__device__ __forceinline__ T pen(uint32_t head, uint32_t target);
-
-// the selection happens on the scalar unit; the result is an SGPR operand
-template <>
-__device__ __forceinline__ float pen<float>(uint32_t head, uint32_t target)
-{
-    return __uint_as_float(uni(head == target ? 0u : 0x7F800000u));
-}
-
-template <>
-__device__ __forceinline__ double pen<double>(uint32_t head, uint32_t target)
-{
-    const uint32_t hi = uni(head == target ? 0u : 0x7FF00000u);
-    return __hiloint2double((int)hi, 0);
-}
-
-// min over next-layer nodes t of nx[t] + pen(head, t): the value at the arc's
-// head (after the last layer, nx is the terminal layer {0, inf, ...})
-template <int W, typename T>
-__device__ __forceinline__ T head_inner(uint32_t head, const T (&nx)[W])
-{
-    T r = nx[0] + pen<T>(head, 0);
-#pragma unroll
-    for (int t = 1; t < W; ++t) r = fmin(r, nx[t] + pen<T>(head, (uint32_t)t));
-    return r;
-}
-
-// Per-lane topologies (mixed tiles): the value at the arc's head is selected
-// per lane; the same values as the penalty form up to the sign of a zero.
-template <int W, typename T>
-__device__ __forceinline__ T head_lane(uint32_t head, const T (&nx)[W])
-{
-    T r = inf_of<T>();
-#pragma unroll
-    for (int t = 0; t < W; ++t) r = head == (uint32_t)t ? nx[t] : r;
-    return r;
-}
-
-// value an arc pair of one node contributes to next-layer node t: v0 along
-// the 0-arc lo, v1 along the 1-arc hi
-template <bool SH, typename T>
-__device__ __forceinline__ T arc_to(uint32_t lo, uint32_t hi, uint32_t t, T v0, T v1)
-{
-    if constexpr (SH) return fmin(v0 + pen<T>(lo, t), v1 + pen<T>(hi, t));
-    else {
-        const T INF = inf_of<T>();
-        return fmin(lo == t ? v0 : INF, hi == t ? v1 : INF);
-    }
-}
-
-template <bool SH, int W, typename T>
-__device__ __forceinline__ T head_at(uint32_t head, const T (&nx)[W])
-{
-    if constexpr (SH) return head_inner<W>(head, nx);
-    else return head_lane<W>(head, nx);
-}
-
-// UPD = false: min-marginal differences at fixed multipliers (Alg. 2),
-// written to mm, which is then output only.  With UPD the slots averaged by
-// the averaging kernel hold their averaged term in mm on entry (stored there
-// just before this sweep); every other slot holds its previous M.
-template <typename T, int DIR, int W, int KMAX, bool UPD, bool SH>
+// One wave per tile of `list` (tiles first, first + 1, ... when first >= 0);
+// the sweep of the tile is sweep_tile.
+template <typename T, int DIR, int W, int KMAX, bool UPD, bool SH, bool GAT>
 __global__ __launch_bounds__(kRegWaves * kLanes) void k_sweep_reg(DevProblem P, T *__restrict__ lam,
                                                                    T *__restrict__ mm, double *__restrict__ tile_lb,
                                                                    Omega<T> w, const int32_t *__restrict__ list,
-                                                                   int64_t tile_count)
+                                                                   int64_t tile_count, int32_t first)
 {
-    const T omega = w.w1;
-    const int lane = threadIdx.x & (kLanes - 1);
+    extern __shared__ __align__(16) unsigned char lds_bytes[];
     const int64_t lt = xcd_block() * (int64_t)(blockDim.x >> 6) + uni(threadIdx.x >> 6);
     if (lt >= tile_count) return;
-    const int64_t tile = (int64_t)uni((uint32_t)list[lt]);
-    const TileView tv = load_tile(P.tiles + tile);
-    constexpr int K = KMAX;   // fast tiles have exactly their class's layer count
-    const T INF = inf_of<T>();
-    // 64-bit bases: every per-layer access below is base + constant offset
-    T *const lrow = lam + tv.pb + lane;
-    T *const mtile = mm + tv.pb;
-    T *const mrow = mtile + lane;
-    const uint16_t *const crow = P.code + tv.cb + lane;
-    // node words: one copy per tile (SH) or one per lane at stride 64
-    const uint32_t *const wrow = P.child + tv.fb + (SH ? 0 : lane);
-
-    // prologue: every load is issued before the first use
-    T l[KMAX], a[KMAX], mo[KMAX];
-    uint32_t cd[KMAX];
-    uint32_t wd[KMAX][W];
-#pragma unroll
-    for (int h = 0; h < KMAX; ++h) {
-        l[h] = T(0);
-        a[h] = T(0);
-        mo[h] = T(0);
-        cd[h] = kCodeSelf;
-#pragma unroll
-        for (int q = 0; q < W; ++q) wd[h][q] = kBot | (kBot << 16);
-    }
-#pragma unroll
-    for (int h = 0; h < KMAX; ++h) {
-        if (h < K) {
-            l[h] = lrow[h * kLanes];
-            if (UPD) {
-                mo[h] = mrow[h * kLanes];
-                cd[h] = crow[h * kLanes];
-            }
-#pragma unroll
-            for (int q = 0; q < W; ++q)
-                wd[h][q] = SH ? uni(wrow[h * W + q]) : wrow[(h * W + q) * kLanes];
-        }
-    }
-    if (UPD) {
-        // a = c * (M + x) with one load and no branch: an in-tile partner
-        // gives c = w2, x = M_partner; a variable of this BDD only gives
-        // c = w2, x = M (w2 * 2M = w1 * M exactly, w2 = w1 / 2); a slot
-        // averaged by the averaging kernel holds its term t in mm and gives
-        // c = 1/2, x = t (t exactly)
-#pragma unroll
-        for (int h = 0; h < KMAX; ++h) {
-            if (h < K) {
-                const uint32_t off = cd[h] < kCodeSelf ? cd[h] : (uint32_t)(h * kLanes + lane);
-                const T c = cd[h] == kCodeGlobal ? T(0.5) : w.w2;
-                a[h] = c * (mo[h] + mtile[off]);
-            }
-        }
-    }
-
-    double lbacc = 0.0;
-    T energy;
-    if (DIR == 0) {
-        // SP(v, top) of every layer under the current multipliers; keep the
-        // values at the heads of every arc for the update pass
-        T hd0[KMAX][W], hd1[KMAX][W];
-        T nx[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) nx[q] = q == 0 ? T(0) : INF;   // terminal layer
-#pragma unroll
-        for (int h = KMAX - 1; h >= 0; --h) {
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                hd0[h][q] = INF;
-                hd1[h][q] = INF;
-            }
-            if (h < K) {
-                T b[W];
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    const T v0 = head_at<SH, W>(lo, nx);
-                    const T v1 = head_at<SH, W>(hi, nx);
-                    hd0[h][q] = v0;
-                    hd1[h][q] = v1;
-                    b[q] = fmin(v0, v1 + l[h]);
-                }
-#pragma unroll
-                for (int q = 0; q < W; ++q) nx[q] = b[q];
-            }
-        }
-        // forward sweep with updates
-        T f[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) f[q] = q == 0 ? T(0) : INF;
-#pragma unroll
-        for (int h = 0; h < KMAX; ++h) {
-            if (h < K) {
-                T m0 = f[0] + hd0[h][0];
-                T m1 = (f[0] + l[h]) + hd1[h][0];
-#pragma unroll
-                for (int q = 1; q < W; ++q) {
-                    m0 = fmin(m0, f[q] + hd0[h][q]);
-                    m1 = fmin(m1, (f[q] + l[h]) + hd1[h][q]);
-                }
-                const T M = m1 - m0;
-                const T lu = UPD ? (l[h] - omega * M) + a[h] : l[h];
-                mrow[h * kLanes] = M;
-                if (UPD) {
-                    lrow[h * kLanes] = lu;
-                    lbacc += (double)fmin(M, T(0));
-                }
-                T fn[W];
-#pragma unroll
-                for (int t = 0; t < W; ++t) fn[t] = INF;
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    const T v1 = f[q] + lu;
-#pragma unroll
-                    for (int t = 0; t < W; ++t) fn[t] = fmin(fn[t], arc_to<SH>(lo, hi, (uint32_t)t, f[q], v1));
-                }
-#pragma unroll
-                for (int t = 0; t < W; ++t) f[t] = fn[t];
-            }
-        }
-        energy = f[0];   // node 0 of the terminal layer: accept
-    } else {
-        // SP(root, v) of every layer under the current multipliers
-        T fw[KMAX][W];
-#pragma unroll
-        for (int h = 0; h < KMAX; ++h)
-#pragma unroll
-            for (int q = 0; q < W; ++q) fw[h][q] = (h == 0 && q == 0) ? T(0) : INF;
-#pragma unroll
-        for (int h = 0; h + 1 < KMAX; ++h) {
-            if (h + 1 < K) {
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    const T v0 = fw[h][q], v1 = fw[h][q] + l[h];
-#pragma unroll
-                    for (int t = 0; t < W; ++t) fw[h + 1][t] = fmin(fw[h + 1][t], arc_to<SH>(lo, hi, (uint32_t)t, v0, v1));
-                }
-            }
-        }
-        // backward sweep with updates
-        T bn[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) bn[q] = q == 0 ? T(0) : INF;   // terminal layer
-#pragma unroll
-        for (int h = KMAX - 1; h >= 0; --h) {
-            if (h < K) {
-                T v0[W], v1[W];
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t lo = wd[h][q] & 0xFFFFu, hi = wd[h][q] >> 16;
-                    v0[q] = head_at<SH, W>(lo, bn);
-                    v1[q] = head_at<SH, W>(hi, bn);
-                }
-                T m0 = fw[h][0] + v0[0];
-                T m1 = (fw[h][0] + l[h]) + v1[0];
-#pragma unroll
-                for (int q = 1; q < W; ++q) {
-                    m0 = fmin(m0, fw[h][q] + v0[q]);
-                    m1 = fmin(m1, (fw[h][q] + l[h]) + v1[q]);
-                }
-                const T M = m1 - m0;
-                const T lu = UPD ? (l[h] - omega * M) + a[h] : l[h];
-                mrow[h * kLanes] = M;
-                if (UPD) {
-                    lrow[h * kLanes] = lu;
-                    lbacc += (double)fmin(M, T(0));
-                }
-#pragma unroll
-                for (int q = 0; q < W; ++q) bn[q] = fmin(v0[q], v1[q] + lu);
-            }
-        }
-        energy = bn[0];
-    }
-    if (UPD && tile_lb) {
-        const double e = wave_sum<T>((double)energy + (double)omega * lbacc);
-        if (lane == 0) tile_lb[tile] = e;
-    }
+    const int64_t tile = first >= 0 ? first + lt : (int64_t)uni((uint32_t)list[lt]);
+    T *sh = reinterpret_cast<T *>(lds_bytes) + (size_t)uni(threadIdx.x >> 6) * KMAX * kLanes;
+    sweep_tile<T, DIR, W, KMAX, UPD, SH, GAT>(P, lam, mm, tile_lb, w, tile, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,15 +343,25 @@ void launch_class(const DevProblem &p, int wi, T *lam, T *mm, double *tile_lb, O
         const int l = fast_list(wi, KI);
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
         if (n > 0)
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, true>), dim3(grid8(n, reg_waves(n))),
-                               dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, true, false>), dim3(grid8(n, reg_waves(n))),
+                               dim3(reg_waves(n) * kLanes), (UPD ? reg_waves(n) * sweep_lds_bytes<T, kKClass[KI]>() : 0),
+                               st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n, p.list_first[l]);
     }
     if constexpr (W == 2 && mix_class_ok(KI)) {
         const int l = mix_list(KI);
         const int64_t n = p.list_off[l + 1] - p.list_off[l];
-        if (n > 0)
-            hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false>), dim3(grid8(n, reg_waves(n))),
-                               dim3(reg_waves(n) * kLanes), 0, st, p, lam, mm, tile_lb, w, p.lists + p.list_off[l], n);
+        if (n > 0) {
+            const size_t lds = UPD ? reg_waves(n) * sweep_lds_bytes<T, kKClass[KI]>() : 0;
+            constexpr bool can_fuse = UPD && fuse_class_ok(sizeof(T), kKClass[KI]);
+            if (can_fuse && p.gmeta)
+                hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false, can_fuse>),
+                                   dim3(grid8(n, reg_waves(n))), dim3(reg_waves(n) * kLanes), lds, st, p, lam, mm,
+                                   tile_lb, w, p.lists + p.list_off[l], n, p.list_first[l]);
+            else
+                hipLaunchKernelGGL((k_sweep_reg<T, DIR, W, kKClass[KI], UPD, false, false>),
+                                   dim3(grid8(n, reg_waves(n))), dim3(reg_waves(n) * kLanes), lds, st, p, lam, mm,
+                                   tile_lb, w, p.lists + p.list_off[l], n, p.list_first[l]);
+        }
     }
 }
 

@@ -137,7 +137,8 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
         const int lds = variant == 3 ? 0 : 128;
         const double merge = variant == 1 ? 0.0 : 32.0 * (1 << 20);
         const int64_t small = variant == 2 ? 0 : 2048;
-        rc = pack_problem(p, lds, 0, fast, merge, small, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, pk, msg);
+        rc = pack_problem(p, lds, 0, fast, merge, small, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, variant == 1 ? 0 : 4 << (variant & 1),
+                          pk, msg);
         check(rc == ST_OK, "pack", seed);
         if (rc != ST_OK) {
             std::fprintf(stderr, "  %s\n", msg.c_str());
@@ -157,6 +158,33 @@ void run(const Csr &c, const std::vector<int64_t> &iv, const std::vector<int64_t
             check(pk.pair_var[s] == p.pair_var[q], "slot variable", seed);
         }
         check((int64_t)pk.inst_tile.size() == p.ilp.n_inst() + 1, "instance tile ranges", seed);
+        // fused averaging: every kernel-averaged variable owns a contiguous
+        // block of entries in ascending row order, each entry's slot points
+        // back at it, and the slot's tile is flagged
+        if (!pk.gmeta.empty()) {
+            check((int64_t)pk.gmeta.size() == pk.n_slots, "gather meta size", seed);
+            int64_t e = 0;
+            for (int32_t v : pk.gvars) {
+                const int32_t a = pk.vptr[v], deg = pk.vptr[v + 1] - a;
+                check(deg >= 1 && deg <= kGatherMaxDeg, "gather degree", seed);
+                for (int32_t r = 0; r < deg; ++r) {
+                    const int32_t sl = pk.vslot[a + r];
+                    check(e + r < (int64_t)pk.gsrc.size() && pk.gsrc[(size_t)(e + r)] == sl, "gather source", seed);
+                    check(pk.gmeta[(size_t)sl] == gather_meta((uint32_t)(e + r), (uint32_t)r, (uint32_t)deg),
+                          "gather meta", seed);
+                    bool flagged = false, class_ok = false;
+                    for (const TileDesc &d : pk.tiles)
+                        if (sl >= (int64_t)d.pair_base && sl < (int64_t)d.pair_base + (int64_t)d.K * kLanes) {
+                            flagged = (d.flags & TILE_GATHER) != 0;
+                            class_ok = fuse_class_ok(4 << (variant & 1), d.K);
+                        }
+                    check(flagged, "gather tile flag", seed);
+                    check(class_ok, "gather tile class", seed);
+                }
+                e += deg;
+            }
+            check(e == (int64_t)pk.gsrc.size(), "gather entries", seed);
+        }
     }
 }
 
@@ -179,7 +207,7 @@ void run_threads(const Csr &c, int64_t seed)
         int rc = ingest_ilp(p[k].ilp, c.n_vars, c.cost.data(), c.n_rows(), c.row_ptr.data(), c.col.data(),
                             c.coef.data(), c.sense.data(), c.rhs.data(), msg);
         if (rc == ST_OK) rc = build_problem(p[k], msg);
-        if (rc == ST_OK) rc = pack_problem(p[k], 128, 0, true, 32.0 * (1 << 20), 2048, 16384, 16, pk[k], msg);
+        if (rc == ST_OK) rc = pack_problem(p[k], 128, 0, true, 32.0 * (1 << 20), 2048, 16384, 16, 4, pk[k], msg);
         check(rc == ST_OK, "threads: construction", seed);
         if (rc != ST_OK) {
             std::fprintf(stderr, "  %s\n", msg.c_str());
@@ -363,7 +391,8 @@ void run_merge(const std::vector<Csr> &cs, int variant, int64_t seed)
         if (rc == ST_OK) rc = build_problem(ps[k], msg);
         if (rc == ST_OK)
             rc = pack_problem(ps[k], variant == 3 ? 0 : 128, 0, variant != 4, variant == 1 ? 0.0 : 32.0 * (1 << 20),
-                              variant == 2 ? 0 : 2048, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, pks[k], msg);
+                              variant == 2 ? 0 : 2048, variant == 0 ? 0 : 16384, variant == 2 ? 3 : 16, 8, pks[k],
+                              msg);
         check(rc == ST_OK, "merge: instance alone", seed);
         if (rc != ST_OK) return;
         parts.push_back(Part{&ps[k], &pks[k]});

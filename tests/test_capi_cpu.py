@@ -28,7 +28,8 @@ def test_default_options():
     assert o.lb_every == 1 and o.rel_tol == 0.0 and o.tau < 0
     assert (o.fast_path, o.perturb_scale, o.sp_in_lds_max_nodes, o.graph_sweeps) == (1, 0, 0, 64)
     assert o.class_merge_kib == 32768 and o.small_tiles == 2048 and o.serial_mma == 0 and o.termination == 0
-    assert o.wide_min_width == 4 and o.wide_lanes == 32 and o.reserved[0] == 0
+    assert o.wide_min_width == 4 and o.wide_lanes == 32 and o.fused_average == 1 and o.persistent == 0
+    assert o.reserved == 0
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=1.5), dict(precision=16), dict(lb_every=0),
@@ -36,7 +37,8 @@ def test_default_options():
                                  dict(sp_in_lds_max_nodes=-2), dict(fast_path=2), dict(perturb_scale=2),
                                  dict(graph_sweeps=-1), dict(class_merge_kib=-1), dict(small_tiles=-1),
                                  dict(serial_mma=2), dict(termination=2), dict(wide_min_width=-1),
-                                 dict(wide_min_width=65536), dict(wide_lanes=8), dict(wide_lanes=48)])
+                                 dict(wide_min_width=65536), dict(wide_lanes=8), dict(wide_lanes=48),
+                                 dict(fused_average=2), dict(persistent=2), dict(reserved=1)])
 def test_invalid_options(bad):
     ilp = I.random_ilp(5, 3, seed=1)
     with pytest.raises(B.BddmmaError) as e:
@@ -302,3 +304,19 @@ def test_bind_static_rejects_problems_above_its_size():
     assert t.bddmma_bind_static(h, None) == B.STATE
     t.bddmma_destroy(h)
 
+
+@pytest.mark.parametrize("name,fused", [("mrf10x10L3", True), ("gm1000k10", False), ("track20x500", False),
+                                        ("mrf256x256L8", False)])
+def test_fused_averaging_eligibility(name, fused):
+    """the sweep averages the variables that span tiles itself when all of
+    them lie in mixed register tiles (small problems) in at most five
+    subproblems each; the matching and tracking workloads have variables in
+    up to 10 and 8 subproblems, the large grid's tiles share one topology: they
+    keep the averaging kernel; the option turns it off and the extra device
+    tables go with it"""
+    ilp = I.workload(name)
+    on = B.Solver(ilp)
+    off = B.Solver(ilp, fused_average=0)
+    assert (on.stats.n_fused_vars > 0) == fused
+    assert off.stats.n_fused_vars == 0
+    assert (on.workspace_bytes() > off.workspace_bytes()) == fused

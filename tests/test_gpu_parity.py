@@ -725,3 +725,81 @@ def test_batch_with_graph_replay_and_checkpoint():
     lbf, _, _ = b.batch_bounds()
     for k, a in enumerate(alone):
         assert abs(lbf[k] - a.lb_history()[-1]) <= 1e-12 * max(1.0, abs(lbf[k]))
+
+
+# ---------------------------------------------------------------- fused averaging
+def small_case(name):
+    if name == "random":
+        return I.random_ilp(300, 200, max_row_len=4, seed=23)
+    if name == "mrf32L8":
+        return I.mrf_grid(32, 32, 8, pairwise="trunc_linear", trunc=2, seed=1)
+    return I.workload(name)
+
+
+@pytest.mark.parametrize("name,prec", [("mrf10x10L3", 64), ("mrf10x10L3", 32), ("mrf32L8", 32), ("random", 64)])
+def test_fused_averaging_matches_averaging_kernel(name, prec):
+    """the sweep averaging the variables that span tiles itself (from the
+    per-variable copy of the previous differences) runs the averaging
+    kernel's operations in the same order: multipliers, differences, bound
+    history and rounding equal those of the separate averaging launch bit for
+    bit, eager and replayed from a graph, across a state load and a reset"""
+    ilp = small_case(name)
+    note("fused averaging", name, prec)
+    for graph in (0, 8):
+        fused = solver(ilp, precision=prec, graph_sweeps=graph)
+        plain = solver(ilp, precision=prec, graph_sweeps=graph, fused_average=0)
+        assert fused.stats.n_fused_vars > 0 and plain.stats.n_fused_vars == 0
+        for s in (fused, plain):
+            s.run_sweeps(3)
+            s.run_sweeps(18)
+        _same_run(fused, plain, "after 21 sweeps")
+        # an external state (the other solver's, perturbed) loaded into both
+        lam, mm, avg = plain.get_state()
+        lam = lam + (np.arange(lam.size) % 7 - 3) * 1e-3
+        for s in (fused, plain):
+            s.set_state(lam, mm, avg)
+            s.run_sweeps(9)
+        _same_run(fused, plain, "after a state load")
+        ra, rb = fused.round_primal(), plain.round_primal()
+        assert ra["rc"] == rb["rc"] and ra["rounds"] == rb["rounds"]
+        if ra["rc"] == 0:
+            assert np.array_equal(ra["x"], rb["x"]) and ra["ub"] == rb["ub"]
+        for s in (fused, plain):
+            s.reset()
+            s.run_dual(12)
+        _same_run(fused, plain, "after a reset")
+
+
+# ---------------------------------------------------------------- persistent kernel
+@pytest.mark.parametrize("name,prec", [("mrf10x10L3", 64), ("mrf10x10L3", 32), ("mrf32L8", 32), ("random", 64)])
+def test_persistent_kernel_matches_per_sweep_launches(name, prec):
+    """blocks of sweeps in one cooperative launch (grid barrier between
+    sweeps) give bit for bit the multipliers, differences and bound history of
+    one launch per sweep, from an even and an odd start, across blocks of the
+    bound-history capacity; in FP64 they also equal the reference"""
+    ilp = small_case(name)
+    note("persistent kernel", name, prec)
+    per = solver(ilp, precision=prec, graph_sweeps=0)
+    pst = solver(ilp, precision=prec, persistent=1)
+    assert pst.stats.persist_tiles == pst.stats.n_tiles > 0
+    for s in (per, pst):
+        s.run_sweeps(1)      # odd start: the block begins with a backward sweep
+        s.run_sweeps(40)
+        s.run_dual(600)      # more sweeps than one launch holds
+    _same_run(per, pst, "after 1241 sweeps")
+    if prec == 64:
+        o = O.Oracle(ilp, threads=oracle_threads())
+        o.init()
+        hist = []
+        for k in range(1241):    # sweep k runs direction k mod 2, as on the GPU
+            o.sweep(k % 2)
+            o.average()
+            hist.append(o.lb_free())
+        hist = np.asarray(hist[41:])
+        lam, mm, avg = pst.get_state()
+        rl, rm, ra = o.get()
+        assert np.array_equal(lam, rl) and np.array_equal(mm, rm)
+        g = pst.lb_history()[-1200:]
+        assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
+    r1, r2 = per.round_primal(), pst.round_primal()
+    assert r1["rc"] == r2["rc"] and r1["rounds"] == r2["rounds"]
