@@ -82,7 +82,7 @@ def log(msg):
 
 
 # device code: the kernels and the headers they are compiled with
-KERNEL_FILES = ("device_common.hpp", "kernels.hip", "kernels.hpp", "layout.hpp", "sweep_reg.hip")
+KERNEL_FILES = ("device_common.hpp", "kernels.hip", "kernels.hpp", "layout.hpp", "sweep_reg.hip", "sweep_tile.hpp")
 
 
 def kernel_sha() -> str:
