@@ -228,10 +228,12 @@ int bddmma_run_sweeps(bddmma_solver *s, int32_t n_sweeps);
 
 /* Lower bounds of the current state (any pointer may be NULL):
  *   lb_free  = sum_j E^j(lambda^j) + omega * sum_ij min(M_ij, 0)  of the last sweep;
- *   lb_cert  = sum_j E^j(lambda^j + omega M^j) - sum_i max(r_i, 0), computed in
- *              FP64 from the stored multipliers, with the multiplier residual
- *              r_i = sum_j (lambda_i^j + omega M_ij) - c_i (Appendix, proof of
- *              Prop. 1: this multiplier sum equals c_i);
+ *   lb_cert  = sum_j E^j(t'^j), the Lagrange dual (Sec. 3, problem (D)) at
+ *              dual-feasible multipliers, computed in FP64 from the stored
+ *              ones: t = lambda + omega M (the terminated multipliers; their
+ *              sum over J_i equals c_i in exact arithmetic, Appendix, proof of
+ *              Prop. 1), residual r_i = sum_j t_i^j - c_i (nonzero in FP32),
+ *              and t'_i^j = t_i^j - r_i / |J_i|, so sum_j t'_i^j = c_i;
  *   max_residual = max_i |r_i|.
  * Both bounds include the presolve constant.  Synchronises. */
 int bddmma_lower_bound(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_residual);
@@ -297,8 +299,8 @@ int bddmma_num_instances(const bddmma_solver *s, int64_t *n_inst);
 
 /* Per-instance bounds (arrays of n_inst doubles, each may be NULL):
  * lb_free of the most recent recorded sweep (STATE if there is none since
- * bind / reset / load_state), lb_cert with its residual correction and the
- * largest multiplier residual, as bddmma_lower_bound computes them for the
+ * bind / reset / load_state), lb_cert at the dual-feasible multipliers and
+ * the largest multiplier residual, as bddmma_lower_bound computes them for the
  * whole problem.  With lb_cert and max_res both NULL the certificate pass and
  * the residuals are skipped.  Synchronises the stream. */
 int bddmma_batch_bounds(bddmma_solver *s, double *lb_free, double *lb_cert, double *max_res);

@@ -672,13 +672,27 @@ static void terminated(const OSolver *s, double *t)
     }
 }
 
-/* LB_cert = sum_j E^j(t^j) - sum_i max(r_i, 0)  (+ offset), t the terminated
- * multipliers (lambda + omega M-bar by default), r_i = sum_j t_i^j - c_i */
+/* LB_cert = sum_j E^j(t'^j) (+ offset): the Lagrange dual (Sec. 3, problem
+ * (D)) at t', the terminated multipliers t (lambda + omega M-bar by default)
+ * made dual feasible by spreading each variable's residual
+ * r_i = sum_j t_i^j - c_i evenly over its subproblems:
+ * t'_i^j = t_i^j - r_i / |J_i|, so sum_j t'_i^j = c_i.  *max_residual gets
+ * max_i |r_i| of t itself. */
 double or_lb_cert(const OSolver *s, double *max_residual)
 {
     double *t = malloc(sizeof(double) * (size_t)(s->np > 0 ? s->np : 1));
     double *Ej = malloc(sizeof(double) * (size_t)(s->nb > 0 ? s->nb : 1));
     terminated(s, t);
+    double mr = 0.0;
+    for (long long i = 0; i < s->n_vars; ++i) {
+        if (s->deg[i] == 0) continue;
+        double sum = 0.0;
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) sum += t[s->vpair[q]];
+        const double r = sum - s->cost[i];
+        if (fabs(r) > mr) mr = fabs(r);
+        const double share = r / (double)s->deg[i];
+        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) t[s->vpair[q]] = t[s->vpair[q]] - share;
+    }
 #pragma omp parallel num_threads(s->nthreads)
     {
         double *F = malloc(sizeof(double) * (size_t)s->maxn);
@@ -695,18 +709,9 @@ double or_lb_cert(const OSolver *s, double *max_residual)
     double e = 0.0;
     for (int j = 0; j < s->nb; ++j) e += Ej[j];
     free(Ej);
-    double corr = 0.0, mr = 0.0;
-    for (long long i = 0; i < s->n_vars; ++i) {
-        if (s->deg[i] == 0) continue;
-        double sum = 0.0;
-        for (long long q = s->vptr[i]; q < s->vptr[i + 1]; ++q) sum += t[s->vpair[q]];
-        double r = sum - s->cost[i];
-        if (r > 0.0) corr += r;
-        if (fabs(r) > mr) mr = fabs(r);
-    }
     free(t);
     if (max_residual) *max_residual = mr;
-    return (e - corr) + s->lb_offset;
+    return e + s->lb_offset;
 }
 
 /* termination step of Alg. 1: lambda <- the terminated multipliers */

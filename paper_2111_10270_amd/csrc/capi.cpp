@@ -59,7 +59,7 @@ struct Layout {
     size_t lam, mm, lam_bak, mm_bak, mmx, avg;
     size_t pair_var, vptr, vslot, code, gbuckets, gslot, child, tiles, lists, layers, cost;
     size_t gmeta, gsrc, gbuf;   // fused averaging (single instances and static batches)
-    size_t lbpart, widepart, tile_e, red, lbh, counter, flag, x, xfull, scratch;
+    size_t lbpart, widepart, tile_e, red, share, lbh, counter, flag, x, xfull, scratch;
     size_t r_ptr, r_col, r_coef, r_sense, r_rhs, preset;
     size_t var_inst, tile_inst, row_inst, inst_var, inst_tile, inst_off, inst_tau, ochunk, oseg, opart, imask, xbest,
         ires;
@@ -184,6 +184,7 @@ Layout make_layout(const bddmma_solver &s)
     L.widepart = take((size_t)(pk.list_off[LIST_WIDE + 1] - pk.list_off[LIST_WIDE]) * kLanes * 8);
     L.tile_e = take(T * 8);
     L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
+    L.share = take((size_t)(V + 1) * 8);
     L.lbh = take((size_t)kLbhCap * 8);
     L.counter = take((size_t)(3 * NI + 16) * 4);
     L.flag = take(V + 1);
@@ -560,17 +561,18 @@ int lower_bound_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *ma
     terminated_pair<T>(s, lam, mm);
     double *red = s->ptr<double>(s->L.red);
     double *tile_e = s->ptr<double>(s->L.tile_e);
-    launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
+    double *share = s->ptr<double>(s->L.share);
+    launch_residual<T>(p, lam, mm, s->opt.omega, red, share, s->st);
+    launch_cert<T>(p, lam, mm, s->opt.omega, share, tile_e, s->st);
     launch_reduce_sum(tile_e, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, red + 2 * kRedBlocks + 4,
                       red + 3 * kRedBlocks + 8, s->st);
-    launch_residual<T>(p, lam, mm, s->opt.omega, red, s->st);
     int rc = check_launch();
     if (rc) return rc;
     double h[3];
     HIPCHK(hipMemcpyAsync(h, red, 16, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(h + 2, red + 3 * kRedBlocks + 8, 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    const double cert = h[2] - h[0];
+    const double cert = h[2];
     if (lb_cert) *lb_cert = cert;
     if (max_res) *max_res = h[1];
     if (lb_free) *lb_free = s->hist.empty() ? cert : s->hist.back();
@@ -799,12 +801,13 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
     if (lb_cert || max_res) {   // the certificate pass and the residuals only when asked for
         T *lam, *mm;
         terminated_pair<T>(s, lam, mm);
-        launch_cert<T>(p, lam, mm, s->opt.omega, tile_e, s->st);
-        launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
         const int64_t nc = (int64_t)s->ochunk.size() - 1;
-        double *opart = s->ptr<double>(s->L.opart);
+        double *opart = s->ptr<double>(s->L.opart), *share = s->ptr<double>(s->L.share);
         launch_residual_seg<T>(p, lam, mm, s->opt.omega, s->ptr<int64_t>(s->L.ochunk), nc,
-                               s->ptr<int64_t>(s->L.oseg), n, opart, opart + nc + 1, res + 2 * n, res + 3 * n, s->st);
+                               s->ptr<int64_t>(s->L.oseg), n, opart, opart + nc + 1, res + 2 * n, res + 3 * n, share,
+                               s->st);
+        launch_cert<T>(p, lam, mm, s->opt.omega, share, tile_e, s->st);
+        launch_seg_sum(tile_e, seg, n, off, res + n, s->st);
     }
     int rc = check_launch();
     if (rc) return rc;
@@ -813,7 +816,7 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
     HIPCHK(hipStreamSynchronize(s->st));
     for (int64_t k = 0; k < n; ++k) {
         if (lb_free) lb_free[k] = h[k];
-        if (lb_cert) lb_cert[k] = h[n + k] - h[2 * n + k];
+        if (lb_cert) lb_cert[k] = h[n + k];
         if (max_res) max_res[k] = h[3 * n + k];
     }
     return BDDMMA_OK;

@@ -421,10 +421,13 @@ __global__ __launch_bounds__(kLanes) void k_wide_lb(const double *__restrict__ p
     if (threadIdx.x == 0) tile_lb[list[blockIdx.x]] = e;
 }
 
-// E^j(lambda + omega M) of every lane in FP64, summed per tile
+// E^j(t') of every lane in FP64, summed per tile: t' = lambda + omega M -
+// share[i], the terminated multipliers made dual feasible (share[i] = r_i /
+// |J_i| from the residual kernel, share[n_vars] = 0 for padding slots)
 template <typename T, bool LDS>
 __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__restrict__ lam,
                                                     const T *__restrict__ mm, double omega,
+                                                    const double *__restrict__ share,
                                                     double *__restrict__ tile_e, const int32_t *__restrict__ list,
                                                     int64_t tile_count)
 {
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_cert(DevProblem P, const T *__rest
         const uint32_t le = uni(layers[h]), noff = le & 0xFFFFu, W = le >> 16, noffn = noff + W;
         const uint32_t Wn = (h + 1 < tv.K) ? (uni(layers[h + 1]) >> 16) : 0u;
         const uint32_t s = tv.pb + h * kLanes + lane;
-        const double cost = (double)lam[s] + omega * (double)mm[s];
+        const double cost = ((double)lam[s] + omega * (double)mm[s]) - share[P.pair_var[s]];
         for (uint32_t q = 0; q < Wn; ++q) F[(size_t)(noffn + q) * kLanes] = INF;
         for (uint32_t q = 0; q < W; ++q) {
             const double f = F[(size_t)(noff + q) * kLanes];
@@ -642,12 +645,13 @@ __global__ __launch_bounds__(256) void k_terminate(int64_t n, T *__restrict__ la
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_residual(DevProblem P, const T *__restrict__ lam,
                                                           const T *__restrict__ mm, double omega,
-                                                          double *__restrict__ red)
+                                                          double *__restrict__ red, double *__restrict__ share)
 {
     __shared__ double sh[kRedThreads];
     const int64_t per = (P.n_vars + gridDim.x - 1) / gridDim.x;
     const int64_t a = (int64_t)blockIdx.x * per, b = a + per < P.n_vars ? a + per : P.n_vars;
     double pos = 0.0, mx = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) share[P.n_vars] = 0.0;
     for (int64_t v = a + threadIdx.x; v < b; v += kRedThreads) {
         const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
         if (q0 == q1) continue;
@@ -657,6 +661,7 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(DevProblem P, const T 
             s += (double)lam[sl] + omega * (double)mm[sl];
         }
         const double r = s - P.cost[v];
+        share[v] = r / (double)(q1 - q0);
         if (r > 0.0) pos += r;
         mx = fmax(mx, fabs(r));
     }
@@ -897,11 +902,13 @@ __global__ __launch_bounds__(kRedThreads) void k_residual_chunk(DevProblem P, co
                                                                 const T *__restrict__ mm, double omega,
                                                                 const int64_t *__restrict__ chunk_begin,
                                                                 double *__restrict__ pos_out,
-                                                                double *__restrict__ max_out)
+                                                                double *__restrict__ max_out,
+                                                                double *__restrict__ share)
 {
     __shared__ double sh[kRedThreads];
     const int64_t a = chunk_begin[blockIdx.x], b = chunk_begin[blockIdx.x + 1];
     double pos = 0.0, mx = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) share[P.n_vars] = 0.0;
     for (int64_t v = a + threadIdx.x; v < b; v += kRedThreads) {
         const int32_t q0 = P.vptr[v], q1 = P.vptr[v + 1];
         if (q0 == q1) continue;
@@ -911,6 +918,7 @@ __global__ __launch_bounds__(kRedThreads) void k_residual_chunk(DevProblem P, co
             s += (double)lam[sl] + omega * (double)mm[sl];
         }
         const double r = s - P.cost[v];
+        share[v] = r / (double)(q1 - q0);
         if (r > 0.0) pos += r;
         mx = fmax(mx, fabs(r));
     }
@@ -1022,18 +1030,19 @@ void launch_sweep(const DevProblem &p, T *lam, T *mm, double *tile_lb, Omega<T> 
 }
 
 template <typename T>
-void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, double *tile_e, hipStream_t st)
+void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, const double *share, double *tile_e,
+                 hipStream_t st)
 {
     const int64_t nl = p.list_off[LIST_GEN_LDS_ALL + 1] - p.list_off[LIST_GEN_LDS_ALL];
     const int64_t ng = p.list_off[LIST_GEN_GLOB_ALL + 1] - p.list_off[LIST_GEN_GLOB_ALL];
     if (nl > 0) {
         const size_t lds = (size_t)kWavesPerBlock * kLanes * p.lds_lane_elems * sizeof(T);
         hipLaunchKernelGGL((k_cert<T, true>), dim3(grid8(nl, kWavesPerBlock)), dim3(kThreads), lds, st, p, lam, mm,
-                           omega, tile_e, p.lists + p.list_off[LIST_GEN_LDS_ALL], nl);
+                           omega, share, tile_e, p.lists + p.list_off[LIST_GEN_LDS_ALL], nl);
     }
     if (ng > 0)
         hipLaunchKernelGGL((k_cert<T, false>), dim3(grid8(ng, kWavesPerBlock)), dim3(kThreads), 0, st, p, lam, mm,
-                           omega, tile_e, p.lists + p.list_off[LIST_GEN_GLOB_ALL], ng);
+                           omega, share, tile_e, p.lists + p.list_off[LIST_GEN_GLOB_ALL], ng);
 }
 
 template <typename T>
@@ -1088,10 +1097,11 @@ void launch_terminate(const DevProblem &p, T *lam, const T *mm, T omega, hipStre
 }
 
 template <typename T>
-void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, hipStream_t st)
+void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, double *share,
+                     hipStream_t st)
 {
     const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (p.n_vars + 1023) / 1024));
-    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(kRedThreads), 0, st, p, lam, mm, omega, red);
+    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(kRedThreads), 0, st, p, lam, mm, omega, red, share);
     hipLaunchKernelGGL(k_residual_stage2, dim3(1), dim3(kRedThreads), 0, st, red, nb);
 }
 
@@ -1159,11 +1169,11 @@ void launch_take_x(const DevProblem &p, const uint8_t *x, uint8_t *xbest, const 
 template <typename T>
 void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, const int64_t *chunk_begin,
                          int64_t n_chunks, const int64_t *seg, int64_t n_inst, double *part_pos, double *part_max,
-                         double *pos, double *mx, hipStream_t st)
+                         double *pos, double *mx, double *share, hipStream_t st)
 {
     if (n_chunks > 0)
         hipLaunchKernelGGL((k_residual_chunk<T>), dim3((unsigned)n_chunks), dim3(kRedThreads), 0, st, p, lam, mm,
-                           omega, chunk_begin, part_pos, part_max);
+                           omega, chunk_begin, part_pos, part_max, share);
     if (n_inst > 0) {
         hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)n_inst), dim3(kRedThreads), 0, st, part_pos, seg,
                            (const double *)nullptr, pos);
@@ -1197,18 +1207,20 @@ void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st)
 
 #define BDDMMA_INSTANTIATE(T)                                                                                        \
     template void launch_sweep<T>(const DevProblem &, T *, T *, double *, Omega<T>, int, int, hipStream_t);         \
-    template void launch_cert<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);          \
+    template void launch_cert<T>(const DevProblem &, const T *, const T *, double, const double *, double *,        \
+                                 hipStream_t);                                                                       \
     template void launch_average<T>(const DevProblem &, T *, double, hipStream_t);                                  \
     template void launch_gather_refresh<T>(const DevProblem &, const T *, int, hipStream_t);                        \
     template void launch_average_all<T>(const DevProblem &, const T *, T *, double, hipStream_t);                   \
     template void launch_init<T>(const DevProblem &, T *, T *, hipStream_t);                                        \
     template void launch_terminate<T>(const DevProblem &, T *, const T *, T, hipStream_t);                          \
-    template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, hipStream_t);      \
+    template void launch_residual<T>(const DevProblem &, const T *, const T *, double, double *, double *,          \
+                                     hipStream_t);                                                                   \
     template void launch_conflicts<T>(const DevProblem &, const T *, double, const uint8_t *, int32_t *, int64_t,   \
                                       hipStream_t);                                                                  \
     template void launch_residual_seg<T>(const DevProblem &, const T *, const T *, double, const int64_t *,         \
                                          int64_t, const int64_t *, int64_t, double *, double *, double *, double *, \
-                                         hipStream_t);                                                               \
+                                         double *, hipStream_t);                                                     \
     template void launch_perturb<T>(const DevProblem &, T *, const T *, double, double, uint64_t, uint64_t, int,    \
                                     const uint8_t *, hipStream_t);                                                   \
     template void launch_decode<T>(const DevProblem &, const T *, uint8_t *, hipStream_t);                          \

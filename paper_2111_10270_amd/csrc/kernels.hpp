@@ -117,14 +117,18 @@ void launch_init(const DevProblem &p, T *lam, T *mm, hipStream_t st);
 template <typename T>
 void launch_terminate(const DevProblem &p, T *lam, const T *mm, T omega, hipStream_t st);
 
-// per-tile energies of lambda + omega * mm in FP64 into tile_e
+// per-tile energies in FP64 into tile_e at the dual-feasible multipliers
+// lam + omega * mm - share[i] (share from launch_residual / _seg)
 template <typename T>
-void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, double *tile_e, hipStream_t st);
+void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, const double *share, double *tile_e,
+                 hipStream_t st);
 
 // red[0] = sum_i max(r_i, 0), red[1] = max_i |r_i| with r_i = sum_j (lam + omega mm) - c_i;
-// red holds 2 + 2 * kRedBlocks doubles
+// red holds 2 + 2 * kRedBlocks doubles; share[i] = r_i / |J_i| ([n_vars + 1]
+// doubles, share[n_vars] = 0)
 template <typename T>
-void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, hipStream_t st);
+void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, double *share,
+                     hipStream_t st);
 
 // counter[k] = number of variables of instance k with a zero / disagreeing
 // min-marginal sign or a flag (counter[0..n_inst) is cleared first)
@@ -153,11 +157,12 @@ void launch_obj_chunks(const double *cost, const uint8_t *x, const int64_t *chun
                        int64_t n_vars, double *part, hipStream_t st);
 
 // per instance: pos[k] = sum max(r_i, 0), mx[k] = max |r_i| over its
-// variables, in the objective's chunks (part_* hold one value per chunk)
+// variables, in the objective's chunks (part_* hold one value per chunk);
+// share[i] = r_i / |J_i| as launch_residual
 template <typename T>
 void launch_residual_seg(const DevProblem &p, const T *lam, const T *mm, double omega, const int64_t *chunk_begin,
                          int64_t n_chunks, const int64_t *seg, int64_t n_inst, double *part_pos, double *part_max,
-                         double *pos, double *mx, hipStream_t st);
+                         double *pos, double *mx, double *share, hipStream_t st);
 
 // x_i = [M_i. < 0] for variables in some subproblem (0 elsewhere)
 template <typename T>

@@ -803,3 +803,40 @@ def test_persistent_kernel_matches_per_sweep_launches(name, prec):
         assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
     r1, r2 = per.round_primal(), pst.round_primal()
     assert r1["rc"] == r2["rc"] and r1["rounds"] == r2["rounds"]
+
+
+# ---------------------------------------------------------------- certified bound off the feasible set
+@pytest.mark.parametrize("prec", [64, 32])
+def test_lb_cert_at_infeasible_multipliers(prec):
+    """the certified bound of multipliers that do not sum to c (the state
+    after FP32 rounding): the hand-derived point of Example A gives OPT = -5
+    and max residual 1 exactly (dyadic values), and at perturbed multipliers
+    of small random ILPs the GPU equals the reference (FP64: 1e-12; FP32
+    multipliers are exact copies of the reference's rounded values)"""
+    from test_oracle import residual_point
+    ilp, _ = example_a()
+    t, mbar, g = residual_point()
+    s = solver(ilp, precision=prec)
+    s.set_state(t - 0.5 * mbar, mbar, np.zeros(4))
+    _, lbc, res = s.lower_bound()
+    assert lbc == float(g["lb_cert"][0][0]) and res == float(g["max_residual"][0][0])
+    rng = np.random.default_rng(5)
+    for seed in range(6):
+        ilp = I.random_ilp(30, 20, max_row_len=5, seed=700 + seed)
+        o = O.Oracle(ilp)
+        if o.status != O.OK:
+            continue
+        s = solver(ilp, precision=prec)
+        o.init()
+        o.run_dual(10)
+        lam, mm, avg = o.get()
+        lam = lam + rng.uniform(-0.5, 0.5, size=lam.size)
+        if prec == 32:   # the reference sees the values the FP32 state holds
+            lam, mm = lam.astype(np.float32).astype(np.float64), mm.astype(np.float32).astype(np.float64)
+        o.set(lam=lam, mm=mm, avg=avg)
+        s.set_state(lam, mm, avg)
+        _, lbc, res = s.lower_bound()
+        rc_, rres = o.lb_cert()
+        scale = max(1.0, abs(rc_))
+        assert abs(lbc - rc_) <= 1e-12 * scale * o.n_pairs, (seed, lbc, rc_)
+        assert abs(res - rres) <= 1e-12 * max(1.0, rres)

@@ -475,9 +475,10 @@ def residual_point():
 
 @pytest.mark.parametrize("with_mbar", [False, True])
 def test_lb_cert_residual_correction_hand_value(with_mbar):
-    """LB_cert subtracts sum_i max(r_i, 0) when the terminated multipliers do
-    not sum to c (the FP32 path always leaves such a residual): the hand
-    value of Example A at a point with r = (1, 0, -0.5, 0) is OPT = -5"""
+    """LB_cert evaluates the dual at the terminated multipliers made feasible
+    by spreading each residual over the variable's subproblems (the FP32 path
+    always leaves a residual): the hand value of Example A at a point with
+    r = (1, 0, -0.5, 0) is OPT = -5"""
     ilp, _ = example_a()
     t, mbar, g = residual_point()
     o = O.Oracle(ilp)
@@ -488,20 +489,34 @@ def test_lb_cert_residual_correction_hand_value(with_mbar):
         o.set(lam=t, mm=np.zeros(6), avg=np.zeros(4))
     lbc, res = o.lb_cert()
     assert lbc == float(g["lb_cert"][0][0]) and res == float(g["max_residual"][0][0])
-    # the energies of the derivation, by enumeration of each row's points
+    # the feasible multipliers and energies of the derivation, by enumeration
+    # of each row's points
+    deg = {0: 1, 1: 2, 2: 2, 3: 1}
+    pv = [0, 1, 2, 1, 2, 3]
+    r = [float(v) for v in g["residual"][0]]
+    tp = [t[p] - r[v] / deg[v] for p, v in enumerate(pv)]
+    assert tp == [float(v) for v in g["tp1"][0] + g["tp2"][0]]
     pts1 = brute.row_points([1, 1, 1], -1, 2)
     pts2 = brute.row_points([1, 1, -1], 0, 0)
-    e = [brute.ExactAlg1.energy(pts1, [Fraction(v) for v in t[:3]]),
-         brute.ExactAlg1.energy(pts2, [Fraction(v) for v in t[3:]])]
+    e = [brute.ExactAlg1.energy(pts1, [Fraction(v) for v in tp[:3]]),
+         brute.ExactAlg1.energy(pts2, [Fraction(v) for v in tp[3:]])]
     assert [float(v) for v in e] == [float(v) for v in g["energies"][0]]
+    assert sum(e) == Fraction(float(g["lb_cert"][0][0]))
     opt, _ = brute.ilp_opt(ilp)
     assert lbc <= float(opt)
 
 
 def _exact_cert(ilp, o, t):
-    """sum_j min over the enumerated points of row j of t^j . x (exact) and
-    the residuals r_i = sum_j t_i^j - c_i (exact)"""
+    """the residuals r_i = sum_j t_i^j - c_i (exact) and sum_j min over the
+    enumerated points of row j of t'^j . x (exact) at the feasible
+    t'_i^j = t_i^j - r_i/|J_i|"""
     pv, pr = o.pairs()
+    acc = [Fraction(0)] * ilp.n_vars
+    for p, v in enumerate(pv):
+        acc[v] += Fraction(float(t[p]))
+    deg = np.bincount(pv, minlength=ilp.n_vars)
+    rr = [acc[i] - Fraction(float(ilp.costs[i])) for i in range(ilp.n_vars)]
+    tp = [Fraction(float(t[p])) - rr[v] / int(deg[v]) for p, v in enumerate(pv)]
     e = Fraction(0)
     start = 0
     while start < pv.size:
@@ -514,23 +529,19 @@ def _exact_cert(ilp, o, t):
         fixed = o.fixed()
         rhs = int(b) - sum(coef[v] * int(fixed[v]) for v in coef if fixed[v] >= 0)
         pts = brute.row_points([coef[v] for v in vs], s, rhs)
-        e += brute.ExactAlg1.energy(pts, [Fraction(float(x)) for x in t[start:end]])
+        e += brute.ExactAlg1.energy(pts, tp[start:end])
         start = end
-    acc = [Fraction(0)] * ilp.n_vars
-    for p, v in enumerate(pv):
-        acc[v] += Fraction(float(t[p]))
-    used = np.bincount(pv, minlength=ilp.n_vars) > 0
-    r = [acc[i] - Fraction(float(ilp.costs[i])) for i in range(ilp.n_vars) if used[i]]
+    r = [rr[i] for i in range(ilp.n_vars) if deg[i] > 0]
     return e, r
 
 
 @pytest.mark.parametrize("seed", range(16))
 def test_lb_cert_is_a_bound_at_any_multipliers(seed):
-    """weak duality with the residual correction (Sec. 3, dual (D)): at
+    """weak duality at the projected multipliers (Sec. 3, dual (D)): at
     multipliers moved off the feasible set in both directions, from a point
     near the dual optimum and from the start, LB_cert stays <= the enumerated
-    optimum and equals the exact enumerated energies minus sum max(r, 0)
-    up to rounding"""
+    optimum and equals the exact enumerated energies at
+    t' = t - r_i/|J_i| up to rounding"""
     ilp = I.random_ilp(9, 6, max_row_len=5, seed=900 + seed)
     o = O.Oracle(ilp)
     if o.status != O.OK:
@@ -549,7 +560,7 @@ def test_lb_cert_is_a_bound_at_any_multipliers(seed):
             assert lbc <= float(opt) + 1e-12 * scale, (iters, amp, lbc, opt)
             t = (lam + d) + 0.5 * mm
             e, r = _exact_cert(ilp, o, t)
-            exact = e - sum(max(v, Fraction(0)) for v in r) + Fraction(o.lb_offset())
+            exact = e + Fraction(o.lb_offset())
             assert abs(lbc - float(exact)) <= 1e-12 * scale * max(1, o.n_pairs)
             assert abs(res - float(max((abs(v) for v in r), default=0))) <= 1e-12 * scale
 
