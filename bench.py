@@ -81,8 +81,8 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-# device code: the kernels and the headers they are compiled with
-KERNEL_FILES = ("device_common.hpp", "kernels.hip", "kernels.hpp", "layout.hpp", "sweep_reg.hip", "sweep_tile.hpp")
+# device code of the sweep kernel (the roofline kernel) and the headers it is compiled with
+KERNEL_FILES = ("device_common.hpp", "kernels.hpp", "layout.hpp", "sweep_reg.hip", "sweep_tile.hpp")
 
 
 def kernel_sha() -> str:

@@ -840,3 +840,35 @@ def test_lb_cert_at_infeasible_multipliers(prec):
         scale = max(1.0, abs(rc_))
         assert abs(lbc - rc_) <= 1e-12 * scale * o.n_pairs, (seed, lbc, rc_)
         assert abs(res - rres) <= 1e-12 * max(1.0, rres)
+
+
+def test_mrf512_first_sweeps_match_reference():
+    """the roofline workload of the benchmark (512x512 grid, 8 labels,
+    77,447,168 pairs, multipliers beyond the last-level cache) in its launch
+    configuration (FP32, eager launches): from lambda = c/|J| the GPU and the
+    FP64 reference run a forward and a backward sweep; multipliers,
+    min-marginal differences, LB_free and LB_cert agree within the scaled
+    1e-4 tolerance after each"""
+    ilp = I.workload("mrf512x512L8")
+    note("mrf512x512L8: load")
+    s = solver(ilp, precision=32, graph_sweeps=0)
+    note("mrf512x512L8: reference")
+    o = O.Oracle(ilp, threads=oracle_threads())
+    o.init()
+    sc = scale_of(ilp)
+    for k in range(2):
+        s.run_sweeps(1)
+        o.sweep(k)
+        o.average()
+        lam, mm, _ = s.get_state()
+        rl, rm, _ = o.get()
+        for name, g, r in (("lambda", lam, rl), ("M", mm, rm)):
+            ok, err = fp32_close(g, r, sc)
+            assert ok, (k, name, err)
+            note(f"  sweep {k + 1}: {name} max scaled error {err:.2e}")
+        del lam, mm, rl, rm
+        lbf = s.lb_history()[-1]
+        _, lc, _ = s.lower_bound()
+        rc_, _ = o.lb_cert()
+        assert abs(lbf - o.lb_free()) <= 1e-4 * abs(o.lb_free()), (k, lbf, o.lb_free())
+        assert abs(lc - rc_) <= 1e-4 * abs(rc_), (k, lc, rc_)
