@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--abl-deferred", type=int, default=1500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
+    ap.add_argument("--stream-sweep", action="store_true",
+                    help="only run the stream probe over a range of array sizes (the sweep's bandwidth ceiling "
+                         "with and without last-level-cache residency)")
     return ap.parse_args()
 
 
@@ -459,9 +462,10 @@ def compression(a, B, I, torch):
     return res
 
 
-def roofline_of(P, precision, sweep_ms, workload, traffic, note):
+def roofline_of(P, precision, sweep_ms, workload, traffic, note, stream=None):
     """roofline object of the sweep kernel: algorithmic bytes of one sweep
-    launch (BYTES_PER_PAIR per pair) over its average launch time"""
+    launch (BYTES_PER_PAIR per pair) over its average launch time; `stream`
+    is the stream probe at the sweep's array size (stream_ceiling)"""
     alg = BYTES_PER_PAIR[precision] * P
     achieved = alg / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -469,7 +473,35 @@ def roofline_of(P, precision, sweep_ms, workload, traffic, note):
             "kernel": "k_sweep_reg (updating sweep)", "workload": workload,
             "alg_bytes_per_launch": alg, "kernel_ms": sweep_ms,
             "traffic_GBs": traffic / (sweep_ms * 1e-3) / 1e9 if traffic and sweep_ms > 0 else None,
+            "stream_probe": stream,
+            "frac_of_stream": achieved / stream["GBs"] if achieved and stream else None,
             "note": note}
+
+
+def stream_ceiling(B, torch, n, precision, reps=10):
+    """bddmma_stream_probe over two arrays of n elements (the size of the
+    sweep's multipliers and differences): mean time of `reps` calls after two
+    warm-up calls, HIP events on the probe's stream; the arrays stay resident
+    between calls, as the sweep's do between sweeps"""
+    dt = torch.float32 if precision == 32 else torch.float64
+    x = torch.zeros(n, dtype=dt, device="cuda:0")
+    y = torch.ones(n, dtype=dt, device="cuda:0")
+    st = torch.cuda.current_stream(x.device)
+    for _ in range(2):
+        B.stream_probe(x, y, st)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        B.stream_probe(x, y, st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = 4 * n * x.element_size()
+    del x, y
+    torch.cuda.empty_cache()
+    return {"GBs": nbytes / (us * 1e-6) / 1e9, "us_per_call": us, "bytes_per_call": nbytes,
+            "elements_per_array": n, "kernel": "k_stream_probe"}
 
 
 def sweep_event_ms(s, B):
@@ -484,7 +516,7 @@ def hbm_leg(a, B, I, torch):
     sweep launch on the library's stream, iterations from the start"""
     ilp = I.workload(a.hbm_workload)
     s = B.Solver(ilp, precision=a.precision, graph_sweeps=0).bind("cuda:0")
-    P = s.stats.n_pairs
+    P, n_slots = s.stats.n_pairs, s.stats.n_slots
     s.run_dual(3)   # warm-up
     s.reset()
     torch.cuda.synchronize()
@@ -503,7 +535,8 @@ def hbm_leg(a, B, I, torch):
     torch.cuda.empty_cache()
     slot_bytes = BYTES_PER_PAIR[a.precision] / 2 * P
     r = roofline_of(P, a.precision, sweep_ms, a.hbm_workload, read_traffic(a.hbm_workload),
-                    f"multipliers + differences {slot_bytes / 1e6:.0f} MB > 256 MB last-level cache")
+                    f"multipliers + differences {slot_bytes / 1e6:.0f} MB > 256 MB last-level cache",
+                    stream_ceiling(B, torch, n_slots, a.precision))
     r.update({"sweep_launches_timed": launches, "pairs": P,
               "dual_iters_per_s": a.hbm_iters / (e0.elapsed_time(e1) * 1e-3), "workspace_bytes": ws,
               "lb_free": lbf, "lb_cert": lbc})
@@ -518,8 +551,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     # the serving stream is generated on forked host processes before any GPU work
-    serve_insts = gen_serving(a.serve) if a.serve > 0 and not (a.ablation or a.calibrate_copy or a.roofline_only) \
-        else None
+    serve_insts = gen_serving(a.serve) if a.serve > 0 and not (a.ablation or a.calibrate_copy or a.roofline_only
+                                                                  or a.stream_sweep) else None
     if serve_insts:
         log(f"serving: {len(serve_insts)} instances generated")
     import torch
@@ -545,6 +578,16 @@ def main():
 
     if a.ablation:
         print(json.dumps(ablation(a, B, I, torch)), flush=True)
+        return
+    if a.stream_sweep:
+        # elements per array: 2-8 Mi, then the slot counts of the 256x256 and
+        # 512x512 grids (8 labels), twice the latter
+        for prec, sizes in ((32, (2 << 20, 4 << 20, 8 << 20, 19390464, 38780928, 77709312, 155418624)),
+                            (64, (19390464, 77709312))):
+            for n in sizes:
+                r = stream_ceiling(B, torch, n, prec)
+                r.update({"precision": prec, "working_set_MB": r["bytes_per_call"] / 2e6})
+                print(json.dumps(r), flush=True)
         return
     if a.roofline_only:
         print(json.dumps({"roofline": hbm_leg(a, B, I, torch), "kernel_sha": kernel_sha()}), flush=True)
@@ -605,7 +648,8 @@ def main():
     lf, lc, res, r = results[-1]
     rl_main = roofline_of(P, a.precision, sweep_ms, a.workload, read_traffic(a.workload),
                           f"multipliers + differences {BYTES_PER_PAIR[a.precision] / 2 * P / 1e6:.0f} MB: resident "
-                          f"in the 256 MB last-level cache between sweeps, so this point is not an HBM measurement")
+                          f"in the 256 MB last-level cache between sweeps, so this point is not an HBM measurement",
+                          stream_ceiling(B, torch, st.n_slots, a.precision))
     out = {
         "metric": "dual iters/s & BDD arcs/s vs HBM roofline; batched solves/s, p50/p99 latency",
         "value": iters / wall,

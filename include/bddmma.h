@@ -543,6 +543,20 @@ int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *co
                     const int64_t *rhs, void *dev_ptr, size_t bytes, void *hip_stream, int32_t sweeps,
                     bddmma_options *best, double *us_per_sweep);
 
+/* Bandwidth ceiling of the updating sweep (for the roofline of Alg. 1's
+ * sweeps).  An updating sweep reads the multipliers and differences of each
+ * slot and writes both back in place; this call moves the same bytes in the
+ * same shape and computes nothing else: each wave owns 9 consecutive rows of
+ * 64 elements of both device arrays a and b (n elements each), loads all of
+ * them, then stores a_i + 1 and b_i * 2.  elem_bytes 4 (float) or 8
+ * (double).  One call moves 4 * n * elem_bytes bytes; its time at a given n
+ * bounds an updating sweep over arrays of that size on this device, including
+ * the last-level cache's share when both arrays fit in it.  The arrays are
+ * caller-owned device memory; asynchronous on hip_stream.  n = 0 does
+ * nothing.  INVALID_ARG for n < 0, another elem_bytes, or a NULL array with
+ * n > 0. */
+int bddmma_stream_probe(void *a, void *b, int64_t n, int32_t elem_bytes, void *hip_stream);
+
 const char *bddmma_last_error(void);
 
 #ifdef __cplusplus

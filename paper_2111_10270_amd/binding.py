@@ -30,7 +30,7 @@ EXPORTS = ("bddmma_options_default", "bddmma_create", "bddmma_destroy", "bddmma_
            "bddmma_pool_submit", "bddmma_pool_submit_loaded", "bddmma_pool_step", "bddmma_pool_wait_compiled",
            "bddmma_pool_poll", "bddmma_pool_result", "bddmma_pool_release", "bddmma_pool_destroy",
            "bddmma_pool_get_counters", "bddmma_run_serial", "bddmma_autotune", "bddmma_pool_primal",
-           "bddmma_encode_rows", "bddmma_bind_static")
+           "bddmma_encode_rows", "bddmma_bind_static", "bddmma_stream_probe")
 STATIC_WORKSPACE_BYTES = 64 << 20
 
 POOL_QUEUED, POOL_READY, POOL_ACTIVE, POOL_DONE, POOL_FAILED = 0, 1, 2, 3, 4
@@ -108,6 +108,7 @@ def lib():
             "bddmma_pool_get_counters": [P, P], "bddmma_run_serial": [P, i32, P], "bddmma_pool_primal": [P, i64, P],
             "bddmma_autotune": [P, i64, P, i64, P, P, P, P, P, P, C.c_size_t, P, i32, P, P],
             "bddmma_encode_rows": [i64, P, i64, P, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P],
+            "bddmma_stream_probe": [P, P, i64, i32, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -128,6 +129,19 @@ def _check(rc):
     if rc != OK:
         raise BddmmaError(rc, lib().bddmma_last_error().decode())
     return rc
+
+
+def stream_probe(a, b, stream=None):
+    """bddmma_stream_probe on two contiguous device tensors of one floating
+    dtype and size, asynchronous on `stream` (default: the current stream)"""
+    import torch
+    if a.dtype != b.dtype or a.dtype not in (torch.float32, torch.float64) or a.numel() != b.numel():
+        raise ValueError("stream_probe: two float32 or two float64 tensors of one size")
+    if not (a.is_cuda and b.is_cuda and a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("stream_probe: contiguous device tensors")
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    _check(lib().bddmma_stream_probe(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), a.numel(),
+                                     a.element_size(), C.c_void_p(st.cuda_stream)))
 
 
 def default_options(**kw) -> Options:

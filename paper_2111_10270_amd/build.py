@@ -13,7 +13,8 @@ LIB = os.path.join(PKG, "libbddmma.so")
 # (precision, direction, update) so its unrolled kernels compile in parallel
 UNITS = [("kernels.hip", "kernels", []), ("problem.cpp", "problem", []), ("capi.cpp", "capi", []), ("pool.cpp", "pool", []),
          ("assemble.hip", "assemble", []), ("serial.hip", "serial", []),
-         ("termination.hip", "termination", []), ("static_workspace.hip", "static_workspace", [])] + [
+         ("termination.hip", "termination", []), ("static_workspace.hip", "static_workspace", []),
+         ("stream_probe.hip", "stream_probe", [])] + [
     ("persist.hip", f"persist_{t}", [f"-DBDDMMA_PERSIST_T={t}"]) for t in ("float", "double")] + [
     ("sweep_reg.hip", f"sweep_reg_{t}_{d}_{u}",
      [f"-DBDDMMA_REG_T={t}", f"-DBDDMMA_REG_DIR={d}", f"-DBDDMMA_REG_UPD={u}"])

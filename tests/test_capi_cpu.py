@@ -320,3 +320,14 @@ def test_fused_averaging_eligibility(name, fused):
     assert (on.stats.n_fused_vars > 0) == fused
     assert off.stats.n_fused_vars == 0
     assert (on.workspace_bytes() > off.workspace_bytes()) == fused
+
+
+def test_stream_probe_rejects_bad_arguments():
+    """the bandwidth probe validates its arguments before any device call"""
+    t = B.lib()
+    assert t.bddmma_stream_probe(None, None, -1, 4, None) == B.INVALID_ARG
+    assert t.bddmma_stream_probe(None, None, 10, 2, None) == B.INVALID_ARG
+    assert "elem_bytes" in t.bddmma_last_error().decode()
+    assert t.bddmma_stream_probe(None, None, 10, 4, None) == B.INVALID_ARG
+    assert "NULL" in t.bddmma_last_error().decode()
+    assert t.bddmma_stream_probe(None, None, 0, 8, None) == B.OK
