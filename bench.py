@@ -478,6 +478,21 @@ def roofline_of(P, precision, sweep_ms, workload, traffic, note, stream=None):
             "note": note}
 
 
+def model_effective(N, P, V, iters_per_s, precision):
+    """bytes per iteration of the node-array cost model (FP32: every node's
+    two child indices and shortest paths, every pair's multiplier, difference,
+    variable index and gathered term, and the averaging's index and value per
+    pair, moved through HBM: 32 N + 56 P + 8 V) at the measured iteration
+    rate; null in FP64, for which the model fixes no byte count"""
+    if precision != 32 or not iters_per_s:
+        return None
+    b = 32 * N + 56 * P + 8 * V
+    return {"bytes_per_iteration": b, "GBs": b * iters_per_s / 1e9, "iters_per_s": iters_per_s,
+            "model": "32 N + 56 P + 8 V bytes per iteration",
+            "note": "the design keeps shortest paths in registers or LDS and shares node words, so it does not "
+                    "move these bytes; above the HBM peak by construction, not a roofline fraction"}
+
+
 def stream_ceiling(B, torch, n, precision, reps=10):
     """bddmma_stream_probe over two arrays of n elements (the size of the
     sweep's multipliers and differences): mean time of `reps` calls after two
@@ -516,7 +531,7 @@ def hbm_leg(a, B, I, torch):
     sweep launch on the library's stream, iterations from the start"""
     ilp = I.workload(a.hbm_workload)
     s = B.Solver(ilp, precision=a.precision, graph_sweeps=0).bind("cuda:0")
-    P, n_slots = s.stats.n_pairs, s.stats.n_slots
+    P, n_slots, st_n, st_v = s.stats.n_pairs, s.stats.n_slots, s.stats.n_nodes, s.stats.n_vars
     s.run_dual(3)   # warm-up
     s.reset()
     torch.cuda.synchronize()
@@ -540,6 +555,7 @@ def hbm_leg(a, B, I, torch):
     r.update({"sweep_launches_timed": launches, "pairs": P,
               "dual_iters_per_s": a.hbm_iters / (e0.elapsed_time(e1) * 1e-3), "workspace_bytes": ws,
               "lb_free": lbf, "lb_cert": lbc})
+    r["model_effective"] = model_effective(st_n, P, st_v, r["dual_iters_per_s"], a.precision)
     log(f"roofline leg on {a.hbm_workload} done")
     return r
 
@@ -668,6 +684,7 @@ def main():
                    "fused_average_vars": st.n_fused_vars, **({"options": extra} if extra else {})},
         "arcs_per_s": 2.0 * N * iters / wall,
         "dual_phase_iters_per_s": a.iters * a.steps / (dual_ms * 1e-3),
+        "model_effective": model_effective(N, P, V, a.iters * a.steps / (dual_ms * 1e-3), a.precision),
         "dual_phase_arcs_per_s": 2.0 * N * a.iters * a.steps / (dual_ms * 1e-3),
         "solves_per_s": a.steps / wall,
         "kernel_ms": {"sweep": sweep_ms},
