@@ -530,7 +530,8 @@ def hbm_leg(a, B, I, torch):
     fit the 256 MB last-level cache: eager launches, HIP events around every
     sweep launch on the library's stream, iterations from the start"""
     ilp = I.workload(a.hbm_workload)
-    s = B.Solver(ilp, precision=a.precision, graph_sweeps=0).bind("cuda:0")
+    extra = {k: int(v) for k, v in (o.split("=", 1) for o in a.opt)}
+    s = B.Solver(ilp, precision=a.precision, graph_sweeps=0, **extra).bind("cuda:0")
     P, n_slots, st_n, st_v = s.stats.n_pairs, s.stats.n_slots, s.stats.n_nodes, s.stats.n_vars
     s.run_dual(3)   # warm-up
     s.reset()

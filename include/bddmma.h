@@ -109,7 +109,7 @@ typedef struct {
                               when the BDDs' LDS regions would not fit one block).  32 */
     int32_t  fused_average;/* 1: when every variable that is not averaged inside one tile lies
                               in tiles of different BDDs on the register kernels (small
-                              problems) and in at most 16 subproblems, the sweep averages
+                              problems) and in at most five subproblems, the sweep averages
                               it itself from a per-variable copy of the previous
                               differences instead of a separate averaging launch per sweep
                               (same operations in the same order, so the same results);
