@@ -493,30 +493,38 @@ def model_effective(N, P, V, iters_per_s, precision):
                     "move these bytes; above the HBM peak by construction, not a roofline fraction"}
 
 
-def stream_ceiling(B, torch, n, precision, reps=10):
+def stream_ceiling(B, torch, n, precision, reps=10, placements=3):
     """bddmma_stream_probe over two arrays of n elements (the size of the
-    sweep's multipliers and differences): mean time of `reps` calls after two
-    warm-up calls, HIP events on the probe's stream; the arrays stay resident
-    between calls, as the sweep's do between sweeps"""
+    sweep's multipliers and differences), both halves of one buffer as in the
+    solver's workspace: mean time of `reps` calls after two warm-up calls, HIP
+    events on the probe's stream; the arrays stay resident between calls, as
+    the sweep's do between sweeps.  The rate depends on where the buffer lands
+    in memory, so `placements` buffers are held at once and the fastest is
+    reported (with every one's time)"""
     dt = torch.float32 if precision == 32 else torch.float64
-    x = torch.zeros(n, dtype=dt, device="cuda:0")
-    y = torch.ones(n, dtype=dt, device="cuda:0")
-    st = torch.cuda.current_stream(x.device)
-    for _ in range(2):
-        B.stream_probe(x, y, st)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        B.stream_probe(x, y, st)
-    e1.record(st)
-    torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / reps
-    nbytes = 4 * n * x.element_size()
-    del x, y
+    st = torch.cuda.current_stream(torch.device("cuda:0"))
+    bufs, times = [], []
+    for _ in range(placements):
+        buf = torch.zeros(2 * n, dtype=dt, device="cuda:0")
+        bufs.append(buf)
+        x, y = buf[:n], buf[n:]
+        y.fill_(1.0)
+        for _ in range(2):
+            B.stream_probe(x, y, st)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            B.stream_probe(x, y, st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e3 / reps)
+    nbytes = 4 * n * bufs[0].element_size()
+    del bufs
     torch.cuda.empty_cache()
-    return {"GBs": nbytes / (us * 1e-6) / 1e9, "us_per_call": us, "bytes_per_call": nbytes,
-            "elements_per_array": n, "kernel": "k_stream_probe"}
+    us = min(times)
+    return {"GBs": nbytes / (us * 1e-6) / 1e9, "us_per_call": us, "us_per_placement": times,
+            "bytes_per_call": nbytes, "elements_per_array": n, "kernel": "k_stream_probe"}
 
 
 def sweep_event_ms(s, B):

@@ -548,7 +548,8 @@ int bddmma_autotune(const bddmma_options *base, int64_t n_vars, const double *co
  * slot and writes both back in place; this call moves the same bytes in the
  * same shape and computes nothing else: each wave owns 9 consecutive rows of
  * 64 elements of both device arrays a and b (n elements each), loads all of
- * them, then stores a_i + 1 and b_i * 2.  elem_bytes 4 (float) or 8
+ * them, then stores a_i + 1 and b_i * 2; blocks map to rows as the sweeps'
+ * blocks map to tiles (consecutive rows on one XCD).  elem_bytes 4 (float) or 8
  * (double).  One call moves 4 * n * elem_bytes bytes; its time at a given n
  * bounds an updating sweep over arrays of that size on this device, including
  * the last-level cache's share when both arrays fit in it.  The arrays are

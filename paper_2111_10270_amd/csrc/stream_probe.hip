@@ -11,6 +11,7 @@
 #include <string>
 
 #include "bddmma.h"
+#include "device_common.hpp"
 #include "solver_internal.hpp"
 
 namespace {
@@ -40,10 +41,13 @@ __device__ __forceinline__ void stream_rows(T *__restrict__ a, T *__restrict__ b
     }
 }
 
+// blocks map to rows as the sweeps' blocks map to tiles (xcd_block: a run of
+// consecutive blocks per XCD; the grid is a multiple of 8, blocks past the
+// end have no rows)
 template <typename T>
 __global__ __launch_bounds__(64 * kProbeWaves) void k_stream_probe(T *__restrict__ a, T *__restrict__ b, int64_t n)
 {
-    const int64_t first = ((int64_t)blockIdx.x * kProbeWaves + (threadIdx.x >> 6)) * (kProbeRows * 64);
+    const int64_t first = (bddmma::xcd_block() * kProbeWaves + (threadIdx.x >> 6)) * (kProbeRows * 64);
     const int64_t base = first + (threadIdx.x & 63);
     // whole rows without per-lane checks, so that all loads are in flight
     // before the first value is used (as in the sweep, whose tiles are whole)
@@ -64,8 +68,8 @@ extern "C" int bddmma_stream_probe(void *a, void *b, int64_t n, int32_t elem_byt
     if (n == 0) return BDDMMA_OK;
     if (!a || !b) return set_error(BDDMMA_ERR_INVALID_ARG, "bddmma_stream_probe: NULL array");
     const int64_t per_block = (int64_t)kProbeRows * 64 * kProbeWaves;
-    const int64_t blocks = (n + per_block - 1) / per_block;
-    if (blocks > 0x7FFFFFFF) return set_error(BDDMMA_ERR_INVALID_ARG, "bddmma_stream_probe: n too large");
+    const int64_t blocks = ((n + per_block - 1) / per_block + 7) & ~int64_t(7);
+    if (blocks > 0x7FFFFFF8) return set_error(BDDMMA_ERR_INVALID_ARG, "bddmma_stream_probe: n too large");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_stream_probe<float>, dim3((unsigned)blocks), dim3(64 * kProbeWaves), 0, st,
