@@ -55,10 +55,10 @@ def parse():
                     help="only the roofline leg on --hbm-workload (for counter runs)")
     ap.add_argument("--no-profile", action="store_true",
                     help="diagnostic: time the steps without per-sweep HIP events (no roofline)")
-    ap.add_argument("--graph-sweeps", type=int, default=0, metavar="G",
-                    help="replay blocks of G sweeps from a captured HIP graph (kernel time then comes from a "
-                         "separate profiled pass after the timed steps); 0 = eager launches, whose sampled "
-                         "sweeps are timed inside the timed steps")
+    ap.add_argument("--graph-sweeps", type=int, default=64, metavar="G",
+                    help="replay blocks of G sweeps from a captured HIP graph, the library's default (kernel "
+                         "time then comes from a separate profiled pass after the timed steps); 0 = eager "
+                         "launches, whose sampled sweeps are timed inside the timed steps")
     ap.add_argument("--serve", type=int, default=512, metavar="N",
                     help="batched serving measurement over N instances of the mixed stream (0 = skip)")
     ap.add_argument("--serve-batch", type=int, default=16)
