@@ -23,7 +23,10 @@
  *    memory (256-byte aligned) and hands them over with bddmma_bind together
  *    with a HIP stream.  The library never frees the buffer; it must stay
  *    allocated until bddmma_destroy.  All device work is ordered on that
- *    stream; calls that return host values synchronise it.
+ *    stream; calls that return host values synchronise it.  A solver bound
+ *    with bddmma_bind keeps one pinned host buffer (hipHostMalloc, allocated
+ *    at its first readback, at most 512 MiB, freed by bddmma_destroy) for the
+ *    values it copies back; one bound with bddmma_bind_static does not.
  *  - Pair order: a "pair" is a (variable i, subproblem j) with i in I_j.
  *    Host-visible pair arrays list subproblems in ascending original row
  *    order and, inside one subproblem, variables in ascending id order.

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <thread>
@@ -120,6 +121,12 @@ struct bddmma_solver {
     bool has_ser = false;         // serial min-marginal averaging tables built
     SerialTables ser;
     int64_t ser_seg[2] = {0, 0};  // host staging of the energy segment
+    // pinned host buffer of the small per-solve readbacks (bounds, conflict
+    // counts, points): allocated at the first readback of a solver bound to
+    // caller memory, never for the static workspace or assembled batches
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    bool pin_tried = false;
 
     template <typename T>
     T *ptr(size_t off) const { return reinterpret_cast<T *>(dev + off); }
@@ -331,6 +338,58 @@ int reduce_history(bddmma_solver *s)
     return check_launch();
 }
 
+// One device-to-host transfer of a readback.
+struct Readback {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+constexpr size_t kPinBytes = size_t(1) << 20;     // first size of the pinned buffer
+constexpr size_t kPinMaxBytes = size_t(1) << 29;  // larger readbacks stay pageable
+
+// Device-to-host copies of `r`, then one synchronisation of the solver's
+// stream.  They go through the pinned buffer (a direct transfer, no staging
+// through pageable memory), which grows to the readback's size up to
+// kPinMaxBytes; beyond that, or without a pinned buffer, straight to their
+// destinations.
+int readback(bddmma_solver *s, std::initializer_list<Readback> r)
+{
+    size_t total = 0;
+    for (const Readback &x : r) total += (x.bytes + 7) & ~size_t(7);
+    if (!s->virt && s->static_dev < 0 && total <= kPinMaxBytes && total > s->pin_bytes &&
+        (!s->pin_tried || s->pin)) {
+        if (s->pin) (void)hipHostFree(s->pin);
+        s->pin = nullptr;
+        s->pin_bytes = 0;
+        s->pin_tried = true;
+        const size_t want = std::max(kPinBytes, total);
+        if (hipHostMalloc(&s->pin, want, hipHostMallocDefault) == hipSuccess) s->pin_bytes = want;
+        else {
+            s->pin = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    const bool via = s->pin && total <= s->pin_bytes;
+    size_t at = 0;
+    for (const Readback &x : r) {
+        if (x.bytes == 0) continue;
+        HIPCHK(hipMemcpyAsync(via ? static_cast<char *>(s->pin) + at : x.dst, x.src, x.bytes, hipMemcpyDeviceToHost,
+                              s->st));
+        at += (x.bytes + 7) & ~size_t(7);
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (via) {
+        at = 0;
+        for (const Readback &x : r) {
+            if (x.bytes == 0) continue;
+            std::memcpy(x.dst, static_cast<const char *>(s->pin) + at, x.bytes);
+            at += (x.bytes + 7) & ~size_t(7);
+        }
+    }
+    return BDDMMA_OK;
+}
+
 // every pending bound to the host
 int flush_history(bddmma_solver *s)
 {
@@ -338,9 +397,8 @@ int flush_history(bddmma_solver *s)
     if (rc) return rc;
     if (s->lbh_n == 0) return BDDMMA_OK;
     s->hist.resize((size_t)(s->hist_synced + s->lbh_n));
-    HIPCHK(hipMemcpyAsync(s->hist.data() + s->hist_synced, s->ptr<double>(s->L.lbh), (size_t)s->lbh_n * 8,
-                          hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    if ((rc = readback(s, {{s->hist.data() + s->hist_synced, s->ptr<double>(s->L.lbh), (size_t)s->lbh_n * 8}})))
+        return rc;
     s->hist_synced += s->lbh_n;
     s->lbh_n = 0;
     return BDDMMA_OK;
@@ -569,9 +627,7 @@ int lower_bound_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *ma
     int rc = check_launch();
     if (rc) return rc;
     double h[3];
-    HIPCHK(hipMemcpyAsync(h, red, 16, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipMemcpyAsync(h + 2, red + 3 * kRedBlocks + 8, 8, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    if ((rc = readback(s, {{h, red, 16}, {h + 2, red + 3 * kRedBlocks + 8, 8}}))) return rc;
     const double cert = h[2];
     if (lb_cert) *lb_cert = cert;
     if (max_res) *max_res = h[1];
@@ -712,8 +768,7 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
     for (int round = 0;; ++round) {
         launch_conflicts<T>(p, mm, s->tau, flag, cnt, n, s->st);
         if ((e = check_launch())) return e;
-        HIPCHK(hipMemcpyAsync(conf.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
-        HIPCHK(hipStreamSynchronize(s->st));
+        if ((e = readback(s, {{conf.data(), cnt, (size_t)n * 4}}))) return e;
         bool any = false;
         for (int64_t k = 0; k < n; ++k) {
             cand[k] = open[k] && conf[k] == 0;
@@ -726,8 +781,7 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
             launch_decode<T>(p, mm, xd, s->st);
             launch_check(p, xd, flag, cnt + n, mask, n, s->st);
             if ((e = check_launch())) return e;
-            HIPCHK(hipMemcpyAsync(bad.data(), cnt + n, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
-            HIPCHK(hipStreamSynchronize(s->st));
+            if ((e = readback(s, {{bad.data(), cnt + n, (size_t)n * 4}}))) return e;
             bool got = false;
             for (int64_t k = 0; k < n; ++k) {
                 take[k] = cand[k] && bad[k] == 0;
@@ -774,10 +828,9 @@ int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t>
     if ((e = check_launch())) return e;
     ub.resize((size_t)n);
     xfull.resize((size_t)V);
-    HIPCHK(hipMemcpyAsync(viol.data(), cnt + 2 * n, (size_t)n * 4, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipMemcpyAsync(ub.data(), res, (size_t)n * 8, hipMemcpyDeviceToHost, s->st));
-    if (V > 0) HIPCHK(hipMemcpyAsync(xfull.data(), xf, (size_t)V, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    if ((e = readback(s, {{viol.data(), cnt + 2 * n, (size_t)n * 4}, {ub.data(), res, (size_t)n * 8},
+                          {xfull.data(), xf, (size_t)V}})))
+        return e;
     status.resize((size_t)n);
     for (int64_t k = 0; k < n; ++k)
         status[k] = open[k] ? BDDMMA_ERR_NOT_CONVERGED : viol[k] ? BDDMMA_ERR_STATE : BDDMMA_OK;
@@ -812,8 +865,7 @@ int batch_bounds_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *m
     int rc = check_launch();
     if (rc) return rc;
     std::vector<double> h((size_t)(4 * n));
-    HIPCHK(hipMemcpyAsync(h.data(), res, (size_t)(4 * n) * 8, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    if ((rc = readback(s, {{h.data(), res, (size_t)(4 * n) * 8}}))) return rc;
     for (int64_t k = 0; k < n; ++k) {
         if (lb_free) lb_free[k] = h[k];
         if (lb_cert) lb_cert[k] = h[n + k];
@@ -1116,6 +1168,7 @@ void bddmma_destroy(bddmma_solver *s)
     drop_graph(s);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
     if (s->static_dev >= 0) bddmma::static_workspace_forget(s, s->static_dev);
+    if (s->pin) (void)hipHostFree(s->pin);
     delete s;
 }
 
