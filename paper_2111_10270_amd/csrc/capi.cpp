@@ -127,6 +127,7 @@ struct bddmma_solver {
     void *pin = nullptr;
     size_t pin_bytes = 0;
     bool pin_tried = false;
+    bool pin_owned = true;        // false: lent by a serving pool (solver_lend_pinned)
 
     template <typename T>
     T *ptr(size_t off) const { return reinterpret_cast<T *>(dev + off); }
@@ -357,7 +358,7 @@ int readback(bddmma_solver *s, std::initializer_list<Readback> r)
 {
     size_t total = 0;
     for (const Readback &x : r) total += (x.bytes + 7) & ~size_t(7);
-    if (!s->virt && s->static_dev < 0 && total <= kPinMaxBytes && total > s->pin_bytes &&
+    if (s->pin_owned && !s->virt && s->static_dev < 0 && total <= kPinMaxBytes && total > s->pin_bytes &&
         (!s->pin_tried || s->pin)) {
         if (s->pin) (void)hipHostFree(s->pin);
         s->pin = nullptr;
@@ -1168,7 +1169,7 @@ void bddmma_destroy(bddmma_solver *s)
     drop_graph(s);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
     if (s->static_dev >= 0) bddmma::static_workspace_forget(s, s->static_dev);
-    if (s->pin) (void)hipHostFree(s->pin);
+    if (s->pin && s->pin_owned) (void)hipHostFree(s->pin);
     delete s;
 }
 
@@ -1811,6 +1812,14 @@ int solver_load_virtual(bddmma_solver *s, const std::vector<const bddmma_solver 
     for (const bddmma_solver *q : parts) s->virt_tau.push_back(q->inst_tau[0]);
     return finish_load(s);
     GUARD_END
+}
+
+void solver_lend_pinned(bddmma_solver *s, void *pin, size_t bytes)
+{
+    if (!s || !pin || (s->pin && s->pin_owned)) return;
+    s->pin = pin;
+    s->pin_bytes = bytes;
+    s->pin_owned = false;
 }
 
 int solver_bind_static(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, int device)

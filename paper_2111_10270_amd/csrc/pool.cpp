@@ -63,6 +63,7 @@ struct Inst {
 
 constexpr double kNaN = std::numeric_limits<double>::quiet_NaN();
 constexpr size_t kAsmBytes = 8u << 20;   // copy descriptors of one assembly
+constexpr size_t kPoolPinBytes = 1u << 20; // pinned readback buffer lent to the batches
 
 double ms_since(std::chrono::steady_clock::time_point t)
 {
@@ -95,6 +96,7 @@ struct bddmma_pool {
     size_t half = 0;
     int side = 0;                   // arena half holding the assembled batch
     hipStream_t st = nullptr;       // the caller's stream: every batch launch
+    void *pin = nullptr;            // pinned host buffer lent to every batch for its readbacks
     bddmma_solver *batch = nullptr;
     bool bound = false;
     bddmma_pool_counters cnt{};
@@ -299,6 +301,7 @@ int reassemble(bddmma_pool *p)
     bddmma_solver *nb = nullptr;
     int rc = bddmma_create(&o, &nb);
     if (rc) return rc;
+    if (p->pin) solver_lend_pinned(nb, p->pin, kPoolPinBytes);
     std::vector<int64_t> off;
     size_t need = 0;
     auto t0 = std::chrono::steady_clock::now();
@@ -349,6 +352,7 @@ int round_members(bddmma_pool *p, const std::vector<Inst *> &mem, const std::vec
     bddmma_solver *rb = nullptr;
     int rc = bddmma_create(&o, &rb);
     if (rc) return rc;
+    if (p->pin) solver_lend_pinned(rb, p->pin, kPoolPinBytes);
     std::vector<int64_t> off;
     size_t need = 0;
     rc = solver_load_virtual(rb, parts, off);
@@ -448,6 +452,10 @@ int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stre
     p->half = half;
     p->st = (hipStream_t)hip_stream;
     p->bound = true;
+    if (!p->pin && hipHostMalloc(&p->pin, kPoolPinBytes, hipHostMallocDefault) != hipSuccess) {
+        p->pin = nullptr;   // the batches then read back through pageable memory
+        (void)hipGetLastError();
+    }
     prefetch_images(p);
     return BDDMMA_OK;
 }
@@ -749,6 +757,7 @@ void bddmma_pool_destroy(bddmma_pool *p)
         bddmma_destroy(kv.second->s);
         bddmma_destroy(kv.second->pre);
     }
+    if (p->pin) (void)hipHostFree(p->pin);
     delete p;
 }
 

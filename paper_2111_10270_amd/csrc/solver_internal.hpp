@@ -51,6 +51,11 @@ int solver_instance_multipliers(bddmma_solver *s, int64_t slot_off, const bddmma
 // later calls fail once another solver holds that device's array.
 int solver_bind_static(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, int device);
 
+// A pinned host buffer of `bytes` that s uses for its readbacks while it
+// fits, owned by the caller (a serving pool lends one to its batches); no
+// effect on a solver that already owns one.
+void solver_lend_pinned(bddmma_solver *s, void *pin, size_t bytes);
+
 // Whether s holds the static workspace of `device` (static_workspace.hip),
 // and its release when s is destroyed.
 bool static_workspace_held(const bddmma_solver *s, int device);
