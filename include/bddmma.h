@@ -399,7 +399,9 @@ int bddmma_pool_create(const bddmma_options *opt, int32_t max_active, int32_t ho
  * two equal halves the resident batch and the next one while it is
  * assembled.  An instance fits when the workspace bytes of all members (each
  * as if alone, an upper bound on the batch's) stay within one half and its
- * image fits the free image space.  Once per pool. */
+ * image fits the free image space.  The pool also allocates a pinned host
+ * buffer of 1 MiB (hipHostMalloc; freed by bddmma_pool_destroy) for its
+ * batches' readbacks.  Once per pool. */
 int bddmma_pool_bind(bddmma_pool *p, void *dev_ptr, size_t bytes, void *hip_stream);
 
 /* Queue one ILP (arguments as bddmma_load_ilp, copied during the call) for
