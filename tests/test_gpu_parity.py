@@ -350,6 +350,30 @@ def test_mrf10_fp64_200_iterations(path):
 
 
 @pytest.mark.parametrize("name", ["gm1000k10", "track20x500"])
+def test_gm_tracking_fp64_500_iterations(name):
+    """the matching and tracking workloads in FP64 (graph replay, the fused
+    and kernel averaging as the defaults choose): multipliers, differences
+    and averaged terms equal the reference's bit for bit after 500
+    iterations; bound history and certified bound within 1e-12"""
+    ilp = I.workload(name)
+    note(name, "fp64 500 iterations")
+    s = solver(ilp, precision=64)
+    o = O.Oracle(ilp, threads=oracle_threads())
+    o.init()
+    s.run_dual(500)
+    hist = o.run_dual(500)
+    g = s.lb_history()
+    assert g.shape == hist.shape
+    assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
+    lam, mm, avg = s.get_state()
+    rl, rm, ra = o.get()
+    assert np.array_equal(lam, rl) and np.array_equal(mm, rm) and np.array_equal(avg, ra)
+    lf, lc, res = s.lower_bound()
+    rc_, rres = o.lb_cert()
+    assert abs(lc - rc_) <= 1e-12 * abs(rc_)
+
+
+@pytest.mark.parametrize("name", ["gm1000k10", "track20x500"])
 def test_gm_tracking_fp32(name):
     ilp = I.workload(name)
     note(name, "fp32")
