@@ -484,6 +484,30 @@ def test_mrf256_trajectory_from_init():
     assert r["ub"] >= lc
 
 
+def test_mrf256_fp64_bitexact_50_iterations():
+    """the benchmark's instance in FP64 (graph replay, one-topology register
+    tiles, the averaging kernel): multipliers, differences and averaged terms
+    equal the reference's bit for bit after 50 iterations (100 sweeps); bound
+    history and certified bound within 1e-12"""
+    ilp = I.workload("mrf256x256L8")
+    note("mrf256x256L8 fp64: load")
+    s = solver(ilp, precision=64)
+    note("mrf256x256L8 fp64: reference")
+    o = O.Oracle(ilp, threads=oracle_threads())
+    o.init()
+    s.run_dual(50)
+    hist = o.run_dual(50)
+    g = s.lb_history()
+    assert g.shape == hist.shape
+    assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
+    lam, mm, avg = s.get_state()
+    rl, rm, ra = o.get()
+    assert np.array_equal(lam, rl) and np.array_equal(mm, rm) and np.array_equal(avg, ra)
+    lf, lc, res = s.lower_bound()
+    rc_, rres = o.lb_cert()
+    assert abs(lc - rc_) <= 1e-12 * abs(rc_)
+
+
 # ---------------------------------------------------------------- Alg. 2
 def test_rounding_fp64_matches_reference():
     cases = [example_a()[0], tie_example()]
