@@ -890,6 +890,30 @@ def test_lb_cert_at_infeasible_multipliers(prec):
         assert abs(res - rres) <= 1e-12 * max(1.0, rres)
 
 
+def test_mrf512_fp64_bitexact_3_iterations():
+    """the roofline workload in FP64, eager launches: all 77M multipliers,
+    differences and averaged terms equal the reference's bit for bit after 3
+    iterations (6 sweeps); bound history and certified bound within 1e-12"""
+    ilp = I.workload("mrf512x512L8")
+    note("mrf512x512L8 fp64: load")
+    s = solver(ilp, precision=64, graph_sweeps=0)
+    note("mrf512x512L8 fp64: reference")
+    o = O.Oracle(ilp, threads=oracle_threads())
+    o.init()
+    s.run_dual(3)
+    hist = o.run_dual(3)
+    g = s.lb_history()
+    assert g.shape == hist.shape
+    assert np.max(np.abs(g - hist)) <= 1e-12 * np.max(np.abs(hist))
+    lam, mm, avg = s.get_state()
+    rl, rm, ra = o.get()
+    assert np.array_equal(lam, rl) and np.array_equal(mm, rm) and np.array_equal(avg, ra)
+    del lam, mm, avg, rl, rm, ra
+    lf, lc, res = s.lower_bound()
+    rc_, rres = o.lb_cert()
+    assert abs(lc - rc_) <= 1e-12 * abs(rc_)
+
+
 def test_mrf512_first_sweeps_match_reference():
     """the roofline workload of the benchmark (512x512 grid, 8 labels,
     77,447,168 pairs, multipliers beyond the last-level cache) in its launch
