@@ -52,6 +52,9 @@ constexpr int64_t kHistBytes = 64ll << 20;  // device budget for per-tile bound 
 constexpr int64_t kLbhCap = 4096;           // reduced bounds kept on the device before a copy to the host
 constexpr int64_t kSerChunk = 256;          // serial iterations whose bounds stay on the device before a copy
 constexpr int kWideLdsBytes = 64 << 10;     // LDS of one wide-kernel block (one BDD)
+// red: residual results and partials (2 + 2 * kResidualBlocks doubles), then the
+// bound sum's scratch (kRedBlocks) and its result
+constexpr size_t kRedSumOff = 2 + 2 * (size_t)kResidualBlocks;
 constexpr int kLdsBytesPerLane = 512;       // 2 waves x 64 lanes x 512 B = 64 KiB per block
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -191,7 +194,7 @@ Layout make_layout(const bddmma_solver &s)
     L.lbpart = take((size_t)s.hist_chunk * T * 8);
     L.widepart = take((size_t)(pk.list_off[LIST_WIDE + 1] - pk.list_off[LIST_WIDE]) * kLanes * 8);
     L.tile_e = take(T * 8);
-    L.red = take((size_t)(3 * kRedBlocks + 16) * 8);
+    L.red = take((size_t)(kRedSumOff + kRedBlocks + 8) * 8);
     L.share = take((size_t)(V + 1) * 8);
     L.lbh = take((size_t)kLbhCap * 8);
     L.counter = take((size_t)(3 * NI + 16) * 4);
@@ -623,12 +626,12 @@ int lower_bound_T(bddmma_solver *s, double *lb_free, double *lb_cert, double *ma
     double *share = s->ptr<double>(s->L.share);
     launch_residual<T>(p, lam, mm, s->opt.omega, red, share, s->st);
     launch_cert<T>(p, lam, mm, s->opt.omega, share, tile_e, s->st);
-    launch_reduce_sum(tile_e, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, red + 2 * kRedBlocks + 4,
-                      red + 3 * kRedBlocks + 8, s->st);
+    launch_reduce_sum(tile_e, (int64_t)s->pk.tiles.size(), s->prob.lb_offset, red + kRedSumOff,
+                      red + kRedSumOff + kRedBlocks, s->st);
     int rc = check_launch();
     if (rc) return rc;
     double h[3];
-    if ((rc = readback(s, {{h, red, 16}, {h + 2, red + 3 * kRedBlocks + 8, 8}}))) return rc;
+    if ((rc = readback(s, {{h, red, 16}, {h + 2, red + kRedSumOff + kRedBlocks, 8}}))) return rc;
     const double cert = h[2];
     if (lb_cert) *lb_cert = cert;
     if (max_res) *max_res = h[1];

@@ -1100,7 +1100,9 @@ template <typename T>
 void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, double *share,
                      hipStream_t st)
 {
-    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (p.n_vars + 1023) / 1024));
+    // about two variables per thread: each thread's variables are dependent
+    // loads (slots, then values), so parallelism hides them
+    const int nb = (int)std::min<int64_t>(kResidualBlocks, std::max<int64_t>(1, (p.n_vars + 511) / 512));
     hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(kRedThreads), 0, st, p, lam, mm, omega, red, share);
     hipLaunchKernelGGL(k_residual_stage2, dim3(1), dim3(kRedThreads), 0, st, red, nb);
 }

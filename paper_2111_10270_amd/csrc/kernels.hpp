@@ -54,6 +54,7 @@ struct DevProblem {
 };
 
 constexpr int kRedBlocks = 512;
+constexpr int kResidualBlocks = 4096;   // blocks of launch_residual (partials in red)
 
 // Weights of the averaged term: w1 = omega, w2 = omega / 2 in working precision.
 template <typename T>
@@ -124,7 +125,7 @@ void launch_cert(const DevProblem &p, const T *lam, const T *mm, double omega, c
                  hipStream_t st);
 
 // red[0] = sum_i max(r_i, 0), red[1] = max_i |r_i| with r_i = sum_j (lam + omega mm) - c_i;
-// red holds 2 + 2 * kRedBlocks doubles; share[i] = r_i / |J_i| ([n_vars + 1]
+// red holds 2 + 2 * kResidualBlocks doubles; share[i] = r_i / |J_i| ([n_vars + 1]
 // doubles, share[n_vars] = 0)
 template <typename T>
 void launch_residual(const DevProblem &p, const T *lam, const T *mm, double omega, double *red, double *share,
