@@ -81,6 +81,28 @@ __device__ __forceinline__ T head_at(uint32_t head, const T (&nx)[W])
     else return head_lane<W>(head, nx);
 }
 
+// The update pass derives its arc tests anew in deep classes.  Kept from
+// the first pass, the tests of every layer do not fit in SGPRs and spill to
+// VGPR lanes, whose v_writelane / v_readlane pairs and wait states cost more
+// than the tests: in mixed tiles the per-lane compare masks from 6 layers
+// on, in tiles of one topology the 2 W^2 scalar penalties per layer (of
+// sizeof(T) / 4 SGPRs each) once they reach about 96 SGPRs.  Shallower
+// classes keep them.  The empty asm only makes the node words opaque to
+// the compiler; it emits no instruction.
+template <typename T, bool SH, int KMAX, int W>
+__device__ __forceinline__ void fresh_arcs(uint32_t (&wd)[KMAX][W])
+{
+    if constexpr (SH ? KMAX * 2 * W * W * (int)sizeof(T) / 4 >= 96 : KMAX >= 6) {
+#pragma unroll
+        for (int h = 0; h < KMAX; ++h)
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if constexpr (SH) asm volatile("" : "+s"(wd[h][q]));
+                else asm volatile("" : "+v"(wd[h][q]));
+            }
+    }
+}
+
 // UPD = false: min-marginal differences at fixed multipliers (Alg. 2),
 // written to mm, which is then output only.  With UPD the slots averaged by
 // the averaging kernel hold their averaged term in mm on entry (stored there
@@ -264,6 +286,7 @@ __device__ __forceinline__ void sweep_tile(const DevProblem &P, T *__restrict__ 
             }
         }
         // forward sweep with updates
+        fresh_arcs<T, SH>(wd);
         T f[W];
 #pragma unroll
         for (int q = 0; q < W; ++q) f[q] = q == 0 ? T(0) : INF;
@@ -321,6 +344,7 @@ __device__ __forceinline__ void sweep_tile(const DevProblem &P, T *__restrict__ 
             }
         }
         // backward sweep with updates
+        fresh_arcs<T, SH>(wd);
         T bn[W];
 #pragma unroll
         for (int q = 0; q < W; ++q) bn[q] = q == 0 ? T(0) : INF;   // terminal layer
