@@ -111,6 +111,7 @@ struct bddmma_solver {
     hipStream_t cap_st = nullptr; // private stream the sweep graph is captured on
     hipGraphExec_t graph = nullptr;
     int64_t graph_len = 0;        // sweeps per replay
+    bool rows_pending = false;    // original rows not yet on the device (upload_rows)
     bool prof = false;
     int prof_stride = 1;          // bracket every prof_stride-th sweep
     Events ev;
@@ -743,10 +744,35 @@ int min_marginals_T(bddmma_solver *s, double *out)
 // result.  Per instance: rounds (round index reached), status (OK,
 // NOT_CONVERGED, or STATE if the point violates an original row), ub; xfull
 // holds the points of the closed instances.
+// The original rows and presolved values (the exact check of a rounded
+// point) reach the device with the first rounding rather than at bind, so a
+// solve that never rounds (dual iterations and bounds only, as a serving
+// batch) does not move them.  Stream-ordered; the host tables stay alive in
+// the solver.
+int upload_rows(bddmma_solver *s)
+{
+    if (!s->rows_pending) return BDDMMA_OK;
+    const Layout &L = s->L;
+    const Ilp &ilp = s->prob.ilp;
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
+    };
+    HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
+    HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
+    HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
+    HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
+    HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
+    HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
+    s->rows_pending = false;
+    return BDDMMA_OK;
+}
+
 template <typename T>
 int round_T(bddmma_solver *s, std::vector<int32_t> &rounds, std::vector<int32_t> &status, std::vector<double> &ub,
             std::vector<uint8_t> &xfull)
 {
+    if (int rc = upload_rows(s)) return rc;
     const DevProblem &p = s->dp;
     const int64_t S = s->pk.n_slots, V = s->prob.ilp.n_vars, n = s->n_inst();
     T *lam = s->ptr<T>(s->L.lam), *mm = s->ptr<T>(s->L.mm);
@@ -947,12 +973,7 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
         }
         HIPCHK(up(L.gmeta, pk.gmeta.data(), pk.gmeta.size() * 4));
         HIPCHK(up(L.gsrc, pk.gsrc.data(), pk.gsrc.size() * 4));
-        HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
-        HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
-        HIPCHK(up(L.r_coef, s->coef32.data(), s->coef32.size() * 4));
-        HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
-        HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
-        HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
+        s->rows_pending = true;   // uploaded by the first rounding (upload_rows)
         HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
         HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
         if (s->has_ser) {
