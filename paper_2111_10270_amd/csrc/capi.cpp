@@ -744,8 +744,9 @@ int min_marginals_T(bddmma_solver *s, double *out)
 // result.  Per instance: rounds (round index reached), status (OK,
 // NOT_CONVERGED, or STATE if the point violates an original row), ub; xfull
 // holds the points of the closed instances.
-// The original rows and presolved values (the exact check of a rounded
-// point) reach the device with the first rounding rather than at bind, so a
+// The original rows, their instances and the presolved values (the exact
+// check of a rounded point) reach the device with the first rounding rather
+// than at bind, so a
 // solve that never rounds (dual iterations and bounds only, as a serving
 // batch) does not move them.  Stream-ordered; the host tables stay alive in
 // the solver.
@@ -764,6 +765,7 @@ int upload_rows(bddmma_solver *s)
     HIPCHK(up(L.r_sense, ilp.sense.data(), ilp.sense.size()));
     HIPCHK(up(L.r_rhs, ilp.rhs.data(), ilp.rhs.size() * 8));
     HIPCHK(up(L.preset, s->preset.data(), s->preset.size()));
+    HIPCHK(up(L.row_inst, s->pk.row_inst.data(), s->pk.row_inst.size() * 4));
     s->rows_pending = false;
     return BDDMMA_OK;
 }
@@ -955,9 +957,11 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     std::vector<Seg> segs;
     std::vector<int64_t> items;
     if (!as) {
-        HIPCHK(up(L.pair_var, pk.pair_var.data(), pk.pair_var.size() * 4));
         HIPCHK(up(L.vptr, pk.vptr.data(), pk.vptr.size() * 4));
         HIPCHK(up(L.vslot, pk.vslot.data(), pk.vslot.size() * 4));
+        // the variable of every slot follows from the lists just uploaded
+        launch_pair_var(s->ptr<int32_t>(L.vptr), s->ptr<int32_t>(L.vslot), s->prob.ilp.n_vars, pk.n_slots,
+                        s->ptr<int32_t>(L.pair_var), s->st);
         HIPCHK(up(L.code, pk.code.data(), pk.code.size() * 2));
         HIPCHK(up(L.gslot, pk.gslot.data(), pk.gslot.size() * 4));
         HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
@@ -974,8 +978,6 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
         HIPCHK(up(L.gmeta, pk.gmeta.data(), pk.gmeta.size() * 4));
         HIPCHK(up(L.gsrc, pk.gsrc.data(), pk.gsrc.size() * 4));
         s->rows_pending = true;   // uploaded by the first rounding (upload_rows)
-        HIPCHK(up(L.var_inst, pk.var_inst.data(), pk.var_inst.size() * 4));
-        HIPCHK(up(L.row_inst, pk.row_inst.data(), pk.row_inst.size() * 4));
         if (s->has_ser) {
             const SerialTables &q = s->ser;
             HIPCHK(up(L.sr_child, q.child.data(), q.child.size() * 4));
@@ -1044,6 +1046,8 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
         // instances (batches)
         HIPCHK(up(L.tile_inst, pk.tile_inst.data(), pk.tile_inst.size() * 4));
         HIPCHK(up(L.inst_var, ilp.inst_var.data(), ilp.inst_var.size() * 8));
+        if (!as && !pk.var_inst.empty())
+            launch_var_inst(s->ptr<int64_t>(L.inst_var), s->n_inst(), ilp.n_vars, s->ptr<int32_t>(L.var_inst), s->st);
         HIPCHK(up(L.inst_tile, pk.inst_tile.data(), pk.inst_tile.size() * 8));
         HIPCHK(up(L.inst_off, s->prob.inst_offset.data(), s->prob.inst_offset.size() * 8));
         HIPCHK(up(L.inst_tau, s->inst_tau.data(), s->inst_tau.size() * 8));

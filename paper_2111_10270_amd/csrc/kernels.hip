@@ -1230,6 +1230,48 @@ void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t 
     }
 }
 
+// pair_var from the variable -> slot lists (thread per variable); the
+// padding slots keep the value the caller filled in before (n_vars)
+__global__ __launch_bounds__(256) void k_pair_var(const int32_t *__restrict__ vptr,
+                                                  const int32_t *__restrict__ vslot, int64_t n_vars,
+                                                  int32_t *__restrict__ pair_var)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vars) return;
+    for (int32_t q = vptr[v]; q < vptr[v + 1]; ++q) pair_var[vslot[q]] = (int32_t)v;
+}
+
+// instance of every variable from the instances' first variables:
+// var_inst[v] = k with inst_var[k] <= v < inst_var[k + 1]
+__global__ __launch_bounds__(256) void k_var_inst(const int64_t *__restrict__ inst_var, int64_t n_inst,
+                                                  int64_t n_vars, int32_t *__restrict__ var_inst)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vars) return;
+    int64_t lo = 0, hi = n_inst;   // inst_var[lo] <= v < inst_var[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (inst_var[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    var_inst[v] = (int32_t)lo;
+}
+
+void launch_pair_var(const int32_t *vptr, const int32_t *vslot, int64_t n_vars, int64_t n_slots, int32_t *pair_var,
+                     hipStream_t st)
+{
+    launch_fill<int32_t>(pair_var, (int32_t)n_vars, n_slots, st);
+    if (n_vars > 0)
+        hipLaunchKernelGGL(k_pair_var, dim3(blocks_for(n_vars, 256)), dim3(256), 0, st, vptr, vslot, n_vars, pair_var);
+}
+
+void launch_var_inst(const int64_t *inst_var, int64_t n_inst, int64_t n_vars, int32_t *var_inst, hipStream_t st)
+{
+    if (n_vars > 0 && n_inst > 0)
+        hipLaunchKernelGGL(k_var_inst, dim3(blocks_for(n_vars, 256)), dim3(256), 0, st, inst_var, n_inst, n_vars,
+                           var_inst);
+}
+
 template <typename T>
 void launch_fill(T *dst, T value, int64_t n, hipStream_t st)
 {

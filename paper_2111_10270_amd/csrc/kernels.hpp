@@ -199,6 +199,13 @@ void launch_check(const DevProblem &p, const uint8_t *x, uint8_t *flag, int32_t 
 template <typename T>
 void launch_fill(T *dst, T value, int64_t n, hipStream_t st);
 
+// tables derived on the device at bind instead of uploaded: the variable of
+// every pair slot (n_vars for padding slots) from the variable -> slot lists,
+// and the instance of every variable from the instances' first variables
+void launch_pair_var(const int32_t *vptr, const int32_t *vslot, int64_t n_vars, int64_t n_slots, int32_t *pair_var,
+                     hipStream_t st);
+void launch_var_inst(const int64_t *inst_var, int64_t n_inst, int64_t n_vars, int32_t *var_inst, hipStream_t st);
+
 template <typename T>
 void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
 
