@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -750,6 +751,8 @@ int min_marginals_T(bddmma_solver *s, double *out)
 // solve that never rounds (dual iterations and bounds only, as a serving
 // batch) does not move them.  Stream-ordered; the host tables stay alive in
 // the solver.
+hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool alloc);
+
 int upload_rows(bddmma_solver *s)
 {
     if (!s->rows_pending) return BDDMMA_OK;
@@ -757,7 +760,7 @@ int upload_rows(bddmma_solver *s)
     const Ilp &ilp = s->prob.ilp;
     auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
         if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
+        return stage_upload(s->dev + off, src, n, s->st, s->static_dev < 0);
     };
     HIPCHK(up(L.r_ptr, ilp.row_ptr.data(), ilp.row_ptr.size() * 8));
     HIPCHK(up(L.r_col, ilp.col.data(), ilp.col.size() * 4));
@@ -938,7 +941,90 @@ struct Assembly {
     size_t scratch_bytes;
 };
 
-int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, const Assembly *as)
+// Host -> device copies of bind go through one pinned buffer per device,
+// shared by all solvers of the process: host threads copy a chunk of a table
+// into one half while the copy engine drains the other.  The runtime copies
+// pageable memory it has not seen before several times slower, and bind's
+// tables are always such memory.  The buffer and its two events are made by
+// the first bind on the device that may allocate and kept until the process
+// ends.
+constexpr size_t kStageHalf = size_t(32) << 20;
+constexpr size_t kStageMin = size_t(1) << 20;   // smaller tables are copied directly
+constexpr int kStageThreads = 8;
+constexpr int kStageDevices = 64;
+
+struct Stager {
+    std::mutex mu;         // guards everything below
+    char *buf = nullptr;   // 2 x kStageHalf pinned bytes
+    hipEvent_t done[2] = {nullptr, nullptr};
+    int half = 0;          // the half the next chunk goes to
+    bool tried = false;
+};
+
+// dst[0, n) = src[0, n) on up to kStageThreads host threads; ranges whose
+// thread could not be started are copied by the calling thread
+void copy_parallel(char *dst, const char *src, size_t n)
+{
+    const size_t per = (n + kStageThreads - 1) / kStageThreads;
+    const int nr = per ? (int)((n + per - 1) / per) : 0;
+    auto range = [=](int t) { std::memcpy(dst + t * per, src + t * per, std::min(per, n - t * per)); };
+    std::vector<std::thread> th;
+    int spawned = 1;   // ranges 1 .. spawned-1 run on threads of their own
+    try {
+        for (int t = 1; t < nr; ++t) {
+            th.emplace_back(range, t);
+            spawned = t + 1;
+        }
+    } catch (...) {
+    }
+    for (int t = 0; t < nr; ++t)
+        if (t == 0 || t >= spawned) range(t);
+    for (std::thread &x : th) x.join();
+}
+Stager g_stager[kStageDevices];
+
+// copy [src, src + n) to device memory dst on stream st; alloc: the buffer
+// may be made here
+hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool alloc)
+{
+    int dev = 0;
+    if (n < kStageMin || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStageDevices)
+        return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    Stager &g = g_stager[dev];
+    std::lock_guard<std::mutex> lk(g.mu);
+    if (!g.buf && !g.tried && alloc) {
+        g.tried = true;
+        void *b = nullptr;
+        if (hipHostMalloc(&b, 2 * kStageHalf, hipHostMallocDefault) == hipSuccess) {
+            if (hipEventCreateWithFlags(&g.done[0], hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&g.done[1], hipEventDisableTiming) == hipSuccess) {
+                g.buf = static_cast<char *>(b);
+            } else {
+                for (hipEvent_t &e : g.done)
+                    if (e) (void)hipEventDestroy(e);
+                g.done[0] = g.done[1] = nullptr;
+                (void)hipHostFree(b);
+            }
+        }
+        (void)hipGetLastError();
+    }
+    if (!g.buf) return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    for (size_t at = 0; at < n; at += kStageHalf) {
+        const size_t c = std::min(kStageHalf, n - at);
+        char *h = g.buf + (size_t)g.half * kStageHalf;
+        // the copy engine is done with this half (an event never recorded is complete)
+        hipError_t e = hipEventSynchronize(g.done[g.half]);
+        if (e != hipSuccess) return e;
+        copy_parallel(h, static_cast<const char *>(src) + at, c);
+        if ((e = hipMemcpyAsync(dst + at, h, c, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+        if ((e = hipEventRecord(g.done[g.half], st)) != hipSuccess) return e;
+        g.half ^= 1;
+    }
+    return hipSuccess;
+}
+
+int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, const Assembly *as,
+              bool static_bind = false)
 {
     if (!s) return fail(BDDMMA_ERR_INVALID_ARG, "solver is NULL");
     if (!s->loaded) return fail(BDDMMA_ERR_STATE, "no ILP loaded");
@@ -952,7 +1038,7 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
     const Layout &L = s->L;
     auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
         if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(s->dev + off, src, n, hipMemcpyHostToDevice, s->st);
+        return stage_upload(s->dev + off, src, n, s->st, !static_bind);
     };
     std::vector<Seg> segs;
     std::vector<int64_t> items;
@@ -1855,7 +1941,7 @@ int solver_bind_static(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_
     GUARD_BEGIN
     Range rg(true, "bddmma bind_static");
     if (s && s->virt) return fail(BDDMMA_ERR_STATE, "an assembled batch is bound by its pool");
-    int rc = bind_impl(s, dev_ptr, bytes, hip_stream, nullptr);
+    int rc = bind_impl(s, dev_ptr, bytes, hip_stream, nullptr, true);
     if (rc == BDDMMA_OK) s->static_dev = device;
     return rc;
     GUARD_END
