@@ -758,6 +758,13 @@ int upload_rows(bddmma_solver *s)
     if (!s->rows_pending) return BDDMMA_OK;
     const Layout &L = s->L;
     const Ilp &ilp = s->prob.ilp;
+    // the coefficients in 32 bits and each variable's presolved value (-1 free)
+    s->coef32.assign(ilp.coef.begin(), ilp.coef.end());
+    s->preset.assign((size_t)ilp.n_vars, -1);
+    for (int64_t i = 0; i < ilp.n_vars; ++i) {
+        if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
+        else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
+    }
     auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
         if (n == 0) return hipSuccess;
         return stage_upload(s->dev + off, src, n, s->st, s->static_dev < 0);
@@ -1053,14 +1060,6 @@ int bind_impl(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream, c
         HIPCHK(up(L.child, pk.child.data(), pk.child.size() * 4));
         HIPCHK(up(L.layers, pk.layers.data(), pk.layers.size() * 4));
         HIPCHK(up(L.cost, s->prob.ilp.cost.data(), s->prob.ilp.cost.size() * 8));
-        // original rows and presolved values, for the final exact check of a primal point
-        const Ilp &ilp = s->prob.ilp;
-        s->coef32.assign(ilp.coef.begin(), ilp.coef.end());
-        s->preset.assign((size_t)ilp.n_vars, -1);
-        for (int64_t i = 0; i < ilp.n_vars; ++i) {
-            if (s->prob.fixed[i] >= 0) s->preset[i] = s->prob.fixed[i];
-            else if (s->prob.deg[i] == 0) s->preset[i] = ilp.cost[i] < 0.0 ? 1 : 0;
-        }
         HIPCHK(up(L.gmeta, pk.gmeta.data(), pk.gmeta.size() * 4));
         HIPCHK(up(L.gsrc, pk.gsrc.data(), pk.gsrc.size() * 4));
         s->rows_pending = true;   // uploaded by the first rounding (upload_rows)
