@@ -27,6 +27,11 @@
  *    with bddmma_bind keeps one pinned host buffer (hipHostMalloc, allocated
  *    at its first readback, at most 512 MiB, freed by bddmma_destroy) for the
  *    values it copies back; one bound with bddmma_bind_static does not.
+ *    Uploads of 1 MB or more go through one pinned host buffer per device
+ *    (64 MiB, two halves filled by host threads while the other is copied),
+ *    shared by all solvers of the process, made by the first bddmma_bind on
+ *    that device and kept until the process ends; bddmma_bind_static never
+ *    makes it (it uses it when it exists).
  *  - Pair order: a "pair" is a (variable i, subproblem j) with i in I_j.
  *    Host-visible pair arrays list subproblems in ascending original row
  *    order and, inside one subproblem, variables in ascending id order.
@@ -187,6 +192,8 @@ int bddmma_workspace_bytes(const bddmma_solver *s, size_t *bytes);
  * bytes) and a HIP stream (hipStream_t passed as void*, NULL = null stream).
  * Copies the packed problem to the device and initialises the dual state:
  * lambda_i^j = c_i / |J_i| and M-bar = 0 (Alg. 1 initialisation, Sec. 3).
+ * The original rows (only the exact check of a rounded point reads them) are
+ * copied by the first rounding call instead.
  * Errors: NO_MEMORY (bytes too small), INVALID_ARG (NULL / misaligned),
  * STATE (not loaded or already bound), HIP. */
 int bddmma_bind(bddmma_solver *s, void *dev_ptr, size_t bytes, void *hip_stream);
