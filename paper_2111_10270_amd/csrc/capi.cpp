@@ -997,6 +997,14 @@ hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bo
     int dev = 0;
     if (n < kStageMin || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStageDevices)
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    // the buffer's events belong to the current device: a stream of another
+    // device copies directly
+    hipDevice_t sdev = dev;
+    if (st && hipStreamGetDevice(st, &sdev) != hipSuccess) {
+        (void)hipGetLastError();   // the failed query's own error
+        sdev = -1;
+    }
+    if (sdev != dev) return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
     Stager &g = g_stager[dev];
     std::lock_guard<std::mutex> lk(g.mu);
     if (!g.buf && !g.tried && alloc) {
@@ -1013,7 +1021,7 @@ hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bo
                 (void)hipHostFree(b);
             }
         }
-        (void)hipGetLastError();
+        if (!g.buf) (void)hipGetLastError();   // the failed allocation's own error
     }
     if (!g.buf) return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
     for (size_t at = 0; at < n; at += kStageHalf) {
