@@ -30,8 +30,8 @@
  *    Uploads of 1 MB or more go through one pinned host buffer per device
  *    (64 MiB, two halves filled by host threads while the other is copied),
  *    shared by all solvers of the process, made by the first bddmma_bind on
- *    that device and kept until the process ends; bddmma_bind_static never
- *    makes it (it uses it when it exists).
+ *    that device and kept until the process ends; a solver bound with
+ *    bddmma_bind_static copies directly and starts no host thread.
  *  - Pair order: a "pair" is a (variable i, subproblem j) with i in I_j.
  *    Host-visible pair arrays list subproblems in ascending original row
  *    order and, inside one subproblem, variables in ascending id order.

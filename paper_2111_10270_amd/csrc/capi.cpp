@@ -751,7 +751,7 @@ int min_marginals_T(bddmma_solver *s, double *out)
 // solve that never rounds (dual iterations and bounds only, as a serving
 // batch) does not move them.  Stream-ordered; the host tables stay alive in
 // the solver.
-hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool alloc);
+hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool staged);
 
 int upload_rows(bddmma_solver *s)
 {
@@ -953,8 +953,8 @@ struct Assembly {
 // into one half while the copy engine drains the other.  The runtime copies
 // pageable memory it has not seen before several times slower, and bind's
 // tables are always such memory.  The buffer and its two events are made by
-// the first bind on the device that may allocate and kept until the process
-// ends.
+// the first staged bind on the device (static binds copy directly) and kept
+// until the process ends.
 constexpr size_t kStageHalf = size_t(32) << 20;
 constexpr size_t kStageMin = size_t(1) << 20;   // smaller tables are copied directly
 constexpr int kStageThreads = 8;
@@ -990,12 +990,13 @@ void copy_parallel(char *dst, const char *src, size_t n)
 }
 Stager g_stager[kStageDevices];
 
-// copy [src, src + n) to device memory dst on stream st; alloc: the buffer
-// may be made here
-hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool alloc)
+// copy [src, src + n) to device memory dst on stream st; staged: through the
+// buffer (made here if need be), else directly (static binds: no host
+// threads, no allocation)
+hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bool staged)
 {
     int dev = 0;
-    if (n < kStageMin || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStageDevices)
+    if (!staged || n < kStageMin || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStageDevices)
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
     // the buffer's events belong to the current device: a stream of another
     // device copies directly
@@ -1007,7 +1008,7 @@ hipError_t stage_upload(char *dst, const void *src, size_t n, hipStream_t st, bo
     if (sdev != dev) return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
     Stager &g = g_stager[dev];
     std::lock_guard<std::mutex> lk(g.mu);
-    if (!g.buf && !g.tried && alloc) {
+    if (!g.buf && !g.tried) {
         g.tried = true;
         void *b = nullptr;
         if (hipHostMalloc(&b, 2 * kStageHalf, hipHostMallocDefault) == hipSuccess) {
