@@ -87,8 +87,10 @@ typedef struct {
                               (rounded down to an even number, capped by the bound-history
                               capacity) from a captured HIP graph, which removes the
                               per-launch host cost of small problems; results are
-                              identical to eager launches.  Not used while profiling.
-                              0 = eager launches.  64 */
+                              identical to eager launches.  A solver captures the graph
+                              in its second run of sweeps, or in a first run of at
+                              least eight blocks, and replays it from then on.  Not
+                              used while profiling.  0 = eager launches.  64 */
     int32_t  class_merge_kib; /* register-kernel tiles of a layer class are padded into the
                               next larger class of their kind while the padding costs at
                               most this many KiB of traffic per sweep (fewer launches);

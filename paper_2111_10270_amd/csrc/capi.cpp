@@ -113,6 +113,7 @@ struct bddmma_solver {
     hipGraphExec_t graph = nullptr;
     int64_t graph_len = 0;        // sweeps per replay
     bool rows_pending = false;    // original rows not yet on the device (upload_rows)
+    int64_t sweep_runs = 0;       // calls of run_sweeps_T so far (graph capture)
     bool prof = false;
     int prof_stride = 1;          // bracket every prof_stride-th sweep
     Events ev;
@@ -481,7 +482,13 @@ int run_sweeps_T(bddmma_solver *s, int64_t n)
 {
     int rc;
     int64_t len = std::min<int64_t>(s->opt.graph_sweeps, s->hist_chunk) & ~int64_t(1);
-    const bool graphs = len >= 2 && !s->prof;
+    // capturing costs about as much host time as launching the block eagerly
+    // plus the instantiation, so a solver captures once it replays often: in
+    // its second run of sweeps, or in a first run of at least kCaptureBlocks
+    // blocks (a one-shot solve of a few hundred sweeps stays eager)
+    constexpr int64_t kCaptureBlocks = 8;
+    const bool graphs = len >= 2 && !s->prof && (s->graph || s->sweep_runs > 0 || n >= kCaptureBlocks * len);
+    ++s->sweep_runs;
     int64_t k = 0;
     // the differences may have changed since the last sweep (state load,
     // reset, rounding): fused averaging reads its copy of them
